@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the real-space Kohn-Sham H*psi / Taylor(4) propagation path.
+
+Default workload (one GPU): the sphere of radius 18 bohr at h = 0.2 bohr
+(3,053,617 points, padded box 181^3), 64 complex128 white-noise orbitals,
+16 Gaussian wells with 4 separable projectors each; K Taylor(4) steps at
+dt = 0.005.  One step = 4 applications of H to the whole batch.
+
+Prints ONE JSON line: throughput in grid-point x orbital H-applications per
+second, the roofline of the dominant (stencil) kernel measured with HIP
+events inside the timed region, and the FP64 oracle timed on the host on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "H·ψ grid-pt·orbital updates/s"
+UNIT = "pt·orb·H/s"
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stencil_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1501_05654_amd", "csrc", "stencil.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM bytes per stencil launch from the committed rocprofv3 counter
+    summary, if it was taken on the current stencil source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_stencil_{workload}.txt")
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    for line in open(p):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("stencil_source_sha256") != stencil_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_sphere_inputs(cfg, positions):
+    import synth
+    wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
+    V = synth.well_potential(positions, wells)
+    proj = synth.kb_projectors(cfg["seed"], positions, wells.centres)
+    return V, proj
+
+
+def cpu_baseline(cfg, seconds: float):
+    """The FP64 oracle on the host: one Taylor(4) step over the full grid on
+    a sample of the orbitals sized to take about `seconds`."""
+    import oracle
+    import synth
+    t0 = time.perf_counter()
+    og = oracle.Grid(cfg["h"], R=cfg["R"])
+    V, proj = build_sphere_inputs(cfg, og.positions())
+    oh = oracle.Ham(og, V=V, kin=-0.5, projectors=proj)
+    psi1 = synth.white_noise(cfg["seed"], og.np, 1, cfg["h"])
+    t = time.perf_counter()
+    oracle.hpsi(oh, psi1)
+    per_orb_h = time.perf_counter() - t
+    n_orb = int(max(1, min(cfg["nst"], round(seconds / (4.0 * per_orb_h)))))
+    psi = synth.white_noise(cfg["seed"], og.np, n_orb, cfg["h"])
+    t = time.perf_counter()
+    oracle.taylor_step(oh, psi, cfg["dt"])
+    el = time.perf_counter() - t
+    log(f"cpu baseline: {n_orb} orbitals, {el:.1f} s (setup {t - t0:.1f} s)")
+    return {
+        "value": og.np * n_orb * 4 / el,
+        "unit": UNIT,
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"1 Taylor(4) step (4 H applications) over all {og.np} points for "
+                  f"{n_orb} of the {cfg['nst']} orbitals, FP64 C oracle, OpenMP over points",
+    }
+
+
+def bench_sphere(args):
+    import numpy as np
+    import torch
+
+    import paper_1501_05654_amd as rsg
+    import synth
+
+    cfg = dict(synth.WORKLOADS[args.workload])
+    torch.cuda.set_device(0)
+    log("grid")
+    gg = rsg.Grid(cfg["h"], R=cfg["R"])
+    pos = gg.positions()
+    V, proj = build_sphere_inputs(cfg, pos)
+    log(f"np={gg.np}, generating {cfg['nst']} orbitals")
+    psi_h = synth.white_noise(cfg["seed"], gg.np, cfg["nst"], cfg["h"])
+    dev = torch.device("cuda:0")
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
+                         projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
+                                     for i, p, E in zip(proj.idx, proj.p, proj.E)])
+    psi = torch.from_numpy(psi_h).to(dev)
+    del psi_h
+    nst = cfg["nst"]
+    ws = torch.empty(gh.workspace_bytes("step", nst, nst), dtype=torch.uint8, device=dev)
+    dt = cfg["dt"]
+    log(f"warmup {args.warmup} steps")
+    rsg.propagate(gh, psi, dt, args.warmup, ws=ws)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    with rsg.kernel_timing() as kt:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rsg.propagate(gh, psi, dt, args.steps, ws=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    el = t1 - t0
+    npts = gg.np
+    value = npts * nst * 4 * args.steps / el
+    # algorithmic HBM bytes of the stencil stages of one step: stage 1 reads
+    # psi and writes w (32 B per point-orbital), stages 2-4 read w and psi and
+    # write (48 B); each stage reads V once (8 B per point)
+    stage_bytes = (npts * nst * (32 + 3 * 48) + 4 * 8 * npts) / 4.0
+    achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
+    traffic = read_traffic(args.workload)
+    norms = rsg.norm2(gg, psi).cpu().numpy()
+    log(f"{el * 1e3 / args.steps:.3f} ms/step, stencil {kt.mean_ms:.4f} ms x {kt.count}, "
+        f"norm range [{norms.min():.6f}, {norms.max():.6f}]")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "np": npts, "nst": nst, "natoms": cfg["natoms"],
+                   "R_bohr": cfg["R"], "h_bohr": cfg["h"], "dt": dt, "taylor_order": 4,
+                   "stencil": "8th-order 25-point star"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": traffic, "kernel": "k_stencil (Horner stage)",
+                     "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
+                     "algorithmic_bytes_per_launch": stage_bytes},
+    }
+    del psi, ws
+    torch.cuda.empty_cache()
+    return out, cfg
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sphere18_wells", choices=["sphere18_wells"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target duration of the oracle CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the path shards over orbitals or systems "
+              "with no exchange, and this build measures the single-GPU share only "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    out, cfg = bench_sphere(args)
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

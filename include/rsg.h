@@ -1,0 +1,270 @@
+/*
+ * rsg.h -- C ABI of the MI355X real-space-grid Kohn-Sham library.
+ *
+ * The library applies the Kohn-Sham Hamiltonian
+ *
+ *     H = kin * Lap_h + V(r) + E * x_axis + sum_a sum_i |p_i^a> E_i^a <p_i^a|
+ *
+ * to a batch ("group of states") of orbitals sampled on a uniform grid
+ * restricted to a spherical or cubic simulation box, and propagates the
+ * batch in time with a 4th-order Taylor expansion of exp(-i dt H).
+ *
+ *   - Uniform grid, integrals as h^3-weighted grid sums, high-order finite
+ *     differences for the Laplacian: section "Introduction".  Lap_h is the
+ *     8th-order 25-point star; orbitals vanish outside the box.
+ *   - Fields are linear arrays over the box points with the grid structure
+ *     held separately; the basic object is a group of several states:
+ *     section "Parallelization, optimizations and graphics processing units".
+ *   - Non-local pseudopotential projectors: section "Magnetic response and
+ *     gauge invariance in real-space grids" (separable form, 4 real
+ *     projectors per atom).
+ *   - Discrete evolution operator U(dt) applied step after step: section
+ *     "Photoemission".
+ *   - Optimal-control gradient eq. (qoctgradient) with a backward-propagated
+ *     costate and a field parametrised by sine (Fourier) coefficients:
+ *     section "Quantum optimal control".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Layout     An orbital batch is [np][ld] complex, interleaved re/im, with
+ *             the orbital index fastest (batch-packed); nst <= ld orbitals
+ *             are used, columns nst..ld-1 are neither read nor written.
+ *             Compact point order is z-major, then y, then x.
+ *  Dtypes     RSG_C128: complex128 (FP64) everywhere.
+ *             RSG_C64_MIXED: the orbital batch the caller passes is still
+ *             complex128; the Hamiltonian arithmetic (stencil, local
+ *             potential, projectors) runs in FP32 on complex64 copies while
+ *             the time-step accumulation of psi stays in FP64.
+ *  Memory     Every pointer named *_dev, and every orbital/workspace
+ *             pointer, is device memory owned by the caller.  Handles are
+ *             opaque, owned by the library, released by rsg_*_destroy; a
+ *             handle keeps its own copies of every table it was given.
+ *  Streams    `stream` is a hipStream_t passed as void* (NULL = default
+ *             stream).  Work is enqueued asynchronously on it; results in
+ *             device memory are ready when the stream reaches them.
+ *  Workspace  Entry points that need scratch device memory take (ws,
+ *             ws_bytes); rsg_workspace_bytes() gives the size.
+ *  Errors     0 on success, a negative RSG_E* code on failure.  Argument
+ *             errors are detected before anything is enqueued.
+ *             rsg_last_error() returns a thread-local message describing
+ *             the last failure.  No C++ exception crosses this interface.
+ */
+#ifndef RSG_H
+#define RSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RSG_OK = 0,
+    RSG_EINVAL = -1,       /* null pointer, bad enum, negative size ... */
+    RSG_ESHAPE = -2,       /* nst > ld, sizes inconsistent with the grid */
+    RSG_EDTYPE = -3,       /* unknown dtype */
+    RSG_EHIP = -4,         /* a HIP runtime call failed */
+    RSG_ENOMEM = -5,       /* workspace too small or allocation failed */
+    RSG_EUNSUPPORTED = -6  /* valid request this build does not serve */
+};
+
+enum { RSG_C128 = 0, RSG_C64_MIXED = 1 };
+enum { RSG_BOX_CUBE = 0, RSG_BOX_SPHERE = 1 };
+
+/* Operations for rsg_workspace_bytes. */
+enum {
+    RSG_OP_HPSI = 0,
+    RSG_OP_STEP = 1,
+    RSG_OP_REDUCE = 2,     /* rsg_dot, rsg_norm2, rsg_dipole_expectation */
+    RSG_OP_ENERGY = 3,
+    RSG_OP_ADJOINT = 4
+};
+
+typedef struct rsg_grid_s *rsg_grid_t;
+typedef struct rsg_ham_s *rsg_ham_t;
+typedef struct rsg_batch_s *rsg_batch_t;
+
+/* ------------------------------------------------------------------ */
+/* Grid                                                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t shape;   /* RSG_BOX_CUBE or RSG_BOX_SPHERE */
+    int32_t n;       /* cube: points per axis (>= 1) */
+    double radius;   /* sphere: radius in bohr (> 0) */
+    double h;        /* grid spacing in bohr (> 0) */
+} rsg_grid_desc;
+
+/* Uniform grid restricted to the box ("Introduction"; "Parallelization,
+ * optimizations and graphics processing units": linear arrays plus grid
+ * metadata).  Sphere: the centre is a grid point and centred integer
+ * offsets (i,j,k) are inside iff i^2+j^2+k^2 <= floor((radius/h)^2 + 1e-9).
+ * Cube: n^3 points, positions h*(i - (n-1)/2) per axis.  The box membership
+ * and compact numbering are computed by GPU kernels on `stream`; the call
+ * returns once the point count is known.  Errors: RSG_EINVAL for a bad
+ * descriptor, RSG_EHIP on a runtime failure. */
+int rsg_grid_create(const rsg_grid_desc *desc, void *stream, rsg_grid_t *out);
+
+/* np: number of box points; dims: tight bounding box (x, y, z); h. Any
+ * output pointer may be NULL. */
+int rsg_grid_info(rsg_grid_t g, int64_t *np, int32_t dims[3], double *h);
+
+/* Host copies: ijk_host [np][3] int32 box coordinates (0 <= ijk < dims),
+ * xyz_host [np][3] float64 positions in bohr. */
+int rsg_grid_coords(rsg_grid_t g, int32_t *ijk_host);
+int rsg_grid_positions(rsg_grid_t g, double *xyz_host);
+int rsg_grid_destroy(rsg_grid_t g);
+
+/* ------------------------------------------------------------------ */
+/* Hamiltonian                                                         */
+/* ------------------------------------------------------------------ */
+
+/* One atom's separable projectors (4 real functions on its support S_a). */
+typedef struct {
+    int64_t n_support;   /* |S_a| >= 0 */
+    const int32_t *idx;  /* device [n_support]: distinct compact indices */
+    const double *p;     /* device [n_support][4]: p_i^a at those points */
+    double E[4];         /* projector energies E_i^a (Hartree) */
+} rsg_proj_desc;
+
+/* H = kin*Lap_h + V + field*x_axis + sum_a sum_i |p_i^a> E_i^a h^3 <p_i^a|.
+ * vloc_dev: device [np] float64 local potential (NULL = 0).  kin: -0.5 for
+ * the Kohn-Sham kinetic energy.  dipole_axis: 0, 1, 2 (x, y, z) or -1.
+ * The handle copies V and every projector table; the grid must outlive the
+ * handle.  Errors: RSG_EINVAL (bad axis, null tables with n_support > 0,
+ * index out of range), RSG_EHIP. */
+int rsg_ham_create(rsg_grid_t g, const double *vloc_dev, double kin, int32_t dipole_axis,
+                   int32_t natoms, const rsg_proj_desc *proj, rsg_ham_t *out);
+int rsg_ham_destroy(rsg_ham_t H);
+
+/* Scratch device bytes an operation needs for a batch of nst orbitals with
+ * leading dimension ld (0 when none). */
+size_t rsg_workspace_bytes(rsg_ham_t H, int32_t op, int64_t nst, int64_t ld, int32_t dtype);
+
+/* hpsi = H psi at the given field value ("application of a Hamiltonian" as
+ * a building block, section "Parallelization, optimizations and graphics
+ * processing units").  psi and hpsi: device [np][ld] complex128, must not
+ * overlap.  dtype RSG_C128 only.  ws: RSG_OP_HPSI bytes. */
+int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ld, int32_t dtype,
+             double field, void *ws, size_t ws_bytes, void *stream);
+
+/* One Taylor(4) step in place: psi <- sum_{k=0}^{4} (-i dt H)^k / k! psi,
+ * with H taken at `field` (the field at the step midpoint); the discrete
+ * evolution operator of section "Photoemission".  psi: device [np][ld]
+ * complex128.  dtype RSG_C128 or RSG_C64_MIXED.  ws: RSG_OP_STEP bytes. */
+int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+                       double field, void *ws, size_t ws_bytes, void *stream);
+
+/* nsteps Taylor(4) steps; step n uses fields_dev[n] (device float64
+ * [nsteps]) or zero field when fields_dev is NULL.  use_graph != 0 captures
+ * the step sequence into a HIP graph once per distinct argument set and
+ * replays it.  Same buffers as rsg_propagate_step. */
+int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+                  int64_t nsteps, const double *fields_dev, int32_t use_graph, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Reductions: <a|b> = h^3 sum_r conj(a(r)) b(r), per orbital           */
+/* (integration as a grid sum, section "Introduction").  Deterministic:  */
+/* fixed two-pass order, identical results run to run.                 */
+/* ------------------------------------------------------------------ */
+
+/* Scratch bytes for rsg_dot / rsg_norm2 / rsg_dipole_expectation. */
+size_t rsg_reduce_workspace_bytes(rsg_grid_t g, int64_t nst);
+
+/* out_dev: device float64 [2*nst] (re, im per orbital). ws: RSG_OP_REDUCE. */
+int rsg_dot(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ld, double *out_dev,
+            void *ws, size_t ws_bytes, void *stream);
+/* out_dev: device float64 [nst], h^3 sum |a|^2. */
+int rsg_norm2(rsg_grid_t g, const void *a, int64_t nst, int64_t ld, double *out_dev, void *ws,
+              size_t ws_bytes, void *stream);
+/* out_dev: device float64 [2*nst], <psi_n|H psi_n> per orbital (the total
+ * energy is the sum of the real parts). ws: RSG_OP_ENERGY bytes. */
+int rsg_energy(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype, double field,
+               double *out_dev, void *ws, size_t ws_bytes, void *stream);
+/* out_dev: device float64 [nst], h^3 sum x_axis |a|^2 along the
+ * Hamiltonian's dipole axis.  ws: RSG_OP_REDUCE bytes. */
+int rsg_dipole_expectation(rsg_ham_t H, const void *a, int64_t nst, int64_t ld, double *out_dev,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Optimal control (section "Quantum optimal control")                 */
+/* ------------------------------------------------------------------ */
+
+/* E(tau_n) = sum_{k=1}^{ncoef} c_k sin(k pi tau_n / T), tau_n = (step0 + n
+ * + 1/2) dt, for n = 0..nsteps-1.  coef_dev device [ncoef], out_dev device
+ * [nsteps]. */
+int rsg_laser_field(const double *coef_dev, int32_t ncoef, double T, double dt, int64_t step0,
+                    int64_t nsteps, double *out_dev, void *stream);
+
+/* grad_dev[k-1] = sum_{n<nsteps} sin(k pi tau_n / T) g_dev[n]: the chain rule
+ * from per-step field derivatives to the sine coefficients.  Fixed-order
+ * sums. */
+int rsg_laser_grad(const double *g_dev, int64_t nsteps, double T, double dt, int32_t ncoef,
+                   double *grad_dev, void *stream);
+
+/* One discrete adjoint step for psi_{n+1} = T4(-i dt H_n) psi_n with
+ * H_n = H(field).  In: psi_n, lambda = lambda_{n+1}.  Out: lambda =
+ * T4(+i dt H_n) lambda_{n+1} (the costate one step back), and
+ * g_dev[0] = dJ/dE_n = 2 Re sum_{l=0}^{3} <H^l lambda_{n+1}| x_axis |w_l>,
+ * w_l = sum_{m=0}^{3-l} a_{l+m+1} H^m psi_n, a_j = (-i dt)^j / j!: the
+ * time-discrete form of eq. (qoctgradient).  Needs a dipole axis.
+ * ws: RSG_OP_ADJOINT bytes. */
+int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, int64_t ld,
+                     double dt, double field, double *g_dev, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Scratch bytes for rsg_control_forward / rsg_control_backward with these
+ * sizes (the checkpoint store is separate and owned by the caller). */
+size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ld, int64_t nsteps,
+                                   int64_t ckpt_every);
+
+/* Forward pass of the control problem: nsteps Taylor(4) steps of psi (in:
+ * psi(0), out: psi(T), T = nsteps*dt) under the field of coef_dev, storing
+ * psi at every step that is a multiple of ckpt_every (step 0 included) in
+ * ckpt_dev [nsteps/ckpt_every + 1][np][ld] complex128.  J_dev[0] =
+ * sum_n <psi_n(T)| x_axis |psi_n(T)>.  ckpt_dev may be NULL (no checkpoints
+ * kept).  ws: rsg_control_workspace_bytes. */
+int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, double dt,
+                        int64_t nsteps, const double *coef_dev, int32_t ncoef,
+                        int64_t ckpt_every, void *ckpt_dev, double *J_dev, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Backward pass: lambda_N = x_axis psi(T); segment by segment, newest
+ * first, recompute the segment's states from its checkpoint, then take
+ * adjoint steps back through it.  grad_dev [ncoef] = dJ/dc; g_steps_dev
+ * [nsteps] (may be NULL) = dJ/dE_n.  psi_T: device [np][ld], unchanged.
+ * ws: rsg_control_workspace_bytes. */
+int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld, double dt,
+                         int64_t nsteps, const double *coef_dev, int32_t ncoef,
+                         int64_t ckpt_every, const void *ckpt_dev, double *grad_dev,
+                         double *g_steps_dev, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Misc                                                                */
+/* ------------------------------------------------------------------ */
+
+/* Thread-local description of the last failure ("" if none). */
+const char *rsg_last_error(void);
+
+/* Library version string. */
+const char *rsg_version(void);
+
+/* Plain device copy of n bytes (16-byte aligned pointers, n % 16 == 0),
+ * one read and one write per byte; used to calibrate HBM traffic counters
+ * and to measure achievable copy bandwidth. */
+int rsg_copy(const void *src, void *dst, size_t nbytes, void *stream);
+
+/* Kernel timing.  While enabled, the library records a HIP event pair
+ * around every launch of the stencil kernel on the launch stream; the
+ * query returns the number of timed launches and their mean duration in
+ * milliseconds (synchronising on the recorded events), then clears them. */
+int rsg_timing_enable(int32_t on);
+int rsg_timing_query(int64_t *count, double *mean_ms, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSG_H */

@@ -1,0 +1,409 @@
+"""MI355X real-space Kohn-Sham H*psi library: thin Python binding.
+
+Argument marshalling only.  Every numeric step runs in the HIP kernels of
+``librsg.so`` (built from ``csrc/`` by ``build.py``); PyTorch supplies device
+memory and the current stream.  Importing this package fails if the library
+has not been built: there is no CPU fallback.
+
+Orbital batches are ``torch.complex128`` CUDA tensors of shape [np, ld]
+(orbital index fastest, compact point order); ``nst <= ld`` columns are
+used.  See ``include/rsg.h`` for the definition of every entry point.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+__all__ = [
+    "RSGError", "Grid", "Hamiltonian", "hpsi", "propagate_step", "propagate", "dot", "norm2",
+    "energy", "dipole_expectation", "adjoint_step", "laser_field", "laser_grad",
+    "control_forward", "control_backward", "OptimalControlJ", "copy", "kernel_timing",
+    "C128", "MIXED", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsg.so")
+
+C128, MIXED = 0, 1
+_OP = {"hpsi": 0, "step": 1, "reduce": 2, "energy": 3, "adjoint": 4}
+
+
+class RSGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rsg error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_1501_05654_amd/build.py`")
+    L = C.CDLL(LIB_PATH)
+    i32, i64, dbl, vp, sz = C.c_int32, C.c_int64, C.c_double, C.c_void_p, C.c_size_t
+    sig = {
+        "rsg_grid_create": (C.c_int, [vp, vp, vp]),
+        "rsg_grid_info": (C.c_int, [vp, vp, vp, vp]),
+        "rsg_grid_coords": (C.c_int, [vp, vp]),
+        "rsg_grid_positions": (C.c_int, [vp, vp]),
+        "rsg_grid_destroy": (C.c_int, [vp]),
+        "rsg_ham_create": (C.c_int, [vp, vp, dbl, i32, i32, vp, vp]),
+        "rsg_ham_destroy": (C.c_int, [vp]),
+        "rsg_workspace_bytes": (sz, [vp, i32, i64, i64, i32]),
+        "rsg_hpsi": (C.c_int, [vp, vp, vp, i64, i64, i32, dbl, vp, sz, vp]),
+        "rsg_propagate_step": (C.c_int, [vp, vp, i64, i64, i32, dbl, dbl, vp, sz, vp]),
+        "rsg_propagate": (C.c_int, [vp, vp, i64, i64, i32, dbl, i64, vp, i32, vp, sz, vp]),
+        "rsg_dot": (C.c_int, [vp, vp, vp, i64, i64, vp, vp, sz, vp]),
+        "rsg_norm2": (C.c_int, [vp, vp, i64, i64, vp, vp, sz, vp]),
+        "rsg_energy": (C.c_int, [vp, vp, i64, i64, i32, dbl, vp, vp, sz, vp]),
+        "rsg_dipole_expectation": (C.c_int, [vp, vp, i64, i64, vp, vp, sz, vp]),
+        "rsg_laser_field": (C.c_int, [vp, i32, dbl, dbl, i64, i64, vp, vp]),
+        "rsg_laser_grad": (C.c_int, [vp, i64, dbl, dbl, i32, vp, vp]),
+        "rsg_adjoint_step": (C.c_int, [vp, vp, vp, i64, i64, dbl, dbl, vp, vp, sz, vp]),
+        "rsg_control_workspace_bytes": (sz, [vp, i64, i64, i64, i64]),
+        "rsg_reduce_workspace_bytes": (sz, [vp, i64]),
+        "rsg_control_forward": (C.c_int, [vp, vp, i64, i64, dbl, i64, vp, i32, i64, vp, vp, vp,
+                                          sz, vp]),
+        "rsg_control_backward": (C.c_int, [vp, vp, i64, i64, dbl, i64, vp, i32, i64, vp, vp, vp,
+                                           vp, sz, vp]),
+        "rsg_last_error": (C.c_char_p, []),
+        "rsg_version": (C.c_char_p, []),
+        "rsg_copy": (C.c_int, [vp, vp, sz, vp]),
+        "rsg_timing_enable": (C.c_int, [i32]),
+        "rsg_timing_query": (C.c_int, [vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib = _load()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise RSGError(rc, _lib.rsg_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _batch(t: torch.Tensor, name: str, np_: int, dtype=torch.complex128) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == dtype and t.dim() == 2 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor [np, ld]")
+    if t.shape[0] != np_:
+        raise ValueError(f"{name} has {t.shape[0]} rows, grid has {np_} points")
+    return t
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class _ProjDesc(C.Structure):
+    _fields_ = [("n_support", C.c_int64), ("idx", C.c_void_p), ("p", C.c_void_p),
+                ("E", C.c_double * 4)]
+
+
+class _GridDesc(C.Structure):
+    _fields_ = [("shape", C.c_int32), ("n", C.c_int32), ("radius", C.c_double), ("h", C.c_double)]
+
+
+class Grid:
+    """Uniform grid restricted to a sphere (radius R) or a cube (n per axis)."""
+
+    def __init__(self, h: float, *, R: float | None = None, n: int | None = None):
+        if (R is None) == (n is None):
+            raise ValueError("give exactly one of R (sphere) or n (cube)")
+        d = _GridDesc(1 if R is not None else 0, int(n or 0), float(R or 0.0), float(h))
+        self._h = C.c_void_p()
+        _check(_lib.rsg_grid_create(C.byref(d), _stream(), C.byref(self._h)))
+        np_ = C.c_int64()
+        dims = (C.c_int32 * 3)()
+        hh = C.c_double()
+        _check(_lib.rsg_grid_info(self._h, C.byref(np_), dims, C.byref(hh)))
+        self.np = int(np_.value)
+        self.dims = tuple(int(x) for x in dims)
+        self.h = float(hh.value)
+        self.R, self.n = R, n
+
+    def coords(self) -> np.ndarray:
+        out = np.empty((self.np, 3), dtype=np.int32)
+        _check(_lib.rsg_grid_coords(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def positions(self) -> np.ndarray:
+        out = np.empty((self.np, 3), dtype=np.float64)
+        _check(_lib.rsg_grid_positions(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rsg_grid_destroy(h)
+            self._h = None
+
+
+class Hamiltonian:
+    """H = kin*Lap_h + V + field*x_axis + separable projectors.
+
+    V: CUDA float64 [np] or None.  projectors: list of (idx int32 CUDA [n],
+    p float64 CUDA [n, 4], E sequence of 4 floats).  The library copies
+    every table."""
+
+    def __init__(self, grid: Grid, V: torch.Tensor | None = None, kin: float = -0.5,
+                 dipole_axis: int = -1, projectors=None):
+        self.grid = grid
+        self.axis = int(dipole_axis)
+        projectors = list(projectors or [])
+        descs = (_ProjDesc * max(1, len(projectors)))()
+        keep = []
+        for k, (idx, p, E) in enumerate(projectors):
+            idx = idx.to(torch.int32).contiguous()
+            p = p.to(torch.float64).contiguous()
+            if not (idx.is_cuda and p.is_cuda and p.shape == (idx.shape[0], 4)):
+                raise ValueError("projector tables must be CUDA tensors idx[n], p[n,4]")
+            keep += [idx, p]
+            descs[k] = _ProjDesc(idx.shape[0], idx.data_ptr(), p.data_ptr(),
+                                 (C.c_double * 4)(*[float(e) for e in E]))
+        if V is not None:
+            V = V.to(torch.float64).contiguous()
+            if not V.is_cuda or V.numel() != grid.np:
+                raise ValueError("V must be a CUDA float64 tensor with np entries")
+        self._h = C.c_void_p()
+        torch.cuda.synchronize()  # tables written on any stream are complete
+        _check(_lib.rsg_ham_create(grid._h, _ptr(V), float(kin), self.axis, len(projectors),
+                                   descs, C.byref(self._h)))
+        torch.cuda.synchronize()
+        self.natoms = len(projectors)
+
+    def workspace_bytes(self, op: str, nst: int, ld: int, dtype: int = C128) -> int:
+        return int(_lib.rsg_workspace_bytes(self._h, _OP[op], nst, ld, dtype))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rsg_ham_destroy(h)
+            self._h = None
+
+
+def _nst(t, nst):
+    return t.shape[1] if nst is None else int(nst)
+
+
+def hpsi(ham: Hamiltonian, psi: torch.Tensor, field: float = 0.0, out: torch.Tensor | None = None,
+         nst: int | None = None) -> torch.Tensor:
+    _batch(psi, "psi", ham.grid.np)
+    out = torch.zeros_like(psi) if out is None else _batch(out, "out", ham.grid.np)
+    n = _nst(psi, nst)
+    ws = _ws(ham.workspace_bytes("hpsi", n, psi.shape[1]), psi.device)
+    _check(_lib.rsg_hpsi(ham._h, _ptr(psi), _ptr(out), n, psi.shape[1], C128, float(field),
+                         _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def _dt(dtype) -> int:
+    return {"c128": C128, "mixed": MIXED, C128: C128, MIXED: MIXED}[dtype]
+
+
+def propagate_step(ham: Hamiltonian, psi: torch.Tensor, dt: float, field: float = 0.0,
+                   dtype="c128", nst: int | None = None, ws: torch.Tensor | None = None):
+    """One Taylor(4) step in place."""
+    _batch(psi, "psi", ham.grid.np)
+    n = _nst(psi, nst)
+    need = ham.workspace_bytes("step", n, psi.shape[1], _dt(dtype))
+    ws = _ws(need, psi.device) if ws is None or ws.numel() < need else ws
+    _check(_lib.rsg_propagate_step(ham._h, _ptr(psi), n, psi.shape[1], _dt(dtype), float(dt),
+                                   float(field), _ptr(ws), ws.numel(), _stream()))
+    return psi
+
+
+def propagate(ham: Hamiltonian, psi: torch.Tensor, dt: float, nsteps: int,
+              fields: torch.Tensor | None = None, graph: bool = False, dtype="c128",
+              nst: int | None = None, ws: torch.Tensor | None = None):
+    """nsteps Taylor(4) steps in place; fields: CUDA float64 [nsteps] or None."""
+    _batch(psi, "psi", ham.grid.np)
+    n = _nst(psi, nst)
+    if fields is not None and (not fields.is_cuda or fields.dtype != torch.float64
+                               or fields.numel() < nsteps):
+        raise ValueError("fields must be a CUDA float64 tensor with nsteps entries")
+    need = ham.workspace_bytes("step", n, psi.shape[1], _dt(dtype))
+    ws = _ws(need, psi.device) if ws is None or ws.numel() < need else ws
+    _check(_lib.rsg_propagate(ham._h, _ptr(psi), n, psi.shape[1], _dt(dtype), float(dt),
+                              int(nsteps), _ptr(fields), 1 if graph else 0, _ptr(ws), ws.numel(),
+                              _stream()))
+    return psi
+
+
+def _grid_of(g):
+    return g.grid if isinstance(g, Hamiltonian) else g
+
+
+def _reduce_ws(grid: Grid, n, device):
+    return _ws(int(_lib.rsg_reduce_workspace_bytes(grid._h, n)), device)
+
+
+def dot(grid: Grid | Hamiltonian, a: torch.Tensor, b: torch.Tensor,
+        nst: int | None = None) -> torch.Tensor:
+    """<a_n|b_n> = h^3 sum conj(a) b per orbital -> complex128 CUDA [nst]."""
+    grid = _grid_of(grid)
+    _batch(a, "a", grid.np)
+    _batch(b, "b", grid.np)
+    if a.shape != b.shape:
+        raise ValueError("a and b must have the same shape")
+    n = _nst(a, nst)
+    out = torch.empty(2 * n, dtype=torch.float64, device=a.device)
+    ws = _reduce_ws(grid, n, a.device)
+    _check(_lib.rsg_dot(grid._h, _ptr(a), _ptr(b), n, a.shape[1], _ptr(out), _ptr(ws),
+                        ws.numel(), _stream()))
+    return torch.view_as_complex(out.view(n, 2))
+
+
+def norm2(grid: Grid | Hamiltonian, a: torch.Tensor, nst: int | None = None) -> torch.Tensor:
+    """h^3 sum |a_n|^2 per orbital -> float64 CUDA [nst]."""
+    grid = _grid_of(grid)
+    _batch(a, "a", grid.np)
+    n = _nst(a, nst)
+    out = torch.empty(n, dtype=torch.float64, device=a.device)
+    ws = _reduce_ws(grid, n, a.device)
+    _check(_lib.rsg_norm2(grid._h, _ptr(a), n, a.shape[1], _ptr(out), _ptr(ws), ws.numel(),
+                          _stream()))
+    return out
+
+
+def energy(ham: Hamiltonian, psi: torch.Tensor, field: float = 0.0,
+           nst: int | None = None) -> torch.Tensor:
+    """<psi_n|H psi_n> per orbital -> complex128 CUDA [nst]."""
+    _batch(psi, "psi", ham.grid.np)
+    n = _nst(psi, nst)
+    out = torch.empty(2 * n, dtype=torch.float64, device=psi.device)
+    ws = _ws(ham.workspace_bytes("energy", n, psi.shape[1]), psi.device)
+    _check(_lib.rsg_energy(ham._h, _ptr(psi), n, psi.shape[1], C128, float(field), _ptr(out),
+                           _ptr(ws), ws.numel(), _stream()))
+    return torch.view_as_complex(out.view(n, 2))
+
+
+def dipole_expectation(ham: Hamiltonian, a: torch.Tensor, nst: int | None = None) -> torch.Tensor:
+    _batch(a, "a", ham.grid.np)
+    n = _nst(a, nst)
+    out = torch.empty(n, dtype=torch.float64, device=a.device)
+    ws = _reduce_ws(ham.grid, n, a.device)
+    _check(_lib.rsg_dipole_expectation(ham._h, _ptr(a), n, a.shape[1], _ptr(out), _ptr(ws),
+                                       ws.numel(), _stream()))
+    return out
+
+
+def adjoint_step(ham: Hamiltonian, psi_n: torch.Tensor, lam: torch.Tensor, dt: float,
+                 field: float, nst: int | None = None) -> torch.Tensor:
+    """lam <- T4(+i dt H) lam in place; returns g_n = dJ/dE_n (CUDA float64 [1])."""
+    _batch(psi_n, "psi_n", ham.grid.np)
+    _batch(lam, "lambda", ham.grid.np)
+    n = _nst(psi_n, nst)
+    g = torch.zeros(1, dtype=torch.float64, device=psi_n.device)
+    ws = _ws(ham.workspace_bytes("adjoint", n, psi_n.shape[1]), psi_n.device)
+    _check(_lib.rsg_adjoint_step(ham._h, _ptr(psi_n), _ptr(lam), n, psi_n.shape[1], float(dt),
+                                 float(field), _ptr(g), _ptr(ws), ws.numel(), _stream()))
+    return g
+
+
+def laser_field(coef: torch.Tensor, T: float, dt: float, nsteps: int, step0: int = 0) -> torch.Tensor:
+    out = torch.empty(int(nsteps), dtype=torch.float64, device=coef.device)
+    c = coef.to(torch.float64).contiguous()
+    _check(_lib.rsg_laser_field(_ptr(c), c.numel(), float(T), float(dt), int(step0), int(nsteps),
+                                _ptr(out), _stream()))
+    return out
+
+
+def laser_grad(g: torch.Tensor, T: float, dt: float, ncoef: int) -> torch.Tensor:
+    out = torch.empty(int(ncoef), dtype=torch.float64, device=g.device)
+    gg = g.to(torch.float64).contiguous()
+    _check(_lib.rsg_laser_grad(_ptr(gg), gg.numel(), float(T), float(dt), int(ncoef), _ptr(out),
+                               _stream()))
+    return out
+
+
+def _control_ws(ham, n, ld, nsteps, ckpt, device):
+    return _ws(int(_lib.rsg_control_workspace_bytes(ham._h, n, ld, nsteps, ckpt)), device)
+
+
+def control_forward(ham: Hamiltonian, psi: torch.Tensor, dt: float, nsteps: int,
+                    coef: torch.Tensor, ckpt_every: int, keep_checkpoints: bool = True):
+    """Propagate psi in place to T = nsteps*dt under the sine-series field.
+    Returns (J as CUDA float64 [1], checkpoint store or None)."""
+    _batch(psi, "psi", ham.grid.np)
+    n, ld = psi.shape[1], psi.shape[1]
+    c = coef.to(torch.float64).contiguous()
+    nck = nsteps // ckpt_every + 1
+    ck = (torch.empty((nck, ham.grid.np, ld), dtype=torch.complex128, device=psi.device)
+          if keep_checkpoints else None)
+    J = torch.zeros(1, dtype=torch.float64, device=psi.device)
+    ws = _control_ws(ham, n, ld, nsteps, ckpt_every, psi.device)
+    _check(_lib.rsg_control_forward(ham._h, _ptr(psi), n, ld, float(dt), int(nsteps), _ptr(c),
+                                    c.numel(), int(ckpt_every), _ptr(ck), _ptr(J), _ptr(ws),
+                                    ws.numel(), _stream()))
+    return J, ck
+
+
+def control_backward(ham: Hamiltonian, psi_T: torch.Tensor, dt: float, nsteps: int,
+                     coef: torch.Tensor, ckpt_every: int, ckpt: torch.Tensor):
+    """(dJ/dc [ncoef], dJ/dE_n [nsteps]) by checkpointed discrete adjoint."""
+    _batch(psi_T, "psi_T", ham.grid.np)
+    n, ld = psi_T.shape[1], psi_T.shape[1]
+    c = coef.to(torch.float64).contiguous()
+    grad = torch.zeros(c.numel(), dtype=torch.float64, device=psi_T.device)
+    gs = torch.zeros(int(nsteps), dtype=torch.float64, device=psi_T.device)
+    ws = _control_ws(ham, n, ld, nsteps, ckpt_every, psi_T.device)
+    _check(_lib.rsg_control_backward(ham._h, _ptr(psi_T), n, ld, float(dt), int(nsteps), _ptr(c),
+                                     c.numel(), int(ckpt_every), _ptr(ckpt), _ptr(grad), _ptr(gs),
+                                     _ptr(ws), ws.numel(), _stream()))
+    return grad, gs
+
+
+class OptimalControlJ(torch.autograd.Function):
+    """J(c) = sum_n <psi_n(T)| x_axis |psi_n(T)> for the field
+    E(t) = sum_k c_k sin(k pi t / T); backward gives dJ/dc by the
+    checkpointed discrete adjoint (section "Quantum optimal control",
+    eq. (qoctgradient))."""
+
+    @staticmethod
+    def forward(ctx, coef, ham, psi0, dt, nsteps, ckpt_every):
+        psi = psi0.detach().clone()
+        J, ck = control_forward(ham, psi, dt, nsteps, coef.detach(), ckpt_every)
+        ctx.ham, ctx.dt, ctx.nsteps, ctx.ckpt_every = ham, dt, nsteps, ckpt_every
+        ctx.save_for_backward(coef.detach(), psi, ck)
+        return J[0]
+
+    @staticmethod
+    def backward(ctx, gJ):
+        coef, psiT, ck = ctx.saved_tensors
+        grad, _ = control_backward(ctx.ham, psiT, ctx.dt, ctx.nsteps, coef, ctx.ckpt_every, ck)
+        return gJ * grad, None, None, None, None, None
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor):
+    nb = src.numel() * src.element_size()
+    _check(_lib.rsg_copy(_ptr(src), _ptr(dst), nb, _stream()))
+
+
+class kernel_timing:
+    """Context manager: HIP-event timing of every stencil-kernel launch.
+    After exit, ``.count`` launches and ``.mean_ms`` average duration."""
+
+    def __enter__(self):
+        _check(_lib.rsg_timing_query(None, None, None))  # drop stale events
+        _check(_lib.rsg_timing_enable(1))
+        return self
+
+    def __exit__(self, *exc):
+        _check(_lib.rsg_timing_enable(0))
+        n, m, t = C.c_int64(), C.c_double(), C.c_double()
+        _check(_lib.rsg_timing_query(C.byref(n), C.byref(m), C.byref(t)))
+        self.count, self.mean_ms, self.total_ms = int(n.value), float(m.value), float(t.value)
+        return False

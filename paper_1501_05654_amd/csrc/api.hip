@@ -1,0 +1,805 @@
+// C-ABI entry points: Hamiltonian handles, H*psi, Taylor(4) propagation,
+// reductions, energy, the discrete adjoint and the checkpointed control
+// gradient.  Everything numeric runs in the kernels of the other units; this
+// file validates arguments, carves workspaces and orders launches.
+#include "rsg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <tuple>
+
+namespace rsg {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+// ------------------------------------------------------------------ timing
+
+namespace {
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+hipEvent_t g_pending = nullptr;
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+}  // namespace
+
+void timing_before(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing || capturing(s)) return;
+    if (hipEventCreate(&g_pending) != hipSuccess) {
+        g_pending = nullptr;
+        return;
+    }
+    (void)hipEventRecord(g_pending, s);
+}
+
+void timing_after(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing || !g_pending) return;
+    hipEvent_t e1;
+    if (hipEventCreate(&e1) != hipSuccess) return;
+    (void)hipEventRecord(e1, s);
+    g_events.emplace_back(g_pending, e1);
+    g_pending = nullptr;
+}
+
+// ------------------------------------------------------------ Ham lifetime
+
+Ham::~Ham() {
+    if (V) (void)hipFree(V);
+    if (V32) (void)hipFree(V32);
+    if (kb_idx) (void)hipFree(kb_idx);
+    if (kb_p) (void)hipFree(kb_p);
+    if (kb_p32) (void)hipFree(kb_p32);
+    if (kb_E) (void)hipFree(kb_E);
+    if (gather_items) (void)hipFree(gather_items);
+    for (auto *p : scatter_items)
+        if (p) (void)hipFree(p);
+}
+
+namespace {
+
+__global__ void k_to_float(const double *src, float *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+__global__ void k_copy16(const int4 *src, int4 *dst, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_sum(const double *v, int64_t n, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += v[i];
+    *out = s;
+}
+
+unsigned nblocks_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+}
+
+// Bump allocator over a caller-provided workspace (256-byte aligned pieces).
+struct Carve {
+    char *base;
+    size_t cap, used = 0;
+    bool ok = true;
+    Carve(void *p, size_t n) : base((char *)p), cap(n) {}
+    void *take(size_t n) {
+        const size_t a = (used + 255) & ~(size_t)255;
+        if (a + n > cap || (!base && n)) {
+            ok = false;
+            return nullptr;
+        }
+        used = a + n;
+        return base + a;
+    }
+    // everything that is left (aligned); *n receives its size
+    void *take_rest(size_t *n) {
+        const size_t a = (used + 255) & ~(size_t)255;
+        if (!base || a >= cap) {
+            ok = false;
+            *n = 0;
+            return nullptr;
+        }
+        *n = cap - a;
+        used = cap;
+        return base + a;
+    }
+};
+
+size_t rounded(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t batch_bytes(const Grid &g, int64_t ld, size_t elem) { return (size_t)g.np * (size_t)ld * elem; }
+
+int check_batch(const Ham *H, const void *p, int64_t nst, int64_t ld, const char *who) {
+    RSG_REQUIRE(H, RSG_EINVAL, "%s: null Hamiltonian", who);
+    RSG_REQUIRE(nst >= 0 && ld >= 1, RSG_ESHAPE, "%s: need nst >= 0 and ld >= 1", who);
+    RSG_REQUIRE(nst <= ld, RSG_ESHAPE, "%s: nst (%lld) > ld (%lld)", who, (long long)nst,
+                (long long)ld);
+    RSG_REQUIRE(p || nst == 0 || H->g->np == 0, RSG_EINVAL, "%s: null orbital pointer", who);
+    RSG_REQUIRE(((uintptr_t)p & 15) == 0, RSG_EINVAL, "%s: orbital pointer not 16-byte aligned", who);
+    return RSG_OK;
+}
+
+// --------------------------------------------------------- internal ops
+
+// out = H(in), FP64.
+int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ld, double field,
+              const double *field_dev, void *D, hipStream_t s) {
+    int rc = launch_kb_gather(H, in, 0, 0, nst, ld, D, s);
+    if (rc) return rc;
+    StageArgs a;
+    a.in = in;
+    a.out = out;
+    a.mode = 0;
+    a.nst = nst;
+    a.ld = ld;
+    a.field = field;
+    a.field_dev = field_dev;
+    rc = launch_stencil(H, a, default_shape(*H.g, nst, 0), s);
+    if (rc) return rc;
+    return launch_kb_scatter(H, out, 0, 0, nst, ld, D, 1.0, 0.0, s);
+}
+
+// One Horner stage: out = base + c H(in).
+int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *out, int out_t,
+               int compute, int64_t nst, int64_t ld, double cre, double cim, double field,
+               const double *field_dev, void *D, hipStream_t s) {
+    int rc = launch_kb_gather(H, in, in_t, compute, nst, ld, D, s);
+    if (rc) return rc;
+    StageArgs a;
+    a.in = in;
+    a.base = base;
+    a.out = out;
+    a.in_t = in_t;
+    a.out_t = out_t;
+    a.compute = compute;
+    a.mode = 1;
+    a.nst = nst;
+    a.ld = ld;
+    a.field = field;
+    a.field_dev = field_dev;
+    a.cre = cre;
+    a.cim = cim;
+    rc = launch_stencil(H, a, default_shape(*H.g, nst, compute), s);
+    if (rc) return rc;
+    return launch_kb_scatter(H, out, out_t, compute, nst, ld, D, cre, cim, s);
+}
+
+size_t step_ws(const Ham &H, int64_t nst, int64_t ld, int32_t dtype) {
+    const size_t e = dtype == RSG_C128 ? 16 : 8;
+    return 2 * rounded(batch_bytes(*H.g, ld, e)) + rounded(kb_workspace_bytes(H, nst)) + 256;
+}
+
+// Taylor(4) in Horner form: y4 = psi, y_{k-1} = psi + (-i dt / k) H y_k,
+// psi <- y0.  Work buffers alternate; the last stage writes psi in place
+// (each output point reads only its own psi value).
+int step_impl(const Ham &H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+              double field, const double *field_dev, void *ws, size_t ws_bytes, hipStream_t s) {
+    const size_t e = dtype == RSG_C128 ? 16 : 8;
+    Carve c(ws, ws_bytes);
+    void *w1 = c.take(batch_bytes(*H.g, ld, e));
+    void *w2 = c.take(batch_bytes(*H.g, ld, e));
+    void *D = c.take(kb_workspace_bytes(H, nst));
+    if (!c.ok) {
+        set_error("propagate: workspace too small (%zu < %zu bytes)", ws_bytes, step_ws(H, nst, ld, dtype));
+        return RSG_ENOMEM;
+    }
+    const int cmp = dtype == RSG_C128 ? 0 : 1;
+    const int wt = dtype == RSG_C128 ? 0 : 1;  // work-buffer type
+    int rc;
+    if ((rc = stage_impl(H, psi, 0, psi, w1, wt, cmp, nst, ld, 0.0, -dt / 4.0, field, field_dev, D, s))) return rc;
+    if ((rc = stage_impl(H, w1, wt, psi, w2, wt, cmp, nst, ld, 0.0, -dt / 3.0, field, field_dev, D, s))) return rc;
+    if ((rc = stage_impl(H, w2, wt, psi, w1, wt, cmp, nst, ld, 0.0, -dt / 2.0, field, field_dev, D, s))) return rc;
+    return stage_impl(H, w1, wt, psi, psi, 0, cmp, nst, ld, 0.0, -dt, field, field_dev, D, s);
+}
+
+size_t adjoint_ws(const Ham &H, int64_t nst, int64_t ld) {
+    return 7 * rounded(batch_bytes(*H.g, ld, 16)) + rounded(kb_workspace_bytes(H, nst)) +
+           rounded(reduce_workspace_bytes(*H.g, nst)) + 256;
+}
+
+// Discrete adjoint of one Taylor(4) step (see rsg_adjoint_step).
+int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int64_t ld, double dt,
+                 double field, const double *field_dev, double *g_dev, void *ws, size_t ws_bytes,
+                 hipStream_t s) {
+    Carve c(ws, ws_bytes);
+    const size_t bb = batch_bytes(*H.g, ld, 16);
+    void *nu[4], *mu[5];
+    nu[0] = const_cast<void *>(psi_n);
+    mu[0] = lambda;
+    for (int k = 1; k < 4; ++k) nu[k] = c.take(bb);
+    for (int k = 1; k < 5; ++k) mu[k] = c.take(bb);
+    void *D = c.take(kb_workspace_bytes(H, nst));
+    const size_t rb = reduce_workspace_bytes(*H.g, nst);
+    void *R = c.take(rb);
+    if (!c.ok) {
+        set_error("adjoint: workspace too small (%zu < %zu bytes)", ws_bytes, adjoint_ws(H, nst, ld));
+        return RSG_ENOMEM;
+    }
+    int rc;
+    for (int k = 1; k < 4; ++k)
+        if ((rc = hpsi_impl(H, nu[k - 1], nu[k], nst, ld, field, field_dev, D, s))) return rc;
+    for (int k = 1; k < 5; ++k)
+        if ((rc = hpsi_impl(H, mu[k - 1], mu[k], nst, ld, field, field_dev, D, s))) return rc;
+    // a_j = (-i dt)^j / j!
+    double2 a[5];
+    a[0] = make_double2(1.0, 0.0);
+    for (int j = 1; j < 5; ++j) {
+        // multiply a[j-1] by (-i dt / j): (x + i y)(-i d) = d y - i d x
+        const double d = dt / j;
+        a[j] = make_double2(d * a[j - 1].y, -d * a[j - 1].x);
+    }
+    double2 pc[16];
+    for (int l = 0; l < 4; ++l)
+        for (int m = 0; m < 4; ++m) pc[4 * l + m] = (l + m <= 3) ? a[l + m + 1] : make_double2(0, 0);
+    const double2 *mup[4] = {(const double2 *)mu[0], (const double2 *)mu[1], (const double2 *)mu[2],
+                             (const double2 *)mu[3]};
+    const double2 *nup[4] = {(const double2 *)nu[0], (const double2 *)nu[1], (const double2 *)nu[2],
+                             (const double2 *)nu[3]};
+    if ((rc = launch_cross_dots(*H.g, H.axis, mup, nup, pc, nst, ld, g_dev, R, rb, s))) return rc;
+    // lambda_n = sum_k conj(a_k) mu_k
+    double2 ca[5];
+    for (int k = 0; k < 5; ++k) ca[k] = make_double2(a[k].x, -a[k].y);
+    const double2 *src[5] = {(const double2 *)mu[0], (const double2 *)mu[1], (const double2 *)mu[2],
+                             (const double2 *)mu[3], (const double2 *)mu[4]};
+    return launch_axpby_list(*H.g, nst, ld, 5, src, ca, (double2 *)lambda, s);
+}
+
+// Graph cache key for rsg_propagate.
+struct GraphKey {
+    const void *psi;
+    int64_t nst, ld;
+    int32_t dtype;
+    double dt;
+    int64_t nsteps;
+    const double *fields;
+    const void *ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(psi, nst, ld, dtype, dt, nsteps, fields, ws, ws_bytes, stream) <
+               std::tie(o.psi, o.nst, o.ld, o.dtype, o.dt, o.nsteps, o.fields, o.ws, o.ws_bytes,
+                        o.stream);
+    }
+};
+
+std::mutex g_graph_mu;
+std::map<const Ham *, std::map<GraphKey, hipGraphExec_t>> g_graphs;
+
+void drop_graphs(const Ham *H) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(H);
+    if (it == g_graphs.end()) return;
+    for (auto &kv : it->second) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.erase(it);
+}
+
+}  // namespace
+
+}  // namespace rsg
+
+using namespace rsg;
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" const char *rsg_last_error(void) { return g_err; }
+extern "C" const char *rsg_version(void) { return "rsg 0.1 (gfx950)"; }
+
+extern "C" int rsg_ham_create(rsg_grid_t g, const double *vloc_dev, double kin, int32_t axis,
+                              int32_t natoms, const rsg_proj_desc *proj, rsg_ham_t *out) {
+    clear_error();
+    RSG_REQUIRE(g && out, RSG_EINVAL, "rsg_ham_create: null argument");
+    RSG_REQUIRE(axis >= -1 && axis <= 2, RSG_EINVAL, "rsg_ham_create: dipole_axis must be -1..2");
+    RSG_REQUIRE(natoms >= 0 && (natoms == 0 || proj), RSG_EINVAL, "rsg_ham_create: bad projector list");
+    RSG_REQUIRE(std::isfinite(kin), RSG_EINVAL, "rsg_ham_create: kinetic prefactor not finite");
+    for (int a = 0; a < natoms; ++a) {
+        RSG_REQUIRE(proj[a].n_support >= 0, RSG_EINVAL, "rsg_ham_create: atom %d negative support", a);
+        RSG_REQUIRE(proj[a].n_support == 0 || (proj[a].idx && proj[a].p), RSG_EINVAL,
+                    "rsg_ham_create: atom %d null projector table", a);
+        RSG_REQUIRE(proj[a].n_support <= g->np, RSG_EINVAL, "rsg_ham_create: atom %d support larger than grid", a);
+    }
+    return guarded([&]() -> int {
+        auto *H = new rsg_ham_s();
+        H->g = g;
+        H->kin = kin;
+        H->axis = axis;
+        H->natoms = natoms;
+        auto fail = [&](const char *what, hipError_t e) {
+            set_error("rsg_ham_create: %s: %s", what, hipGetErrorString(e));
+            delete H;
+            return RSG_EHIP;
+        };
+        hipError_t e;
+        const int64_t np = g->np;
+        if (vloc_dev && np > 0) {
+            if ((e = hipMalloc(&H->V, sizeof(double) * np)) != hipSuccess) return fail("V", e);
+            if ((e = hipMalloc(&H->V32, sizeof(float) * np)) != hipSuccess) return fail("V32", e);
+            if ((e = hipMemcpy(H->V, vloc_dev, sizeof(double) * np, hipMemcpyDeviceToDevice)) != hipSuccess)
+                return fail("V copy", e);
+            k_to_float<<<nblocks_for(np), 256>>>(H->V, H->V32, np);
+        }
+        if (natoms > 0) {
+            // pad every support to a multiple of 16 entries (p = 0, index of
+            // the atom's first point, or 0 for an empty support)
+            H->kb_off.assign(natoms + 1, 0);
+            H->kb_len.assign(natoms, 0);
+            for (int a = 0; a < natoms; ++a) {
+                H->kb_len[a] = proj[a].n_support;
+                const int64_t padded = std::max<int64_t>(16, (proj[a].n_support + 15) / 16 * 16);
+                H->kb_off[a + 1] = H->kb_off[a] + padded;
+            }
+            const int64_t total = H->kb_off[natoms];
+            std::vector<int32_t> idx_h(total, 0);
+            std::vector<double> p_h((size_t)total * 4, 0.0);
+            std::vector<double> E_h((size_t)natoms * 4);
+            for (int a = 0; a < natoms; ++a) {
+                const int64_t n = proj[a].n_support;
+                if (n > 0) {
+                    if ((e = hipMemcpy(idx_h.data() + H->kb_off[a], proj[a].idx, sizeof(int32_t) * n,
+                                       hipMemcpyDeviceToHost)) != hipSuccess)
+                        return fail("projector index copy", e);
+                    if ((e = hipMemcpy(p_h.data() + 4 * H->kb_off[a], proj[a].p, sizeof(double) * 4 * n,
+                                       hipMemcpyDeviceToHost)) != hipSuccess)
+                        return fail("projector value copy", e);
+                }
+                for (int64_t k = n; k < H->kb_off[a + 1] - H->kb_off[a]; ++k)
+                    idx_h[H->kb_off[a] + k] = n > 0 ? idx_h[H->kb_off[a]] : 0;
+                for (int i = 0; i < 4; ++i) E_h[4 * a + i] = proj[a].E[i];
+            }
+            // validate indices: in range and distinct within an atom
+            std::vector<int32_t> mark(np > 0 ? np : 1, -1);
+            for (int a = 0; a < natoms; ++a)
+                for (int64_t k = 0; k < H->kb_len[a]; ++k) {
+                    const int32_t r = idx_h[H->kb_off[a] + k];
+                    if (r < 0 || r >= np) {
+                        set_error("rsg_ham_create: atom %d projector index %d outside [0, %lld)", a, r,
+                                  (long long)np);
+                        delete H;
+                        return RSG_EINVAL;
+                    }
+                    if (mark[r] == a) {
+                        set_error("rsg_ham_create: atom %d lists point %d twice", a, r);
+                        delete H;
+                        return RSG_EINVAL;
+                    }
+                    mark[r] = a;
+                }
+            // greedy colouring: atoms whose supports overlap get different
+            // colours, so one scatter launch never updates a point twice
+            std::vector<int> colour(natoms, -1);
+            std::vector<std::vector<char>> used;
+            for (int a = 0; a < natoms; ++a) {
+                int c = 0;
+                for (;; ++c) {
+                    if (c == (int)used.size()) used.emplace_back(np > 0 ? np : 1, 0);
+                    bool clash = false;
+                    for (int64_t k = 0; k < H->kb_len[a] && !clash; ++k)
+                        clash = used[c][idx_h[H->kb_off[a] + k]] != 0;
+                    if (!clash) break;
+                }
+                colour[a] = c;
+                for (int64_t k = 0; k < H->kb_len[a]; ++k) used[c][idx_h[H->kb_off[a] + k]] = 1;
+            }
+            std::vector<int4> atoms(natoms);
+            std::vector<std::vector<int2>> sc(used.size());
+            for (int a = 0; a < natoms; ++a) {
+                const int64_t padded = H->kb_off[a + 1] - H->kb_off[a];
+                atoms[a] = make_int4((int)H->kb_off[a], (int)padded, (int)H->kb_len[a], a);
+                for (int64_t k = 0; k < H->kb_len[a]; k += 16)
+                    sc[colour[a]].push_back(make_int2(a, (int)(H->kb_off[a] + k)));
+            }
+            if ((e = hipMalloc(&H->kb_idx, sizeof(int32_t) * total)) != hipSuccess) return fail("idx", e);
+            if ((e = hipMalloc(&H->kb_p, sizeof(double) * 4 * total)) != hipSuccess) return fail("p", e);
+            if ((e = hipMalloc(&H->kb_p32, sizeof(float) * 4 * total)) != hipSuccess) return fail("p32", e);
+            if ((e = hipMalloc(&H->kb_E, sizeof(double) * 4 * natoms)) != hipSuccess) return fail("E", e);
+            if ((e = hipMalloc(&H->gather_items, sizeof(int4) * natoms)) != hipSuccess) return fail("atoms", e);
+            if ((e = hipMemcpy(H->kb_idx, idx_h.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice)) != hipSuccess)
+                return fail("idx upload", e);
+            if ((e = hipMemcpy(H->kb_p, p_h.data(), sizeof(double) * 4 * total, hipMemcpyHostToDevice)) != hipSuccess)
+                return fail("p upload", e);
+            if ((e = hipMemcpy(H->kb_E, E_h.data(), sizeof(double) * 4 * natoms, hipMemcpyHostToDevice)) != hipSuccess)
+                return fail("E upload", e);
+            if ((e = hipMemcpy(H->gather_items, atoms.data(), sizeof(int4) * natoms, hipMemcpyHostToDevice)) != hipSuccess)
+                return fail("atom upload", e);
+            k_to_float<<<nblocks_for(4 * total), 256>>>(H->kb_p, H->kb_p32, 4 * total);
+            for (auto &v : sc) {
+                int2 *d = nullptr;
+                if (!v.empty()) {
+                    if ((e = hipMalloc(&d, sizeof(int2) * v.size())) != hipSuccess) return fail("scatter", e);
+                    if ((e = hipMemcpy(d, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+                        (void)hipFree(d);
+                        return fail("scatter upload", e);
+                    }
+                }
+                H->scatter_items.push_back(d);
+                H->scatter_counts.push_back((int32_t)v.size());
+            }
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return fail("conversion", e);
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return fail("sync", e);
+        *out = H;
+        return RSG_OK;
+    });
+}
+
+extern "C" int rsg_ham_destroy(rsg_ham_t H) {
+    clear_error();
+    if (H) drop_graphs(H);
+    delete H;
+    return RSG_OK;
+}
+
+extern "C" size_t rsg_workspace_bytes(rsg_ham_t H, int32_t op, int64_t nst, int64_t ld, int32_t dtype) {
+    if (!H || nst < 0 || ld < 1) return 0;
+    switch (op) {
+        case RSG_OP_HPSI: return rounded(kb_workspace_bytes(*H, nst)) + 256;
+        case RSG_OP_STEP: return step_ws(*H, nst, ld, dtype);
+        case RSG_OP_REDUCE: return reduce_workspace_bytes(*H->g, nst);
+        case RSG_OP_ENERGY:
+            return rounded(batch_bytes(*H->g, ld, 16)) + rounded(kb_workspace_bytes(*H, nst)) +
+                   rounded(reduce_workspace_bytes(*H->g, nst)) + 256;
+        case RSG_OP_ADJOINT: return adjoint_ws(*H, nst, ld);
+        default: return 0;
+    }
+}
+
+extern "C" int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ld,
+                        int32_t dtype, double field, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_batch(H, psi, nst, ld, "rsg_hpsi");
+    if (rc) return rc;
+    RSG_REQUIRE(dtype == RSG_C128, dtype == RSG_C64_MIXED ? RSG_EUNSUPPORTED : RSG_EDTYPE,
+                "rsg_hpsi: dtype must be RSG_C128");
+    RSG_REQUIRE(hpsi || nst == 0, RSG_EINVAL, "rsg_hpsi: null output");
+    RSG_REQUIRE(((uintptr_t)hpsi & 15) == 0, RSG_EINVAL, "rsg_hpsi: output not 16-byte aligned");
+    const size_t bb = batch_bytes(*H->g, ld, 16);
+    const char *a0 = (const char *)psi, *b0 = (const char *)hpsi;
+    RSG_REQUIRE(nst == 0 || a0 + bb <= b0 || b0 + bb <= a0, RSG_EINVAL, "rsg_hpsi: psi and hpsi overlap");
+    Carve c(ws, ws_bytes);
+    void *D = c.take(kb_workspace_bytes(*H, nst));
+    RSG_REQUIRE(c.ok, RSG_ENOMEM, "rsg_hpsi: workspace too small");
+    if (nst == 0 || H->g->np == 0) return RSG_OK;
+    return hpsi_impl(*H, psi, hpsi, nst, ld, field, nullptr, D, (hipStream_t)stream);
+}
+
+extern "C" int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype,
+                                  double dt, double field, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_batch(H, psi, nst, ld, "rsg_propagate_step");
+    if (rc) return rc;
+    RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_propagate_step: bad dtype %d", dtype);
+    RSG_REQUIRE(std::isfinite(dt) && std::isfinite(field), RSG_EINVAL, "rsg_propagate_step: dt/field not finite");
+    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ld, dtype) - 256 || nst == 0, RSG_ENOMEM,
+                "rsg_propagate_step: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ld, dtype));
+    if (nst == 0 || H->g->np == 0) return RSG_OK;
+    return step_impl(*H, psi, nst, ld, dtype, dt, field, nullptr, ws, ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+                             int64_t nsteps, const double *fields_dev, int32_t use_graph, void *ws,
+                             size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_batch(H, psi, nst, ld, "rsg_propagate");
+    if (rc) return rc;
+    RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_propagate: bad dtype %d", dtype);
+    RSG_REQUIRE(nsteps >= 0 && std::isfinite(dt), RSG_EINVAL, "rsg_propagate: bad nsteps/dt");
+    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ld, dtype) - 256 || nst == 0, RSG_ENOMEM,
+                "rsg_propagate: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ld, dtype));
+    if (nst == 0 || H->g->np == 0 || nsteps == 0) return RSG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    auto run = [&]() -> int {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            const int r = step_impl(*H, psi, nst, ld, dtype, dt, 0.0, fields_dev ? fields_dev + n : nullptr,
+                                    ws, ws_bytes, s);
+            if (r) return r;
+        }
+        return RSG_OK;
+    };
+    if (!use_graph) return run();
+    RSG_REQUIRE(s != nullptr, RSG_EINVAL, "rsg_propagate: graph capture needs a non-default stream");
+    // make sure every launch plan exists before capture (plan creation syncs)
+    int err = RSG_OK;
+    for (int cmp = 0; cmp < 2; ++cmp) {
+        TileShape sh = default_shape(*H->g, nst, cmp);
+        if (!H->g->plan(sh, s, &err)) return err;
+    }
+    GraphKey key{psi, nst, ld, dtype, dt, nsteps, fields_dev, ws, ws_bytes, s};
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        auto &m = g_graphs[H];
+        auto it = m.find(key);
+        if (it != m.end()) exec = it->second;
+    }
+    if (!exec) {
+        RSG_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int r = run();
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &graph);
+        if (r) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return r;
+        }
+        if (e != hipSuccess) {
+            set_error("rsg_propagate: capture failed: %s", hipGetErrorString(e));
+            return RSG_EHIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            set_error("rsg_propagate: graph instantiate failed: %s", hipGetErrorString(ei));
+            return RSG_EHIP;
+        }
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        g_graphs[H][key] = exec;
+    }
+    RSG_CHECK_HIP(hipGraphLaunch(exec, s));
+    return RSG_OK;
+}
+
+static int check_reduce(const Grid *g, const void *a, int64_t nst, int64_t ld, const void *out, const char *who) {
+    RSG_REQUIRE(g, RSG_EINVAL, "%s: null grid", who);
+    RSG_REQUIRE(nst >= 0 && ld >= 1 && nst <= ld, RSG_ESHAPE, "%s: need 0 <= nst <= ld", who);
+    RSG_REQUIRE(nst == 0 || (a && out), RSG_EINVAL, "%s: null pointer", who);
+    RSG_REQUIRE(((uintptr_t)a & 15) == 0, RSG_EINVAL, "%s: pointer not 16-byte aligned", who);
+    return RSG_OK;
+}
+
+extern "C" size_t rsg_reduce_workspace_bytes(rsg_grid_t g, int64_t nst) {
+    if (!g || nst < 0) return 0;
+    return reduce_workspace_bytes(*g, nst);
+}
+
+extern "C" int rsg_dot(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ld, double *out,
+                       void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_reduce(g, a, nst, ld, out, "rsg_dot");
+    if (rc) return rc;
+    RSG_REQUIRE(nst == 0 || b, RSG_EINVAL, "rsg_dot: null pointer");
+    RSG_REQUIRE(((uintptr_t)b & 15) == 0, RSG_EINVAL, "rsg_dot: pointer not 16-byte aligned");
+    return launch_reduce(*g, 0, 0, (const double2 *)a, (const double2 *)b, nst, ld, out, ws, ws_bytes,
+                         (hipStream_t)stream);
+}
+
+extern "C" int rsg_norm2(rsg_grid_t g, const void *a, int64_t nst, int64_t ld, double *out, void *ws,
+                         size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_reduce(g, a, nst, ld, out, "rsg_norm2");
+    if (rc) return rc;
+    return launch_reduce(*g, 1, 0, (const double2 *)a, nullptr, nst, ld, out, ws, ws_bytes,
+                         (hipStream_t)stream);
+}
+
+extern "C" int rsg_dipole_expectation(rsg_ham_t H, const void *a, int64_t nst, int64_t ld, double *out,
+                                      void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    RSG_REQUIRE(H, RSG_EINVAL, "rsg_dipole_expectation: null Hamiltonian");
+    RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "rsg_dipole_expectation: Hamiltonian has no dipole axis");
+    int rc = check_reduce(H->g, a, nst, ld, out, "rsg_dipole_expectation");
+    if (rc) return rc;
+    return launch_reduce(*H->g, 2, H->axis, (const double2 *)a, nullptr, nst, ld, out, ws, ws_bytes,
+                         (hipStream_t)stream);
+}
+
+extern "C" int rsg_energy(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype, double field,
+                          double *out, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_batch(H, psi, nst, ld, "rsg_energy");
+    if (rc) return rc;
+    RSG_REQUIRE(dtype == RSG_C128, RSG_EDTYPE, "rsg_energy: dtype must be RSG_C128");
+    RSG_REQUIRE(nst == 0 || out, RSG_EINVAL, "rsg_energy: null output");
+    Carve c(ws, ws_bytes);
+    void *hp = c.take(batch_bytes(*H->g, ld, 16));
+    void *D = c.take(kb_workspace_bytes(*H, nst));
+    const size_t rb = reduce_workspace_bytes(*H->g, nst);
+    void *R = c.take(rb);
+    RSG_REQUIRE(c.ok, RSG_ENOMEM, "rsg_energy: workspace too small");
+    if (nst == 0) return RSG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = hpsi_impl(*H, psi, hp, nst, ld, field, nullptr, D, s))) return rc;
+    return launch_reduce(*H->g, 0, 0, (const double2 *)psi, (const double2 *)hp, nst, ld, out, R, rb, s);
+}
+
+extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, int64_t ld,
+                                double dt, double field, double *g_dev, void *ws, size_t ws_bytes,
+                                void *stream) {
+    clear_error();
+    int rc = check_batch(H, psi_n, nst, ld, "rsg_adjoint_step");
+    if (rc) return rc;
+    rc = check_batch(H, lambda, nst, ld, "rsg_adjoint_step");
+    if (rc) return rc;
+    RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "rsg_adjoint_step: Hamiltonian has no dipole axis");
+    RSG_REQUIRE(g_dev, RSG_EINVAL, "rsg_adjoint_step: null gradient output");
+    RSG_REQUIRE(ws_bytes >= adjoint_ws(*H, nst, ld) - 256, RSG_ENOMEM,
+                "rsg_adjoint_step: workspace too small (%zu < %zu)", ws_bytes, adjoint_ws(*H, nst, ld));
+    RSG_REQUIRE(nst > 0, RSG_ESHAPE, "rsg_adjoint_step: nst must be > 0");
+    return adjoint_impl(*H, psi_n, lambda, nst, ld, dt, field, nullptr, g_dev, ws, ws_bytes,
+                        (hipStream_t)stream);
+}
+
+static size_t control_ws(const Ham &H, int64_t nst, int64_t ld, int64_t nsteps, int64_t ckpt) {
+    const size_t bb = rounded(batch_bytes(*H.g, ld, 16));
+    return rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 + rounded(sizeof(double) * (size_t)nst) +
+           bb + (size_t)std::max<int64_t>(ckpt, 1) * bb + std::max(step_ws(H, nst, ld, RSG_C128), adjoint_ws(H, nst, ld)) +
+           256;
+}
+
+extern "C" size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ld, int64_t nsteps,
+                                              int64_t ckpt_every) {
+    if (!H || nst < 0 || ld < 1 || nsteps < 0 || ckpt_every < 1) return 0;
+    return control_ws(*H, nst, ld, nsteps, ckpt_every);
+}
+
+static int check_control(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, double dt, int64_t nsteps,
+                         const double *coef, int32_t ncoef, int64_t ckpt, size_t ws_bytes, const char *who) {
+    int rc = check_batch(H, psi, nst, ld, who);
+    if (rc) return rc;
+    RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "%s: Hamiltonian has no dipole axis", who);
+    RSG_REQUIRE(nst > 0 && nsteps > 0 && dt > 0 && std::isfinite(dt), RSG_EINVAL, "%s: need nst, nsteps, dt > 0", who);
+    RSG_REQUIRE(ncoef >= 0 && (ncoef == 0 || coef), RSG_EINVAL, "%s: bad coefficient array", who);
+    RSG_REQUIRE(ckpt >= 1, RSG_EINVAL, "%s: ckpt_every must be >= 1", who);
+    RSG_REQUIRE(ws_bytes >= control_ws(*H, nst, ld, nsteps, ckpt) - 256, RSG_ENOMEM,
+                "%s: workspace too small (%zu < %zu)", who, ws_bytes, control_ws(*H, nst, ld, nsteps, ckpt));
+    return RSG_OK;
+}
+
+extern "C" int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, double dt, int64_t nsteps,
+                                   const double *coef, int32_t ncoef, int64_t ckpt_every, void *ckpt_dev,
+                                   double *J_dev, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_control(H, psi, nst, ld, dt, nsteps, coef, ncoef, ckpt_every, ws_bytes, "rsg_control_forward");
+    if (rc) return rc;
+    RSG_REQUIRE(J_dev, RSG_EINVAL, "rsg_control_forward: null J output");
+    hipStream_t s = (hipStream_t)stream;
+    const double T = dt * (double)nsteps;
+    const size_t bb = batch_bytes(*H->g, ld, 16);
+    Carve c(ws, ws_bytes);
+    double *fields = (double *)c.take(sizeof(double) * nsteps);
+    (void)c.take(sizeof(double) * nsteps);
+    double *per = (double *)c.take(sizeof(double) * nst);
+    (void)c.take(bb);
+    (void)c.take(std::max<int64_t>(ckpt_every, 1) * rounded(bb));
+    size_t rest = 0;
+    void *sws = c.take_rest(&rest);
+    if (!c.ok) {
+        set_error("rsg_control_forward: workspace carve failed");
+        return RSG_ENOMEM;
+    }
+    if ((rc = rsg_laser_field(coef, ncoef, T, dt, 0, nsteps, fields, stream))) return rc;
+    if (ckpt_dev) RSG_CHECK_HIP(hipMemcpyAsync(ckpt_dev, psi, bb, hipMemcpyDeviceToDevice, s));
+    for (int64_t n = 0; n < nsteps; ++n) {
+        if ((rc = step_impl(*H, psi, nst, ld, RSG_C128, dt, 0.0, fields + n, sws, rest, s))) return rc;
+        if (ckpt_dev && (n + 1) % ckpt_every == 0)
+            RSG_CHECK_HIP(hipMemcpyAsync((char *)ckpt_dev + (size_t)((n + 1) / ckpt_every) * bb, psi, bb,
+                                         hipMemcpyDeviceToDevice, s));
+    }
+    const size_t rb = reduce_workspace_bytes(*H->g, nst);
+    if ((rc = launch_reduce(*H->g, 2, H->axis, (const double2 *)psi, nullptr, nst, ld, per, sws, rb, s))) return rc;
+    k_sum<<<1, 64, 0, s>>>(per, nst, J_dev);
+    RSG_CHECK_HIP(hipGetLastError());
+    return RSG_OK;
+}
+
+extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld, double dt,
+                                    int64_t nsteps, const double *coef, int32_t ncoef, int64_t ckpt_every,
+                                    const void *ckpt_dev, double *grad_dev, double *g_steps_dev, void *ws,
+                                    size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_control(H, psi_T, nst, ld, dt, nsteps, coef, ncoef, ckpt_every, ws_bytes, "rsg_control_backward");
+    if (rc) return rc;
+    RSG_REQUIRE(ckpt_dev, RSG_EINVAL, "rsg_control_backward: null checkpoint store");
+    RSG_REQUIRE(ncoef == 0 || grad_dev, RSG_EINVAL, "rsg_control_backward: null gradient output");
+    hipStream_t s = (hipStream_t)stream;
+    const double T = dt * (double)nsteps;
+    const size_t bb = batch_bytes(*H->g, ld, 16);
+    const size_t bbr = rounded(bb);
+    Carve c(ws, ws_bytes);
+    double *fields = (double *)c.take(sizeof(double) * nsteps);
+    double *gs = (double *)c.take(sizeof(double) * nsteps);
+    (void)c.take(sizeof(double) * nst);
+    void *lam = c.take(bb);
+    char *states = (char *)c.take(std::max<int64_t>(ckpt_every, 1) * bbr);
+    size_t rest = 0;
+    void *sws = c.take_rest(&rest);
+    if (!c.ok) {
+        set_error("rsg_control_backward: workspace carve failed");
+        return RSG_ENOMEM;
+    }
+    if (g_steps_dev) gs = g_steps_dev;
+    if ((rc = rsg_laser_field(coef, ncoef, T, dt, 0, nsteps, fields, stream))) return rc;
+    if ((rc = launch_mul_axis(*H->g, H->axis, (const double2 *)psi_T, (double2 *)lam, nst, ld, s))) return rc;
+    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * ckpt_every, s1 = std::min(nsteps, s0 + ckpt_every);
+        // states[k] = psi_{s0 + k}, k = 0 .. s1 - s0 - 1
+        RSG_CHECK_HIP(hipMemcpyAsync(states, (const char *)ckpt_dev + (size_t)seg * bb, bb,
+                                     hipMemcpyDeviceToDevice, s));
+        for (int64_t k = 1; k < s1 - s0; ++k) {
+            RSG_CHECK_HIP(hipMemcpyAsync(states + k * bbr, states + (k - 1) * bbr, bb, hipMemcpyDeviceToDevice, s));
+            if ((rc = step_impl(*H, states + k * bbr, nst, ld, RSG_C128, dt, 0.0, fields + s0 + k - 1, sws, rest, s)))
+                return rc;
+        }
+        for (int64_t n = s1 - 1; n >= s0; --n) {
+            if ((rc = adjoint_impl(*H, states + (n - s0) * bbr, lam, nst, ld, dt, 0.0, fields + n, gs + n, sws,
+                                   rest, s)))
+                return rc;
+        }
+    }
+    return rsg_laser_grad(gs, nsteps, T, dt, ncoef, grad_dev, stream);
+}
+
+extern "C" int rsg_copy(const void *src, void *dst, size_t nbytes, void *stream) {
+    clear_error();
+    RSG_REQUIRE(nbytes % 16 == 0, RSG_EINVAL, "rsg_copy: size must be a multiple of 16");
+    RSG_REQUIRE(nbytes == 0 || (src && dst), RSG_EINVAL, "rsg_copy: null pointer");
+    RSG_REQUIRE((((uintptr_t)src | (uintptr_t)dst) & 15) == 0, RSG_EINVAL, "rsg_copy: unaligned pointer");
+    if (nbytes == 0) return RSG_OK;
+    const int64_t n16 = (int64_t)(nbytes / 16);
+    int64_t nb = (n16 + 255) / 256;
+    nb = std::min<int64_t>(nb, 256 * 64);
+    timing_before((hipStream_t)stream);
+    k_copy16<<<(unsigned)nb, 256, 0, (hipStream_t)stream>>>((const int4 *)src, (int4 *)dst, n16);
+    timing_after((hipStream_t)stream);
+    RSG_CHECK_HIP(hipGetLastError());
+    return RSG_OK;
+}
+
+extern "C" int rsg_timing_enable(int32_t on) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return RSG_OK;
+}
+
+extern "C" int rsg_timing_query(int64_t *count, double *mean_ms, double *total_ms) {
+    clear_error();
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        ev.swap(g_events);
+    }
+    double tot = 0.0;
+    int64_t n = 0;
+    int rc = RSG_OK;
+    for (auto &p : ev) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second) == hipSuccess && hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) {
+            tot += ms;
+            ++n;
+        } else {
+            rc = RSG_EHIP;
+        }
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (count) *count = n;
+    if (total_ms) *total_ms = tot;
+    if (mean_ms) *mean_ms = n ? tot / n : 0.0;
+    if (rc) set_error("rsg_timing_query: event query failed");
+    return rc;
+}

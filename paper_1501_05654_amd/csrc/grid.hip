@@ -1,0 +1,277 @@
+// Grid setup: box membership, compact numbering and stencil launch plans.
+//
+// A field on the grid is a linear array over the points of the simulation
+// box, with the grid structure kept separately (section "Parallelization,
+// optimizations and graphics processing units").  The structure kept here is
+// one entry per (y, z) row of the tight bounding box: the x-range of the row
+// inside the box and the compact index of its first point.  Compact order is
+// z-major, then y, then x, so every row is contiguous in memory and a point's
+// index is rows[z*ny + y].base + x.
+#include "rsg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace rsg {
+
+namespace {
+
+__device__ int64_t isqrt_dev(int64_t q) {
+    int64_t m = (int64_t)sqrt((double)q);
+    while ((m + 1) * (m + 1) <= q) ++m;
+    while (m * m > q) --m;
+    return m;
+}
+
+// Row extents: sphere rows hold the x with (x-M)^2 <= Q - (y-M)^2 - (z-M)^2.
+__global__ void k_row_extent(int shape, int32_t nx, int32_t ny, int32_t nz, int64_t Q, int32_t M,
+                             int32_t *x0, int32_t *len) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (int64_t)ny * nz) return;
+    const int64_t y = r % ny, z = r / ny;
+    if (shape == RSG_BOX_SPHERE) {
+        const int64_t dy = y - M, dz = z - M;
+        const int64_t rem = Q - dy * dy - dz * dz;
+        if (rem < 0) {
+            x0[r] = 0;
+            len[r] = 0;
+        } else {
+            const int64_t xm = isqrt_dev(rem);
+            x0[r] = (int32_t)(M - xm);
+            len[r] = (int32_t)(2 * xm + 1);
+        }
+    } else {
+        x0[r] = 0;
+        len[r] = nx;
+    }
+}
+
+// Exclusive scan of the row lengths in one workgroup (fixed order): each
+// thread sums a contiguous chunk, the 1024 chunk totals are scanned in LDS,
+// then each thread writes its rows.  Writes rows[] and the total.
+__global__ void __launch_bounds__(1024) k_row_scan(const int32_t *x0, const int32_t *len,
+                                                   int64_t nrows, int2 *rows, int64_t *total) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (nrows + 1023) / 1024;
+    const int64_t r0 = t * chunk, r1 = min(nrows, r0 + chunk);
+    int64_t s = 0;
+    for (int64_t r = r0; r < r1; ++r) s += len[r];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t start = t == 0 ? 0 : part[t - 1];
+    for (int64_t r = r0; r < r1; ++r) {
+        const int32_t a = x0[r], l = len[r];
+        rows[r] = make_int2((int32_t)(start - a), a | ((a + l) << 16));
+        start += l;
+    }
+    if (t == 1023) *total = part[1023];
+}
+
+// Box coordinates of every compact point, one thread per (row, x).
+__global__ void k_coords(const int2 *rows, int32_t nx, int32_t ny, int64_t nrows, int32_t *ijk) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nrows * nx) return;
+    const int64_t r = g / nx;
+    const int32_t x = (int32_t)(g % nx);
+    const int2 row = rows[r];
+    const int32_t a = row.y & 0xffff, b = (row.y >> 16) & 0xffff;
+    if (x < a || x >= b) return;
+    const int64_t p = (int64_t)row.x + x;
+    ijk[3 * p + 0] = x;
+    ijk[3 * p + 1] = (int32_t)(r % ny);
+    ijk[3 * p + 2] = (int32_t)(r / ny);
+}
+
+}  // namespace
+
+Grid::~Grid() {
+    for (auto &kv : plans)
+        if (kv.second.items) (void)hipFree(kv.second.items);
+    if (rows) (void)hipFree(rows);
+    if (ijk) (void)hipFree(ijk);
+}
+
+// Work items for one tile shape: every (tx, ty) tile that holds box points,
+// with its z-extent split into chunks of at most ZC planes.  Items are ordered
+// z-chunk major, then ty, then tx, so that workgroups launched together cover
+// neighbouring tiles at similar depths.
+const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
+    auto it = plans.find(s);
+    if (it != plans.end()) return &it->second;
+    const int nx = n[0], ny = n[1], nz = n[2];
+    const int ntx = (nx + s.TX - 1) / s.TX, nty = (ny + s.TY - 1) / s.TY;
+    std::vector<int> zlo((size_t)ntx * nty, nz), zhi((size_t)ntx * nty, -1);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const int2 r = rows_host[(size_t)z * ny + y];
+            const int a = r.y & 0xffff, b = (r.y >> 16) & 0xffff;
+            if (a >= b) continue;
+            const int ty = y / s.TY;
+            for (int tx = a / s.TX; tx <= (b - 1) / s.TX; ++tx) {
+                const size_t k = (size_t)ty * ntx + tx;
+                zlo[k] = std::min(zlo[k], z);
+                zhi[k] = std::max(zhi[k], z);
+            }
+        }
+    int maxchunks = 0;
+    for (size_t k = 0; k < zlo.size(); ++k)
+        if (zhi[k] >= zlo[k])
+            maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);
+    std::vector<int4> items;
+    for (int c = 0; c < maxchunks; ++c)
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) {
+                const size_t k = (size_t)ty * ntx + tx;
+                if (zhi[k] < zlo[k]) continue;
+                const int z0 = zlo[k] + c * s.ZC;
+                if (z0 > zhi[k]) continue;
+                const int z1 = std::min(zhi[k] + 1, z0 + s.ZC);
+                items.push_back(make_int4(tx, ty, z0, z1));
+            }
+    TilePlan p;
+    p.nitems = (int32_t)items.size();
+    if (p.nitems > 0) {
+        hipError_t e = hipMalloc(&p.items, sizeof(int4) * items.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p.items, items.data(), sizeof(int4) * items.size(),
+                               hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            set_error("tile plan upload failed: %s", hipGetErrorString(e));
+            if (p.items) (void)hipFree(p.items);
+            *err = RSG_EHIP;
+            return nullptr;
+        }
+    }
+    *err = RSG_OK;
+    return &(plans[s] = p);
+}
+
+}  // namespace rsg
+
+using namespace rsg;
+
+extern "C" int rsg_grid_create(const rsg_grid_desc *d, void *stream, rsg_grid_t *out) {
+    clear_error();
+    RSG_REQUIRE(d && out, RSG_EINVAL, "rsg_grid_create: null argument");
+    RSG_REQUIRE(d->h > 0 && std::isfinite(d->h), RSG_EINVAL, "rsg_grid_create: h must be > 0");
+    RSG_REQUIRE(d->shape == RSG_BOX_CUBE || d->shape == RSG_BOX_SPHERE, RSG_EINVAL,
+                "rsg_grid_create: unknown box shape %d", d->shape);
+    int64_t Q = 0;
+    int32_t M = 0, nx;
+    if (d->shape == RSG_BOX_SPHERE) {
+        RSG_REQUIRE(d->radius > 0 && std::isfinite(d->radius), RSG_EINVAL,
+                    "rsg_grid_create: radius must be > 0");
+        const double q = std::floor((d->radius / d->h) * (d->radius / d->h) + 1e-9);
+        RSG_REQUIRE(q < 1.0e8, RSG_EINVAL, "rsg_grid_create: sphere too large (R/h > 10^4)");
+        Q = (int64_t)q;
+        int64_t m = (int64_t)std::sqrt((double)Q);
+        while ((m + 1) * (m + 1) <= Q) ++m;
+        while (m * m > Q) --m;
+        M = (int32_t)m;
+        nx = 2 * M + 1;
+    } else {
+        RSG_REQUIRE(d->n >= 1, RSG_EINVAL, "rsg_grid_create: cube needs n >= 1");
+        nx = d->n;
+    }
+    RSG_REQUIRE(nx < 32768, RSG_EINVAL, "rsg_grid_create: box wider than 32767 points");
+    return guarded([&]() -> int {
+        hipStream_t s = (hipStream_t)stream;
+        auto *g = new rsg_grid_s();
+        g->shape = d->shape;
+        g->n[0] = g->n[1] = g->n[2] = nx;
+        g->h = d->h;
+        const int64_t nrows = (int64_t)nx * nx;
+        int32_t *x0 = nullptr, *len = nullptr;
+        int64_t *total = nullptr;
+        auto fail = [&](hipError_t e) {
+            set_error("rsg_grid_create: %s", hipGetErrorString(e));
+            if (x0) (void)hipFree(x0);
+            if (len) (void)hipFree(len);
+            if (total) (void)hipFree(total);
+            delete g;
+            return RSG_EHIP;
+        };
+        hipError_t e;
+        if ((e = hipMalloc(&x0, sizeof(int32_t) * nrows)) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&len, sizeof(int32_t) * nrows)) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&total, sizeof(int64_t))) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&g->rows, sizeof(int2) * nrows)) != hipSuccess) return fail(e);
+        const int bs = 256;
+        k_row_extent<<<(unsigned)((nrows + bs - 1) / bs), bs, 0, s>>>(d->shape, nx, nx, nx, Q, M,
+                                                                     x0, len);
+        k_row_scan<<<1, 1024, 0, s>>>(x0, len, nrows, g->rows, total);
+        if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+        int64_t np = 0;
+        if ((e = hipMemcpyAsync(&np, total, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return fail(e);
+        g->rows_host.resize(nrows);
+        if ((e = hipMemcpyAsync(g->rows_host.data(), g->rows, sizeof(int2) * nrows,
+                                hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return fail(e);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+        if (np >= INT32_MAX) {
+            set_error("rsg_grid_create: %lld points exceed the int32 index range", (long long)np);
+            (void)hipFree(x0);
+            (void)hipFree(len);
+            (void)hipFree(total);
+            delete g;
+            return RSG_EUNSUPPORTED;
+        }
+        g->np = np;
+        if ((e = hipMalloc(&g->ijk, sizeof(int32_t) * 3 * (np > 0 ? np : 1))) != hipSuccess)
+            return fail(e);
+        const int64_t work = nrows * nx;
+        k_coords<<<(unsigned)((work + bs - 1) / bs), bs, 0, s>>>(g->rows, nx, nx, nrows, g->ijk);
+        if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+        (void)hipFree(x0);
+        (void)hipFree(len);
+        (void)hipFree(total);
+        *out = g;
+        return RSG_OK;
+    });
+}
+
+extern "C" int rsg_grid_info(rsg_grid_t g, int64_t *np, int32_t dims[3], double *h) {
+    clear_error();
+    RSG_REQUIRE(g, RSG_EINVAL, "rsg_grid_info: null grid");
+    if (np) *np = g->np;
+    if (dims) std::memcpy(dims, g->n, sizeof(int32_t) * 3);
+    if (h) *h = g->h;
+    return RSG_OK;
+}
+
+extern "C" int rsg_grid_coords(rsg_grid_t g, int32_t *ijk_host) {
+    clear_error();
+    RSG_REQUIRE(g && ijk_host, RSG_EINVAL, "rsg_grid_coords: null argument");
+    RSG_CHECK_HIP(hipMemcpy(ijk_host, g->ijk, sizeof(int32_t) * 3 * g->np, hipMemcpyDeviceToHost));
+    return RSG_OK;
+}
+
+extern "C" int rsg_grid_positions(rsg_grid_t g, double *xyz) {
+    clear_error();
+    RSG_REQUIRE(g && xyz, RSG_EINVAL, "rsg_grid_positions: null argument");
+    return guarded([&]() -> int {
+        std::vector<int32_t> ijk((size_t)3 * g->np);
+        RSG_CHECK_HIP(hipMemcpy(ijk.data(), g->ijk, sizeof(int32_t) * ijk.size(), hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < g->np; ++p)
+            for (int a = 0; a < 3; ++a)
+                xyz[3 * p + a] = g->h * ((double)ijk[3 * p + a] - 0.5 * (double)(g->n[a] - 1));
+        return RSG_OK;
+    });
+}
+
+extern "C" int rsg_grid_destroy(rsg_grid_t g) {
+    clear_error();
+    delete g;
+    return RSG_OK;
+}

@@ -1,0 +1,184 @@
+// Separable non-local projectors on MFMA.
+//
+//   V_nl psi_n = sum_a sum_i p_i^a E_i^a D[a][i][n],
+//   D[a][i][n] = h^3 sum_{r in S_a} p_i^a(r) psi_n(r)
+//
+// The non-local pseudopotential and its projectors are the electron-ion
+// term named in section "Magnetic response and gauge invariance in
+// real-space grids"; the separable form with four real projectors per atom
+// is this library's reading.  Both halves are dense contractions:
+//
+//   gather : D^T[cols x 4] = psi^T[cols x |S_a|] * P[|S_a| x 4]
+//   scatter: Y[|S_a| x cols] += P[|S_a| x 4] * F[4 x cols],  F = c E D
+//
+// where cols are the 2*nst real columns of the interleaved complex batch.
+// Both run on v_mfma_{f64,f32}_16x16x4: the gather puts 16 columns on M,
+// 4 support points on K and the 4 projectors on N (zero-padded to 16); the
+// scatter puts 16 support points on M, the 4 projectors on K and 16
+// columns on N, which fills the instruction exactly.
+//
+// MFMA operand layout (lane l of a wave of 64):
+//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+//   D[i][j] element r in lane j + 16*(i/4) with r = i % 4.
+//
+// Supports are padded to a multiple of 16 entries with p = 0 (and a valid
+// index); padded entries contribute zero and are never written.  Atoms whose
+// supports overlap are scattered in different launches (colours), so no two
+// lanes of one launch update the same point: the result is deterministic
+// without atomics.
+#include "rsg_internal.h"
+
+namespace rsg {
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <class T> struct V4;
+template <> struct V4<double> { using type = d4_t; };
+template <> struct V4<float> { using type = f4_t; };
+
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// blockIdx.x = atom, blockIdx.y = tile of 16 real columns; 4 waves split
+// the support in groups of 4 entries (wave w takes groups w, w+4, ...), and
+// their partial products are added in wave order.
+template <class Tin, class Tc>
+__global__ void __launch_bounds__(256) k_kb_gather(const Tin *__restrict__ in, int64_t ldr,
+                                                   int64_t ncols, const int4 *__restrict__ atoms,
+                                                   const int32_t *__restrict__ idx,
+                                                   const Tc *__restrict__ p, Tc h3,
+                                                   Tc *__restrict__ D) {
+    using V = typename V4<Tc>::type;
+    __shared__ Tc red[4][64][4];
+    const int a = blockIdx.x, ct = blockIdx.y;
+    const int4 at = atoms[a];  // {offset, padded length, length, -}
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int lo = l & 15, hi = l >> 4;
+    const int64_t col = (int64_t)ct * 16 + lo;
+    const bool cok = col < ncols;
+    V acc = {0, 0, 0, 0};
+    const int ngroups = at.y >> 2;
+    for (int gq = w; gq < ngroups; gq += 4) {
+        const int64_t e = (int64_t)at.x + 4 * gq + hi;
+        const Tc av = cok ? (Tc)in[(int64_t)idx[e] * ldr + col] : (Tc)0;
+        const Tc bv = lo < 4 ? p[e * 4 + lo] : (Tc)0;
+        acc = mfma16(av, bv, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w][l][r] = acc[r];
+    __syncthreads();
+    if (w == 0 && lo < 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const Tc v = ((red[0][l][r] + red[1][l][r]) + red[2][l][r]) + red[3][l][r];
+            const int64_t c = (int64_t)ct * 16 + 4 * hi + r;
+            if (c < ncols) D[((int64_t)a * 4 + lo) * ncols + c] = h3 * v;
+        }
+    }
+}
+
+// One wave per (16-entry support tile, 16-column tile).
+template <class Tout, class Tc>
+__global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int64_t ldr, int64_t ncols,
+                                                    const int2 *__restrict__ items, int32_t nitems,
+                                                    const int4 *__restrict__ atoms,
+                                                    const int32_t *__restrict__ idx,
+                                                    const Tc *__restrict__ p,
+                                                    const double *__restrict__ E,
+                                                    const Tc *__restrict__ D, double cre,
+                                                    double cim) {
+    using V = typename V4<Tc>::type;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + w;
+    if (item >= nitems) return;
+    const int2 itm = items[item];  // {atom, first entry}
+    const int4 at = atoms[itm.x];
+    const int lo = l & 15, hi = l >> 4;
+    const Tc av = p[((int64_t)itm.y + lo) * 4 + hi];
+    const int64_t col = (int64_t)blockIdx.y * 16 + lo;
+    Tc bv = 0;
+    if (col < ncols) {
+        const int64_t n = col >> 1;
+        const double dre = (double)D[((int64_t)itm.x * 4 + hi) * ncols + 2 * n];
+        const double dim = (double)D[((int64_t)itm.x * 4 + hi) * ncols + 2 * n + 1];
+        const double e = E[itm.x * 4 + hi];
+        bv = (Tc)((col & 1) ? e * (cre * dim + cim * dre) : e * (cre * dre - cim * dim));
+    }
+    V zero = {0, 0, 0, 0};
+    const V acc = mfma16(av, bv, zero);
+    const int64_t end = (int64_t)at.x + at.z;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t e = (int64_t)itm.y + 4 * hi + r;
+        if (e < end && col < ncols) {
+            Tout *dst = out + (int64_t)idx[e] * ldr + col;
+            *dst = (Tout)((double)*dst + (double)acc[r]);
+        }
+    }
+}
+
+}  // namespace
+
+size_t kb_workspace_bytes(const Ham &H, int64_t nst) {
+    return (size_t)H.natoms * 4 * 2 * (size_t)nst * sizeof(double);
+}
+
+int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ld,
+                     void *D, hipStream_t s) {
+    if (H.natoms == 0 || nst == 0) return RSG_OK;
+    const int64_t ncols = 2 * nst;
+    const dim3 grid((unsigned)H.natoms, (unsigned)((ncols + 15) / 16));
+    const double h3 = H.g->h * H.g->h * H.g->h;
+    if (compute == 0) {
+        if (in_t != 0) return RSG_EUNSUPPORTED;
+        k_kb_gather<double, double><<<grid, 256, 0, s>>>((const double *)in, 2 * ld, ncols,
+                                                        H.gather_items, H.kb_idx, H.kb_p, h3,
+                                                        (double *)D);
+    } else if (in_t == 0) {
+        k_kb_gather<double, float><<<grid, 256, 0, s>>>((const double *)in, 2 * ld, ncols,
+                                                       H.gather_items, H.kb_idx, H.kb_p32,
+                                                       (float)h3, (float *)D);
+    } else {
+        k_kb_gather<float, float><<<grid, 256, 0, s>>>((const float *)in, 2 * ld, ncols,
+                                                      H.gather_items, H.kb_idx, H.kb_p32,
+                                                      (float)h3, (float *)D);
+    }
+    RSG_CHECK_HIP(hipGetLastError());
+    return RSG_OK;
+}
+
+int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ld,
+                      const void *D, double cre, double cim, hipStream_t s) {
+    if (H.natoms == 0 || nst == 0) return RSG_OK;
+    const int64_t ncols = 2 * nst;
+    for (size_t c = 0; c < H.scatter_items.size(); ++c) {
+        const int32_t n = H.scatter_counts[c];
+        if (n == 0) continue;
+        const dim3 grid((unsigned)((n + 3) / 4), (unsigned)((ncols + 15) / 16));
+        if (compute == 0) {
+            if (out_t != 0) return RSG_EUNSUPPORTED;
+            k_kb_scatter<double, double><<<grid, 256, 0, s>>>(
+                (double *)out, 2 * ld, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
+                H.kb_p, H.kb_E, (const double *)D, cre, cim);
+        } else if (out_t == 0) {
+            k_kb_scatter<double, float><<<grid, 256, 0, s>>>(
+                (double *)out, 2 * ld, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
+                H.kb_p32, H.kb_E, (const float *)D, cre, cim);
+        } else {
+            k_kb_scatter<float, float><<<grid, 256, 0, s>>>(
+                (float *)out, 2 * ld, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
+                H.kb_p32, H.kb_E, (const float *)D, cre, cim);
+        }
+        RSG_CHECK_HIP(hipGetLastError());
+    }
+    return RSG_OK;
+}
+
+}  // namespace rsg

@@ -1,0 +1,171 @@
+// Internal declarations shared by the HIP translation units of librsg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rsg.h"
+
+namespace rsg {
+
+// ---------------------------------------------------------------- errors --
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define RSG_CHECK_HIP(expr)                                                        \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::rsg::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                  \
+            return RSG_EHIP;                                                       \
+        }                                                                          \
+    } while (0)
+
+#define RSG_REQUIRE(cond, code, ...)      \
+    do {                                  \
+        if (!(cond)) {                    \
+            ::rsg::set_error(__VA_ARGS__); \
+            return (code);                \
+        }                                 \
+    } while (0)
+
+// Run a body that may throw (host allocation) and convert to an error code.
+template <class F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return RSG_ENOMEM;
+    } catch (...) {
+        set_error("unexpected host exception");
+        return RSG_EINVAL;
+    }
+}
+
+// ----------------------------------------------------------- launch plan --
+
+// Tile shape of the z-marching stencil: B orbitals x TX x TY points per
+// workgroup, marching along z in chunks of at most ZC planes.
+struct TileShape {
+    int B, TX, TY, ZC;
+    bool operator<(const TileShape &o) const {
+        if (B != o.B) return B < o.B;
+        if (TX != o.TX) return TX < o.TX;
+        if (TY != o.TY) return TY < o.TY;
+        return ZC < o.ZC;
+    }
+};
+
+// Work items of one tile shape on one grid: (tx, ty, z0, z1) per item,
+// items ordered z-chunk major, then ty, then tx.
+struct TilePlan {
+    int4 *items = nullptr;  // device
+    int32_t nitems = 0;
+};
+
+// ------------------------------------------------------------------ grid --
+
+struct Grid {
+    int32_t shape = 0;
+    int32_t n[3] = {0, 0, 0};  // tight box x, y, z
+    int64_t np = 0;
+    double h = 0;
+    // rows[z*ny + y] = {base, x0 | x1 << 16}: point (x,y,z) is in the box iff
+    // x0 <= x < x1, with compact index base + x.
+    int2 *rows = nullptr;       // device [ny*nz]
+    std::vector<int2> rows_host;
+    int32_t *ijk = nullptr;     // device [np][3]
+    std::map<TileShape, TilePlan> plans;
+    ~Grid();
+    const TilePlan *plan(const TileShape &s, hipStream_t stream, int *err);
+};
+
+// ----------------------------------------------------------- Hamiltonian --
+
+struct Ham {
+    Grid *g = nullptr;
+    double kin = -0.5;
+    int32_t axis = -1;
+    double *V = nullptr;     // device [np] or null
+    float *V32 = nullptr;    // device [np] FP32 copy or null
+    // projectors, padded per atom to a multiple of 16 support entries
+    int32_t natoms = 0;
+    int32_t *kb_idx = nullptr;   // device [total_padded]
+    double *kb_p = nullptr;      // device [total_padded][4]
+    float *kb_p32 = nullptr;     // device FP32 copy
+    double *kb_E = nullptr;      // device [natoms][4]
+    std::vector<int64_t> kb_off; // host [natoms+1] padded offsets
+    std::vector<int64_t> kb_len; // host [natoms] true support sizes
+    int4 *gather_items = nullptr;   // device: one per atom {atom, off, len, 0}
+    // scatter work: per colour a device list of {atom, entry0} (16 entries each)
+    std::vector<int2 *> scatter_items;
+    std::vector<int32_t> scatter_counts;
+    ~Ham();
+};
+
+// ------------------------------------------------------------ complex ----
+
+template <class T> struct cpx;
+template <> struct cpx<double> { using type = double2; };
+template <> struct cpx<float> { using type = float2; };
+
+// ------------------------------------------------------------ launchers --
+
+// Stencil stage: out = [base +] c * (kin Lap + V + field x_axis)(in).
+// mode 0: out = H in (no base, c = 1).  mode 1: out = base + c H in.
+// in_t / out_t: 0 = complex128, 1 = complex64.  compute: 0 = FP64, 1 = FP32.
+struct StageArgs {
+    const void *in = nullptr;
+    const void *base = nullptr;
+    void *out = nullptr;
+    int in_t = 0, out_t = 0, compute = 0, mode = 0;
+    int64_t nst = 0, ld = 0;
+    double field = 0;
+    const double *field_dev = nullptr;
+    double cre = 1, cim = 0;
+};
+int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s);
+TileShape default_shape(const Grid &g, int64_t nst, int compute);
+
+// KB projectors.  gather: D[a][i][col] = h^3 sum_e p[e][i] in[idx[e]][col]
+// (col over the 2*nst real columns); scatter: out[idx[e]][col] +=
+// sum_i p[e][i] (c E_i D[a][i][.])[col].
+int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ld,
+                     void *D, hipStream_t s);
+int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ld,
+                      const void *D, double cre, double cim, hipStream_t s);
+size_t kb_workspace_bytes(const Ham &H, int64_t nst);
+
+// Reductions: partial sums per block then a fixed-order final pass.
+// kind 0: <a|b> (complex out [2*nst]); 1: |a|^2 (out [nst]);
+// 2: x_axis |a|^2 (out [nst]); all scaled by h^3.
+size_t reduce_workspace_bytes(const Grid &g, int64_t nst);
+int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const double2 *b,
+                  int64_t nst, int64_t ld, double *out, void *ws, size_t ws_bytes, hipStream_t s);
+
+// Pointwise helpers.
+int launch_axpby_list(const Grid &g, int64_t nst, int64_t ld, int nterms, const double2 *const *src,
+                      const double2 *coef, double2 *dst, hipStream_t s);
+int launch_mul_axis(const Grid &g, int axis, const double2 *src, double2 *dst, int64_t nst,
+                    int64_t ld, hipStream_t s);
+int launch_cross_dots(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
+                      const double2 *pair_coef, int64_t nst, int64_t ld, double *out, void *ws,
+                      size_t ws_bytes, hipStream_t s);
+int launch_accumulate(const double *src, double *dst, hipStream_t s);
+
+// Kernel timing hooks around stencil launches.
+void timing_before(hipStream_t s);
+void timing_after(hipStream_t s);
+
+}  // namespace rsg
+
+struct rsg_grid_s : rsg::Grid {};
+struct rsg_ham_s : rsg::Ham {};

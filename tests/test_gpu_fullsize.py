@@ -1,0 +1,68 @@
+"""Full-size parity on the benchmark workload: the 3,053,617-point sphere
+(R = 18 bohr, h = 0.2) with 64 orbitals, 16 wells and 4 projectors each.
+The GPU runs all 64 orbitals in the launch configuration the benchmark
+times; the oracle recomputes a sample of orbitals, which is exact because
+orbitals are independent under H (pinned in the oracle tests)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_common import orbital_rel_err, rsg
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = [0, 29, 63]
+
+
+@pytest.fixture(scope="module")
+def sphere18():
+    cfg = synth.WORKLOADS["sphere18_wells"]
+    R = rsg()
+    og = oracle.Grid(cfg["h"], R=cfg["R"])
+    gg = R.Grid(cfg["h"], R=cfg["R"])
+    assert gg.np == og.np == 3053617
+    np.testing.assert_array_equal(gg.coords(), og.ijk)
+    pos = og.positions()
+    wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
+    V = synth.well_potential(pos, wells)
+    proj = synth.kb_projectors(cfg["seed"], pos, wells.centres)
+    psi = synth.white_noise(cfg["seed"], og.np, cfg["nst"], cfg["h"])
+    oh = oracle.Ham(og, V=V, kin=-0.5, projectors=proj)
+    dev = torch.device("cuda")
+    gh = R.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
+                       projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
+                                   for i, p, E in zip(proj.idx, proj.p, proj.E)])
+    return dict(cfg=cfg, og=og, oh=oh, gg=gg, gh=gh, psi=psi)
+
+
+def test_sphere18_hpsi_sampled_orbitals(sphere18):
+    s = sphere18
+    psi = torch.from_numpy(s["psi"]).cuda()
+    out = rsg().hpsi(s["gh"], psi)
+    got = out[:, SAMPLE].cpu().numpy()
+    ref = oracle.hpsi(s["oh"], np.ascontiguousarray(s["psi"][:, SAMPLE]))
+    assert orbital_rel_err(got, ref, len(SAMPLE)) <= 1e-12
+
+
+def test_sphere18_taylor_step_sampled_orbitals(sphere18):
+    s = sphere18
+    psi = torch.from_numpy(s["psi"]).cuda()
+    rsg().propagate_step(s["gh"], psi, s["cfg"]["dt"])
+    got = psi[:, SAMPLE].cpu().numpy()
+    ref = oracle.taylor_step(s["oh"], np.ascontiguousarray(s["psi"][:, SAMPLE]), s["cfg"]["dt"])
+    assert orbital_rel_err(got, ref, len(SAMPLE)) <= 1e-12
+
+
+def test_sphere18_norm_conserved_over_steps(sphere18):
+    """Property at full size: 5 steps change each orbital's norm only by the
+    Taylor(4) amplification of its highest modes (|T4(ix)|^2 <= 1)."""
+    s = sphere18
+    R = rsg()
+    psi = torch.from_numpy(s["psi"]).cuda()
+    n0 = R.norm2(s["gg"], psi).cpu().numpy()
+    R.propagate(s["gh"], psi, s["cfg"]["dt"], 5)
+    n1 = R.norm2(s["gg"], psi).cpu().numpy()
+    assert np.all(n1 <= n0 * (1 + 1e-12))
+    assert np.all(n1 > 0.5 * n0)

@@ -1,0 +1,236 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle on the same
+seeded inputs.  FP64 results must agree to 1e-12 relative per orbital
+(||gpu_n - oracle_n||_2 / ||oracle_n||_2, max over orbitals)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_common import System, orbital_rel_err, rsg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.mark.parametrize("kind,h,size", [("cube", 0.3, 32), ("cube", 0.4, 5), ("cube", 0.3, 1),
+                                         ("sphere", 0.25, 4.0), ("sphere", 0.2, 18.0),
+                                         ("sphere", 0.3, 0.2), ("sphere", 0.3, 3.33)])
+def test_grid_matches_oracle(kind, h, size):
+    R = rsg()
+    if kind == "cube":
+        g, o = R.Grid(h, n=size), oracle.Grid(h, n=size)
+    else:
+        g, o = R.Grid(h, R=size), oracle.Grid(h, R=size)
+    assert g.np == o.np and g.dims == tuple(o.dims)
+    np.testing.assert_array_equal(g.coords(), o.ijk)
+    np.testing.assert_array_equal(g.positions(), o.positions())
+
+
+def test_hpsi_cube32_harmonic_ten_calls():
+    """32^3 cube, V = r^2/2, 4 white-noise orbitals: 10 hpsi calls on the
+    same input, parity on every output."""
+    s = System(0.3, n=32, potential="harmonic", nst=4, seed=1)
+    ref = oracle.hpsi(s.oh, s.psi)
+    psi = s.to_gpu(s.psi)
+    for _ in range(10):
+        out = rsg().hpsi(s.gh, psi).cpu().numpy()
+        assert orbital_rel_err(out, ref, 4) <= TOL
+
+
+@pytest.mark.parametrize("nst,ld", [(1, 1), (3, 4), (5, 8), (8, 8), (13, 16), (33, 40)])
+def test_hpsi_sphere_projectors_dipole(nst, ld):
+    """Sphere with wells, overlapping projector supports and a dipole field;
+    ragged orbital counts with padding columns that must stay untouched."""
+    s = System(0.3, R=4.1, potential="wells", natoms=5, nst=nst, ld=ld, seed=7, dipole_axis=2,
+               well_ball=1.5)
+    ref = oracle.hpsi(s.oh, s.psi, field=0.23, nst=nst)
+    psi = s.to_gpu(s.psi)
+    out = torch.full_like(psi, 3.0 + 1.0j)
+    rsg().hpsi(s.gh, psi, field=0.23, out=out, nst=nst)
+    got = out.cpu().numpy()
+    assert orbital_rel_err(got, ref, nst) <= TOL
+    assert np.all(got[:, nst:] == 3.0 + 1.0j)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_hpsi_dipole_axes(axis):
+    s = System(0.35, R=3.0, potential="harmonic", nst=2, seed=3, dipole_axis=axis)
+    ref = oracle.hpsi(s.oh, s.psi, field=-0.7)
+    got = rsg().hpsi(s.gh, s.to_gpu(s.psi), field=-0.7).cpu().numpy()
+    assert orbital_rel_err(got, ref, 2) <= TOL
+
+
+def test_hpsi_tiny_boxes():
+    """Boxes smaller than the stencil reach: a 1-point sphere, a 3^3 cube."""
+    for kw in (dict(R=0.2), dict(n=3), dict(n=2)):
+        s = System(0.3, potential="harmonic", nst=2, seed=5, **kw)
+        ref = oracle.hpsi(s.oh, s.psi)
+        got = rsg().hpsi(s.gh, s.to_gpu(s.psi)).cpu().numpy()
+        assert orbital_rel_err(got, ref, 2) <= TOL
+
+
+def test_taylor_steps_cube32():
+    """10 Taylor(4) steps at dt = 0.01 on the 32^3 harmonic system."""
+    s = System(0.3, n=32, potential="harmonic", nst=4, seed=1)
+    ref = oracle.propagate(s.oh, s.psi, 0.01, 10)
+    psi = s.to_gpu(s.psi)
+    for _ in range(10):
+        rsg().propagate_step(s.gh, psi, 0.01)
+    assert orbital_rel_err(psi.cpu().numpy(), ref, 4) <= TOL
+
+
+def test_propagate_fields_sphere_projectors():
+    """Steps with a per-step field array, projectors and padding columns."""
+    s = System(0.3, R=4.0, potential="wells", natoms=4, nst=6, ld=8, seed=9, dipole_axis=1,
+               well_ball=1.2)
+    fields = np.linspace(-0.3, 0.4, 6)
+    ref = oracle.propagate(s.oh, s.psi, 0.005, 6, fields=fields, nst=6)
+    psi = s.to_gpu(s.psi)
+    rsg().propagate(s.gh, psi, 0.005, 6, fields=torch.from_numpy(fields).cuda(), nst=6)
+    got = psi.cpu().numpy()
+    assert orbital_rel_err(got, ref, 6) <= TOL
+    np.testing.assert_array_equal(got[:, 6:], s.psi[:, 6:])
+
+
+def test_propagate_graph_replays_match_eager():
+    """A captured step sequence, replayed several times with eager work and
+    synchronisations in between, matches the eager sequence every time."""
+    s = System(0.3, n=24, potential="harmonic", nst=4, seed=2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        eager = s.to_gpu(s.psi)
+        graphed = s.to_gpu(s.psi)
+        ws = torch.empty(s.gh.workspace_bytes("step", 4, 4), dtype=torch.uint8, device="cuda")
+        for rep in range(3):
+            rsg().propagate(s.gh, eager, 0.01, 5, ws=ws)
+            rsg().propagate(s.gh, graphed, 0.01, 5, graph=True, ws=ws)
+            torch.cuda.synchronize()
+            _ = (eager.abs() ** 2).sum().item()  # eager library work between replays
+            np.testing.assert_array_equal(graphed.cpu().numpy(), eager.cpu().numpy())
+    ref = oracle.propagate(s.oh, s.psi, 0.01, 15)
+    assert orbital_rel_err(graphed.cpu().numpy(), ref, 4) <= TOL
+
+
+def test_reductions_and_energy():
+    s = System(0.3, R=4.5, potential="wells", natoms=3, nst=5, ld=6, seed=4, dipole_axis=0,
+               well_ball=1.0)
+    phi = synth.white_noise(77, s.og.np, 5, s.og.h, ld=6)
+    R = rsg()
+    a, b = s.to_gpu(phi), s.to_gpu(s.psi)
+    d = R.dot(s.gg, a, b, nst=5).cpu().numpy()
+    np.testing.assert_allclose(d, oracle.dot(s.og, phi, s.psi, nst=5), rtol=TOL, atol=TOL * np.abs(d).max())
+    n2 = R.norm2(s.gg, b, nst=5).cpu().numpy()
+    np.testing.assert_allclose(n2, oracle.norm2(s.og, s.psi, nst=5), rtol=TOL)
+    e = R.energy(s.gh, b, field=0.1, nst=5).cpu().numpy()
+    np.testing.assert_allclose(e, oracle.energy(s.oh, s.psi, field=0.1, nst=5)[1], rtol=TOL,
+                               atol=TOL * np.abs(e).max())
+    x = R.dipole_expectation(s.gh, b, nst=5).cpu().numpy()
+    ref = np.array([s.og.h ** 3 * np.sum(s.pos[:, 0] * np.abs(s.psi[:, k]) ** 2) for k in range(5)])
+    np.testing.assert_allclose(x, ref, rtol=1e-11, atol=1e-13)
+
+
+def test_reductions_deterministic():
+    s = System(0.2, R=6.0, potential="harmonic", nst=16, seed=6)
+    R = rsg()
+    b = s.to_gpu(s.psi)
+    d1 = R.dot(s.gg, b, b).cpu().numpy()
+    d2 = R.dot(s.gg, b, b).cpu().numpy()
+    np.testing.assert_array_equal(d1, d2)
+    h1 = R.hpsi(s.gh, b).cpu().numpy()
+    h2 = R.hpsi(s.gh, b).cpu().numpy()
+    np.testing.assert_array_equal(h1, h2)
+
+
+def test_adjoint_step_matches_oracle():
+    s = System(0.3, R=3.6, potential="wells", natoms=3, nst=3, ld=4, seed=12, dipole_axis=2,
+               well_ball=1.0)
+    lam0 = synth.white_noise(31, s.og.np, 3, s.og.h, ld=4)
+    lam_ref, g_ref = oracle.adjoint_step(s.oh, s.psi, lam0, 0.02, 0.15, nst=3)
+    lam = s.to_gpu(lam0)
+    g = rsg().adjoint_step(s.gh, s.to_gpu(s.psi), lam, 0.02, 0.15, nst=3).item()
+    assert orbital_rel_err(lam.cpu().numpy(), lam_ref, 3) <= TOL
+    assert g == pytest.approx(g_ref, rel=1e-11, abs=1e-14)
+
+
+def test_control_gradient_matches_oracle():
+    """Checkpointed discrete adjoint (ragged last segment) against the
+    oracle's store-everything adjoint."""
+    s = System(0.4, n=14, potential="wells", natoms=0, nst=2, seed=5, dipole_axis=2,
+               well_box=1.5, orbitals="packets", packet_box=1.0)
+    coef = synth.laser_coefficients(5, 6, sigma=0.3)
+    dt, nsteps, ck = 0.05, 23, 5
+    J_ref, g_ref, gs_ref = oracle.control_gradient(s.oh, s.psi, dt, nsteps, coef)
+    R = rsg()
+    psi = s.to_gpu(s.psi)
+    c = torch.from_numpy(coef).cuda()
+    J, store = R.control_forward(s.gh, psi, dt, nsteps, c, ck)
+    grad, gs = R.control_backward(s.gh, psi, dt, nsteps, c, ck, store)
+    assert J.item() == pytest.approx(J_ref, rel=1e-12)
+    np.testing.assert_allclose(gs.cpu().numpy(), gs_ref, rtol=1e-10, atol=1e-12 * np.abs(gs_ref).max())
+    np.testing.assert_allclose(grad.cpu().numpy(), g_ref, rtol=1e-10, atol=1e-12 * np.abs(g_ref).max())
+
+
+def test_optimal_control_autograd_matches_central_differences():
+    s = System(0.4, n=14, potential="wells", natoms=0, nst=2, seed=8, dipole_axis=2,
+               well_box=1.5, orbitals="packets", packet_box=1.0)
+    R = rsg()
+    dt, nsteps, ck = 0.05, 20, 4
+    coef = torch.from_numpy(synth.laser_coefficients(8, 5, sigma=0.3)).cuda().requires_grad_(True)
+    psi0 = s.to_gpu(s.psi)
+    J = R.OptimalControlJ.apply(coef, s.gh, psi0, dt, nsteps, ck)
+    J.backward()
+    grad = coef.grad.cpu().numpy()
+    eps = 1e-4
+    fd = np.zeros_like(grad)
+    for k in range(grad.size):
+        e = torch.zeros_like(coef)
+        e[k] = eps
+        jp = R.OptimalControlJ.apply((coef + e).detach(), s.gh, psi0, dt, nsteps, ck).item()
+        jm = R.OptimalControlJ.apply((coef - e).detach(), s.gh, psi0, dt, nsteps, ck).item()
+        fd[k] = (jp - jm) / (2 * eps)
+    assert np.abs(fd - grad).max() <= 1e-6 * np.abs(grad).max()
+
+
+def test_mixed_precision_step_error():
+    """FP32 Hamiltonian / FP64 accumulation: error vs the FP64 oracle stays
+    at the FP32 rounding level after 10 steps."""
+    s = System(0.3, n=32, potential="harmonic", nst=4, seed=4)
+    ref = oracle.propagate(s.oh, s.psi, 0.01, 10)
+    psi = s.to_gpu(s.psi)
+    for _ in range(10):
+        rsg().propagate_step(s.gh, psi, 0.01, dtype="mixed")
+    err = orbital_rel_err(psi.cpu().numpy(), ref, 4)
+    assert err < 1e-5, err
+    assert err > 1e-13  # really ran in FP32
+
+
+def test_mixed_precision_projectors():
+    s = System(0.3, R=4.0, potential="wells", natoms=4, nst=5, ld=8, seed=10, well_ball=1.2)
+    ref = oracle.propagate(s.oh, s.psi, 0.005, 3, nst=5)
+    psi = s.to_gpu(s.psi)
+    rsg().propagate(s.gh, psi, 0.005, 3, dtype="mixed", nst=5)
+    assert orbital_rel_err(psi.cpu().numpy(), ref, 5) < 1e-5
+
+
+def test_error_codes():
+    R = rsg()
+    s = System(0.3, n=8, potential="harmonic", nst=2, seed=1)
+    psi = s.to_gpu(s.psi)
+    with pytest.raises(R.RSGError) as ei:
+        R.hpsi(s.gh, psi, nst=3)  # nst > ld
+    assert ei.value.code == -2
+    with pytest.raises(R.RSGError) as ei:
+        R.adjoint_step(s.gh, psi, psi.clone(), 0.01, 0.0)  # no dipole axis
+    assert ei.value.code == -1
+    # the C call rejects a too-small workspace before enqueuing anything
+    import ctypes as C
+    rc = R._lib.rsg_propagate_step(s.gh._h, C.c_void_p(psi.data_ptr()), 2, 2, 0, 0.01, 0.0,
+                                   C.c_void_p(psi.data_ptr()), 16, None)
+    assert rc == -5
+    rc = R._lib.rsg_hpsi(s.gh._h, C.c_void_p(psi.data_ptr()), C.c_void_p(psi.data_ptr()), 2, 2, 0,
+                         0.0, None, 0, None)
+    assert rc == -1  # psi and hpsi overlap
