@@ -17,9 +17,11 @@
 // scatter puts 16 support points on M, the 4 projectors on K and 16
 // columns on N, which fills the instruction exactly.
 //
-// MFMA operand layout (lane l of a wave of 64):
-//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
-//   D[i][j] element r in lane j + 16*(i/4) with r = i % 4.
+// MFMA operand layout (lane l of a wave of 64), measured on gfx950:
+//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
+//   accumulator element r of lane l holds D[i][j] with j = l % 16 and
+//     i = l/16 + 4r      for v_mfma_f64_16x16x4f64,
+//     i = 4(l/16) + r    for v_mfma_f32_16x16x4f32.
 //
 // Supports are padded to a multiple of 16 entries with p = 0 (and a valid
 // index); padded entries contribute zero and are never written.  Atoms whose
@@ -38,6 +40,10 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 template <class T> struct V4;
 template <> struct V4<double> { using type = d4_t; };
 template <> struct V4<float> { using type = f4_t; };
+
+// Row of the accumulator element r held by lane group hi = l / 16.
+__device__ __forceinline__ int acc_row(double, int hi, int r) { return hi + 4 * r; }
+__device__ __forceinline__ int acc_row(float, int hi, int r) { return 4 * hi + r; }
 
 __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -78,7 +84,7 @@ __global__ void __launch_bounds__(256) k_kb_gather(const Tin *__restrict__ in, i
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const Tc v = ((red[0][l][r] + red[1][l][r]) + red[2][l][r]) + red[3][l][r];
-            const int64_t c = (int64_t)ct * 16 + 4 * hi + r;
+            const int64_t c = (int64_t)ct * 16 + acc_row(Tc(0), hi, r);
             if (c < ncols) D[((int64_t)a * 4 + lo) * ncols + c] = h3 * v;
         }
     }
@@ -116,7 +122,7 @@ __global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int6
     const int64_t end = (int64_t)at.x + at.z;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int64_t e = (int64_t)itm.y + 4 * hi + r;
+        const int64_t e = (int64_t)itm.y + acc_row(Tc(0), hi, r);
         if (e < end && col < ncols) {
             Tout *dst = out + (int64_t)idx[e] * ldr + col;
             *dst = (Tout)((double)*dst + (double)acc[r]);
