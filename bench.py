@@ -117,6 +117,14 @@ def bench_sphere(args):
     nst = cfg["nst"]
     ws = torch.empty(gh.workspace_bytes("step", nst, nst), dtype=torch.uint8, device=dev)
     dt = cfg["dt"]
+    tile = None
+    if args.tile:
+        B, TX, TY, ZC, PD, PT, BO = (int(v) for v in args.tile.split(","))
+        rsg.set_tile(gh, nst, B, TX, TY, ZC, PD, PT, BO)
+        tile = rsg.get_tile(gh, nst)
+    elif not args.no_autotune:
+        tile, tile_ms = rsg.autotune(gh, psi, reps=2)
+        log(f"autotuned tile {tile}: {tile_ms:.3f} ms per stage")
     log(f"warmup {args.warmup} steps")
     rsg.propagate(gh, psi, dt, args.warmup, ws=ws)
     torch.cuda.synchronize()
@@ -137,6 +145,18 @@ def bench_sphere(args):
     achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
     traffic = read_traffic(args.workload)
     norms = rsg.norm2(gg, psi).cpu().numpy()
+    # plain device copy of 1 GiB: achievable copy bandwidth, and the
+    # reference kernel for scaling the HBM byte counters
+    cbytes = 1 << 30
+    src = torch.empty(cbytes, dtype=torch.uint8, device=dev)
+    dstb = torch.empty_like(src)
+    rsg.copy(src, dstb)
+    with rsg.kernel_timing() as ct:
+        for _ in range(3):
+            rsg.copy(src, dstb)
+        torch.cuda.synchronize()
+    copy_gbs = 2 * cbytes / (ct.mean_ms * 1e-3) / 1e9
+    del src, dstb
     log(f"{el * 1e3 / args.steps:.3f} ms/step, stencil {kt.mean_ms:.4f} ms x {kt.count}, "
         f"norm range [{norms.min():.6f}, {norms.max():.6f}]")
     out = {
@@ -157,9 +177,10 @@ def bench_sphere(args):
                    "stencil": "8th-order 25-point star"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "kernel": "k_stencil (Horner stage)",
+                     "traffic": traffic, "kernel": "k_stencil_r (Horner stage)",
                      "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
-                     "algorithmic_bytes_per_launch": stage_bytes},
+                     "algorithmic_bytes_per_launch": stage_bytes, "tile": tile,
+                     "copy_gbs": copy_gbs},
     }
     del psi, ws
     torch.cuda.empty_cache()
@@ -175,6 +196,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default tile shape instead of timing the candidates")
+    ap.add_argument("--tile", default="",
+                    help="B,TX,TY,ZC,PD,PT,BO: use this stencil tile instead of autotuning")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

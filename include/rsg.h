@@ -242,6 +242,38 @@ int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld
                          double *g_steps_dev, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Stencil tile shapes and the autotuner                               */
+/* ------------------------------------------------------------------ */
+
+/* Tile of the z-marching stencil kernel: B orbitals x TX x TY grid columns
+ * per workgroup, marching along z in chunks of ZC planes (0 = whole box),
+ * prefetching PD planes ahead (FP64 kernel: 1..3; ignored for the mixed
+ * path).  PT > 0 launches tiles in PT x PT patches that share a z-range so
+ * that neighbouring workgroups march together (0 = no patches).  BO = 0
+ * launches the orbital batches of a tile together, BO = 1 sweeps all tiles
+ * of one batch before the next. */
+typedef struct {
+    int32_t B, TX, TY, ZC, PD, PT, BO;
+} rsg_tile;
+
+/* Compiled tile shapes for a dtype (ZC = 0).  Writes up to max entries and
+ * the total count. */
+int rsg_tile_candidates(int32_t dtype, rsg_tile *out, int32_t max, int32_t *count);
+
+/* Use tile t for batches of nst orbitals in dtype on this Hamiltonian.
+ * RSG_EUNSUPPORTED if (B, TX, TY) is not compiled. */
+int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_tile *t);
+int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
+
+/* Time one Horner stage on psi (device [np][ld], left unchanged) for every
+ * compiled tile shape and several z-chunk lengths with HIP events (best of
+ * reps launches after a warm-up launch), keep the fastest for (nst, dtype)
+ * and return it in *best and its time in *best_ms (either may be NULL).
+ * ws: RSG_OP_STEP bytes.  Synchronises the stream. */
+int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype, void *ws,
+                 size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Misc                                                                */
 /* ------------------------------------------------------------------ */
 

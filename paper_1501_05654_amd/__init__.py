@@ -21,7 +21,7 @@ __all__ = [
     "RSGError", "Grid", "Hamiltonian", "hpsi", "propagate_step", "propagate", "dot", "norm2",
     "energy", "dipole_expectation", "adjoint_step", "laser_field", "laser_grad",
     "control_forward", "control_backward", "OptimalControlJ", "copy", "kernel_timing",
-    "C128", "MIXED", "LIB_PATH",
+    "C128", "MIXED", "LIB_PATH", "autotune", "set_tile", "get_tile", "tile_candidates",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsg.so")
@@ -71,6 +71,10 @@ def _load():
         "rsg_copy": (C.c_int, [vp, vp, sz, vp]),
         "rsg_timing_enable": (C.c_int, [i32]),
         "rsg_timing_query": (C.c_int, [vp, vp, vp]),
+        "rsg_tile_candidates": (C.c_int, [i32, vp, i32, vp]),
+        "rsg_set_tile": (C.c_int, [vp, i64, i32, vp]),
+        "rsg_get_tile": (C.c_int, [vp, i64, i32, vp]),
+        "rsg_autotune": (C.c_int, [vp, vp, i64, i64, i32, vp, sz, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -407,3 +411,46 @@ class kernel_timing:
         _check(_lib.rsg_timing_query(C.byref(n), C.byref(m), C.byref(t)))
         self.count, self.mean_ms, self.total_ms = int(n.value), float(m.value), float(t.value)
         return False
+
+
+class _Tile(C.Structure):
+    _fields_ = [("B", C.c_int32), ("TX", C.c_int32), ("TY", C.c_int32), ("ZC", C.c_int32),
+                ("PD", C.c_int32), ("PT", C.c_int32), ("BO", C.c_int32)]
+
+
+def _tile_dict(t: _Tile) -> dict:
+    return {"B": t.B, "TX": t.TX, "TY": t.TY, "ZC": t.ZC, "PD": t.PD, "PT": t.PT, "BO": t.BO}
+
+
+def tile_candidates(dtype="c128") -> list:
+    n = C.c_int32()
+    _check(_lib.rsg_tile_candidates(_dt(dtype), None, 0, C.byref(n)))
+    arr = (_Tile * n.value)()
+    _check(_lib.rsg_tile_candidates(_dt(dtype), arr, n.value, C.byref(n)))
+    return [_tile_dict(t) for t in arr]
+
+
+def set_tile(ham: Hamiltonian, nst: int, B: int, TX: int, TY: int, ZC: int = 0, PD: int = 1,
+             PT: int = 0, BO: int = 0, dtype="c128"):
+    t = _Tile(B, TX, TY, ZC, PD, PT, BO)
+    _check(_lib.rsg_set_tile(ham._h, int(nst), _dt(dtype), C.byref(t)))
+
+
+def get_tile(ham: Hamiltonian, nst: int, dtype="c128") -> dict:
+    t = _Tile()
+    _check(_lib.rsg_get_tile(ham._h, int(nst), _dt(dtype), C.byref(t)))
+    return _tile_dict(t)
+
+
+def autotune(ham: Hamiltonian, psi: torch.Tensor, dtype="c128", reps: int = 3,
+             nst: int | None = None):
+    """Time every compiled tile shape on one Horner stage of psi and keep the
+    fastest for this (nst, dtype); returns (tile, milliseconds)."""
+    _batch(psi, "psi", ham.grid.np)
+    n = _nst(psi, nst)
+    ws = _ws(ham.workspace_bytes("step", n, psi.shape[1], _dt(dtype)), psi.device)
+    t = _Tile()
+    ms = C.c_double()
+    _check(_lib.rsg_autotune(ham._h, _ptr(psi), n, psi.shape[1], _dt(dtype), _ptr(ws), ws.numel(),
+                             int(reps), C.byref(t), C.byref(ms), _stream()))
+    return _tile_dict(t), float(ms.value)

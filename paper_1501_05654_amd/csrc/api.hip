@@ -84,10 +84,18 @@ __global__ void k_to_float(const double *src, float *dst, int64_t n) {
         dst[i] = (float)src[i];
 }
 
-__global__ void k_copy16(const int4 *src, int4 *dst, int64_t n16) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// Plain copy, four 16-byte loads in flight per thread per iteration.
+__global__ void __launch_bounds__(256) k_copy16(const int4 *src, int4 *dst, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const int4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_sum(const double *v, int64_t n, double *out) {
@@ -160,7 +168,7 @@ int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ld, 
     a.ld = ld;
     a.field = field;
     a.field_dev = field_dev;
-    rc = launch_stencil(H, a, default_shape(*H.g, nst, 0), s);
+    rc = launch_stencil(H, a, H.tile_for(nst, 0), s);
     if (rc) return rc;
     return launch_kb_scatter(H, out, 0, 0, nst, ld, D, 1.0, 0.0, s);
 }
@@ -185,7 +193,8 @@ int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *o
     a.field_dev = field_dev;
     a.cre = cre;
     a.cim = cim;
-    rc = launch_stencil(H, a, default_shape(*H.g, nst, compute), s);
+    a.first = in == base && in_t == 0;
+    rc = launch_stencil(H, a, H.tile_for(nst, compute), s);
     if (rc) return rc;
     return launch_kb_scatter(H, out, out_t, compute, nst, ld, D, cre, cim, s);
 }
@@ -336,12 +345,18 @@ extern "C" int rsg_ham_create(rsg_grid_t g, const double *vloc_dev, double kin, 
         };
         hipError_t e;
         const int64_t np = g->np;
-        if (vloc_dev && np > 0) {
-            if ((e = hipMalloc(&H->V, sizeof(double) * np)) != hipSuccess) return fail("V", e);
-            if ((e = hipMalloc(&H->V32, sizeof(float) * np)) != hipSuccess) return fail("V32", e);
-            if ((e = hipMemcpy(H->V, vloc_dev, sizeof(double) * np, hipMemcpyDeviceToDevice)) != hipSuccess)
-                return fail("V copy", e);
-            k_to_float<<<nblocks_for(np), 256>>>(H->V, H->V32, np);
+        // the kernels always read V (zeros when none is given)
+        {
+            const int64_t nv = np > 0 ? np : 1;
+            if ((e = hipMalloc(&H->V, sizeof(double) * nv)) != hipSuccess) return fail("V", e);
+            if ((e = hipMalloc(&H->V32, sizeof(float) * nv)) != hipSuccess) return fail("V32", e);
+            if (vloc_dev && np > 0) {
+                if ((e = hipMemcpy(H->V, vloc_dev, sizeof(double) * np, hipMemcpyDeviceToDevice)) != hipSuccess)
+                    return fail("V copy", e);
+            } else if ((e = hipMemset(H->V, 0, sizeof(double) * nv)) != hipSuccess) {
+                return fail("V clear", e);
+            }
+            k_to_float<<<nblocks_for(nv), 256>>>(H->V, H->V32, nv);
         }
         if (natoms > 0) {
             // pad every support to a multiple of 16 entries (p = 0, index of
@@ -525,7 +540,8 @@ extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, in
     // make sure every launch plan exists before capture (plan creation syncs)
     int err = RSG_OK;
     for (int cmp = 0; cmp < 2; ++cmp) {
-        TileShape sh = default_shape(*H->g, nst, cmp);
+        TileShape sh = H->tile_for(nst, cmp);
+        if (sh.ZC <= 0) sh.ZC = H->g->n[2];
         if (!H->g->plan(sh, s, &err)) return err;
     }
     GraphKey key{psi, nst, ld, dtype, dt, nsteps, fields_dev, ws, ws_bytes, s};
@@ -753,6 +769,130 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     return rsg_laser_grad(gs, nsteps, T, dt, ncoef, grad_dev, stream);
 }
 
+static int tile_compute(int32_t dtype) { return dtype == RSG_C128 ? 0 : 1; }
+
+extern "C" int rsg_tile_candidates(int32_t dtype, rsg_tile *out, int32_t max, int32_t *count) {
+    clear_error();
+    RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_tile_candidates: bad dtype");
+    RSG_REQUIRE(count && (max <= 0 || out), RSG_EINVAL, "rsg_tile_candidates: null output");
+    const auto v = tile_candidates(tile_compute(dtype));
+    *count = (int32_t)v.size();
+    for (int32_t k = 0; k < max && k < (int32_t)v.size(); ++k) out[k] = rsg_tile{v[k].B, v[k].TX, v[k].TY, 0, v[k].PD, 0, 0};
+    return RSG_OK;
+}
+
+extern "C" int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_tile *t) {
+    clear_error();
+    RSG_REQUIRE(H && t, RSG_EINVAL, "rsg_set_tile: null argument");
+    RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_set_tile: bad dtype");
+    RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "rsg_set_tile: ZC must be >= 0");
+    bool ok = false;
+    const int pd = tile_compute(dtype) == 0 ? t->PD : 1;
+    for (const auto &c : tile_candidates(tile_compute(dtype)))
+        ok = ok || (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == pd);
+    RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_set_tile: %dx%dx%d (depth %d) is not a compiled tile shape", t->B,
+                t->TX, t->TY, t->PD);
+    RSG_REQUIRE(t->PT >= 0 && t->PT <= 64, RSG_EINVAL, "rsg_set_tile: PT must be in 0..64");
+    RSG_REQUIRE(t->BO == 0 || t->BO == 1, RSG_EINVAL, "rsg_set_tile: BO must be 0 or 1");
+    TileShape sh{t->B, t->TX, t->TY, t->ZC};
+    sh.PD = pd;
+    sh.PT = t->PT;
+    sh.BO = t->BO;
+    H->tiles[std::make_pair(nst, tile_compute(dtype))] = sh;
+    drop_graphs(H);
+    return RSG_OK;
+}
+
+extern "C" int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t) {
+    clear_error();
+    RSG_REQUIRE(H && t, RSG_EINVAL, "rsg_get_tile: null argument");
+    RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_get_tile: bad dtype");
+    const TileShape s = H->tile_for(nst, tile_compute(dtype));
+    *t = rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, s.PT, s.BO};
+    return RSG_OK;
+}
+
+// Times one Horner stage (out = psi + c H psi into the workspace, psi
+// untouched) for every compiled tile shape and z-chunk length, keeps the
+// fastest for (nst, dtype) and reports it.
+extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype,
+                            void *ws, size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms,
+                            void *stream) {
+    clear_error();
+    int rc = check_batch(H, psi, nst, ld, "rsg_autotune");
+    if (rc) return rc;
+    RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_autotune: bad dtype");
+    RSG_REQUIRE(nst > 0 && reps > 0, RSG_EINVAL, "rsg_autotune: need nst > 0 and reps > 0");
+    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ld, dtype) - 256, RSG_ENOMEM, "rsg_autotune: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int cmp = tile_compute(dtype);
+    const int wt = cmp;  // work-buffer type: complex64 for the mixed path
+    Carve c(ws, ws_bytes);
+    void *w1 = c.take(batch_bytes(*H->g, ld, cmp ? 8 : 16));
+    if (!c.ok) {
+        set_error("rsg_autotune: workspace carve failed");
+        return RSG_ENOMEM;
+    }
+    return guarded([&]() -> int {
+        std::vector<int> zcs = {0};
+        for (int z : {64, 32})
+            if (z < H->g->n[2]) zcs.push_back(z);
+        const std::vector<int> pts = {0, 4};
+        hipEvent_t e0, e1;
+        RSG_CHECK_HIP(hipEventCreate(&e0));
+        RSG_CHECK_HIP(hipEventCreate(&e1));
+        double bt = 1e300;
+        TileShape bs = default_shape(*H->g, nst, cmp);
+        int err = RSG_OK;
+        for (const auto &cand : tile_candidates(cmp)) {
+            for (int zpi = 0; zpi < (int)(zcs.size() * pts.size() * 2); ++zpi) {
+                const int zc = zcs[zpi % zcs.size()];
+                TileShape sh = cand;
+                sh.ZC = zc > 0 ? zc : H->g->n[2];
+                sh.PT = pts[(zpi / zcs.size()) % pts.size()];
+                sh.BO = zpi / (int)(zcs.size() * pts.size());
+                if (!H->g->plan(sh, s, &err)) break;
+                StageArgs a;
+                a.in = psi;
+                a.base = psi;
+                a.out = w1;
+                a.in_t = 0;
+                a.out_t = wt;
+                a.compute = cmp;
+                a.mode = 1;
+                a.nst = nst;
+                a.ld = ld;
+                a.cim = -1e-3;
+                double tmin = 1e300;
+                for (int r = 0; r <= reps; ++r) {  // first launch warms up
+                    RSG_CHECK_HIP(hipEventRecord(e0, s));
+                    if ((rc = launch_stencil(*H, a, sh, s))) break;
+                    RSG_CHECK_HIP(hipEventRecord(e1, s));
+                    RSG_CHECK_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    RSG_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (r > 0) tmin = std::min(tmin, (double)ms);
+                }
+                if (rc) break;
+                if (tmin < bt) {
+                    bt = tmin;
+                    bs = sh;
+                }
+            }
+            if (rc || err) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (err) return err;
+        if (rc) return rc;
+        H->tiles[std::make_pair(nst, cmp)] = bs;
+        drop_graphs(H);
+        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, bs.PT, bs.BO};
+        if (best_ms) *best_ms = bt;
+        return RSG_OK;
+    });
+}
+
 extern "C" int rsg_copy(const void *src, void *dst, size_t nbytes, void *stream) {
     clear_error();
     RSG_REQUIRE(nbytes % 16 == 0, RSG_EINVAL, "rsg_copy: size must be a multiple of 16");
@@ -761,7 +901,7 @@ extern "C" int rsg_copy(const void *src, void *dst, size_t nbytes, void *stream)
     if (nbytes == 0) return RSG_OK;
     const int64_t n16 = (int64_t)(nbytes / 16);
     int64_t nb = (n16 + 255) / 256;
-    nb = std::min<int64_t>(nb, 256 * 64);
+    nb = std::min<int64_t>(nb, 256 * 16);
     timing_before((hipStream_t)stream);
     k_copy16<<<(unsigned)nb, 256, 0, (hipStream_t)stream>>>((const int4 *)src, (int4 *)dst, n16);
     timing_after((hipStream_t)stream);

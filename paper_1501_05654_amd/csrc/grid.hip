@@ -96,15 +96,21 @@ Grid::~Grid() {
     for (auto &kv : plans)
         if (kv.second.items) (void)hipFree(kv.second.items);
     if (rows) (void)hipFree(rows);
+    if (zeros) (void)hipFree(zeros);
     if (ijk) (void)hipFree(ijk);
 }
 
 // Work items for one tile shape: every (tx, ty) tile that holds box points,
-// with its z-extent split into chunks of at most ZC planes.  Items are ordered
-// z-chunk major, then ty, then tx, so that workgroups launched together cover
-// neighbouring tiles at similar depths.
+// with its z-extent split into chunks of at most ZC planes.  Without patches
+// (PT = 0) items are ordered z-chunk major, then ty, then tx.  With patches,
+// tiles are grouped into PT x PT patches; all tiles of a patch march over the
+// patch's common z-extent, and items are ordered patch-major, then chunk,
+// then tile, so that a patch's workgroups are launched together.
 const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
-    auto it = plans.find(s);
+    TileShape key{0, s.TX, s.TY, s.ZC};
+    key.PD = 0;
+    key.PT = s.PT;
+    auto it = plans.find(key);
     if (it != plans.end()) return &it->second;
     const int nx = n[0], ny = n[1], nz = n[2];
     const int ntx = (nx + s.TX - 1) / s.TX, nty = (ny + s.TY - 1) / s.TY;
@@ -121,21 +127,42 @@ const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
                 zhi[k] = std::max(zhi[k], z);
             }
         }
-    int maxchunks = 0;
-    for (size_t k = 0; k < zlo.size(); ++k)
-        if (zhi[k] >= zlo[k])
-            maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);
     std::vector<int4> items;
-    for (int c = 0; c < maxchunks; ++c)
-        for (int ty = 0; ty < nty; ++ty)
-            for (int tx = 0; tx < ntx; ++tx) {
-                const size_t k = (size_t)ty * ntx + tx;
-                if (zhi[k] < zlo[k]) continue;
-                const int z0 = zlo[k] + c * s.ZC;
-                if (z0 > zhi[k]) continue;
-                const int z1 = std::min(zhi[k] + 1, z0 + s.ZC);
-                items.push_back(make_int4(tx, ty, z0, z1));
+    if (s.PT <= 0) {
+        int maxchunks = 0;
+        for (size_t k = 0; k < zlo.size(); ++k)
+            if (zhi[k] >= zlo[k]) maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);
+        for (int c = 0; c < maxchunks; ++c)
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < ntx; ++tx) {
+                    const size_t k = (size_t)ty * ntx + tx;
+                    if (zhi[k] < zlo[k]) continue;
+                    const int z0 = zlo[k] + c * s.ZC;
+                    if (z0 > zhi[k]) continue;
+                    items.push_back(make_int4(tx, ty, z0, std::min(zhi[k] + 1, z0 + s.ZC)));
+                }
+    } else {
+        const int npx = (ntx + s.PT - 1) / s.PT, npy = (nty + s.PT - 1) / s.PT;
+        for (int py = 0; py < npy; ++py)
+            for (int px = 0; px < npx; ++px) {
+                int plo = nz, phi = -1;
+                for (int ty = py * s.PT; ty < std::min(nty, (py + 1) * s.PT); ++ty)
+                    for (int tx = px * s.PT; tx < std::min(ntx, (px + 1) * s.PT); ++tx) {
+                        const size_t k = (size_t)ty * ntx + tx;
+                        if (zhi[k] < zlo[k]) continue;
+                        plo = std::min(plo, zlo[k]);
+                        phi = std::max(phi, zhi[k]);
+                    }
+                if (phi < plo) continue;
+                for (int z0 = plo; z0 <= phi; z0 += s.ZC)
+                    for (int ty = py * s.PT; ty < std::min(nty, (py + 1) * s.PT); ++ty)
+                        for (int tx = px * s.PT; tx < std::min(ntx, (px + 1) * s.PT); ++tx) {
+                            const size_t k = (size_t)ty * ntx + tx;
+                            if (zhi[k] < zlo[k]) continue;
+                            items.push_back(make_int4(tx, ty, z0, std::min(phi + 1, z0 + s.ZC)));
+                        }
             }
+    }
     TilePlan p;
     p.nitems = (int32_t)items.size();
     if (p.nitems > 0) {
@@ -152,7 +179,7 @@ const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
         }
     }
     *err = RSG_OK;
-    return &(plans[s] = p);
+    return &(plans[key] = p);
 }
 
 }  // namespace rsg
@@ -204,7 +231,10 @@ extern "C" int rsg_grid_create(const rsg_grid_desc *d, void *stream, rsg_grid_t 
         if ((e = hipMalloc(&x0, sizeof(int32_t) * nrows)) != hipSuccess) return fail(e);
         if ((e = hipMalloc(&len, sizeof(int32_t) * nrows)) != hipSuccess) return fail(e);
         if ((e = hipMalloc(&total, sizeof(int64_t))) != hipSuccess) return fail(e);
-        if ((e = hipMalloc(&g->rows, sizeof(int2) * nrows)) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&g->rows, sizeof(int2) * (nrows + 1))) != hipSuccess) return fail(e);
+        if ((e = hipMemsetAsync(g->rows + nrows, 0, sizeof(int2), s)) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&g->zeros, 256)) != hipSuccess) return fail(e);
+        if ((e = hipMemsetAsync(g->zeros, 0, 256, s)) != hipSuccess) return fail(e);
         const int bs = 256;
         k_row_extent<<<(unsigned)((nrows + bs - 1) / bs), bs, 0, s>>>(d->shape, nx, nx, nx, Q, M,
                                                                      x0, len);

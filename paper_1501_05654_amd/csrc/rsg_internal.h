@@ -54,13 +54,24 @@ int guarded(F &&f) {
 
 // Tile shape of the z-marching stencil: B orbitals x TX x TY points per
 // workgroup, marching along z in chunks of at most ZC planes.
+// PD is the software-pipeline depth of the FP64 kernel (planes prefetched
+// ahead, 1..3).  PT > 0 groups tiles into PT x PT patches that share one
+// z-range and are launched consecutively, so the workgroups of a patch march
+// in step and read each other's halos from L2.  The launch plan depends on
+// (TX, TY, ZC, PT).
 struct TileShape {
     int B, TX, TY, ZC;
+    int PD = 1;
+    int PT = 0;
+    int BO = 0;  // block order: 0 = orbital batch fastest, 1 = batch slowest
     bool operator<(const TileShape &o) const {
         if (B != o.B) return B < o.B;
         if (TX != o.TX) return TX < o.TX;
         if (TY != o.TY) return TY < o.TY;
-        return ZC < o.ZC;
+        if (ZC != o.ZC) return ZC < o.ZC;
+        if (PD != o.PD) return PD < o.PD;
+        if (PT != o.PT) return PT < o.PT;
+        return BO < o.BO;
     }
 };
 
@@ -80,7 +91,8 @@ struct Grid {
     double h = 0;
     // rows[z*ny + y] = {base, x0 | x1 << 16}: point (x,y,z) is in the box iff
     // x0 <= x < x1, with compact index base + x.
-    int2 *rows = nullptr;       // device [ny*nz]
+    int2 *rows = nullptr;       // device [ny*nz + 1]; entry ny*nz is an empty row
+    double *zeros = nullptr;    // device, 256 zero bytes: target of masked-off loads
     std::vector<int2> rows_host;
     int32_t *ijk = nullptr;     // device [np][3]
     std::map<TileShape, TilePlan> plans;
@@ -108,6 +120,9 @@ struct Ham {
     // scatter work: per colour a device list of {atom, entry0} (16 entries each)
     std::vector<int2 *> scatter_items;
     std::vector<int32_t> scatter_counts;
+    // stencil tile shape per (nst, compute) chosen by rsg_autotune / rsg_set_tile
+    std::map<std::pair<int64_t, int>, TileShape> tiles;
+    TileShape tile_for(int64_t nst, int compute) const;
     ~Ham();
 };
 
@@ -127,6 +142,7 @@ struct StageArgs {
     const void *base = nullptr;
     void *out = nullptr;
     int in_t = 0, out_t = 0, compute = 0, mode = 0;
+    bool first = false;  // base == in (first Horner stage)
     int64_t nst = 0, ld = 0;
     double field = 0;
     const double *field_dev = nullptr;
@@ -134,6 +150,7 @@ struct StageArgs {
 };
 int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s);
 TileShape default_shape(const Grid &g, int64_t nst, int compute);
+std::vector<TileShape> tile_candidates(int compute);
 
 // KB projectors.  gather: D[a][i][col] = h^3 sum_e p[e][i] in[idx[e]][col]
 // (col over the 2*nst real columns); scatter: out[idx[e]][col] +=

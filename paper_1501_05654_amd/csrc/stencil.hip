@@ -50,6 +50,7 @@ struct KParams {
     void *out;
     const int4 *items;
     const int2 *rows;
+    const double *zeros;
     const void *V;
     const double *field_dev;
     int64_t nst, ld;
@@ -59,6 +60,8 @@ struct KParams {
     double off[3];
     double cre, cim;
     int32_t nob;
+    int32_t nitems;
+    int32_t batch_slowest;
     int32_t ny, nz;
     int32_t axis;
 };
@@ -68,6 +71,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int per = nb >> 3, rem = nb & 7;
     const int xcd = b & 7, local = b >> 3;
     return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + local;
+}
+
+// Block order.  Batch fastest: the orbital batches of a tile run together,
+// so the whole ld-orbital row of each point is read at about the same time
+// (DRAM row locality).  Batch slowest: each XCD sweeps a band of tiles of one
+// batch, so neighbouring tiles can find each other's halos in L2.
+__device__ __forceinline__ void block_item(const KParams &a, int blk, int *ob, int *item) {
+    if (a.batch_slowest) {
+        *ob = blk / a.nitems;
+        *item = blk - *ob * a.nitems;
+    } else {
+        *item = blk / a.nob;
+        *ob = blk - *item * a.nob;
+    }
 }
 
 __device__ __forceinline__ int64_t point_index(const KParams &a, int x, int y, int z) {
@@ -96,8 +113,10 @@ __device__ __forceinline__ typename CT<Tc>::c2 fetch(const Tin *in, int64_t idx,
     return C2{(Tc)v.x, (Tc)v.y};
 }
 
+// Complex-lane variant (one complex value per lane), used by the mixed
+// path: FP32 arithmetic on complex64 or complex128 input.
 template <int B, int TX, int TY, class Tin, class Tc, int MODE, class Tout>
-__global__ void __launch_bounds__(B * TX * TY) k_stencil(KParams a) {
+__global__ void __launch_bounds__(B * TX * TY) k_stencil_c(KParams a) {
     using C2 = typename CT<Tc>::c2;
     constexpr int NT = B * TX * TY;
     constexpr int LX = TX + 8, LY = TY + 8;
@@ -106,8 +125,9 @@ __global__ void __launch_bounds__(B * TX * TY) k_stencil(KParams a) {
     constexpr int HPT = (NH + NT - 1) / NT;
     __shared__ C2 tile[LY * LX * B];
 
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int item = blk / a.nob, ob = blk - item * a.nob;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // block order: see k_stencil_r
+    int ob, item;
+    block_item(a, blk, &ob, &item);
     const int4 it = a.items[item];
     const int t = threadIdx.x;
     const int o = t % B, lx = (t / B) % TX, ly = t / (B * TX);
@@ -217,40 +237,294 @@ __global__ void __launch_bounds__(B * TX * TY) k_stencil(KParams a) {
     }
 }
 
-template <int B, int TX, int TY, class Tin, class Tc, int MODE, class Tout>
-int launch_one(const KParams &p, int nblocks, hipStream_t s) {
-    k_stencil<B, TX, TY, Tin, Tc, MODE, Tout><<<nblocks, B * TX * TY, 0, s>>>(p);
+// Real-lane variant for FP64: lanes run over the 2*nst real columns of the
+// interleaved batch (re and im of an orbital in adjacent lanes), so a thread
+// carries one double per plane instead of a complex pair; the Horner
+// epilogue gets the partner component with one xor-1 lane shuffle.
+//
+// Software pipeline over z, depth D: at step z (output plane z) a thread
+//   - issues the row-table reads for the loads of step z+1,
+//   - issues the data loads of plane z+4+D (own column, entering the
+//     register queue D steps later), of the halo of plane z+D, and the V and
+//     base values of plane z+D, all from row entries read one step earlier,
+//   - computes plane z from data that arrived during earlier steps.
+// No load is waited on in the step that issues it, and no data load waits on
+// a row-table read of the same step.  FIRST: base == in, whose value at the
+// point is the centre tap.
+// Branch-free row lookup: an out-of-box row reads the empty sentinel entry
+// that follows the table.  Loads are never masked after they return (the
+// compiler would place the select where the load is issued and wait there);
+// a masked-off lane loads from a location that holds the neutral value.
+__device__ __forceinline__ int2 row_of(const KParams &a, int y, int z) {
+    const bool v = y >= 0 && y < a.ny && z >= 0 && z < a.nz;
+    return a.rows[v ? z * a.ny + y : a.ny * a.nz];
+}
+__device__ __forceinline__ int idx_in_row(int2 r, int x) {
+    const int x0 = r.y & 0xffff, x1 = (r.y >> 16) & 0xffff;
+    return (x >= x0 && x < x1) ? r.x + x : -1;
+}
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
+
+template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
+__global__ void __launch_bounds__(RB * TX * TY) k_stencil_r(KParams a) {
+    constexpr int NT = RB * TX * TY;
+    constexpr int LX = TX + 8, LY = TY + 8;
+    constexpr int NHP = 8 * TX + 8 * TY;
+    constexpr int NH = NHP * RB;
+    constexpr int HPT = (NH + NT - 1) / NT;
+    constexpr int YS = LX * RB;
+    // Register rings, all indexed by compile-time constants after unrolling:
+    //   col[Q]  own-column values of planes z-4 .. z+4+D (loads land in place),
+    //   oid[Q]  own compact index of the same planes,
+    //   hal[D]: halo of planes z .. z+D-1,
+    //   vr[D+1], br[D+1]: V and base, loaded into the slot consumed last step
+    //     so that a new load never targets a register still being read,
+    //   rfr[2], rhl[2]: row entries read one step before the loads using them.
+    constexpr int Q = D == 1 ? 10 : 12;  // >= 9 + D, and keeps the unroll period at 10 or 12
+    constexpr int VD = D + 1;
+    constexpr int P = clcm(clcm(clcm(Q, D), VD), 2);  // unroll period of the z loop
+    __shared__ double tile[LY * LX * RB];
+
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    int ob, item;
+    block_item(a, blk, &ob, &item);
+    const int4 it = a.items[item];
+    const int t = threadIdx.x;
+    const int c = t % RB, lx = (t / RB) % TX, ly = t / (RB * TX);
+    const int x = it.x * TX + lx, y = it.y * TY + ly;
+    const int ncols = (int)(2 * a.nst);
+    const int col = ob * RB + c;
+    const bool cok = col < ncols;
+    const int64_t ldr = 2 * a.ld;
+    const double *in = static_cast<const double *>(a.in);
+    const double *base = static_cast<const double *>(a.base);
+    const double *Vp = static_cast<const double *>(a.V);
+
+    int hl[HPT], hx[HPT], hy[HPT], hc[HPT];
+    bool hok[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+        const int j = t + k * NT;
+        const int oh = j % RB, hp = j / RB;
+        int lxl, lyl;
+        if (hp < 8 * TX) {
+            const int yh = hp / TX;
+            lxl = hp % TX + 4;
+            lyl = yh < 4 ? yh : TY + yh;
+        } else {
+            const int q = hp - 8 * TX;
+            const int cc = q % 8;
+            lyl = q / 8 + 4;
+            lxl = cc < 4 ? cc : TX + cc;
+        }
+        hl[k] = (lyl * LX + lxl) * RB + oh;
+        hx[k] = it.x * TX + lxl - 4;
+        hy[k] = it.y * TY + lyl - 4;
+        hc[k] = ob * RB + oh;
+        hok[k] = j < NH && hc[k] < ncols;
+    }
+    // Loads are unconditional: a tap outside the box (or a padding column)
+    // reads the zero pad; V and base of an outside point read a valid entry
+    // whose value is never stored.
+    const double *zp = a.zeros;
+    auto fetch = [&](int idx, int cc, bool ok) -> double {
+        const double *pa = (ok && idx >= 0) ? in + (int64_t)idx * ldr + cc : zp;
+        return *pa;
+    };
+    auto fetch_v = [&](int idx) -> double { return Vp[idx >= 0 ? idx : 0]; };
+    auto fetch_b = [&](int idx) -> double {
+        if (MODE != 1 || FIRST) return 0.0;
+        const bool v = idx >= 0 && cok;
+        return base[(int64_t)(v ? idx : 0) * ldr + (v ? col : 0)];
+    };
+
+    const int z0 = it.z, z1 = it.w;
+    // prologue: planes z0-4 .. z0+3+D into ring slots 0 .. Q-2 (slot of plane
+    // z0 + m is m + 4), halo/V/base of planes z0 .. z0+D-1, rows for step z0
+    double cv[Q];
+    int oid[Q];
+#pragma unroll
+    for (int j = 0; j < Q - 1; ++j) {
+        oid[j] = idx_in_row(row_of(a, y, z0 - 4 + j), x);
+        cv[j] = fetch(oid[j], col, cok);
+    }
+    cv[Q - 1] = 0.0;
+    oid[Q - 1] = -1;
+    double hal[D][HPT], vr[VD], br[VD];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int k = 0; k < HPT; ++k)
+            hal[d][k] = fetch(idx_in_row(row_of(a, hy[k], z0 + d), hx[k]), hc[k], hok[k]);
+        vr[d] = fetch_v(oid[4 + d]);
+        br[d] = fetch_b(oid[4 + d]);
+    }
+    vr[D] = 0.0;
+    br[D] = 0.0;
+    // step z reads row slot (z - z0) % 2 and fills the other one
+    int2 rfr[2], rhl[2][HPT];
+    rfr[0] = row_of(a, y, z0 + 4 + D);
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of(a, hy[k], z0 + D);
+    rfr[1] = make_int2(0, 0);
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) rhl[1][k] = make_int2(0, 0);
+
+    const double E = a.field_dev ? *a.field_dev : a.field;
+    const double kin_h2 = a.kin_h2;
+    const int own = ((ly + 4) * LX + lx + 4) * RB + c;
+    double *out = static_cast<double *>(a.out);
+
+    for (int zb = z0; zb < z1; zb += P) {
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            const int z = zb + s;
+            if (z >= z1) break;
+            const int sd = s % D, sr = s % 2, srp = (s + 1) % 2;
+            const int sv = s % VD, svn = (s + D) % VD;  // V/base: read slot, load slot
+            // ring slot of plane z + m
+#define SLOT(m) ((s + (m) + 4 + Q) % Q)
+            tile[own] = cv[SLOT(0)];
+#pragma unroll
+            for (int k = 0; k < HPT; ++k)
+                if (t + k * NT < NH) tile[hl[k]] = hal[sd][k];
+            const int idx_c = oid[SLOT(0)];
+            const double v_c = vr[sv], b_c = br[sv];
+            __syncthreads();
+            {
+                // row entries for the next step first, then the loads that use
+                // the entries read last step: own column plane z+4+D, halo and
+                // V/base of plane z+D
+                rfr[srp] = row_of(a, y, z + 5 + D);
+#pragma unroll
+                for (int k = 0; k < HPT; ++k) rhl[srp][k] = row_of(a, hy[k], z + 1 + D);
+                const int idf = (z + 4 + D < z1 + 4) ? idx_in_row(rfr[sr], x) : -1;
+                oid[SLOT(4 + D)] = idf;
+                cv[SLOT(4 + D)] = fetch(idf, col, cok);
+                const bool live = z + D < z1;
+#pragma unroll
+                for (int k = 0; k < HPT; ++k)
+                    hal[sd][k] = fetch(idx_in_row(rhl[sr][k], hx[k]), hc[k], hok[k] && live);
+                const int idv = live ? oid[SLOT(D)] : -1;
+                vr[svn] = fetch_v(idv);
+                br[svn] = fetch_b(idv);
+            }
+            const double q0 = cv[SLOT(0)];
+            const double lap =
+                3.0 * FD<double>::c0 * q0 +
+                FD<double>::c1 * ((tile[own - RB] + tile[own + RB]) + (tile[own - YS] + tile[own + YS]) + (cv[SLOT(-1)] + cv[SLOT(1)])) +
+                FD<double>::c2 * ((tile[own - 2 * RB] + tile[own + 2 * RB]) + (tile[own - 2 * YS] + tile[own + 2 * YS]) + (cv[SLOT(-2)] + cv[SLOT(2)])) +
+                FD<double>::c3 * ((tile[own - 3 * RB] + tile[own + 3 * RB]) + (tile[own - 3 * YS] + tile[own + 3 * YS]) + (cv[SLOT(-3)] + cv[SLOT(3)])) +
+                FD<double>::c4 * ((tile[own - 4 * RB] + tile[own + 4 * RB]) + (tile[own - 4 * YS] + tile[own + 4 * YS]) + (cv[SLOT(-4)] + cv[SLOT(4)]));
+#undef SLOT
+            double vloc = v_c;
+            if (a.axis >= 0) {
+                const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
+                vloc += E * (a.h * ((double)cc - a.off[a.axis]));
+            }
+            const double hval = kin_h2 * lap + vloc * q0;
+            if (MODE == 0) {
+                if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = hval;
+            } else {
+                const double hpart = __shfl_xor(hval, 1);  // the other component of this orbital
+                const double bb = FIRST ? q0 : b_c;
+                // re: b + cre*Hre - cim*Him ; im: b + cre*Him + cim*Hre
+                const double r = (c & 1) ? bb + (a.cre * hval + a.cim * hpart)
+                                         : bb + (a.cre * hval - a.cim * hpart);
+                if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = r;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int B, int TX, int TY>
+int launch_c(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
+    constexpr int NT = B * TX * TY;
+    if (a.compute == 0 || a.mode != 1) return RSG_EUNSUPPORTED;
+    if (a.in_t == 0 && a.out_t == 1)
+        k_stencil_c<B, TX, TY, double2, float, 1, float2><<<nb, NT, 0, s>>>(p);
+    else if (a.in_t == 1 && a.out_t == 1)
+        k_stencil_c<B, TX, TY, float2, float, 1, float2><<<nb, NT, 0, s>>>(p);
+    else if (a.in_t == 1 && a.out_t == 0)
+        k_stencil_c<B, TX, TY, float2, float, 1, double2><<<nb, NT, 0, s>>>(p);
+    else
+        return RSG_EUNSUPPORTED;
     return RSG_OK;
 }
 
-// Type combinations used by the library: FP64 throughout, and the mixed
-// path (FP32 Hamiltonian on complex64 or complex128 input, FP64 base).
+template <int RB, int TX, int TY, int D>
+int launch_rd(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
+    constexpr int NT = RB * TX * TY;
+    if (a.mode == 0)
+        k_stencil_r<RB, TX, TY, 0, false, D><<<nb, NT, 0, s>>>(p);
+    else if (a.first)
+        k_stencil_r<RB, TX, TY, 1, true, D><<<nb, NT, 0, s>>>(p);
+    else
+        k_stencil_r<RB, TX, TY, 1, false, D><<<nb, NT, 0, s>>>(p);
+    return RSG_OK;
+}
+
 template <int B, int TX, int TY>
-int dispatch_types(const StageArgs &a, const KParams &p, int nblocks, hipStream_t s) {
-    if (a.compute == 0) {
-        if (a.in_t != 0 || a.out_t != 0) return RSG_EUNSUPPORTED;
-        return a.mode == 0 ? launch_one<B, TX, TY, double2, double, 0, double2>(p, nblocks, s)
-                           : launch_one<B, TX, TY, double2, double, 1, double2>(p, nblocks, s);
-    }
-    if (a.mode != 1) return RSG_EUNSUPPORTED;
-    if (a.in_t == 0 && a.out_t == 1) return launch_one<B, TX, TY, double2, float, 1, float2>(p, nblocks, s);
-    if (a.in_t == 1 && a.out_t == 1) return launch_one<B, TX, TY, float2, float, 1, float2>(p, nblocks, s);
-    if (a.in_t == 1 && a.out_t == 0) return launch_one<B, TX, TY, float2, float, 1, double2>(p, nblocks, s);
-    return RSG_EUNSUPPORTED;
+int launch_r(const StageArgs &a, const KParams &p, int nb, hipStream_t s, int D) {
+    constexpr int RB = 2 * B;
+    if (a.compute != 0 || a.in_t != 0 || a.out_t != 0) return RSG_EUNSUPPORTED;
+    if (D == 1) return launch_rd<RB, TX, TY, 1>(a, p, nb, s);
+    if (D == 2) return launch_rd<RB, TX, TY, 2>(a, p, nb, s);
+    return launch_rd<RB, TX, TY, 3>(a, p, nb, s);
+    return RSG_OK;
 }
 
 }  // namespace
 
-// FP64 uses 512-thread tiles (about 150 VGPRs, no spills); the FP32 path
-// fits 1024-thread tiles in registers.
+// Tile shapes compiled into the library: {orbitals per workgroup B, TX, TY}.
+// FP64 kernels have 2B real lanes per point, FP32 kernels B complex lanes.
+#define RSG_FP64_SHAPES(X) \
+    X(1, 16, 16) X(2, 16, 8) X(2, 8, 8) X(4, 8, 8) X(4, 16, 4) X(4, 8, 4) \
+    X(8, 8, 4) X(8, 4, 8) X(8, 4, 4) X(16, 4, 4)
+#define RSG_FP32_SHAPES(X) X(1, 16, 16) X(2, 16, 16) X(4, 16, 16) X(4, 16, 8) X(8, 16, 8) X(8, 8, 8)
+
+std::vector<TileShape> tile_candidates(int compute) {
+    std::vector<TileShape> shapes, v;
+#define RSG_ADD(B_, X_, Y_) shapes.push_back(TileShape{B_, X_, Y_, 0});
+    if (compute == 0) {
+        RSG_FP64_SHAPES(RSG_ADD)
+    } else {
+        RSG_FP32_SHAPES(RSG_ADD)
+    }
+#undef RSG_ADD
+    const int maxd = compute == 0 ? 3 : 1;
+    for (int d = 1; d <= maxd; ++d)
+        for (auto sh : shapes) {
+            sh.PD = d;
+            v.push_back(sh);
+        }
+    return v;
+}
+
 TileShape default_shape(const Grid &g, int64_t nst, int compute) {
     TileShape sh;
-    if (nst <= 1) sh = {1, 16, 16, 0};
-    else if (nst <= 2) sh = {2, 16, 16, 0};
-    else if (nst <= 4) sh = compute == 0 ? TileShape{4, 16, 8, 0} : TileShape{4, 16, 16, 0};
-    else sh = compute == 0 ? TileShape{8, 8, 8, 0} : TileShape{8, 16, 8, 0};
+    if (compute == 0) {
+        if (nst <= 1) sh = {1, 16, 16, 0, 1};
+        else if (nst <= 2) sh = {2, 16, 8, 0, 1};
+        else if (nst <= 4) sh = {4, 8, 8, 0, 1};
+        else sh = {4, 8, 8, 0, 1};
+    } else {
+        if (nst <= 1) sh = {1, 16, 16, 0};
+        else if (nst <= 2) sh = {2, 16, 16, 0};
+        else if (nst <= 4) sh = {4, 16, 16, 0};
+        else sh = {8, 16, 8, 0};
+    }
     sh.ZC = g.n[2];
     return sh;
+}
+
+TileShape Ham::tile_for(int64_t nst, int compute) const {
+    auto it = tiles.find(std::make_pair(nst, compute));
+    if (it != tiles.end()) return it->second;
+    return default_shape(*g, nst, compute);
 }
 
 int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s) {
@@ -267,6 +541,7 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     p.out = a.out;
     p.items = plan->items;
     p.rows = g.rows;
+    p.zeros = g.zeros;
     p.V = a.compute == 0 ? (const void *)H.V : (const void *)H.V32;
     p.field_dev = a.field_dev;
     p.nst = a.nst;
@@ -278,6 +553,8 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     p.cre = a.cre;
     p.cim = a.cim;
     p.nob = (int32_t)((a.nst + shape.B - 1) / shape.B);
+    p.nitems = plan->nitems;
+    p.batch_slowest = shape.BO;
     p.ny = g.n[1];
     p.nz = g.n[2];
     p.axis = H.axis;
@@ -289,18 +566,17 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     const int nb = (int)nb64;
     timing_before(s);
     int rc = RSG_EUNSUPPORTED;
-#define RSG_SHAPE(B_, X_, Y_) \
-    if (shape.B == B_ && shape.TX == X_ && shape.TY == Y_) rc = dispatch_types<B_, X_, Y_>(a, p, nb, s);
-    RSG_SHAPE(1, 16, 16)
-    else RSG_SHAPE(2, 16, 16)
-    else RSG_SHAPE(4, 16, 16)
-    else RSG_SHAPE(4, 16, 8)
-    else RSG_SHAPE(8, 16, 8)
-    else RSG_SHAPE(8, 8, 8)
-#undef RSG_SHAPE
+    bool found = false;
+#define RSG_TRY_R(B_, X_, Y_) \
+    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) { found = true; rc = launch_r<B_, X_, Y_>(a, p, nb, s, shape.PD); }
+#define RSG_TRY_C(B_, X_, Y_) \
+    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) { found = true; rc = launch_c<B_, X_, Y_>(a, p, nb, s); }
+    if (a.compute == 0) { RSG_FP64_SHAPES(RSG_TRY_R) } else { RSG_FP32_SHAPES(RSG_TRY_C) }
+#undef RSG_TRY_R
+#undef RSG_TRY_C
     timing_after(s);
     if (rc == RSG_EUNSUPPORTED) {
-        set_error("stencil: unsupported tile shape %dx%dx%d / type combination", shape.B, shape.TX,
+        set_error("stencil: unsupported tile shape %dx%dx%d for this precision", shape.B, shape.TX,
                   shape.TY);
         return rc;
     }
