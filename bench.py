@@ -187,12 +187,220 @@ def bench_sphere(args):
     return out, cfg
 
 
+def bench_batch(args):
+    """256 independent spheres (R ~ U(4,12) bohr at h = 0.25, 1..32 orbitals,
+    1..8 wells with projectors): K Taylor(4) steps of all systems (50 in the
+    reference workload), every stage one persistent launch, the step sequence
+    replayed from a HIP graph.  Also times the same systems propagated one by
+    one (eager) for comparison."""
+    import numpy as np
+    import torch
+
+    import paper_1501_05654_amd as rsg
+    import synth
+
+    cfg = dict(synth.WORKLOADS["batch256"])
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    specs = synth.batch_specs(cfg["seed"], cfg["nsys"], cfg["Rmin"], cfg["Rmax"], cfg["h"],
+                              cfg["nst_max"], cfg["atoms_max"])
+    if args.nsys:
+        specs = specs[: args.nsys]
+    systems, keep = [], []
+    tot = 0
+    log(f"building {len(specs)} systems")
+    for k, sp in enumerate(specs):
+        gg = rsg.Grid(sp.h, R=sp.R)
+        pos = gg.positions()
+        V = synth.well_potential(pos, sp.wells)
+        proj = synth.kb_projectors(sp.seed, pos, sp.wells.centres)
+        gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
+                             projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
+                                         for i, p, E in zip(proj.idx, proj.p, proj.E)])
+        psi = torch.from_numpy(synth.white_noise(sp.seed, gg.np, sp.nst, sp.h)).to(dev)
+        systems.append((gh, psi, sp.nst))
+        keep.append(gg)
+        tot += gg.np * sp.nst
+    log(f"sum np*nst = {tot:.4e}")
+    stream = torch.cuda.Stream()
+    dt = cfg["dt"]
+    with torch.cuda.stream(stream):
+        b = rsg.Batch(systems)
+        tile, tms = b.autotune(reps=1)
+        log(f"batch tile {tile}: {tms:.3f} ms per stage")
+        # eager steps with per-launch HIP-event timing of the stencil kernel
+        with rsg.kernel_timing() as kt:
+            b.propagate(dt, max(1, args.warmup))
+            torch.cuda.synchronize()
+        b.propagate(dt, args.steps, graph=True)  # capture and first replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.propagate(dt, args.steps, graph=True)  # timed replay
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        # one by one (eager), a few steps
+        per_steps = max(1, min(5, args.steps))
+        for gh, psi, nst in systems:
+            rsg.set_tile(gh, nst, tile["B"], tile["TX"], tile["TY"], tile["ZC"], tile["PD"])
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for gh, psi, nst in systems:
+            rsg.propagate(gh, psi, dt, per_steps, nst=nst)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+    el = t1 - t0
+    value = tot * 4 * args.steps / el
+    stage_bytes = tot * 176 / 4.0
+    achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
+    return {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch256", "nsys": len(specs), "sum_np_nst": tot, "h_bohr": cfg["h"],
+                   "dt": dt, "tile": tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "kernel": "k_stencil_batch (persistent, all systems)",
+                     "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count},
+        "per_system_eager_value": tot * 4 * per_steps / (t5 - t4),
+        "cpu_baseline": None,
+    }
+
+
+def bench_mixed(args):
+    """The 32^3 harmonic system, 4 orbitals: FP32 Hamiltonian with FP64
+    accumulation against the FP64 oracle at steps 1, 10, 100, 1000, for
+    white-noise orbitals and for smooth low harmonic-oscillator states."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1501_05654_amd as rsg
+    import synth
+
+    cfg = dict(synth.WORKLOADS["cube32_mixed"])
+    n, h, nst, dt = cfg["n"], cfg["h"], cfg["nst"], cfg["dt"]
+    nsteps = args.steps if args.steps else cfg["steps"]
+    gg = rsg.Grid(h, n=n)
+    og = oracle.Grid(h, n=n)
+    pos = og.positions()
+    V = synth.harmonic_potential(pos)
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).cuda(), kin=-0.5)
+    oh = oracle.Ham(og, V=V, kin=-0.5)
+    marks = [m for m in (1, 10, 100, 1000) if m <= nsteps]
+    report = {}
+    timing = {}
+    for name, psi0 in (("white_noise", synth.white_noise(cfg["seed"], og.np, nst, h)),
+                       ("ho_low_states", synth.ho_low_states(pos, nst))):
+        ref = psi0.copy()
+        mixed = torch.from_numpy(psi0).cuda()
+        full = torch.from_numpy(psi0).cuda()
+        rows, prev = [], 0
+        tm = tf = 0.0
+        for m in marks:
+            ref = oracle.propagate(oh, ref, dt, m - prev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rsg.propagate(gh, mixed, dt, m - prev, dtype="mixed")
+            torch.cuda.synchronize()
+            tm += time.perf_counter() - t
+            t = time.perf_counter()
+            rsg.propagate(gh, full, dt, m - prev)
+            torch.cuda.synchronize()
+            tf += time.perf_counter() - t
+            prev = m
+            gm, gf = mixed.cpu().numpy(), full.cpu().numpy()
+            err = np.linalg.norm(gm - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            errf = np.linalg.norm(gf - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            nm = rsg.norm2(gg, mixed).cpu().numpy()
+            no = oracle.norm2(og, ref)
+            em = rsg.energy(gh, mixed).cpu().numpy().real.sum()
+            eo = oracle.energy(oh, ref)[0]
+            rows.append({"step": m, "orbital_rel_err_max": float(err.max()),
+                         "fp64_gpu_rel_err_max": float(errf.max()),
+                         "norm_abs_err_max": float(np.abs(nm - no).max()),
+                         "energy_rel_err": float(abs(em - eo) / abs(eo))})
+            log(f"{name} step {m}: {rows[-1]}")
+        report[name] = rows
+        timing[name] = {"mixed_ms_per_step": tm * 1e3 / nsteps, "fp64_ms_per_step": tf * 1e3 / nsteps}
+    tot = og.np * nst
+    return {
+        "metric": "mixed-precision orbital error vs FP64 oracle", "value":
+            report["white_noise"][-1]["orbital_rel_err_max"], "unit": "relative 2-norm",
+        "n_gpus": 1, "steps": nsteps, "warmup": 0, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 H / f64 accumulation", "data": "synthetic",
+        "config": {"workload": "cube32_mixed", "np": og.np, "nst": nst, "dt": dt},
+        "errors": report, "timing": timing,
+        "mixed_value_pt_orb_H_per_s": tot * 4 * nsteps / (timing["white_noise"]["mixed_ms_per_step"] * nsteps * 1e-3),
+        "cpu_baseline": None,
+    }
+
+
+def bench_control(args):
+    """Optimal control on the 96^3 cube (h = 0.3, 8 orthonormal packets,
+    4 wells, dipole along z, 64 sine coefficients): forward propagation with
+    checkpoints every 50 steps, then the checkpointed discrete adjoint; the
+    ratio of their times, and dJ/dc against a central difference along a
+    random direction."""
+    import numpy as np
+    import torch
+
+    import paper_1501_05654_amd as rsg
+    import synth
+
+    cfg = dict(synth.WORKLOADS["cube96_control"])
+    n, h, nst, dt = cfg["n"], cfg["h"], cfg["nst"], cfg["dt"]
+    nsteps = args.steps if args.steps else cfg["steps"]
+    ck = cfg["checkpoint"]
+    gg = rsg.Grid(h, n=n)
+    pos = gg.positions()
+    wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], box=cfg["well_box"])
+    V = synth.well_potential(pos, wells)
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).cuda(), kin=-0.5, dipole_axis=2)
+    psi0 = torch.from_numpy(synth.gaussian_packets(cfg["seed"], pos, nst, h)).cuda()
+    coef = torch.from_numpy(synth.laser_coefficients(cfg["seed"], cfg["ncoef"])).cuda()
+    psi = psi0.clone()
+    rsg.control_forward(gh, psi, dt, min(nsteps, 20), coef, ck)  # warm-up (plans, tiles)
+    torch.cuda.synchronize()
+    psi = psi0.clone()
+    t0 = time.perf_counter()
+    J, store = rsg.control_forward(gh, psi, dt, nsteps, coef, ck)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grad, gsteps = rsg.control_backward(gh, psi, dt, nsteps, coef, ck, store)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    # central difference along a random unit direction d: (J(c+eps d) - J(c-eps d)) / 2 eps
+    d = torch.from_numpy(synth.random_unit(cfg["seed"], cfg["ncoef"])).cuda()
+    eps = 1e-4 * float(coef.abs().max())
+    jp, _ = rsg.control_forward(gh, psi0.clone(), dt, nsteps, coef + eps * d, ck, keep_checkpoints=False)
+    jm, _ = rsg.control_forward(gh, psi0.clone(), dt, nsteps, coef - eps * d, ck, keep_checkpoints=False)
+    fd = (jp.item() - jm.item()) / (2 * eps)
+    ad = float((grad * d).sum())
+    log(f"forward {fwd:.3f} s, gradient {bwd:.3f} s, J = {J.item():.10f}, "
+        f"d.grad = {ad:.10e}, central FD = {fd:.10e}")
+    return {
+        "metric": "adjoint grad time/fwd time", "value": bwd / fwd, "unit": "ratio",
+        "n_gpus": 1, "steps": nsteps, "warmup": 20, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "cube96_control", "np": gg.np, "nst": nst, "dt": dt, "ncoef": cfg["ncoef"],
+                   "checkpoint_every": ck},
+        "forward_s": fwd, "gradient_s": bwd, "J": J.item(),
+        "forward_value_pt_orb_H_per_s": gg.np * nst * 4 * nsteps / fwd,
+        "directional_derivative": ad, "central_fd": fd, "fd_rel_err": abs(ad - fd) / max(abs(fd), 1e-300),
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sphere18_wells", choices=["sphere18_wells"])
+    ap.add_argument("--workload", default="sphere18_wells",
+                    choices=["sphere18_wells", "batch256", "cube32_mixed", "cube96_control"])
+    ap.add_argument("--nsys", type=int, default=0, help="batch256: use only the first N systems")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -207,8 +415,15 @@ def main():
               "with no exchange, and this build measures the single-GPU share only "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
-    out, cfg = bench_sphere(args)
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
+    if args.workload == "batch256":
+        out = bench_batch(args)
+    elif args.workload == "cube32_mixed":
+        out = bench_mixed(args)
+    elif args.workload == "cube96_control":
+        out = bench_control(args)
+    else:
+        out, cfg = bench_sphere(args)
+        out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

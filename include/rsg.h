@@ -274,6 +274,49 @@ int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t 
                  size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Many independent systems                                            */
+/* ------------------------------------------------------------------ */
+
+/* One system of a batch: its Hamiltonian (and grid) and its orbitals,
+ * device [np][ld] complex128, propagated in place.  No dipole field. */
+typedef struct {
+    rsg_ham_t ham;
+    void *psi;
+    int64_t nst, ld;
+} rsg_system_desc;
+
+/* Scratch bytes rsg_batch_create needs for these systems. */
+size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc *sys);
+
+/* Group nsys independent systems (the group of states of section
+ * "Parallelization, optimizations and graphics processing units", extended
+ * across systems) so that each stage of a Taylor(4) step of all of them runs
+ * as one persistent stencil launch over a cost-sorted list of (system, tile,
+ * z-range, orbital batch) items, with one projector gather launch and one
+ * scatter launch per colour.  ws (rsg_batch_workspace_bytes) holds the work
+ * buffers and must outlive the batch, as must every Hamiltonian and orbital
+ * array named in sys.  Results are bitwise equal to propagating each system
+ * alone with the same tile.  Errors: RSG_EINVAL, RSG_ESHAPE, RSG_ENOMEM,
+ * RSG_EUNSUPPORTED (a system with a dipole axis), RSG_EHIP. */
+int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *ws, size_t ws_bytes, void *stream,
+                     rsg_batch_t *out);
+int rsg_batch_destroy(rsg_batch_t b);
+
+/* Tile shape used for every system of the batch (FP64 shapes of
+ * rsg_tile_candidates; PT and BO are ignored). */
+int rsg_batch_set_tile(rsg_batch_t b, const rsg_tile *t, void *stream);
+int rsg_batch_get_tile(rsg_batch_t b, rsg_tile *t);
+
+/* Time one batched stage for every compiled tile shape (best of reps after a
+ * warm-up) and keep the fastest.  The orbitals are not modified. */
+int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
+
+/* nsteps Taylor(4) steps of every system at time step dt, zero field.
+ * use_graph != 0 captures the launch sequence into a HIP graph once per
+ * (dt, nsteps, stream) and replays it; needs a non-default stream. */
+int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_graph, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Misc                                                                */
 /* ------------------------------------------------------------------ */
 

@@ -21,7 +21,7 @@ __all__ = [
     "RSGError", "Grid", "Hamiltonian", "hpsi", "propagate_step", "propagate", "dot", "norm2",
     "energy", "dipole_expectation", "adjoint_step", "laser_field", "laser_grad",
     "control_forward", "control_backward", "OptimalControlJ", "copy", "kernel_timing",
-    "C128", "MIXED", "LIB_PATH", "autotune", "set_tile", "get_tile", "tile_candidates",
+    "C128", "MIXED", "LIB_PATH", "autotune", "set_tile", "get_tile", "tile_candidates", "Batch",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsg.so")
@@ -75,6 +75,13 @@ def _load():
         "rsg_set_tile": (C.c_int, [vp, i64, i32, vp]),
         "rsg_get_tile": (C.c_int, [vp, i64, i32, vp]),
         "rsg_autotune": (C.c_int, [vp, vp, i64, i64, i32, vp, sz, i32, vp, vp, vp]),
+        "rsg_batch_workspace_bytes": (sz, [i32, vp]),
+        "rsg_batch_create": (C.c_int, [i32, vp, vp, sz, vp, vp]),
+        "rsg_batch_destroy": (C.c_int, [vp]),
+        "rsg_batch_set_tile": (C.c_int, [vp, vp, vp]),
+        "rsg_batch_get_tile": (C.c_int, [vp, vp]),
+        "rsg_batch_autotune": (C.c_int, [vp, i32, vp, vp, vp]),
+        "rsg_batch_propagate": (C.c_int, [vp, dbl, i64, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -454,3 +461,58 @@ def autotune(ham: Hamiltonian, psi: torch.Tensor, dtype="c128", reps: int = 3,
     _check(_lib.rsg_autotune(ham._h, _ptr(psi), n, psi.shape[1], _dt(dtype), _ptr(ws), ws.numel(),
                              int(reps), C.byref(t), C.byref(ms), _stream()))
     return _tile_dict(t), float(ms.value)
+
+
+class _SysDesc(C.Structure):
+    _fields_ = [("ham", C.c_void_p), ("psi", C.c_void_p), ("nst", C.c_int64), ("ld", C.c_int64)]
+
+
+class Batch:
+    """Many independent systems propagated together: each stage of a
+    Taylor(4) step of all systems is one persistent stencil launch.
+
+    systems: list of (Hamiltonian, psi, nst) with psi a CUDA complex128
+    [np, ld] tensor propagated in place.  The Hamiltonians and tensors must
+    stay alive while the batch is used."""
+
+    def __init__(self, systems):
+        self.systems = list(systems)
+        n = len(self.systems)
+        descs = (_SysDesc * n)()
+        for k, (ham, psi, nst) in enumerate(self.systems):
+            _batch(psi, "psi", ham.grid.np)
+            descs[k] = _SysDesc(ham._h.value, psi.data_ptr(), int(nst), psi.shape[1])
+        self._descs = descs
+        nbytes = int(_lib.rsg_batch_workspace_bytes(n, descs))
+        if nbytes == 0:
+            raise ValueError("invalid system list")
+        self.ws = _ws(nbytes, self.systems[0][1].device)
+        self._h = C.c_void_p()
+        torch.cuda.synchronize()
+        _check(_lib.rsg_batch_create(n, descs, _ptr(self.ws), self.ws.numel(), _stream(),
+                                     C.byref(self._h)))
+
+    def set_tile(self, B: int, TX: int, TY: int, ZC: int = 0, PD: int = 1):
+        t = _Tile(B, TX, TY, ZC, PD, 0, 0)
+        _check(_lib.rsg_batch_set_tile(self._h, C.byref(t), _stream()))
+
+    def get_tile(self) -> dict:
+        t = _Tile()
+        _check(_lib.rsg_batch_get_tile(self._h, C.byref(t)))
+        return _tile_dict(t)
+
+    def autotune(self, reps: int = 2):
+        t = _Tile()
+        ms = C.c_double()
+        _check(_lib.rsg_batch_autotune(self._h, int(reps), C.byref(t), C.byref(ms), _stream()))
+        return _tile_dict(t), float(ms.value)
+
+    def propagate(self, dt: float, nsteps: int, graph: bool = False):
+        _check(_lib.rsg_batch_propagate(self._h, float(dt), int(nsteps), 1 if graph else 0,
+                                        _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rsg_batch_destroy(h)
+            self._h = None

@@ -1,0 +1,376 @@
+// Many independent systems propagated together.
+//
+// The paper's basic object is a group of states rather than one state
+// (section "Parallelization, optimizations and graphics processing units");
+// here the group extends across systems: every stage of a Taylor(4) step of
+// every system runs as one persistent stencil launch over a cost-sorted list
+// of (system, tile, z-range, orbital batch) items, preceded by one projector
+// gather launch and followed by one scatter launch per colour, all systems at
+// once.  A step sequence can be captured once into a HIP graph and replayed.
+// Each output point is computed by the same arithmetic as the single-system
+// path, so the results are bitwise equal to propagating each system alone
+// with the same tile shape.
+#include "rsg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <tuple>
+
+namespace rsg {
+
+struct Batch {
+    std::vector<rsg_system_desc> sys;
+    std::vector<void *> w1, w2, D;  // per-system work buffers inside the caller's workspace
+    TileShape tile{1, 16, 16, 0};
+    int grid_first = 0, grid_rest = 0;  // persistent workgroups per stencil launch
+    KParams *sp[4] = {nullptr, nullptr, nullptr, nullptr};  // device, per stage, one per system
+    KbSys *kb[4] = {nullptr, nullptr, nullptr, nullptr};
+    BatchItem *items = nullptr;
+    int32_t nitems = 0;
+    int4 *gitems = nullptr;
+    int32_t ngitems = 0;
+    std::vector<int4 *> sitems;  // scatter items per colour
+    std::vector<int32_t> nsitems;
+    std::map<std::tuple<double, int64_t, hipStream_t>, hipGraphExec_t> graphs;
+    void free_tables() {
+        for (int k = 0; k < 4; ++k) {
+            if (sp[k]) (void)hipFree(sp[k]);
+            if (kb[k]) (void)hipFree(kb[k]);
+            sp[k] = nullptr;
+            kb[k] = nullptr;
+        }
+        if (items) (void)hipFree(items);
+        if (gitems) (void)hipFree(gitems);
+        for (auto *p : sitems)
+            if (p) (void)hipFree(p);
+        items = nullptr;
+        gitems = nullptr;
+        sitems.clear();
+        nsitems.clear();
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+    ~Batch() { free_tables(); }
+};
+
+namespace {
+
+size_t rnd(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t sys_bytes(const rsg_system_desc &d) {
+    const Ham &H = *d.ham;
+    return 2 * rnd((size_t)H.g->np * (size_t)d.ld * 16) + rnd(kb_workspace_bytes(H, d.nst));
+}
+
+template <class T>
+int upload(T **dst, const std::vector<T> &v, hipStream_t s) {
+    if (v.empty()) return RSG_OK;
+    RSG_CHECK_HIP(hipMalloc(dst, sizeof(T) * v.size()));
+    RSG_CHECK_HIP(hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return RSG_OK;
+}
+
+// Stage k (0..3) of the Horner scheme: in, base, out buffers of system i.
+void stage_buffers(const Batch &b, size_t i, int k, const void **in, const void **base, void **out) {
+    void *psi = b.sys[i].psi;
+    *base = psi;
+    switch (k) {
+        case 0: *in = psi; *out = b.w1[i]; break;
+        case 1: *in = b.w1[i]; *out = b.w2[i]; break;
+        case 2: *in = b.w2[i]; *out = b.w1[i]; break;
+        default: *in = b.w1[i]; *out = psi; break;
+    }
+}
+
+// (Re)build the item lists and per-system parameter tables for the tile.
+int build_tables(Batch &b, hipStream_t s) {
+    b.free_tables();
+    std::vector<BatchItem> items;
+    std::vector<int4> gitems;
+    std::vector<std::vector<int4>> sitems;
+    std::vector<KParams> sp[4];
+    std::vector<KbSys> kb[4];
+    int err = RSG_OK;
+    for (size_t i = 0; i < b.sys.size(); ++i) {
+        const rsg_system_desc &d = b.sys[i];
+        Ham &H = *d.ham;
+        TileShape sh = b.tile;
+        sh.PT = 0;
+        sh.BO = 0;
+        sh.ZC = sh.ZC > 0 ? sh.ZC : H.g->n[2];
+        const TilePlan *plan = H.g->plan(sh, s, &err);
+        if (!plan) return err;
+        // copy the plan's items back to the host to expand them per batch
+        std::vector<int4> pit(plan->nitems);
+        if (plan->nitems)
+            RSG_CHECK_HIP(hipMemcpy(pit.data(), plan->items, sizeof(int4) * plan->nitems, hipMemcpyDeviceToHost));
+        const int nob = (int)((d.nst + sh.B - 1) / sh.B);
+        for (const int4 &t : pit)
+            for (int ob = 0; ob < nob; ++ob) items.push_back(BatchItem{t, (int32_t)i, ob});
+        for (int k = 0; k < 4; ++k) {
+            StageArgs a;
+            stage_buffers(b, i, k, &a.in, &a.base, &a.out);
+            a.mode = 1;
+            a.nst = d.nst;
+            a.ld = d.ld;
+            a.first = k == 0;
+            sp[k].push_back(make_params(H, a, sh, plan));
+            KbSys ks;
+            ks.in = (const double *)a.in;
+            ks.out = (double *)a.out;
+            ks.ldr = 2 * d.ld;
+            ks.ncols = 2 * d.nst;
+            ks.atoms = H.gather_items;
+            ks.idx = H.kb_idx;
+            ks.p = H.kb_p;
+            ks.E = H.kb_E;
+            ks.D = (double *)b.D[i];
+            ks.h3 = H.g->h * H.g->h * H.g->h;
+            kb[k].push_back(ks);
+        }
+        const int nct = (int)((2 * d.nst + 15) / 16);
+        for (int a = 0; a < H.natoms; ++a)
+            for (int ct = 0; ct < nct; ++ct) gitems.push_back(make_int4((int)i, a, ct, 0));
+        if (H.natoms > 0) {
+            // host copy of this system's scatter lists, per colour
+            for (size_t c = 0; c < H.scatter_items.size(); ++c) {
+                if (sitems.size() <= c) sitems.resize(c + 1);
+                std::vector<int2> v(H.scatter_counts[c]);
+                if (!v.empty())
+                    RSG_CHECK_HIP(hipMemcpy(v.data(), H.scatter_items[c], sizeof(int2) * v.size(),
+                                            hipMemcpyDeviceToHost));
+                for (const int2 &e : v)
+                    for (int ct = 0; ct < nct; ++ct) sitems[c].push_back(make_int4((int)i, e.x, e.y, ct));
+            }
+        }
+    }
+    // longest items first: with a fixed stride over the list, every
+    // workgroup gets a similar total amount of z-marching
+    std::stable_sort(items.begin(), items.end(), [](const BatchItem &x, const BatchItem &y) {
+        return (x.tile.w - x.tile.z) > (y.tile.w - y.tile.z);
+    });
+    int rc;
+    b.grid_first = stencil_batch_grid(b.tile, true);
+    b.grid_rest = stencil_batch_grid(b.tile, false);
+    if (b.grid_first <= 0 || b.grid_rest <= 0) return b.grid_first <= 0 ? b.grid_first : b.grid_rest;
+    for (int k = 0; k < 4; ++k) {
+        if ((rc = upload(&b.sp[k], sp[k], s))) return rc;
+        if ((rc = upload(&b.kb[k], kb[k], s))) return rc;
+    }
+    if ((rc = upload(&b.items, items, s))) return rc;
+    if ((rc = upload(&b.gitems, gitems, s))) return rc;
+    b.nitems = (int32_t)items.size();
+    b.ngitems = (int32_t)gitems.size();
+    for (auto &v : sitems) {
+        int4 *dptr = nullptr;
+        if ((rc = upload(&dptr, v, s))) return rc;
+        b.sitems.push_back(dptr);
+        b.nsitems.push_back((int32_t)v.size());
+    }
+    RSG_CHECK_HIP(hipStreamSynchronize(s));
+    return RSG_OK;
+}
+
+int stage_launches(const Batch &b, int k, double dt, hipStream_t s) {
+    const double cim = -dt / (double)(4 - k);  // c = -i dt / (4 - k): stages k = 0..3 use 1/4, 1/3, 1/2, 1
+    int rc;
+    if ((rc = launch_kb_gather_batch(b.kb[k], b.gitems, b.ngitems, s))) return rc;
+    if ((rc = launch_stencil_batch(b.tile, 1, k == 0, b.sp[k], b.items, b.nitems, 0.0, cim,
+                                   k == 0 ? b.grid_first : b.grid_rest, s)))
+        return rc;
+    for (size_t c = 0; c < b.sitems.size(); ++c)
+        if ((rc = launch_kb_scatter_batch(b.kb[k], b.sitems[c], b.nsitems[c], 0.0, cim, s))) return rc;
+    return RSG_OK;
+}
+
+int steps(const Batch &b, double dt, int64_t nsteps, hipStream_t s) {
+    for (int64_t n = 0; n < nsteps; ++n)
+        for (int k = 0; k < 4; ++k) {
+            const int rc = stage_launches(b, k, dt, s);
+            if (rc) return rc;
+        }
+    return RSG_OK;
+}
+
+}  // namespace
+
+}  // namespace rsg
+
+using namespace rsg;
+
+struct rsg_batch_s : rsg::Batch {};
+
+static int check_systems(int32_t nsys, const rsg_system_desc *sys) {
+    RSG_REQUIRE(nsys >= 1 && sys, RSG_EINVAL, "batch: need at least one system");
+    for (int32_t i = 0; i < nsys; ++i) {
+        const rsg_system_desc &d = sys[i];
+        RSG_REQUIRE(d.ham, RSG_EINVAL, "batch: system %d has no Hamiltonian", i);
+        RSG_REQUIRE(d.nst >= 1 && d.ld >= d.nst, RSG_ESHAPE, "batch: system %d needs 1 <= nst <= ld", i);
+        RSG_REQUIRE(d.psi && ((uintptr_t)d.psi & 15) == 0, RSG_EINVAL, "batch: system %d orbital pointer", i);
+        RSG_REQUIRE(d.ham->axis < 0, RSG_EUNSUPPORTED, "batch: system %d has a dipole field (not batched)", i);
+    }
+    return RSG_OK;
+}
+
+extern "C" size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc *sys) {
+    if (nsys < 1 || !sys) return 0;
+    size_t n = 256;
+    for (int32_t i = 0; i < nsys; ++i) {
+        if (!sys[i].ham || sys[i].ld < 1 || sys[i].nst < 0) return 0;
+        n += sys_bytes(sys[i]);
+    }
+    return n;
+}
+
+extern "C" int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *ws, size_t ws_bytes,
+                                void *stream, rsg_batch_t *out) {
+    clear_error();
+    int rc = check_systems(nsys, sys);
+    if (rc) return rc;
+    RSG_REQUIRE(out, RSG_EINVAL, "rsg_batch_create: null output");
+    RSG_REQUIRE(ws && ws_bytes >= rsg_batch_workspace_bytes(nsys, sys), RSG_ENOMEM,
+                "rsg_batch_create: workspace too small (%zu < %zu)", ws_bytes, rsg_batch_workspace_bytes(nsys, sys));
+    return guarded([&]() -> int {
+        hipStream_t s = (hipStream_t)stream;
+        auto *b = new rsg_batch_s();
+        b->sys.assign(sys, sys + nsys);
+        char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        int64_t maxnst = 0;
+        for (int32_t i = 0; i < nsys; ++i) {
+            const Ham &H = *sys[i].ham;
+            const size_t bb = rnd((size_t)H.g->np * (size_t)sys[i].ld * 16);
+            b->w1.push_back(base);
+            b->w2.push_back(base + bb);
+            b->D.push_back(base + 2 * bb);
+            base += sys_bytes(sys[i]);
+            maxnst = std::max(maxnst, sys[i].nst);
+        }
+        // zero the work buffers once, so timing runs never read garbage
+        const hipError_t e = hipMemsetAsync(ws, 0, ws_bytes, s);
+        if (e != hipSuccess) {
+            set_error("rsg_batch_create: %s", hipGetErrorString(e));
+            delete b;
+            return RSG_EHIP;
+        }
+        b->tile = default_shape(*sys[0].ham->g, maxnst >= 4 ? 4 : maxnst, 0);
+        b->tile.ZC = 0;
+        const int r = build_tables(*b, s);
+        if (r) {
+            delete b;
+            return r;
+        }
+        *out = b;
+        return RSG_OK;
+    });
+}
+
+extern "C" int rsg_batch_destroy(rsg_batch_t b) {
+    clear_error();
+    delete b;
+    return RSG_OK;
+}
+
+extern "C" int rsg_batch_set_tile(rsg_batch_t b, const rsg_tile *t, void *stream) {
+    clear_error();
+    RSG_REQUIRE(b && t, RSG_EINVAL, "rsg_batch_set_tile: null argument");
+    bool ok = false;
+    for (const auto &c : tile_candidates(0)) ok = ok || (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == t->PD);
+    RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_batch_set_tile: not a compiled FP64 tile");
+    RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "rsg_batch_set_tile: ZC must be >= 0");
+    b->tile = TileShape{t->B, t->TX, t->TY, t->ZC};
+    b->tile.PD = t->PD;
+    return guarded([&]() { return build_tables(*b, (hipStream_t)stream); });
+}
+
+extern "C" int rsg_batch_get_tile(rsg_batch_t b, rsg_tile *t) {
+    clear_error();
+    RSG_REQUIRE(b && t, RSG_EINVAL, "rsg_batch_get_tile: null argument");
+    *t = rsg_tile{b->tile.B, b->tile.TX, b->tile.TY, b->tile.ZC, b->tile.PD, 0, 0};
+    return RSG_OK;
+}
+
+extern "C" int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, double *best_ms, void *stream) {
+    clear_error();
+    RSG_REQUIRE(b && reps > 0, RSG_EINVAL, "rsg_batch_autotune: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&]() -> int {
+        hipEvent_t e0, e1;
+        RSG_CHECK_HIP(hipEventCreate(&e0));
+        RSG_CHECK_HIP(hipEventCreate(&e1));
+        double bt = 1e300;
+        TileShape bs = b->tile;
+        int rc = RSG_OK;
+        for (const auto &cand : tile_candidates(0)) {
+            for (int zc : {0, 32}) {
+                b->tile = cand;
+                b->tile.ZC = zc;
+                if ((rc = build_tables(*b, s))) break;
+                double tmin = 1e300;
+                for (int r = 0; r <= reps; ++r) {
+                    // stage 2 (w1 -> w2): leaves the orbitals untouched
+                    RSG_CHECK_HIP(hipEventRecord(e0, s));
+                    if ((rc = launch_stencil_batch(b->tile, 1, false, b->sp[1], b->items, b->nitems, 0.0, -1e-3,
+                                                   b->grid_rest, s)))
+                        break;
+                    RSG_CHECK_HIP(hipEventRecord(e1, s));
+                    RSG_CHECK_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    RSG_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (r > 0) tmin = std::min(tmin, (double)ms);
+                }
+                if (rc) break;
+                if (tmin < bt) {
+                    bt = tmin;
+                    bs = b->tile;
+                }
+            }
+            if (rc) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->tile = bs;
+        const int r2 = build_tables(*b, s);
+        if (rc) return rc;
+        if (r2) return r2;
+        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, 0, 0};
+        if (best_ms) *best_ms = bt;
+        return RSG_OK;
+    });
+}
+
+extern "C" int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_graph, void *stream) {
+    clear_error();
+    RSG_REQUIRE(b, RSG_EINVAL, "rsg_batch_propagate: null batch");
+    RSG_REQUIRE(nsteps >= 0 && std::isfinite(dt), RSG_EINVAL, "rsg_batch_propagate: bad nsteps or dt");
+    hipStream_t s = (hipStream_t)stream;
+    if (nsteps == 0) return RSG_OK;
+    if (!use_graph) return steps(*b, dt, nsteps, s);
+    RSG_REQUIRE(s != nullptr, RSG_EINVAL, "rsg_batch_propagate: graph capture needs a non-default stream");
+    const auto key = std::make_tuple(dt, nsteps, s);
+    auto it = b->graphs.find(key);
+    hipGraphExec_t exec = it == b->graphs.end() ? nullptr : it->second;
+    if (!exec) {
+        RSG_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int r = steps(*b, dt, nsteps, s);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &graph);
+        if (r) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return r;
+        }
+        if (e != hipSuccess) {
+            set_error("rsg_batch_propagate: capture failed: %s", hipGetErrorString(e));
+            return RSG_EHIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            set_error("rsg_batch_propagate: instantiate failed: %s", hipGetErrorString(ei));
+            return RSG_EHIP;
+        }
+        b->graphs[key] = exec;
+    }
+    RSG_CHECK_HIP(hipGraphLaunch(exec, s));
+    return RSG_OK;
+}

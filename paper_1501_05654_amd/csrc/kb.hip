@@ -52,19 +52,16 @@ __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// blockIdx.x = atom, blockIdx.y = tile of 16 real columns; 4 waves split
-// the support in groups of 4 entries (wave w takes groups w, w+4, ...), and
-// their partial products are added in wave order.
+// Gather for one (atom, 16-column tile): 4 waves split the support in groups
+// of 4 entries (wave w takes groups w, w+4, ...) and their partial products
+// are added in wave order.  Called by all 256 threads of a workgroup.
 template <class Tin, class Tc>
-__global__ void __launch_bounds__(256) k_kb_gather(const Tin *__restrict__ in, int64_t ldr,
-                                                   int64_t ncols, const int4 *__restrict__ atoms,
-                                                   const int32_t *__restrict__ idx,
-                                                   const Tc *__restrict__ p, Tc h3,
-                                                   Tc *__restrict__ D) {
+__device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t ldr, int64_t ncols,
+                                            const int4 at, int a, int ct,
+                                            const int32_t *__restrict__ idx,
+                                            const Tc *__restrict__ p, Tc h3, Tc *__restrict__ D,
+                                            Tc (*red)[64][4]) {
     using V = typename V4<Tc>::type;
-    __shared__ Tc red[4][64][4];
-    const int a = blockIdx.x, ct = blockIdx.y;
-    const int4 at = atoms[a];  // {offset, padded length, length, -}
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int lo = l & 15, hi = l >> 4;
     const int64_t col = (int64_t)ct * 16 + lo;
@@ -90,25 +87,30 @@ __global__ void __launch_bounds__(256) k_kb_gather(const Tin *__restrict__ in, i
     }
 }
 
-// One wave per (16-entry support tile, 16-column tile).
+// blockIdx.x = atom, blockIdx.y = tile of 16 real columns.
+template <class Tin, class Tc>
+__global__ void __launch_bounds__(256) k_kb_gather(const Tin *__restrict__ in, int64_t ldr,
+                                                   int64_t ncols, const int4 *__restrict__ atoms,
+                                                   const int32_t *__restrict__ idx,
+                                                   const Tc *__restrict__ p, Tc h3,
+                                                   Tc *__restrict__ D) {
+    __shared__ Tc red[4][64][4];
+    gather_tile<Tin, Tc>(in, ldr, ncols, atoms[blockIdx.x], blockIdx.x, blockIdx.y, idx, p, h3, D, red);
+}
+
+// Scatter for one (16-entry support tile, 16-column tile), one wave.
 template <class Tout, class Tc>
-__global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int64_t ldr, int64_t ncols,
-                                                    const int2 *__restrict__ items, int32_t nitems,
-                                                    const int4 *__restrict__ atoms,
-                                                    const int32_t *__restrict__ idx,
-                                                    const Tc *__restrict__ p,
-                                                    const double *__restrict__ E,
-                                                    const Tc *__restrict__ D, double cre,
-                                                    double cim) {
+__device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldr, int64_t ncols,
+                                             const int2 itm, const int4 at, int ct,
+                                             const int32_t *__restrict__ idx,
+                                             const Tc *__restrict__ p,
+                                             const double *__restrict__ E,
+                                             const Tc *__restrict__ D, double cre, double cim) {
     using V = typename V4<Tc>::type;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + w;
-    if (item >= nitems) return;
-    const int2 itm = items[item];  // {atom, first entry}
-    const int4 at = atoms[itm.x];
+    const int l = threadIdx.x & 63;
     const int lo = l & 15, hi = l >> 4;
     const Tc av = p[((int64_t)itm.y + lo) * 4 + hi];
-    const int64_t col = (int64_t)blockIdx.y * 16 + lo;
+    const int64_t col = (int64_t)ct * 16 + lo;
     Tc bv = 0;
     if (col < ncols) {
         const int64_t n = col >> 1;
@@ -128,6 +130,44 @@ __global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int6
             *dst = (Tout)((double)*dst + (double)acc[r]);
         }
     }
+}
+
+// One wave per (16-entry support tile, 16-column tile).
+template <class Tout, class Tc>
+__global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int64_t ldr, int64_t ncols,
+                                                    const int2 *__restrict__ items, int32_t nitems,
+                                                    const int4 *__restrict__ atoms,
+                                                    const int32_t *__restrict__ idx,
+                                                    const Tc *__restrict__ p,
+                                                    const double *__restrict__ E,
+                                                    const Tc *__restrict__ D, double cre,
+                                                    double cim) {
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    const int2 itm = items[item];  // {atom, first entry}
+    scatter_tile<Tout, Tc>(out, ldr, ncols, itm, atoms[itm.x], blockIdx.y, idx, p, E, D, cre, cim);
+}
+
+// Batched forms over many systems (FP64): item {system, atom, column tile}
+// for the gather, {system, atom, first entry, column tile} for the scatter.
+__global__ void __launch_bounds__(256) k_kb_gather_batch(const KbSys *__restrict__ sys,
+                                                         const int4 *__restrict__ items) {
+    __shared__ double red[4][64][4];
+    const int4 it = items[blockIdx.x];
+    const KbSys &s = sys[it.x];
+    gather_tile<double, double>(s.in, s.ldr, s.ncols, s.atoms[it.y], it.y, it.z, s.idx, s.p, s.h3, s.D,
+                                red);
+}
+
+__global__ void __launch_bounds__(256) k_kb_scatter_batch(const KbSys *__restrict__ sys,
+                                                          const int4 *__restrict__ items, int32_t nitems,
+                                                          double cre, double cim) {
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    const int4 it = items[item];
+    const KbSys &s = sys[it.x];
+    scatter_tile<double, double>(s.out, s.ldr, s.ncols, make_int2(it.y, it.z), s.atoms[it.y], it.w, s.idx,
+                                 s.p, s.E, s.D, cre, cim);
 }
 
 }  // namespace
@@ -184,6 +224,21 @@ int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t n
         }
         RSG_CHECK_HIP(hipGetLastError());
     }
+    return RSG_OK;
+}
+
+int launch_kb_gather_batch(const KbSys *sys, const int4 *items, int32_t nitems, hipStream_t s) {
+    if (nitems == 0) return RSG_OK;
+    k_kb_gather_batch<<<(unsigned)nitems, 256, 0, s>>>(sys, items);
+    RSG_CHECK_HIP(hipGetLastError());
+    return RSG_OK;
+}
+
+int launch_kb_scatter_batch(const KbSys *sys, const int4 *items, int32_t nitems, double cre, double cim,
+                            hipStream_t s) {
+    if (nitems == 0) return RSG_OK;
+    k_kb_scatter_batch<<<(unsigned)((nitems + 3) / 4), 256, 0, s>>>(sys, items, nitems, cre, cim);
+    RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }
 

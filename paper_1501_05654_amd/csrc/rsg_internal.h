@@ -148,7 +148,42 @@ struct StageArgs {
     const double *field_dev = nullptr;
     double cre = 1, cim = 0;
 };
+// Kernel parameters of one stencil stage on one system (also stored in
+// device memory, one per system, by the batched path).
+struct KParams {
+    const void *in;
+    const void *base;
+    void *out;
+    const int4 *items;
+    const int2 *rows;
+    const double *zeros;
+    const void *V;
+    const double *field_dev;
+    int64_t nst, ld;
+    double kin_h2;
+    double field;
+    double h;
+    double off[3];
+    double cre, cim;
+    int32_t nob;
+    int32_t nitems;
+    int32_t batch_slowest;
+    int32_t ny, nz;
+    int32_t axis;
+};
+// One work item of the batched stencil: tile (tx, ty, z0, z1) of system sys,
+// orbital batch ob.
+struct BatchItem {
+    int4 tile;
+    int32_t sys, ob;
+};
+KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, const TilePlan *plan);
 int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s);
+int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
+                         const BatchItem *items, int32_t nitems, double cre, double cim, int grid,
+                         hipStream_t s);
+// Resident workgroups of the batched kernel for this shape (or an error code).
+int stencil_batch_grid(const TileShape &shape, bool first);
 TileShape default_shape(const Grid &g, int64_t nst, int compute);
 std::vector<TileShape> tile_candidates(int compute);
 
@@ -160,6 +195,22 @@ int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_
 int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ld,
                       const void *D, double cre, double cim, hipStream_t s);
 size_t kb_workspace_bytes(const Ham &H, int64_t nst);
+
+// Per-system projector parameters of one stage of the batched path (FP64).
+struct KbSys {
+    const double *in;   // gather input (interleaved complex as doubles)
+    double *out;        // scatter output
+    int64_t ldr, ncols; // 2*ld, 2*nst
+    const int4 *atoms;  // {offset, padded length, length, atom}
+    const int32_t *idx;
+    const double *p;
+    const double *E;
+    double *D;          // [natoms][4][ncols]
+    double h3;
+};
+int launch_kb_gather_batch(const KbSys *sys, const int4 *items, int32_t nitems, hipStream_t s);
+int launch_kb_scatter_batch(const KbSys *sys, const int4 *items, int32_t nitems, double cre, double cim,
+                            hipStream_t s);
 
 // Reductions: partial sums per block then a fixed-order final pass.
 // kind 0: <a|b> (complex out [2*nst]); 1: |a|^2 (out [nst]);

@@ -27,6 +27,8 @@
 //     contiguous range of tiles.
 #include "rsg_internal.h"
 
+#include <algorithm>
+
 namespace rsg {
 
 namespace {
@@ -42,28 +44,6 @@ struct FD {
     static constexpr Tc c2 = (Tc)(-1.0 / 5.0);
     static constexpr Tc c3 = (Tc)(8.0 / 315.0);
     static constexpr Tc c4 = (Tc)(-1.0 / 560.0);
-};
-
-struct KParams {
-    const void *in;
-    const void *base;
-    void *out;
-    const int4 *items;
-    const int2 *rows;
-    const double *zeros;
-    const void *V;
-    const double *field_dev;
-    int64_t nst, ld;
-    double kin_h2;
-    double field;
-    double h;
-    double off[3];
-    double cre, cim;
-    int32_t nob;
-    int32_t nitems;
-    int32_t batch_slowest;
-    int32_t ny, nz;
-    int32_t axis;
 };
 
 // Workgroup b of nb runs on XCD b % 8; give each XCD a contiguous range.
@@ -267,10 +247,12 @@ __device__ __forceinline__ int idx_in_row(int2 r, int x) {
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
 
+// One work item of the FP64 kernel: tile it = (tx, ty, z0, z1), orbital
+// batch ob, with the shared-memory plane `tile` of the calling workgroup.
 template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
-__global__ void __launch_bounds__(RB * TX * TY) k_stencil_r(KParams a) {
+__device__ __forceinline__ void march_r(const KParams &a, const int4 it, const int ob, double *tile) {
     constexpr int NT = RB * TX * TY;
-    constexpr int LX = TX + 8, LY = TY + 8;
+    constexpr int LX = TX + 8;
     constexpr int NHP = 8 * TX + 8 * TY;
     constexpr int NH = NHP * RB;
     constexpr int HPT = (NH + NT - 1) / NT;
@@ -285,12 +267,6 @@ __global__ void __launch_bounds__(RB * TX * TY) k_stencil_r(KParams a) {
     constexpr int Q = D == 1 ? 10 : 12;  // >= 9 + D, and keeps the unroll period at 10 or 12
     constexpr int VD = D + 1;
     constexpr int P = clcm(clcm(clcm(Q, D), VD), 2);  // unroll period of the z loop
-    __shared__ double tile[LY * LX * RB];
-
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    int ob, item;
-    block_item(a, blk, &ob, &item);
-    const int4 it = a.items[item];
     const int t = threadIdx.x;
     const int c = t % RB, lx = (t / RB) % TX, ly = t / (RB * TX);
     const int x = it.x * TX + lx, y = it.y * TY + ly;
@@ -440,6 +416,33 @@ __global__ void __launch_bounds__(RB * TX * TY) k_stencil_r(KParams a) {
     }
 }
 
+template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
+__global__ void __launch_bounds__(RB * TX * TY) k_stencil_r(KParams a) {
+    __shared__ double tile[(TY + 8) * (TX + 8) * RB];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    int ob, item;
+    block_item(a, blk, &ob, &item);
+    march_r<RB, TX, TY, MODE, FIRST, D>(a, a.items[item], ob, tile);
+}
+
+// Persistent form over many independent systems: workgroup g takes items
+// g, g + G, g + 2G, ... of the cost-sorted list {system, tx, ty, z0, z1, ob};
+// each system's parameters come from sysp[system].
+template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
+__global__ void __launch_bounds__(RB * TX * TY) k_stencil_batch(const KParams *__restrict__ sysp,
+                                                                const BatchItem *__restrict__ items,
+                                                                int32_t nitems, double cre, double cim) {
+    __shared__ double tile[(TY + 8) * (TX + 8) * RB];
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        const BatchItem bi = items[w];
+        KParams a = sysp[bi.sys];
+        a.cre = cre;
+        a.cim = cim;
+        march_r<RB, TX, TY, MODE, FIRST, D>(a, bi.tile, bi.ob, tile);
+        __syncthreads();  // the next item reuses the plane buffer
+    }
+}
+
 template <int B, int TX, int TY>
 int launch_c(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
     constexpr int NT = B * TX * TY;
@@ -527,14 +530,8 @@ TileShape Ham::tile_for(int64_t nst, int compute) const {
     return default_shape(*g, nst, compute);
 }
 
-int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s) {
+KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, const TilePlan *plan) {
     const Grid &g = *H.g;
-    int err = RSG_OK;
-    TileShape key = shape;
-    if (key.ZC <= 0) key.ZC = g.n[2];
-    const TilePlan *plan = const_cast<Grid &>(g).plan(key, s, &err);
-    if (!plan) return err;
-    if (plan->nitems == 0 || a.nst == 0) return RSG_OK;
     KParams p;
     p.in = a.in;
     p.base = a.base;
@@ -553,11 +550,23 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     p.cre = a.cre;
     p.cim = a.cim;
     p.nob = (int32_t)((a.nst + shape.B - 1) / shape.B);
-    p.nitems = plan->nitems;
+    p.nitems = plan ? plan->nitems : 0;
     p.batch_slowest = shape.BO;
     p.ny = g.n[1];
     p.nz = g.n[2];
     p.axis = H.axis;
+    return p;
+}
+
+int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s) {
+    const Grid &g = *H.g;
+    int err = RSG_OK;
+    TileShape key = shape;
+    if (key.ZC <= 0) key.ZC = g.n[2];
+    const TilePlan *plan = const_cast<Grid &>(g).plan(key, s, &err);
+    if (!plan) return err;
+    if (plan->nitems == 0 || a.nst == 0) return RSG_OK;
+    const KParams p = make_params(H, a, shape, plan);
     const int64_t nb64 = (int64_t)plan->nitems * p.nob;
     if (nb64 > INT32_MAX) {
         set_error("stencil launch too large");
@@ -578,6 +587,83 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     if (rc == RSG_EUNSUPPORTED) {
         set_error("stencil: unsupported tile shape %dx%dx%d for this precision", shape.B, shape.TX,
                   shape.TY);
+        return rc;
+    }
+    RSG_CHECK_HIP(hipGetLastError());
+    return RSG_OK;
+}
+
+namespace {
+// grid < 0: return the number of resident workgroups of this kernel on the
+// device (occupancy query, not allowed during graph capture); grid > 0:
+// launch with that many persistent workgroups.
+template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
+int launch_batch_inst(const KParams *sysp, const BatchItem *items, int32_t nitems, double cre, double cim,
+                      int grid, hipStream_t s) {
+    constexpr int NT = RB * TX * TY;
+    auto kern = k_stencil_batch<RB, TX, TY, MODE, FIRST, D>;
+    if (grid < 0) {
+        int per_cu = 0, dev = 0;
+        hipDeviceProp_t prop;
+        RSG_CHECK_HIP(hipGetDevice(&dev));
+        RSG_CHECK_HIP(hipGetDeviceProperties(&prop, dev));
+        RSG_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0));
+        return std::max(1, per_cu) * prop.multiProcessorCount;
+    }
+    kern<<<(int)std::min<int64_t>(nitems, grid), NT, 0, s>>>(sysp, items, nitems, cre, cim);
+    return RSG_OK;
+}
+
+template <int B, int TX, int TY>
+int launch_batch_shape(int mode, bool first, int D, const KParams *sysp, const BatchItem *items, int32_t nitems,
+                       double cre, double cim, int grid, hipStream_t s) {
+    constexpr int RB = 2 * B;
+#define RSG_BD(DD)                                                                                          \
+    if (D == DD) {                                                                                          \
+        if (mode == 0) return launch_batch_inst<RB, TX, TY, 0, false, DD>(sysp, items, nitems, cre, cim, grid, s); \
+        if (first) return launch_batch_inst<RB, TX, TY, 1, true, DD>(sysp, items, nitems, cre, cim, grid, s);      \
+        return launch_batch_inst<RB, TX, TY, 1, false, DD>(sysp, items, nitems, cre, cim, grid, s);               \
+    }
+    RSG_BD(1) RSG_BD(2) RSG_BD(3)
+#undef RSG_BD
+    return RSG_EUNSUPPORTED;
+}
+}  // namespace
+
+int stencil_batch_grid(const TileShape &shape, bool first) {
+    int g = RSG_EUNSUPPORTED;
+    bool found = false;
+#define RSG_TRY_G(B_, X_, Y_)                                                                          \
+    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) {                                 \
+        found = true;                                                                                  \
+        g = launch_batch_shape<B_, X_, Y_>(1, first, shape.PD, nullptr, nullptr, 0, 0.0, 0.0, -1, nullptr); \
+    }
+    RSG_FP64_SHAPES(RSG_TRY_G)
+#undef RSG_TRY_G
+    return g;
+}
+
+int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
+                         const BatchItem *items, int32_t nitems, double cre, double cim, int grid,
+                         hipStream_t s) {
+    if (nitems == 0) return RSG_OK;
+    if (grid <= 0) {
+        set_error("batched stencil: persistent grid size must be > 0");
+        return RSG_EINVAL;
+    }
+    int rc = RSG_EUNSUPPORTED;
+    bool found = false;
+    timing_before(s);
+#define RSG_TRY_B(B_, X_, Y_)                                                                              \
+    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) {                                     \
+        found = true;                                                                                      \
+        rc = launch_batch_shape<B_, X_, Y_>(mode, first, shape.PD, sysp, items, nitems, cre, cim, grid, s); \
+    }
+    RSG_FP64_SHAPES(RSG_TRY_B)
+#undef RSG_TRY_B
+    timing_after(s);
+    if (rc != RSG_OK) {
+        if (rc == RSG_EUNSUPPORTED) set_error("batched stencil: unsupported tile %dx%dx%d", shape.B, shape.TX, shape.TY);
         return rc;
     }
     RSG_CHECK_HIP(hipGetLastError());
