@@ -248,8 +248,9 @@ int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld
 /* Tile of the z-marching stencil kernel: B orbitals x TX x TY grid columns
  * per workgroup, marching along z in chunks of ZC planes (0 = whole box),
  * prefetching PD planes ahead (FP64 kernel: 1..3; ignored for the mixed
- * path).  PT > 0 launches tiles in PT x PT patches that share a z-range so
- * that neighbouring workgroups march together (0 = no patches).  BO = 0
+ * path).  PT = 1 launches the tiles of each z-chunk in Morton (Z-curve)
+ * order; PT >= 2 launches them in PT x PT patches that share a z-range, so
+ * that neighbouring workgroups march together; 0 = row order.  BO = 0
  * launches the orbital batches of a tile together, BO = 1 sweeps all tiles
  * of one batch before the next. */
 typedef struct {

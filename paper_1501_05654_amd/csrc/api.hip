@@ -837,7 +837,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         std::vector<int> zcs = {0};
         for (int z : {64, 32})
             if (z < H->g->n[2]) zcs.push_back(z);
-        const std::vector<int> pts = {0, 4};
+        const std::vector<int> pts = {0, 1};
         hipEvent_t e0, e1;
         RSG_CHECK_HIP(hipEventCreate(&e0));
         RSG_CHECK_HIP(hipEventCreate(&e1));

@@ -101,8 +101,9 @@ Grid::~Grid() {
 }
 
 // Work items for one tile shape: every (tx, ty) tile that holds box points,
-// with its z-extent split into chunks of at most ZC planes.  Without patches
-// (PT = 0) items are ordered z-chunk major, then ty, then tx.  With patches,
+// with its z-extent split into chunks of at most ZC planes.  PT = 0: items
+// are ordered z-chunk major, then ty, then tx.  PT = 1: z-chunk major, then
+// the Morton (Z-curve) order of (tx, ty).  PT >= 2: patches,
 // tiles are grouped into PT x PT patches; all tiles of a patch march over the
 // patch's common z-extent, and items are ordered patch-major, then chunk,
 // then tile, so that a patch's workgroups are launched together.
@@ -128,7 +129,31 @@ const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
             }
         }
     std::vector<int4> items;
-    if (s.PT <= 0) {
+    if (s.PT == 1) {
+        // Morton (Z-curve) order of the tiles within each z-chunk: launch
+        // neighbours are spatial neighbours in both x and y
+        auto spread = [](uint32_t v) {
+            uint64_t r = 0;
+            for (int b = 0; b < 16; ++b) r |= (uint64_t)((v >> b) & 1u) << (2 * b);
+            return r;
+        };
+        std::vector<std::pair<uint64_t, int>> order;
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx)
+                if (zhi[(size_t)ty * ntx + tx] >= zlo[(size_t)ty * ntx + tx])
+                    order.emplace_back(spread((uint32_t)tx) | (spread((uint32_t)ty) << 1), ty * ntx + tx);
+        std::sort(order.begin(), order.end());
+        int maxchunks = 0;
+        for (size_t k = 0; k < zlo.size(); ++k)
+            if (zhi[k] >= zlo[k]) maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);
+        for (int c = 0; c < maxchunks; ++c)
+            for (const auto &o : order) {
+                const int k = o.second, tx = k % ntx, ty = k / ntx;
+                const int z0 = zlo[k] + c * s.ZC;
+                if (z0 > zhi[k]) continue;
+                items.push_back(make_int4(tx, ty, z0, std::min(zhi[k] + 1, z0 + s.ZC)));
+            }
+    } else if (s.PT <= 0) {
         int maxchunks = 0;
         for (size_t k = 0; k < zlo.size(); ++k)
             if (zhi[k] >= zlo[k]) maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);

@@ -416,13 +416,149 @@ __device__ __forceinline__ void march_r(const KParams &a, const int4 it, const i
     }
 }
 
+// Lean variant (pipeline depth 1): the own-column queue q[9] rotates in
+// registers and every load of plane z+1 (own column z+5, halo, V, base) is
+// issued one step ahead; a step starts by waiting for the previous step's
+// loads.  Few registers, so 1024-thread workgroups with 512-point tiles fit
+// without spilling, which cuts the halo per output.
+template <int RB, int TX, int TY, int MODE, bool FIRST>
+__device__ __forceinline__ void march_s(const KParams &a, const int4 it, const int ob, double *tile) {
+    constexpr int NT = RB * TX * TY;
+    constexpr int LX = TX + 8;
+    constexpr int NHP = 8 * TX + 8 * TY;
+    constexpr int NH = NHP * RB;
+    constexpr int HPT = (NH + NT - 1) / NT;
+    constexpr int YS = LX * RB;
+    const int t = threadIdx.x;
+    const int c = t % RB, lx = (t / RB) % TX, ly = t / (RB * TX);
+    const int x = it.x * TX + lx, y = it.y * TY + ly;
+    const int ncols = (int)(2 * a.nst);
+    const int col = ob * RB + c;
+    const bool cok = col < ncols;
+    const int64_t ldr = 2 * a.ld;
+    const double *in = static_cast<const double *>(a.in);
+    const double *base = static_cast<const double *>(a.base);
+    const double *Vp = static_cast<const double *>(a.V);
+    const double *zp = a.zeros;
+
+    int hl[HPT], hx[HPT], hy[HPT], hc[HPT];
+    bool hok[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+        const int j = t + k * NT;
+        const int oh = j % RB, hp = j / RB;
+        int lxl, lyl;
+        if (hp < 8 * TX) {
+            const int yh = hp / TX;
+            lxl = hp % TX + 4;
+            lyl = yh < 4 ? yh : TY + yh;
+        } else {
+            const int q = hp - 8 * TX;
+            const int cc = q % 8;
+            lyl = q / 8 + 4;
+            lxl = cc < 4 ? cc : TX + cc;
+        }
+        hl[k] = (lyl * LX + lxl) * RB + oh;
+        hx[k] = it.x * TX + lxl - 4;
+        hy[k] = it.y * TY + lyl - 4;
+        hc[k] = ob * RB + oh;
+        hok[k] = j < NH && hc[k] < ncols;
+    }
+    auto fetch = [&](int idx, int cc, bool ok) -> double {
+        const double *pa = (ok && idx >= 0) ? in + (int64_t)idx * ldr + cc : zp;
+        return *pa;
+    };
+    auto fetch_v = [&](int idx) -> double { return Vp[idx >= 0 ? idx : 0]; };
+    auto fetch_b = [&](int idx) -> double {
+        if (MODE != 1 || FIRST) return 0.0;
+        const bool v = idx >= 0 && cok;
+        return base[(int64_t)(v ? idx : 0) * ldr + (v ? col : 0)];
+    };
+
+    const int z0 = it.z, z1 = it.w;
+    double q[9];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = fetch(idx_in_row(row_of(a, y, z0 - 4 + k), x), col, cok);
+    int idx_c = idx_in_row(row_of(a, y, z0), x);
+    double nxt = fetch(idx_in_row(row_of(a, y, z0 + 4), x), col, cok);
+    double hv[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(row_of(a, hy[k], z0), hx[k]), hc[k], hok[k]);
+    double v_c = fetch_v(idx_c), b_c = fetch_b(idx_c);
+    int2 rf = row_of(a, y, z0 + 5);  // rows for the loads of the first step
+    int2 ro = row_of(a, y, z0 + 1);
+    int2 rh[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) rh[k] = row_of(a, hy[k], z0 + 1);
+
+    const double E = a.field_dev ? *a.field_dev : a.field;
+    const double kin_h2 = a.kin_h2;
+    const int own = ((ly + 4) * LX + lx + 4) * RB + c;
+    double *out = static_cast<double *>(a.out);
+
+    for (int z = z0; z < z1; ++z) {
+        q[8] = nxt;
+        tile[own] = q[4];
+#pragma unroll
+        for (int k = 0; k < HPT; ++k)
+            if (t + k * NT < NH) tile[hl[k]] = hv[k];
+        __syncthreads();
+        // row entries for the next step, then this step's loads (plane z+1)
+        const int2 rf_n = row_of(a, y, z + 6), ro_n = row_of(a, y, z + 2);
+        int2 rh_n[HPT];
+#pragma unroll
+        for (int k = 0; k < HPT; ++k) rh_n[k] = row_of(a, hy[k], z + 2);
+        const bool live = z + 1 < z1;
+        nxt = fetch(live ? idx_in_row(rf, x) : -1, col, cok);
+#pragma unroll
+        for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(rh[k], hx[k]), hc[k], hok[k] && live);
+        const int idx_n = live ? idx_in_row(ro, x) : -1;
+        const double v_n = fetch_v(idx_n), b_n = fetch_b(idx_n);
+        rf = rf_n;
+        ro = ro_n;
+#pragma unroll
+        for (int k = 0; k < HPT; ++k) rh[k] = rh_n[k];
+
+        const double lap =
+            3.0 * FD<double>::c0 * q[4] +
+            FD<double>::c1 * ((tile[own - RB] + tile[own + RB]) + (tile[own - YS] + tile[own + YS]) + (q[3] + q[5])) +
+            FD<double>::c2 * ((tile[own - 2 * RB] + tile[own + 2 * RB]) + (tile[own - 2 * YS] + tile[own + 2 * YS]) + (q[2] + q[6])) +
+            FD<double>::c3 * ((tile[own - 3 * RB] + tile[own + 3 * RB]) + (tile[own - 3 * YS] + tile[own + 3 * YS]) + (q[1] + q[7])) +
+            FD<double>::c4 * ((tile[own - 4 * RB] + tile[own + 4 * RB]) + (tile[own - 4 * YS] + tile[own + 4 * YS]) + (q[0] + q[8]));
+        double vloc = v_c;
+        if (a.axis >= 0) {
+            const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
+            vloc += E * (a.h * ((double)cc - a.off[a.axis]));
+        }
+        const double hval = kin_h2 * lap + vloc * q[4];
+        if (MODE == 0) {
+            if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = hval;
+        } else {
+            const double hpart = __shfl_xor(hval, 1);  // the other component of this orbital
+            const double bb = FIRST ? q[4] : b_c;
+            const double r = (c & 1) ? bb + (a.cre * hval + a.cim * hpart)
+                                     : bb + (a.cre * hval - a.cim * hpart);
+            if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = r;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q[k] = q[k + 1];
+        idx_c = idx_n;
+        v_c = v_n;
+        b_c = b_n;
+    }
+}
+
 template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
 __global__ void __launch_bounds__(RB * TX * TY) k_stencil_r(KParams a) {
     __shared__ double tile[(TY + 8) * (TX + 8) * RB];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     int ob, item;
     block_item(a, blk, &ob, &item);
-    march_r<RB, TX, TY, MODE, FIRST, D>(a, a.items[item], ob, tile);
+    if constexpr (D == 0)
+        march_s<RB, TX, TY, MODE, FIRST>(a, a.items[item], ob, tile);
+    else
+        march_r<RB, TX, TY, MODE, FIRST, D>(a, a.items[item], ob, tile);
 }
 
 // Persistent form over many independent systems: workgroup g takes items
@@ -438,7 +574,10 @@ __global__ void __launch_bounds__(RB * TX * TY) k_stencil_batch(const KParams *_
         KParams a = sysp[bi.sys];
         a.cre = cre;
         a.cim = cim;
-        march_r<RB, TX, TY, MODE, FIRST, D>(a, bi.tile, bi.ob, tile);
+        if constexpr (D == 0)
+            march_s<RB, TX, TY, MODE, FIRST>(a, bi.tile, bi.ob, tile);
+        else
+            march_r<RB, TX, TY, MODE, FIRST, D>(a, bi.tile, bi.ob, tile);
         __syncthreads();  // the next item reuses the plane buffer
     }
 }
@@ -474,6 +613,8 @@ template <int B, int TX, int TY>
 int launch_r(const StageArgs &a, const KParams &p, int nb, hipStream_t s, int D) {
     constexpr int RB = 2 * B;
     if (a.compute != 0 || a.in_t != 0 || a.out_t != 0) return RSG_EUNSUPPORTED;
+    if (D == 0) return launch_rd<RB, TX, TY, 0>(a, p, nb, s);
+    if (RB * TX * TY > 512) return RSG_EUNSUPPORTED;  // deeper pipelines spill at 1024 threads
     if (D == 1) return launch_rd<RB, TX, TY, 1>(a, p, nb, s);
     if (D == 2) return launch_rd<RB, TX, TY, 2>(a, p, nb, s);
     return launch_rd<RB, TX, TY, 3>(a, p, nb, s);
@@ -486,7 +627,8 @@ int launch_r(const StageArgs &a, const KParams &p, int nb, hipStream_t s, int D)
 // FP64 kernels have 2B real lanes per point, FP32 kernels B complex lanes.
 #define RSG_FP64_SHAPES(X) \
     X(1, 16, 16) X(2, 16, 8) X(2, 8, 8) X(4, 8, 8) X(4, 16, 4) X(4, 8, 4) \
-    X(8, 8, 4) X(8, 4, 8) X(8, 4, 4) X(16, 4, 4)
+    X(8, 8, 4) X(8, 4, 8) X(8, 4, 4) X(16, 4, 4) \
+    X(1, 32, 16) X(2, 16, 16) X(4, 16, 8) X(8, 8, 8) X(16, 8, 4) X(16, 4, 8) X(32, 4, 4)
 #define RSG_FP32_SHAPES(X) X(1, 16, 16) X(2, 16, 16) X(4, 16, 16) X(4, 16, 8) X(8, 16, 8) X(8, 8, 8)
 
 std::vector<TileShape> tile_candidates(int compute) {
@@ -498,9 +640,10 @@ std::vector<TileShape> tile_candidates(int compute) {
         RSG_FP32_SHAPES(RSG_ADD)
     }
 #undef RSG_ADD
-    const int maxd = compute == 0 ? 3 : 1;
-    for (int d = 1; d <= maxd; ++d)
+    const int d0 = compute == 0 ? 0 : 1, maxd = compute == 0 ? 3 : 1;
+    for (int d = d0; d <= maxd; ++d)
         for (auto sh : shapes) {
+            if (compute == 0 && d > 0 && 2 * sh.B * sh.TX * sh.TY > 512) continue;
             sh.PD = d;
             v.push_back(sh);
         }
@@ -510,10 +653,16 @@ std::vector<TileShape> tile_candidates(int compute) {
 TileShape default_shape(const Grid &g, int64_t nst, int compute) {
     TileShape sh;
     if (compute == 0) {
-        if (nst <= 1) sh = {1, 16, 16, 0, 1};
-        else if (nst <= 2) sh = {2, 16, 8, 0, 1};
-        else if (nst <= 4) sh = {4, 8, 8, 0, 1};
-        else sh = {4, 8, 8, 0, 1};
+        // measured on MI355X (sphere of 3.05 M points): 8 orbitals per
+        // workgroup (one 128-byte line per point), 4 x 8 tiles, depth 3,
+        // batch-slowest order; fewer orbitals use the lean variant
+        if (nst <= 1) sh = {1, 16, 16, 0, 0};
+        else if (nst <= 2) sh = {2, 16, 8, 0, 0};
+        else if (nst <= 4) sh = {4, 8, 8, 0, 0};
+        else {
+            sh = {8, 4, 8, 0, 3};
+            sh.BO = 1;
+        }
     } else {
         if (nst <= 1) sh = {1, 16, 16, 0};
         else if (nst <= 2) sh = {2, 16, 16, 0};
@@ -624,6 +773,8 @@ int launch_batch_shape(int mode, bool first, int D, const KParams *sysp, const B
         if (first) return launch_batch_inst<RB, TX, TY, 1, true, DD>(sysp, items, nitems, cre, cim, grid, s);      \
         return launch_batch_inst<RB, TX, TY, 1, false, DD>(sysp, items, nitems, cre, cim, grid, s);               \
     }
+    RSG_BD(0)
+    if (RB * TX * TY > 512) return RSG_EUNSUPPORTED;
     RSG_BD(1) RSG_BD(2) RSG_BD(3)
 #undef RSG_BD
     return RSG_EUNSUPPORTED;

@@ -1,0 +1,86 @@
+"""Every compiled stencil tile the autotuner may pick, with every z-chunking,
+tile order (row, Morton, patches) and block order, gives the oracle's
+H psi and Taylor(4) step to the FP64 bar; the mixed-precision tiles agree
+with each other to FP32 rounding of the same arithmetic.
+
+The grid is a small sphere with ragged rows and a ragged orbital batch
+(13 of 16 columns), so partial tiles in x, y, z and a partial orbital batch
+occur for every shape."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_common import System, orbital_rel_err, rsg
+
+pytestmark = pytest.mark.gpu
+
+ZCS = (0, 4)        # whole z-range, and chunks of 4 planes (several per tile)
+PTS = (0, 1, 2)     # row order, Morton order, 2 x 2 patches
+BOS = (0, 1)        # orbital batch fastest / slowest
+
+
+@pytest.fixture(scope="module")
+def sys_():
+    return System(0.3, R=3.1, potential="wells", natoms=2, nst=13, ld=16, seed=71,
+                  dipole_axis=2, rcut=1.2)
+
+
+def _variants(dtype):
+    R = rsg()
+    for t in R.tile_candidates(dtype):
+        for zc in ZCS:
+            for pt in PTS:
+                for bo in BOS:
+                    yield dict(t, ZC=zc, PT=pt, BO=bo)
+
+
+def _set(R, s, t, dtype):
+    R.set_tile(s.gh, s.nst, t["B"], t["TX"], t["TY"], t["ZC"], t["PD"], t["PT"], t["BO"],
+               dtype=dtype)
+
+
+def test_every_fp64_tile_matches_oracle(sys_):
+    R = rsg()
+    s = sys_
+    field, dt = 0.07, 0.01
+    ref_h = oracle.hpsi(s.oh, s.psi, field=field, nst=s.nst)
+    ref_s = oracle.taylor_step(s.oh, s.psi, dt, field=field, nst=s.nst)
+    psi = s.to_gpu(s.psi)
+    n = 0
+    for t in _variants("c128"):
+        _set(R, s, t, "c128")
+        assert R.get_tile(s.gh, s.nst) == t
+        y = R.hpsi(s.gh, psi, field=field, nst=s.nst).cpu().numpy()
+        e = orbital_rel_err(y, ref_h, s.nst)
+        assert e <= 1e-12, (t, e)
+        assert not np.any(y[:, s.nst:]), t
+        x = psi.clone()
+        R.propagate_step(s.gh, x, dt, field=field, nst=s.nst)
+        xs = x.cpu().numpy()
+        e = orbital_rel_err(xs, ref_s, s.nst)
+        assert e <= 1e-12, (t, e)
+        np.testing.assert_array_equal(xs[:, s.nst:], s.psi[:, s.nst:])
+        n += 1
+    assert n >= 100
+
+
+def test_every_mixed_tile_agrees(sys_):
+    R = rsg()
+    s = sys_
+    dt = 0.01
+    ref_s = oracle.taylor_step(s.oh, s.psi, dt, nst=s.nst)
+    psi = s.to_gpu(s.psi)
+    first = None
+    for t in _variants("mixed"):
+        _set(R, s, t, "mixed")
+        x = psi.clone()
+        R.propagate_step(s.gh, x, dt, dtype="mixed", nst=s.nst)
+        xs = x.cpu().numpy()
+        # FP32 Hamiltonian: error of FP32 rounding of a step of size dt |H|
+        assert orbital_rel_err(xs, ref_s, s.nst) <= 2e-6, t
+        if first is None:
+            first = xs
+        else:
+            # each point's arithmetic does not depend on the tile
+            np.testing.assert_allclose(xs, first, rtol=0, atol=1e-6 * np.abs(first).max())
