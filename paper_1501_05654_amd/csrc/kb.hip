@@ -52,9 +52,14 @@ __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Gather for one (atom, 16-column tile): 4 waves split the support in groups
-// of 4 entries (wave w takes groups w, w+4, ...) and their partial products
-// are added in wave order.  Called by all 256 threads of a workgroup.
+// Gather for one (atom, 16-column tile): the GW waves of the workgroup split
+// the support in groups of 4 entries (wave w takes groups w, w+GW, ...; each
+// wave accumulates its groups in ascending order) and the partial products
+// are added in wave order, so the result does not depend on timing.  The
+// group loop issues the index loads of GU groups, then their data loads,
+// then the MFMAs, so GU gathers are in flight per wave.
+constexpr int GW = 16;  // waves per gather workgroup
+constexpr int GU = 4;   // groups in flight per wave
 template <class Tin, class Tc>
 __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t ldr, int64_t ncols,
                                             const int4 at, int a, int ct,
@@ -68,7 +73,23 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
     const bool cok = col < ncols;
     V acc = {0, 0, 0, 0};
     const int ngroups = at.y >> 2;
-    for (int gq = w; gq < ngroups; gq += 4) {
+    int gq = w;
+    for (; gq + (GU - 1) * GW < ngroups; gq += GU * GW) {
+        int64_t e[GU];
+        int32_t ix[GU];
+        Tc bv[GU], av[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            e[u] = (int64_t)at.x + 4 * (gq + u * GW) + hi;
+            ix[u] = idx[e[u]];
+            bv[u] = lo < 4 ? p[e[u] * 4 + lo] : (Tc)0;
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) av[u] = cok ? (Tc)in[(int64_t)ix[u] * ldr + col] : (Tc)0;
+#pragma unroll
+        for (int u = 0; u < GU; ++u) acc = mfma16(av[u], bv[u], acc);
+    }
+    for (; gq < ngroups; gq += GW) {
         const int64_t e = (int64_t)at.x + 4 * gq + hi;
         const Tc av = cok ? (Tc)in[(int64_t)idx[e] * ldr + col] : (Tc)0;
         const Tc bv = lo < 4 ? p[e * 4 + lo] : (Tc)0;
@@ -80,7 +101,9 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
     if (w == 0 && lo < 4) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const Tc v = ((red[0][l][r] + red[1][l][r]) + red[2][l][r]) + red[3][l][r];
+            Tc v = red[0][l][r];
+#pragma unroll
+            for (int k = 1; k < GW; ++k) v += red[k][l][r];
             const int64_t c = (int64_t)ct * 16 + acc_row(Tc(0), hi, r);
             if (c < ncols) D[((int64_t)a * 4 + lo) * ncols + c] = h3 * v;
         }
@@ -89,12 +112,12 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
 
 // blockIdx.x = atom, blockIdx.y = tile of 16 real columns.
 template <class Tin, class Tc>
-__global__ void __launch_bounds__(256) k_kb_gather(const Tin *__restrict__ in, int64_t ldr,
-                                                   int64_t ncols, const int4 *__restrict__ atoms,
-                                                   const int32_t *__restrict__ idx,
-                                                   const Tc *__restrict__ p, Tc h3,
-                                                   Tc *__restrict__ D) {
-    __shared__ Tc red[4][64][4];
+__global__ void __launch_bounds__(GW * 64) k_kb_gather(const Tin *__restrict__ in, int64_t ldr,
+                                                       int64_t ncols, const int4 *__restrict__ atoms,
+                                                       const int32_t *__restrict__ idx,
+                                                       const Tc *__restrict__ p, Tc h3,
+                                                       Tc *__restrict__ D) {
+    __shared__ Tc red[GW][64][4];
     gather_tile<Tin, Tc>(in, ldr, ncols, atoms[blockIdx.x], blockIdx.x, blockIdx.y, idx, p, h3, D, red);
 }
 
@@ -150,9 +173,9 @@ __global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int6
 
 // Batched forms over many systems (FP64): item {system, atom, column tile}
 // for the gather, {system, atom, first entry, column tile} for the scatter.
-__global__ void __launch_bounds__(256) k_kb_gather_batch(const KbSys *__restrict__ sys,
-                                                         const int4 *__restrict__ items) {
-    __shared__ double red[4][64][4];
+__global__ void __launch_bounds__(GW * 64) k_kb_gather_batch(const KbSys *__restrict__ sys,
+                                                             const int4 *__restrict__ items) {
+    __shared__ double red[GW][64][4];
     const int4 it = items[blockIdx.x];
     const KbSys &s = sys[it.x];
     gather_tile<double, double>(s.in, s.ldr, s.ncols, s.atoms[it.y], it.y, it.z, s.idx, s.p, s.h3, s.D,
@@ -184,15 +207,15 @@ int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_
     const double h3 = H.g->h * H.g->h * H.g->h;
     if (compute == 0) {
         if (in_t != 0) return RSG_EUNSUPPORTED;
-        k_kb_gather<double, double><<<grid, 256, 0, s>>>((const double *)in, 2 * ld, ncols,
+        k_kb_gather<double, double><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ld, ncols,
                                                         H.gather_items, H.kb_idx, H.kb_p, h3,
                                                         (double *)D);
     } else if (in_t == 0) {
-        k_kb_gather<double, float><<<grid, 256, 0, s>>>((const double *)in, 2 * ld, ncols,
+        k_kb_gather<double, float><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ld, ncols,
                                                        H.gather_items, H.kb_idx, H.kb_p32,
                                                        (float)h3, (float *)D);
     } else {
-        k_kb_gather<float, float><<<grid, 256, 0, s>>>((const float *)in, 2 * ld, ncols,
+        k_kb_gather<float, float><<<grid, GW * 64, 0, s>>>((const float *)in, 2 * ld, ncols,
                                                       H.gather_items, H.kb_idx, H.kb_p32,
                                                       (float)h3, (float *)D);
     }
@@ -229,7 +252,7 @@ int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t n
 
 int launch_kb_gather_batch(const KbSys *sys, const int4 *items, int32_t nitems, hipStream_t s) {
     if (nitems == 0) return RSG_OK;
-    k_kb_gather_batch<<<(unsigned)nitems, 256, 0, s>>>(sys, items);
+    k_kb_gather_batch<<<(unsigned)nitems, GW * 64, 0, s>>>(sys, items);
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }

@@ -116,7 +116,7 @@ struct Ham {
     double *kb_E = nullptr;      // device [natoms][4]
     std::vector<int64_t> kb_off; // host [natoms+1] padded offsets
     std::vector<int64_t> kb_len; // host [natoms] true support sizes
-    int4 *gather_items = nullptr;   // device: one per atom {atom, off, len, 0}
+    int4 *gather_items = nullptr;   // device: one per atom {offset, padded length, length, atom}
     // scatter work: per colour a device list of {atom, entry0} (16 entries each)
     std::vector<int2 *> scatter_items;
     std::vector<int32_t> scatter_counts;
