@@ -112,10 +112,11 @@ def bench_sphere(args):
     gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
                          projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
                                      for i, p, E in zip(proj.idx, proj.p, proj.E)])
-    psi = torch.from_numpy(psi_h).to(dev)
+    # the library's layout is orbital-major [nst, np]
+    psi = torch.from_numpy(psi_h).to(dev).t().contiguous()
     del psi_h
     nst = cfg["nst"]
-    ws = torch.empty(gh.workspace_bytes("step", nst, nst), dtype=torch.uint8, device=dev)
+    ws = torch.empty(gh.workspace_bytes("step", nst, psi.shape[1]), dtype=torch.uint8, device=dev)
     dt = cfg["dt"]
     tile = None
     if args.tile:
@@ -177,7 +178,7 @@ def bench_sphere(args):
                    "stencil": "8th-order 25-point star"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "kernel": "k_stencil_r (Horner stage)",
+                     "traffic": traffic, "kernel": "k_stencil (Horner stage)",
                      "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
                      "algorithmic_bytes_per_launch": stage_bytes, "tile": tile,
                      "copy_gbs": copy_gbs},
@@ -217,7 +218,7 @@ def bench_batch(args):
         gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
                              projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
                                          for i, p, E in zip(proj.idx, proj.p, proj.E)])
-        psi = torch.from_numpy(synth.white_noise(sp.seed, gg.np, sp.nst, sp.h)).to(dev)
+        psi = torch.from_numpy(synth.white_noise(sp.seed, gg.np, sp.nst, sp.h)).to(dev).t().contiguous()
         systems.append((gh, psi, sp.nst))
         keep.append(gg)
         tot += gg.np * sp.nst
@@ -293,8 +294,8 @@ def bench_mixed(args):
     for name, psi0 in (("white_noise", synth.white_noise(cfg["seed"], og.np, nst, h)),
                        ("ho_low_states", synth.ho_low_states(pos, nst))):
         ref = psi0.copy()
-        mixed = torch.from_numpy(psi0).cuda()
-        full = torch.from_numpy(psi0).cuda()
+        mixed = torch.from_numpy(psi0).cuda().t().contiguous()  # orbital-major
+        full = torch.from_numpy(psi0).cuda().t().contiguous()
         rows, prev = [], 0
         tm = tf = 0.0
         for m in marks:
@@ -309,7 +310,7 @@ def bench_mixed(args):
             torch.cuda.synchronize()
             tf += time.perf_counter() - t
             prev = m
-            gm, gf = mixed.cpu().numpy(), full.cpu().numpy()
+            gm, gf = mixed.cpu().numpy().T, full.cpu().numpy().T
             err = np.linalg.norm(gm - ref, axis=0) / np.linalg.norm(ref, axis=0)
             errf = np.linalg.norm(gf - ref, axis=0) / np.linalg.norm(ref, axis=0)
             nm = rsg.norm2(gg, mixed).cpu().numpy()
@@ -357,7 +358,7 @@ def bench_control(args):
     wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], box=cfg["well_box"])
     V = synth.well_potential(pos, wells)
     gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).cuda(), kin=-0.5, dipole_axis=2)
-    psi0 = torch.from_numpy(synth.gaussian_packets(cfg["seed"], pos, nst, h)).cuda()
+    psi0 = torch.from_numpy(synth.gaussian_packets(cfg["seed"], pos, nst, h)).cuda().t().contiguous()
     coef = torch.from_numpy(synth.laser_coefficients(cfg["seed"], cfg["ncoef"])).cuda()
     psi = psi0.clone()
     rsg.control_forward(gh, psi, dt, min(nsteps, 20), coef, ck)  # warm-up (plans, tiles)

@@ -26,10 +26,12 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  Layout     An orbital batch is [np][ld] complex, interleaved re/im, with
- *             the orbital index fastest (batch-packed); nst <= ld orbitals
- *             are used, columns nst..ld-1 are neither read nor written.
- *             Compact point order is z-major, then y, then x.
+ *  Layout     An orbital batch is orbital-major, [nst][ldp] complex with
+ *             interleaved re/im: orbital n holds its value at compact point
+ *             i at element n*ldp + i.  ldp >= np; elements np..ldp-1 of each
+ *             orbital are neither read nor written.  Compact point order is
+ *             z-major, then y, then x, so each grid row of an orbital is
+ *             contiguous.
  *  Dtypes     RSG_C128: complex128 (FP64) everywhere.
  *             RSG_C64_MIXED: the orbital batch the caller passes is still
  *             complex128; the Hamiltonian arithmetic (stencil, local
@@ -62,7 +64,7 @@ extern "C" {
 enum {
     RSG_OK = 0,
     RSG_EINVAL = -1,       /* null pointer, bad enum, negative size ... */
-    RSG_ESHAPE = -2,       /* nst > ld, sizes inconsistent with the grid */
+    RSG_ESHAPE = -2,       /* ldp < np, sizes inconsistent with the grid */
     RSG_EDTYPE = -3,       /* unknown dtype */
     RSG_EHIP = -4,         /* a HIP runtime call failed */
     RSG_ENOMEM = -5,       /* workspace too small or allocation failed */
@@ -139,28 +141,28 @@ int rsg_ham_create(rsg_grid_t g, const double *vloc_dev, double kin, int32_t dip
 int rsg_ham_destroy(rsg_ham_t H);
 
 /* Scratch device bytes an operation needs for a batch of nst orbitals with
- * leading dimension ld (0 when none). */
-size_t rsg_workspace_bytes(rsg_ham_t H, int32_t op, int64_t nst, int64_t ld, int32_t dtype);
+ * orbital stride ldp (0 when the arguments are invalid). */
+size_t rsg_workspace_bytes(rsg_ham_t H, int32_t op, int64_t nst, int64_t ldp, int32_t dtype);
 
 /* hpsi = H psi at the given field value ("application of a Hamiltonian" as
  * a building block, section "Parallelization, optimizations and graphics
- * processing units").  psi and hpsi: device [np][ld] complex128, must not
+ * processing units").  psi and hpsi: device [nst][ldp] complex128, must not
  * overlap.  dtype RSG_C128 only.  ws: RSG_OP_HPSI bytes. */
-int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ld, int32_t dtype,
+int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ldp, int32_t dtype,
              double field, void *ws, size_t ws_bytes, void *stream);
 
 /* One Taylor(4) step in place: psi <- sum_{k=0}^{4} (-i dt H)^k / k! psi,
  * with H taken at `field` (the field at the step midpoint); the discrete
- * evolution operator of section "Photoemission".  psi: device [np][ld]
+ * evolution operator of section "Photoemission".  psi: device [nst][ldp]
  * complex128.  dtype RSG_C128 or RSG_C64_MIXED.  ws: RSG_OP_STEP bytes. */
-int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
                        double field, void *ws, size_t ws_bytes, void *stream);
 
 /* nsteps Taylor(4) steps; step n uses fields_dev[n] (device float64
  * [nsteps]) or zero field when fields_dev is NULL.  use_graph != 0 captures
  * the step sequence into a HIP graph once per distinct argument set and
  * replays it.  Same buffers as rsg_propagate_step. */
-int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
                   int64_t nsteps, const double *fields_dev, int32_t use_graph, void *ws,
                   size_t ws_bytes, void *stream);
 
@@ -174,18 +176,18 @@ int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype
 size_t rsg_reduce_workspace_bytes(rsg_grid_t g, int64_t nst);
 
 /* out_dev: device float64 [2*nst] (re, im per orbital). ws: RSG_OP_REDUCE. */
-int rsg_dot(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ld, double *out_dev,
+int rsg_dot(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ldp, double *out_dev,
             void *ws, size_t ws_bytes, void *stream);
 /* out_dev: device float64 [nst], h^3 sum |a|^2. */
-int rsg_norm2(rsg_grid_t g, const void *a, int64_t nst, int64_t ld, double *out_dev, void *ws,
+int rsg_norm2(rsg_grid_t g, const void *a, int64_t nst, int64_t ldp, double *out_dev, void *ws,
               size_t ws_bytes, void *stream);
 /* out_dev: device float64 [2*nst], <psi_n|H psi_n> per orbital (the total
  * energy is the sum of the real parts). ws: RSG_OP_ENERGY bytes. */
-int rsg_energy(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype, double field,
+int rsg_energy(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, double field,
                double *out_dev, void *ws, size_t ws_bytes, void *stream);
 /* out_dev: device float64 [nst], h^3 sum x_axis |a|^2 along the
  * Hamiltonian's dipole axis.  ws: RSG_OP_REDUCE bytes. */
-int rsg_dipole_expectation(rsg_ham_t H, const void *a, int64_t nst, int64_t ld, double *out_dev,
+int rsg_dipole_expectation(rsg_ham_t H, const void *a, int64_t nst, int64_t ldp, double *out_dev,
                            void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
@@ -211,22 +213,22 @@ int rsg_laser_grad(const double *g_dev, int64_t nsteps, double T, double dt, int
  * w_l = sum_{m=0}^{3-l} a_{l+m+1} H^m psi_n, a_j = (-i dt)^j / j!: the
  * time-discrete form of eq. (qoctgradient).  Needs a dipole axis.
  * ws: RSG_OP_ADJOINT bytes. */
-int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, int64_t ld,
+int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, int64_t ldp,
                      double dt, double field, double *g_dev, void *ws, size_t ws_bytes,
                      void *stream);
 
 /* Scratch bytes for rsg_control_forward / rsg_control_backward with these
  * sizes (the checkpoint store is separate and owned by the caller). */
-size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ld, int64_t nsteps,
+size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
                                    int64_t ckpt_every);
 
 /* Forward pass of the control problem: nsteps Taylor(4) steps of psi (in:
  * psi(0), out: psi(T), T = nsteps*dt) under the field of coef_dev, storing
  * psi at every step that is a multiple of ckpt_every (step 0 included) in
- * ckpt_dev [nsteps/ckpt_every + 1][np][ld] complex128.  J_dev[0] =
+ * ckpt_dev [nsteps/ckpt_every + 1][nst][ldp] complex128.  J_dev[0] =
  * sum_n <psi_n(T)| x_axis |psi_n(T)>.  ckpt_dev may be NULL (no checkpoints
  * kept).  ws: rsg_control_workspace_bytes. */
-int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, double dt,
+int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, double dt,
                         int64_t nsteps, const double *coef_dev, int32_t ncoef,
                         int64_t ckpt_every, void *ckpt_dev, double *J_dev, void *ws,
                         size_t ws_bytes, void *stream);
@@ -234,9 +236,9 @@ int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, double 
 /* Backward pass: lambda_N = x_axis psi(T); segment by segment, newest
  * first, recompute the segment's states from its checkpoint, then take
  * adjoint steps back through it.  grad_dev [ncoef] = dJ/dc; g_steps_dev
- * [nsteps] (may be NULL) = dJ/dE_n.  psi_T: device [np][ld], unchanged.
+ * [nsteps] (may be NULL) = dJ/dE_n.  psi_T: device [nst][ldp], unchanged.
  * ws: rsg_control_workspace_bytes. */
-int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld, double dt,
+int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ldp, double dt,
                          int64_t nsteps, const double *coef_dev, int32_t ncoef,
                          int64_t ckpt_every, const void *ckpt_dev, double *grad_dev,
                          double *g_steps_dev, void *ws, size_t ws_bytes, void *stream);
@@ -245,14 +247,13 @@ int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld
 /* Stencil tile shapes and the autotuner                               */
 /* ------------------------------------------------------------------ */
 
-/* Tile of the z-marching stencil kernel: B orbitals x TX x TY grid columns
- * per workgroup, marching along z in chunks of ZC planes (0 = whole box),
- * prefetching PD planes ahead (FP64 kernel: 1..3; ignored for the mixed
- * path).  PT = 1 launches the tiles of each z-chunk in Morton (Z-curve)
- * order; PT >= 2 launches them in PT x PT patches that share a z-range, so
- * that neighbouring workgroups march together; 0 = row order.  BO = 0
- * launches the orbital batches of a tile together, BO = 1 sweeps all tiles
- * of one batch before the next. */
+/* Tile of the z-marching stencil kernel: B orbitals (1) x TX x TY grid
+ * columns per workgroup, marching along z in chunks of ZC planes (0 = whole
+ * box), with PD planes in flight (1..3: pipelined march; 0: lean march).
+ * PT = 1 launches the tiles of each z-chunk in Morton (Z-curve) order;
+ * PT >= 2 launches them in PT x PT patches that share a z-range, so that
+ * neighbouring workgroups march together; 0 = row order.  BO = 0 launches the orbitals of a tile
+ * together, BO = 1 sweeps all tiles of one orbital before the next. */
 typedef struct {
     int32_t B, TX, TY, ZC, PD, PT, BO;
 } rsg_tile;
@@ -262,16 +263,16 @@ typedef struct {
 int rsg_tile_candidates(int32_t dtype, rsg_tile *out, int32_t max, int32_t *count);
 
 /* Use tile t for batches of nst orbitals in dtype on this Hamiltonian.
- * RSG_EUNSUPPORTED if (B, TX, TY) is not compiled. */
+ * RSG_EUNSUPPORTED if (B, TX, TY, PD) is not compiled. */
 int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_tile *t);
 int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
 
-/* Time one Horner stage on psi (device [np][ld], left unchanged) for every
+/* Time one Horner stage on psi (device [nst][ldp], left unchanged) for every
  * compiled tile shape and several z-chunk lengths with HIP events (best of
  * reps launches after a warm-up launch), keep the fastest for (nst, dtype)
  * and return it in *best and its time in *best_ms (either may be NULL).
  * ws: RSG_OP_STEP bytes.  Synchronises the stream. */
-int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype, void *ws,
+int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, void *ws,
                  size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
 
 /* ------------------------------------------------------------------ */
@@ -279,11 +280,11 @@ int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t 
 /* ------------------------------------------------------------------ */
 
 /* One system of a batch: its Hamiltonian (and grid) and its orbitals,
- * device [np][ld] complex128, propagated in place.  No dipole field. */
+ * device [nst][ldp] complex128, propagated in place.  No dipole field. */
 typedef struct {
     rsg_ham_t ham;
     void *psi;
-    int64_t nst, ld;
+    int64_t nst, ldp;
 } rsg_system_desc;
 
 /* Scratch bytes rsg_batch_create needs for these systems. */
@@ -293,7 +294,7 @@ size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc *sys);
  * "Parallelization, optimizations and graphics processing units", extended
  * across systems) so that each stage of a Taylor(4) step of all of them runs
  * as one persistent stencil launch over a cost-sorted list of (system, tile,
- * z-range, orbital batch) items, with one projector gather launch and one
+ * z-range, orbital) items, with one projector gather launch and one
  * scatter launch per colour.  ws (rsg_batch_workspace_bytes) holds the work
  * buffers and must outlive the batch, as must every Hamiltonian and orbital
  * array named in sys.  Results are bitwise equal to propagating each system

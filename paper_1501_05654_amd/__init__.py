@@ -5,9 +5,11 @@ Argument marshalling only.  Every numeric step runs in the HIP kernels of
 memory and the current stream.  Importing this package fails if the library
 has not been built: there is no CPU fallback.
 
-Orbital batches are ``torch.complex128`` CUDA tensors of shape [np, ld]
-(orbital index fastest, compact point order); ``nst <= ld`` columns are
-used.  See ``include/rsg.h`` for the definition of every entry point.
+Orbital batches are orbital-major ``torch.complex128`` CUDA tensors of shape
+[nst, ldp] with ``ldp >= np``: row n is orbital n over the compact points
+(z-major, y, x); the first ``nst`` rows (default: all) are used and entries
+np..ldp-1 of each row are never touched.  See ``include/rsg.h`` for the
+definition of every entry point.
 """
 from __future__ import annotations
 
@@ -108,9 +110,9 @@ def _ptr(t: torch.Tensor | None):
 
 def _batch(t: torch.Tensor, name: str, np_: int, dtype=torch.complex128) -> torch.Tensor:
     if not (t.is_cuda and t.dtype == dtype and t.dim() == 2 and t.is_contiguous()):
-        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor [np, ld]")
-    if t.shape[0] != np_:
-        raise ValueError(f"{name} has {t.shape[0]} rows, grid has {np_} points")
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor [nst, ldp]")
+    if t.shape[1] < np_:
+        raise ValueError(f"{name} rows hold {t.shape[1]} points, grid has {np_}")
     return t
 
 
@@ -195,8 +197,8 @@ class Hamiltonian:
         torch.cuda.synchronize()
         self.natoms = len(projectors)
 
-    def workspace_bytes(self, op: str, nst: int, ld: int, dtype: int = C128) -> int:
-        return int(_lib.rsg_workspace_bytes(self._h, _OP[op], nst, ld, dtype))
+    def workspace_bytes(self, op: str, nst: int, ldp: int, dtype: int = C128) -> int:
+        return int(_lib.rsg_workspace_bytes(self._h, _OP[op], nst, ldp, dtype))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -206,7 +208,10 @@ class Hamiltonian:
 
 
 def _nst(t, nst):
-    return t.shape[1] if nst is None else int(nst)
+    n = t.shape[0] if nst is None else int(nst)
+    if not 0 <= n <= t.shape[0]:
+        raise ValueError(f"nst = {n} outside 0..{t.shape[0]}")
+    return n
 
 
 def hpsi(ham: Hamiltonian, psi: torch.Tensor, field: float = 0.0, out: torch.Tensor | None = None,
@@ -340,8 +345,8 @@ def laser_grad(g: torch.Tensor, T: float, dt: float, ncoef: int) -> torch.Tensor
     return out
 
 
-def _control_ws(ham, n, ld, nsteps, ckpt, device):
-    return _ws(int(_lib.rsg_control_workspace_bytes(ham._h, n, ld, nsteps, ckpt)), device)
+def _control_ws(ham, n, ldp, nsteps, ckpt, device):
+    return _ws(int(_lib.rsg_control_workspace_bytes(ham._h, n, ldp, nsteps, ckpt)), device)
 
 
 def control_forward(ham: Hamiltonian, psi: torch.Tensor, dt: float, nsteps: int,
@@ -349,14 +354,14 @@ def control_forward(ham: Hamiltonian, psi: torch.Tensor, dt: float, nsteps: int,
     """Propagate psi in place to T = nsteps*dt under the sine-series field.
     Returns (J as CUDA float64 [1], checkpoint store or None)."""
     _batch(psi, "psi", ham.grid.np)
-    n, ld = psi.shape[1], psi.shape[1]
+    n, ldp = psi.shape[0], psi.shape[1]
     c = coef.to(torch.float64).contiguous()
     nck = nsteps // ckpt_every + 1
-    ck = (torch.empty((nck, ham.grid.np, ld), dtype=torch.complex128, device=psi.device)
+    ck = (torch.empty((nck, n, ldp), dtype=torch.complex128, device=psi.device)
           if keep_checkpoints else None)
     J = torch.zeros(1, dtype=torch.float64, device=psi.device)
-    ws = _control_ws(ham, n, ld, nsteps, ckpt_every, psi.device)
-    _check(_lib.rsg_control_forward(ham._h, _ptr(psi), n, ld, float(dt), int(nsteps), _ptr(c),
+    ws = _control_ws(ham, n, ldp, nsteps, ckpt_every, psi.device)
+    _check(_lib.rsg_control_forward(ham._h, _ptr(psi), n, ldp, float(dt), int(nsteps), _ptr(c),
                                     c.numel(), int(ckpt_every), _ptr(ck), _ptr(J), _ptr(ws),
                                     ws.numel(), _stream()))
     return J, ck
@@ -366,12 +371,14 @@ def control_backward(ham: Hamiltonian, psi_T: torch.Tensor, dt: float, nsteps: i
                      coef: torch.Tensor, ckpt_every: int, ckpt: torch.Tensor):
     """(dJ/dc [ncoef], dJ/dE_n [nsteps]) by checkpointed discrete adjoint."""
     _batch(psi_T, "psi_T", ham.grid.np)
-    n, ld = psi_T.shape[1], psi_T.shape[1]
+    n, ldp = psi_T.shape[0], psi_T.shape[1]
+    if ckpt is None or tuple(ckpt.shape) != (nsteps // ckpt_every + 1, n, ldp):
+        raise ValueError("checkpoint store does not match psi_T and the step count")
     c = coef.to(torch.float64).contiguous()
     grad = torch.zeros(c.numel(), dtype=torch.float64, device=psi_T.device)
     gs = torch.zeros(int(nsteps), dtype=torch.float64, device=psi_T.device)
-    ws = _control_ws(ham, n, ld, nsteps, ckpt_every, psi_T.device)
-    _check(_lib.rsg_control_backward(ham._h, _ptr(psi_T), n, ld, float(dt), int(nsteps), _ptr(c),
+    ws = _control_ws(ham, n, ldp, nsteps, ckpt_every, psi_T.device)
+    _check(_lib.rsg_control_backward(ham._h, _ptr(psi_T), n, ldp, float(dt), int(nsteps), _ptr(c),
                                      c.numel(), int(ckpt_every), _ptr(ckpt), _ptr(grad), _ptr(gs),
                                      _ptr(ws), ws.numel(), _stream()))
     return grad, gs
@@ -464,7 +471,7 @@ def autotune(ham: Hamiltonian, psi: torch.Tensor, dtype="c128", reps: int = 3,
 
 
 class _SysDesc(C.Structure):
-    _fields_ = [("ham", C.c_void_p), ("psi", C.c_void_p), ("nst", C.c_int64), ("ld", C.c_int64)]
+    _fields_ = [("ham", C.c_void_p), ("psi", C.c_void_p), ("nst", C.c_int64), ("ldp", C.c_int64)]
 
 
 class Batch:
@@ -472,7 +479,7 @@ class Batch:
     Taylor(4) step of all systems is one persistent stencil launch.
 
     systems: list of (Hamiltonian, psi, nst) with psi a CUDA complex128
-    [np, ld] tensor propagated in place.  The Hamiltonians and tensors must
+    [>= nst, ldp] orbital-major tensor propagated in place.  The Hamiltonians and tensors must
     stay alive while the batch is used."""
 
     def __init__(self, systems):
@@ -481,6 +488,8 @@ class Batch:
         descs = (_SysDesc * n)()
         for k, (ham, psi, nst) in enumerate(self.systems):
             _batch(psi, "psi", ham.grid.np)
+            if not 1 <= int(nst) <= psi.shape[0]:
+                raise ValueError(f"system {k}: nst = {nst} outside 1..{psi.shape[0]}")
             descs[k] = _SysDesc(ham._h.value, psi.data_ptr(), int(nst), psi.shape[1])
         self._descs = descs
         nbytes = int(_lib.rsg_batch_workspace_bytes(n, descs))

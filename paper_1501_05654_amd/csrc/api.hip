@@ -141,13 +141,14 @@ struct Carve {
 
 size_t rounded(size_t n) { return (n + 255) & ~(size_t)255; }
 
-size_t batch_bytes(const Grid &g, int64_t ld, size_t elem) { return (size_t)g.np * (size_t)ld * elem; }
+// Bytes of an orbital-major batch of nst orbitals with stride ldp.
+size_t batch_bytes(int64_t nst, int64_t ldp, size_t elem) { return (size_t)nst * (size_t)ldp * elem; }
 
-int check_batch(const Ham *H, const void *p, int64_t nst, int64_t ld, const char *who) {
+int check_batch(const Ham *H, const void *p, int64_t nst, int64_t ldp, const char *who) {
     RSG_REQUIRE(H, RSG_EINVAL, "%s: null Hamiltonian", who);
-    RSG_REQUIRE(nst >= 0 && ld >= 1, RSG_ESHAPE, "%s: need nst >= 0 and ld >= 1", who);
-    RSG_REQUIRE(nst <= ld, RSG_ESHAPE, "%s: nst (%lld) > ld (%lld)", who, (long long)nst,
-                (long long)ld);
+    RSG_REQUIRE(nst >= 0 && ldp >= 1 && ldp >= H->g->np, RSG_ESHAPE,
+                "%s: need nst >= 0 and ldp >= np (ldp %lld, np %lld)", who, (long long)ldp,
+                (long long)H->g->np);
     RSG_REQUIRE(p || nst == 0 || H->g->np == 0, RSG_EINVAL, "%s: null orbital pointer", who);
     RSG_REQUIRE(((uintptr_t)p & 15) == 0, RSG_EINVAL, "%s: orbital pointer not 16-byte aligned", who);
     return RSG_OK;
@@ -156,28 +157,28 @@ int check_batch(const Ham *H, const void *p, int64_t nst, int64_t ld, const char
 // --------------------------------------------------------- internal ops
 
 // out = H(in), FP64.
-int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ld, double field,
+int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ldp, double field,
               const double *field_dev, void *D, hipStream_t s) {
-    int rc = launch_kb_gather(H, in, 0, 0, nst, ld, D, s);
+    int rc = launch_kb_gather(H, in, 0, 0, nst, ldp, D, s);
     if (rc) return rc;
     StageArgs a;
     a.in = in;
     a.out = out;
     a.mode = 0;
     a.nst = nst;
-    a.ld = ld;
+    a.ldp = ldp;
     a.field = field;
     a.field_dev = field_dev;
     rc = launch_stencil(H, a, H.tile_for(nst, 0), s);
     if (rc) return rc;
-    return launch_kb_scatter(H, out, 0, 0, nst, ld, D, 1.0, 0.0, s);
+    return launch_kb_scatter(H, out, 0, 0, nst, ldp, D, 1.0, 0.0, s);
 }
 
 // One Horner stage: out = base + c H(in).
 int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *out, int out_t,
-               int compute, int64_t nst, int64_t ld, double cre, double cim, double field,
+               int compute, int64_t nst, int64_t ldp, double cre, double cim, double field,
                const double *field_dev, void *D, hipStream_t s) {
-    int rc = launch_kb_gather(H, in, in_t, compute, nst, ld, D, s);
+    int rc = launch_kb_gather(H, in, in_t, compute, nst, ldp, D, s);
     if (rc) return rc;
     StageArgs a;
     a.in = in;
@@ -188,7 +189,7 @@ int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *o
     a.compute = compute;
     a.mode = 1;
     a.nst = nst;
-    a.ld = ld;
+    a.ldp = ldp;
     a.field = field;
     a.field_dev = field_dev;
     a.cre = cre;
@@ -196,48 +197,48 @@ int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *o
     a.first = in == base && in_t == 0;
     rc = launch_stencil(H, a, H.tile_for(nst, compute), s);
     if (rc) return rc;
-    return launch_kb_scatter(H, out, out_t, compute, nst, ld, D, cre, cim, s);
+    return launch_kb_scatter(H, out, out_t, compute, nst, ldp, D, cre, cim, s);
 }
 
-size_t step_ws(const Ham &H, int64_t nst, int64_t ld, int32_t dtype) {
+size_t step_ws(const Ham &H, int64_t nst, int64_t ldp, int32_t dtype) {
     const size_t e = dtype == RSG_C128 ? 16 : 8;
-    return 2 * rounded(batch_bytes(*H.g, ld, e)) + rounded(kb_workspace_bytes(H, nst)) + 256;
+    return 2 * rounded(batch_bytes(nst, ldp, e)) + rounded(kb_workspace_bytes(H, nst)) + 256;
 }
 
 // Taylor(4) in Horner form: y4 = psi, y_{k-1} = psi + (-i dt / k) H y_k,
 // psi <- y0.  Work buffers alternate; the last stage writes psi in place
 // (each output point reads only its own psi value).
-int step_impl(const Ham &H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+int step_impl(const Ham &H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
               double field, const double *field_dev, void *ws, size_t ws_bytes, hipStream_t s) {
     const size_t e = dtype == RSG_C128 ? 16 : 8;
     Carve c(ws, ws_bytes);
-    void *w1 = c.take(batch_bytes(*H.g, ld, e));
-    void *w2 = c.take(batch_bytes(*H.g, ld, e));
+    void *w1 = c.take(batch_bytes(nst, ldp, e));
+    void *w2 = c.take(batch_bytes(nst, ldp, e));
     void *D = c.take(kb_workspace_bytes(H, nst));
     if (!c.ok) {
-        set_error("propagate: workspace too small (%zu < %zu bytes)", ws_bytes, step_ws(H, nst, ld, dtype));
+        set_error("propagate: workspace too small (%zu < %zu bytes)", ws_bytes, step_ws(H, nst, ldp, dtype));
         return RSG_ENOMEM;
     }
     const int cmp = dtype == RSG_C128 ? 0 : 1;
     const int wt = dtype == RSG_C128 ? 0 : 1;  // work-buffer type
     int rc;
-    if ((rc = stage_impl(H, psi, 0, psi, w1, wt, cmp, nst, ld, 0.0, -dt / 4.0, field, field_dev, D, s))) return rc;
-    if ((rc = stage_impl(H, w1, wt, psi, w2, wt, cmp, nst, ld, 0.0, -dt / 3.0, field, field_dev, D, s))) return rc;
-    if ((rc = stage_impl(H, w2, wt, psi, w1, wt, cmp, nst, ld, 0.0, -dt / 2.0, field, field_dev, D, s))) return rc;
-    return stage_impl(H, w1, wt, psi, psi, 0, cmp, nst, ld, 0.0, -dt, field, field_dev, D, s);
+    if ((rc = stage_impl(H, psi, 0, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 4.0, field, field_dev, D, s))) return rc;
+    if ((rc = stage_impl(H, w1, wt, psi, w2, wt, cmp, nst, ldp, 0.0, -dt / 3.0, field, field_dev, D, s))) return rc;
+    if ((rc = stage_impl(H, w2, wt, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 2.0, field, field_dev, D, s))) return rc;
+    return stage_impl(H, w1, wt, psi, psi, 0, cmp, nst, ldp, 0.0, -dt, field, field_dev, D, s);
 }
 
-size_t adjoint_ws(const Ham &H, int64_t nst, int64_t ld) {
-    return 7 * rounded(batch_bytes(*H.g, ld, 16)) + rounded(kb_workspace_bytes(H, nst)) +
+size_t adjoint_ws(const Ham &H, int64_t nst, int64_t ldp) {
+    return 7 * rounded(batch_bytes(nst, ldp, 16)) + rounded(kb_workspace_bytes(H, nst)) +
            rounded(reduce_workspace_bytes(*H.g, nst)) + 256;
 }
 
 // Discrete adjoint of one Taylor(4) step (see rsg_adjoint_step).
-int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int64_t ld, double dt,
+int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int64_t ldp, double dt,
                  double field, const double *field_dev, double *g_dev, void *ws, size_t ws_bytes,
                  hipStream_t s) {
     Carve c(ws, ws_bytes);
-    const size_t bb = batch_bytes(*H.g, ld, 16);
+    const size_t bb = batch_bytes(nst, ldp, 16);
     void *nu[4], *mu[5];
     nu[0] = const_cast<void *>(psi_n);
     mu[0] = lambda;
@@ -247,14 +248,14 @@ int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int
     const size_t rb = reduce_workspace_bytes(*H.g, nst);
     void *R = c.take(rb);
     if (!c.ok) {
-        set_error("adjoint: workspace too small (%zu < %zu bytes)", ws_bytes, adjoint_ws(H, nst, ld));
+        set_error("adjoint: workspace too small (%zu < %zu bytes)", ws_bytes, adjoint_ws(H, nst, ldp));
         return RSG_ENOMEM;
     }
     int rc;
     for (int k = 1; k < 4; ++k)
-        if ((rc = hpsi_impl(H, nu[k - 1], nu[k], nst, ld, field, field_dev, D, s))) return rc;
+        if ((rc = hpsi_impl(H, nu[k - 1], nu[k], nst, ldp, field, field_dev, D, s))) return rc;
     for (int k = 1; k < 5; ++k)
-        if ((rc = hpsi_impl(H, mu[k - 1], mu[k], nst, ld, field, field_dev, D, s))) return rc;
+        if ((rc = hpsi_impl(H, mu[k - 1], mu[k], nst, ldp, field, field_dev, D, s))) return rc;
     // a_j = (-i dt)^j / j!
     double2 a[5];
     a[0] = make_double2(1.0, 0.0);
@@ -270,19 +271,19 @@ int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int
                              (const double2 *)mu[3]};
     const double2 *nup[4] = {(const double2 *)nu[0], (const double2 *)nu[1], (const double2 *)nu[2],
                              (const double2 *)nu[3]};
-    if ((rc = launch_cross_dots(*H.g, H.axis, mup, nup, pc, nst, ld, g_dev, R, rb, s))) return rc;
+    if ((rc = launch_cross_dots(*H.g, H.axis, mup, nup, pc, nst, ldp, g_dev, R, rb, s))) return rc;
     // lambda_n = sum_k conj(a_k) mu_k
     double2 ca[5];
     for (int k = 0; k < 5; ++k) ca[k] = make_double2(a[k].x, -a[k].y);
     const double2 *src[5] = {(const double2 *)mu[0], (const double2 *)mu[1], (const double2 *)mu[2],
                              (const double2 *)mu[3], (const double2 *)mu[4]};
-    return launch_axpby_list(*H.g, nst, ld, 5, src, ca, (double2 *)lambda, s);
+    return launch_axpby_list(*H.g, nst, ldp, 5, src, ca, (double2 *)lambda, s);
 }
 
 // Graph cache key for rsg_propagate.
 struct GraphKey {
     const void *psi;
-    int64_t nst, ld;
+    int64_t nst, ldp;
     int32_t dtype;
     double dt;
     int64_t nsteps;
@@ -291,8 +292,8 @@ struct GraphKey {
     size_t ws_bytes;
     hipStream_t stream;
     bool operator<(const GraphKey &o) const {
-        return std::tie(psi, nst, ld, dtype, dt, nsteps, fields, ws, ws_bytes, stream) <
-               std::tie(o.psi, o.nst, o.ld, o.dtype, o.dt, o.nsteps, o.fields, o.ws, o.ws_bytes,
+        return std::tie(psi, nst, ldp, dtype, dt, nsteps, fields, ws, ws_bytes, stream) <
+               std::tie(o.psi, o.nst, o.ldp, o.dtype, o.dt, o.nsteps, o.fields, o.ws, o.ws_bytes,
                         o.stream);
     }
 };
@@ -469,67 +470,67 @@ extern "C" int rsg_ham_destroy(rsg_ham_t H) {
     return RSG_OK;
 }
 
-extern "C" size_t rsg_workspace_bytes(rsg_ham_t H, int32_t op, int64_t nst, int64_t ld, int32_t dtype) {
-    if (!H || nst < 0 || ld < 1) return 0;
+extern "C" size_t rsg_workspace_bytes(rsg_ham_t H, int32_t op, int64_t nst, int64_t ldp, int32_t dtype) {
+    if (!H || nst < 0 || ldp < 1) return 0;
     switch (op) {
         case RSG_OP_HPSI: return rounded(kb_workspace_bytes(*H, nst)) + 256;
-        case RSG_OP_STEP: return step_ws(*H, nst, ld, dtype);
+        case RSG_OP_STEP: return step_ws(*H, nst, ldp, dtype);
         case RSG_OP_REDUCE: return reduce_workspace_bytes(*H->g, nst);
         case RSG_OP_ENERGY:
-            return rounded(batch_bytes(*H->g, ld, 16)) + rounded(kb_workspace_bytes(*H, nst)) +
+            return rounded(batch_bytes(nst, ldp, 16)) + rounded(kb_workspace_bytes(*H, nst)) +
                    rounded(reduce_workspace_bytes(*H->g, nst)) + 256;
-        case RSG_OP_ADJOINT: return adjoint_ws(*H, nst, ld);
+        case RSG_OP_ADJOINT: return adjoint_ws(*H, nst, ldp);
         default: return 0;
     }
 }
 
-extern "C" int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ld,
+extern "C" int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ldp,
                         int32_t dtype, double field, void *ws, size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_batch(H, psi, nst, ld, "rsg_hpsi");
+    int rc = check_batch(H, psi, nst, ldp, "rsg_hpsi");
     if (rc) return rc;
     RSG_REQUIRE(dtype == RSG_C128, dtype == RSG_C64_MIXED ? RSG_EUNSUPPORTED : RSG_EDTYPE,
                 "rsg_hpsi: dtype must be RSG_C128");
     RSG_REQUIRE(hpsi || nst == 0, RSG_EINVAL, "rsg_hpsi: null output");
     RSG_REQUIRE(((uintptr_t)hpsi & 15) == 0, RSG_EINVAL, "rsg_hpsi: output not 16-byte aligned");
-    const size_t bb = batch_bytes(*H->g, ld, 16);
+    const size_t bb = batch_bytes(nst, ldp, 16);
     const char *a0 = (const char *)psi, *b0 = (const char *)hpsi;
     RSG_REQUIRE(nst == 0 || a0 + bb <= b0 || b0 + bb <= a0, RSG_EINVAL, "rsg_hpsi: psi and hpsi overlap");
     Carve c(ws, ws_bytes);
     void *D = c.take(kb_workspace_bytes(*H, nst));
     RSG_REQUIRE(c.ok, RSG_ENOMEM, "rsg_hpsi: workspace too small");
     if (nst == 0 || H->g->np == 0) return RSG_OK;
-    return hpsi_impl(*H, psi, hpsi, nst, ld, field, nullptr, D, (hipStream_t)stream);
+    return hpsi_impl(*H, psi, hpsi, nst, ldp, field, nullptr, D, (hipStream_t)stream);
 }
 
-extern "C" int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype,
+extern "C" int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, int32_t dtype,
                                   double dt, double field, void *ws, size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_batch(H, psi, nst, ld, "rsg_propagate_step");
+    int rc = check_batch(H, psi, nst, ldp, "rsg_propagate_step");
     if (rc) return rc;
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_propagate_step: bad dtype %d", dtype);
     RSG_REQUIRE(std::isfinite(dt) && std::isfinite(field), RSG_EINVAL, "rsg_propagate_step: dt/field not finite");
-    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ld, dtype) - 256 || nst == 0, RSG_ENOMEM,
-                "rsg_propagate_step: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ld, dtype));
+    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ldp, dtype) - 256 || nst == 0, RSG_ENOMEM,
+                "rsg_propagate_step: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ldp, dtype));
     if (nst == 0 || H->g->np == 0) return RSG_OK;
-    return step_impl(*H, psi, nst, ld, dtype, dt, field, nullptr, ws, ws_bytes, (hipStream_t)stream);
+    return step_impl(*H, psi, nst, ldp, dtype, dt, field, nullptr, ws, ws_bytes, (hipStream_t)stream);
 }
 
-extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, int32_t dtype, double dt,
+extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
                              int64_t nsteps, const double *fields_dev, int32_t use_graph, void *ws,
                              size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_batch(H, psi, nst, ld, "rsg_propagate");
+    int rc = check_batch(H, psi, nst, ldp, "rsg_propagate");
     if (rc) return rc;
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_propagate: bad dtype %d", dtype);
     RSG_REQUIRE(nsteps >= 0 && std::isfinite(dt), RSG_EINVAL, "rsg_propagate: bad nsteps/dt");
-    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ld, dtype) - 256 || nst == 0, RSG_ENOMEM,
-                "rsg_propagate: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ld, dtype));
+    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ldp, dtype) - 256 || nst == 0, RSG_ENOMEM,
+                "rsg_propagate: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ldp, dtype));
     if (nst == 0 || H->g->np == 0 || nsteps == 0) return RSG_OK;
     hipStream_t s = (hipStream_t)stream;
     auto run = [&]() -> int {
         for (int64_t n = 0; n < nsteps; ++n) {
-            const int r = step_impl(*H, psi, nst, ld, dtype, dt, 0.0, fields_dev ? fields_dev + n : nullptr,
+            const int r = step_impl(*H, psi, nst, ldp, dtype, dt, 0.0, fields_dev ? fields_dev + n : nullptr,
                                     ws, ws_bytes, s);
             if (r) return r;
         }
@@ -544,7 +545,7 @@ extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, in
         if (sh.ZC <= 0) sh.ZC = H->g->n[2];
         if (!H->g->plan(sh, s, &err)) return err;
     }
-    GraphKey key{psi, nst, ld, dtype, dt, nsteps, fields_dev, ws, ws_bytes, s};
+    GraphKey key{psi, nst, ldp, dtype, dt, nsteps, fields_dev, ws, ws_bytes, s};
     hipGraphExec_t exec = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -578,9 +579,9 @@ extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, in
     return RSG_OK;
 }
 
-static int check_reduce(const Grid *g, const void *a, int64_t nst, int64_t ld, const void *out, const char *who) {
+static int check_reduce(const Grid *g, const void *a, int64_t nst, int64_t ldp, const void *out, const char *who) {
     RSG_REQUIRE(g, RSG_EINVAL, "%s: null grid", who);
-    RSG_REQUIRE(nst >= 0 && ld >= 1 && nst <= ld, RSG_ESHAPE, "%s: need 0 <= nst <= ld", who);
+    RSG_REQUIRE(nst >= 0 && ldp >= 1 && ldp >= g->np, RSG_ESHAPE, "%s: need nst >= 0 and ldp >= np", who);
     RSG_REQUIRE(nst == 0 || (a && out), RSG_EINVAL, "%s: null pointer", who);
     RSG_REQUIRE(((uintptr_t)a & 15) == 0, RSG_EINVAL, "%s: pointer not 16-byte aligned", who);
     return RSG_OK;
@@ -591,109 +592,109 @@ extern "C" size_t rsg_reduce_workspace_bytes(rsg_grid_t g, int64_t nst) {
     return reduce_workspace_bytes(*g, nst);
 }
 
-extern "C" int rsg_dot(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ld, double *out,
+extern "C" int rsg_dot(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ldp, double *out,
                        void *ws, size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_reduce(g, a, nst, ld, out, "rsg_dot");
+    int rc = check_reduce(g, a, nst, ldp, out, "rsg_dot");
     if (rc) return rc;
     RSG_REQUIRE(nst == 0 || b, RSG_EINVAL, "rsg_dot: null pointer");
     RSG_REQUIRE(((uintptr_t)b & 15) == 0, RSG_EINVAL, "rsg_dot: pointer not 16-byte aligned");
-    return launch_reduce(*g, 0, 0, (const double2 *)a, (const double2 *)b, nst, ld, out, ws, ws_bytes,
+    return launch_reduce(*g, 0, 0, (const double2 *)a, (const double2 *)b, nst, ldp, out, ws, ws_bytes,
                          (hipStream_t)stream);
 }
 
-extern "C" int rsg_norm2(rsg_grid_t g, const void *a, int64_t nst, int64_t ld, double *out, void *ws,
+extern "C" int rsg_norm2(rsg_grid_t g, const void *a, int64_t nst, int64_t ldp, double *out, void *ws,
                          size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_reduce(g, a, nst, ld, out, "rsg_norm2");
+    int rc = check_reduce(g, a, nst, ldp, out, "rsg_norm2");
     if (rc) return rc;
-    return launch_reduce(*g, 1, 0, (const double2 *)a, nullptr, nst, ld, out, ws, ws_bytes,
+    return launch_reduce(*g, 1, 0, (const double2 *)a, nullptr, nst, ldp, out, ws, ws_bytes,
                          (hipStream_t)stream);
 }
 
-extern "C" int rsg_dipole_expectation(rsg_ham_t H, const void *a, int64_t nst, int64_t ld, double *out,
+extern "C" int rsg_dipole_expectation(rsg_ham_t H, const void *a, int64_t nst, int64_t ldp, double *out,
                                       void *ws, size_t ws_bytes, void *stream) {
     clear_error();
     RSG_REQUIRE(H, RSG_EINVAL, "rsg_dipole_expectation: null Hamiltonian");
     RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "rsg_dipole_expectation: Hamiltonian has no dipole axis");
-    int rc = check_reduce(H->g, a, nst, ld, out, "rsg_dipole_expectation");
+    int rc = check_reduce(H->g, a, nst, ldp, out, "rsg_dipole_expectation");
     if (rc) return rc;
-    return launch_reduce(*H->g, 2, H->axis, (const double2 *)a, nullptr, nst, ld, out, ws, ws_bytes,
+    return launch_reduce(*H->g, 2, H->axis, (const double2 *)a, nullptr, nst, ldp, out, ws, ws_bytes,
                          (hipStream_t)stream);
 }
 
-extern "C" int rsg_energy(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype, double field,
+extern "C" int rsg_energy(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, double field,
                           double *out, void *ws, size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_batch(H, psi, nst, ld, "rsg_energy");
+    int rc = check_batch(H, psi, nst, ldp, "rsg_energy");
     if (rc) return rc;
     RSG_REQUIRE(dtype == RSG_C128, RSG_EDTYPE, "rsg_energy: dtype must be RSG_C128");
     RSG_REQUIRE(nst == 0 || out, RSG_EINVAL, "rsg_energy: null output");
     Carve c(ws, ws_bytes);
-    void *hp = c.take(batch_bytes(*H->g, ld, 16));
+    void *hp = c.take(batch_bytes(nst, ldp, 16));
     void *D = c.take(kb_workspace_bytes(*H, nst));
     const size_t rb = reduce_workspace_bytes(*H->g, nst);
     void *R = c.take(rb);
     RSG_REQUIRE(c.ok, RSG_ENOMEM, "rsg_energy: workspace too small");
     if (nst == 0) return RSG_OK;
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = hpsi_impl(*H, psi, hp, nst, ld, field, nullptr, D, s))) return rc;
-    return launch_reduce(*H->g, 0, 0, (const double2 *)psi, (const double2 *)hp, nst, ld, out, R, rb, s);
+    if ((rc = hpsi_impl(*H, psi, hp, nst, ldp, field, nullptr, D, s))) return rc;
+    return launch_reduce(*H->g, 0, 0, (const double2 *)psi, (const double2 *)hp, nst, ldp, out, R, rb, s);
 }
 
-extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, int64_t ld,
+extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, int64_t ldp,
                                 double dt, double field, double *g_dev, void *ws, size_t ws_bytes,
                                 void *stream) {
     clear_error();
-    int rc = check_batch(H, psi_n, nst, ld, "rsg_adjoint_step");
+    int rc = check_batch(H, psi_n, nst, ldp, "rsg_adjoint_step");
     if (rc) return rc;
-    rc = check_batch(H, lambda, nst, ld, "rsg_adjoint_step");
+    rc = check_batch(H, lambda, nst, ldp, "rsg_adjoint_step");
     if (rc) return rc;
     RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "rsg_adjoint_step: Hamiltonian has no dipole axis");
     RSG_REQUIRE(g_dev, RSG_EINVAL, "rsg_adjoint_step: null gradient output");
-    RSG_REQUIRE(ws_bytes >= adjoint_ws(*H, nst, ld) - 256, RSG_ENOMEM,
-                "rsg_adjoint_step: workspace too small (%zu < %zu)", ws_bytes, adjoint_ws(*H, nst, ld));
+    RSG_REQUIRE(ws_bytes >= adjoint_ws(*H, nst, ldp) - 256, RSG_ENOMEM,
+                "rsg_adjoint_step: workspace too small (%zu < %zu)", ws_bytes, adjoint_ws(*H, nst, ldp));
     RSG_REQUIRE(nst > 0, RSG_ESHAPE, "rsg_adjoint_step: nst must be > 0");
-    return adjoint_impl(*H, psi_n, lambda, nst, ld, dt, field, nullptr, g_dev, ws, ws_bytes,
+    return adjoint_impl(*H, psi_n, lambda, nst, ldp, dt, field, nullptr, g_dev, ws, ws_bytes,
                         (hipStream_t)stream);
 }
 
-static size_t control_ws(const Ham &H, int64_t nst, int64_t ld, int64_t nsteps, int64_t ckpt) {
-    const size_t bb = rounded(batch_bytes(*H.g, ld, 16));
+static size_t control_ws(const Ham &H, int64_t nst, int64_t ldp, int64_t nsteps, int64_t ckpt) {
+    const size_t bb = rounded(batch_bytes(nst, ldp, 16));
     return rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 + rounded(sizeof(double) * (size_t)nst) +
-           bb + (size_t)std::max<int64_t>(ckpt, 1) * bb + std::max(step_ws(H, nst, ld, RSG_C128), adjoint_ws(H, nst, ld)) +
+           bb + (size_t)std::max<int64_t>(ckpt, 1) * bb + std::max(step_ws(H, nst, ldp, RSG_C128), adjoint_ws(H, nst, ldp)) +
            256;
 }
 
-extern "C" size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ld, int64_t nsteps,
+extern "C" size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
                                               int64_t ckpt_every) {
-    if (!H || nst < 0 || ld < 1 || nsteps < 0 || ckpt_every < 1) return 0;
-    return control_ws(*H, nst, ld, nsteps, ckpt_every);
+    if (!H || nst < 0 || ldp < 1 || nsteps < 0 || ckpt_every < 1) return 0;
+    return control_ws(*H, nst, ldp, nsteps, ckpt_every);
 }
 
-static int check_control(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, double dt, int64_t nsteps,
+static int check_control(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, double dt, int64_t nsteps,
                          const double *coef, int32_t ncoef, int64_t ckpt, size_t ws_bytes, const char *who) {
-    int rc = check_batch(H, psi, nst, ld, who);
+    int rc = check_batch(H, psi, nst, ldp, who);
     if (rc) return rc;
     RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "%s: Hamiltonian has no dipole axis", who);
     RSG_REQUIRE(nst > 0 && nsteps > 0 && dt > 0 && std::isfinite(dt), RSG_EINVAL, "%s: need nst, nsteps, dt > 0", who);
     RSG_REQUIRE(ncoef >= 0 && (ncoef == 0 || coef), RSG_EINVAL, "%s: bad coefficient array", who);
     RSG_REQUIRE(ckpt >= 1, RSG_EINVAL, "%s: ckpt_every must be >= 1", who);
-    RSG_REQUIRE(ws_bytes >= control_ws(*H, nst, ld, nsteps, ckpt) - 256, RSG_ENOMEM,
-                "%s: workspace too small (%zu < %zu)", who, ws_bytes, control_ws(*H, nst, ld, nsteps, ckpt));
+    RSG_REQUIRE(ws_bytes >= control_ws(*H, nst, ldp, nsteps, ckpt) - 256, RSG_ENOMEM,
+                "%s: workspace too small (%zu < %zu)", who, ws_bytes, control_ws(*H, nst, ldp, nsteps, ckpt));
     return RSG_OK;
 }
 
-extern "C" int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ld, double dt, int64_t nsteps,
+extern "C" int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, double dt, int64_t nsteps,
                                    const double *coef, int32_t ncoef, int64_t ckpt_every, void *ckpt_dev,
                                    double *J_dev, void *ws, size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_control(H, psi, nst, ld, dt, nsteps, coef, ncoef, ckpt_every, ws_bytes, "rsg_control_forward");
+    int rc = check_control(H, psi, nst, ldp, dt, nsteps, coef, ncoef, ckpt_every, ws_bytes, "rsg_control_forward");
     if (rc) return rc;
     RSG_REQUIRE(J_dev, RSG_EINVAL, "rsg_control_forward: null J output");
     hipStream_t s = (hipStream_t)stream;
     const double T = dt * (double)nsteps;
-    const size_t bb = batch_bytes(*H->g, ld, 16);
+    const size_t bb = batch_bytes(nst, ldp, 16);
     Carve c(ws, ws_bytes);
     double *fields = (double *)c.take(sizeof(double) * nsteps);
     (void)c.take(sizeof(double) * nsteps);
@@ -709,30 +710,30 @@ extern "C" int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t 
     if ((rc = rsg_laser_field(coef, ncoef, T, dt, 0, nsteps, fields, stream))) return rc;
     if (ckpt_dev) RSG_CHECK_HIP(hipMemcpyAsync(ckpt_dev, psi, bb, hipMemcpyDeviceToDevice, s));
     for (int64_t n = 0; n < nsteps; ++n) {
-        if ((rc = step_impl(*H, psi, nst, ld, RSG_C128, dt, 0.0, fields + n, sws, rest, s))) return rc;
+        if ((rc = step_impl(*H, psi, nst, ldp, RSG_C128, dt, 0.0, fields + n, sws, rest, s))) return rc;
         if (ckpt_dev && (n + 1) % ckpt_every == 0)
             RSG_CHECK_HIP(hipMemcpyAsync((char *)ckpt_dev + (size_t)((n + 1) / ckpt_every) * bb, psi, bb,
                                          hipMemcpyDeviceToDevice, s));
     }
     const size_t rb = reduce_workspace_bytes(*H->g, nst);
-    if ((rc = launch_reduce(*H->g, 2, H->axis, (const double2 *)psi, nullptr, nst, ld, per, sws, rb, s))) return rc;
+    if ((rc = launch_reduce(*H->g, 2, H->axis, (const double2 *)psi, nullptr, nst, ldp, per, sws, rb, s))) return rc;
     k_sum<<<1, 64, 0, s>>>(per, nst, J_dev);
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }
 
-extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld, double dt,
+extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ldp, double dt,
                                     int64_t nsteps, const double *coef, int32_t ncoef, int64_t ckpt_every,
                                     const void *ckpt_dev, double *grad_dev, double *g_steps_dev, void *ws,
                                     size_t ws_bytes, void *stream) {
     clear_error();
-    int rc = check_control(H, psi_T, nst, ld, dt, nsteps, coef, ncoef, ckpt_every, ws_bytes, "rsg_control_backward");
+    int rc = check_control(H, psi_T, nst, ldp, dt, nsteps, coef, ncoef, ckpt_every, ws_bytes, "rsg_control_backward");
     if (rc) return rc;
     RSG_REQUIRE(ckpt_dev, RSG_EINVAL, "rsg_control_backward: null checkpoint store");
     RSG_REQUIRE(ncoef == 0 || grad_dev, RSG_EINVAL, "rsg_control_backward: null gradient output");
     hipStream_t s = (hipStream_t)stream;
     const double T = dt * (double)nsteps;
-    const size_t bb = batch_bytes(*H->g, ld, 16);
+    const size_t bb = batch_bytes(nst, ldp, 16);
     const size_t bbr = rounded(bb);
     Carve c(ws, ws_bytes);
     double *fields = (double *)c.take(sizeof(double) * nsteps);
@@ -748,7 +749,7 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     }
     if (g_steps_dev) gs = g_steps_dev;
     if ((rc = rsg_laser_field(coef, ncoef, T, dt, 0, nsteps, fields, stream))) return rc;
-    if ((rc = launch_mul_axis(*H->g, H->axis, (const double2 *)psi_T, (double2 *)lam, nst, ld, s))) return rc;
+    if ((rc = launch_mul_axis(*H->g, H->axis, (const double2 *)psi_T, (double2 *)lam, nst, ldp, s))) return rc;
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t s0 = seg * ckpt_every, s1 = std::min(nsteps, s0 + ckpt_every);
@@ -757,11 +758,11 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
                                      hipMemcpyDeviceToDevice, s));
         for (int64_t k = 1; k < s1 - s0; ++k) {
             RSG_CHECK_HIP(hipMemcpyAsync(states + k * bbr, states + (k - 1) * bbr, bb, hipMemcpyDeviceToDevice, s));
-            if ((rc = step_impl(*H, states + k * bbr, nst, ld, RSG_C128, dt, 0.0, fields + s0 + k - 1, sws, rest, s)))
+            if ((rc = step_impl(*H, states + k * bbr, nst, ldp, RSG_C128, dt, 0.0, fields + s0 + k - 1, sws, rest, s)))
                 return rc;
         }
         for (int64_t n = s1 - 1; n >= s0; --n) {
-            if ((rc = adjoint_impl(*H, states + (n - s0) * bbr, lam, nst, ld, dt, 0.0, fields + n, gs + n, sws,
+            if ((rc = adjoint_impl(*H, states + (n - s0) * bbr, lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws,
                                    rest, s)))
                 return rc;
         }
@@ -787,7 +788,7 @@ extern "C" int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_t
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_set_tile: bad dtype");
     RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "rsg_set_tile: ZC must be >= 0");
     bool ok = false;
-    const int pd = tile_compute(dtype) == 0 ? t->PD : 1;
+    const int pd = t->PD;
     for (const auto &c : tile_candidates(tile_compute(dtype)))
         ok = ok || (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == pd);
     RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_set_tile: %dx%dx%d (depth %d) is not a compiled tile shape", t->B,
@@ -815,20 +816,20 @@ extern "C" int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t
 // Times one Horner stage (out = psi + c H psi into the workspace, psi
 // untouched) for every compiled tile shape and z-chunk length, keeps the
 // fastest for (nst, dtype) and reports it.
-extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ld, int32_t dtype,
+extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype,
                             void *ws, size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms,
                             void *stream) {
     clear_error();
-    int rc = check_batch(H, psi, nst, ld, "rsg_autotune");
+    int rc = check_batch(H, psi, nst, ldp, "rsg_autotune");
     if (rc) return rc;
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_autotune: bad dtype");
     RSG_REQUIRE(nst > 0 && reps > 0, RSG_EINVAL, "rsg_autotune: need nst > 0 and reps > 0");
-    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ld, dtype) - 256, RSG_ENOMEM, "rsg_autotune: workspace too small");
+    RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ldp, dtype) - 256, RSG_ENOMEM, "rsg_autotune: workspace too small");
     hipStream_t s = (hipStream_t)stream;
     const int cmp = tile_compute(dtype);
     const int wt = cmp;  // work-buffer type: complex64 for the mixed path
     Carve c(ws, ws_bytes);
-    void *w1 = c.take(batch_bytes(*H->g, ld, cmp ? 8 : 16));
+    void *w1 = c.take(batch_bytes(nst, ldp, cmp ? 8 : 16));
     if (!c.ok) {
         set_error("rsg_autotune: workspace carve failed");
         return RSG_ENOMEM;
@@ -861,7 +862,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
                 a.compute = cmp;
                 a.mode = 1;
                 a.nst = nst;
-                a.ld = ld;
+                a.ldp = ldp;
                 a.cim = -1e-3;
                 double tmin = 1e300;
                 for (int r = 0; r <= reps; ++r) {  // first launch warms up

@@ -4,7 +4,7 @@
 // (section "Parallelization, optimizations and graphics processing units");
 // here the group extends across systems: every stage of a Taylor(4) step of
 // every system runs as one persistent stencil launch over a cost-sorted list
-// of (system, tile, z-range, orbital batch) items, preceded by one projector
+// of (system, tile, z-range, orbital) items, preceded by one projector
 // gather launch and followed by one scatter launch per colour, all systems at
 // once.  A step sequence can be captured once into a HIP graph and replayed.
 // Each output point is computed by the same arithmetic as the single-system
@@ -22,7 +22,7 @@ namespace rsg {
 struct Batch {
     std::vector<rsg_system_desc> sys;
     std::vector<void *> w1, w2, D;  // per-system work buffers inside the caller's workspace
-    TileShape tile{1, 16, 16, 0};
+    TileShape tile{1, 32, 8, 0};
     int grid_first = 0, grid_rest = 0;  // persistent workgroups per stencil launch
     KParams *sp[4] = {nullptr, nullptr, nullptr, nullptr};  // device, per stage, one per system
     KbSys *kb[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -60,7 +60,7 @@ size_t rnd(size_t n) { return (n + 255) & ~(size_t)255; }
 
 size_t sys_bytes(const rsg_system_desc &d) {
     const Ham &H = *d.ham;
-    return 2 * rnd((size_t)H.g->np * (size_t)d.ld * 16) + rnd(kb_workspace_bytes(H, d.nst));
+    return 2 * rnd((size_t)d.nst * (size_t)d.ldp * 16) + rnd(kb_workspace_bytes(H, d.nst));
 }
 
 template <class T>
@@ -101,25 +101,24 @@ int build_tables(Batch &b, hipStream_t s) {
         sh.ZC = sh.ZC > 0 ? sh.ZC : H.g->n[2];
         const TilePlan *plan = H.g->plan(sh, s, &err);
         if (!plan) return err;
-        // copy the plan's items back to the host to expand them per batch
+        // copy the plan's items back to the host to expand them per orbital
         std::vector<int4> pit(plan->nitems);
         if (plan->nitems)
             RSG_CHECK_HIP(hipMemcpy(pit.data(), plan->items, sizeof(int4) * plan->nitems, hipMemcpyDeviceToHost));
-        const int nob = (int)((d.nst + sh.B - 1) / sh.B);
         for (const int4 &t : pit)
-            for (int ob = 0; ob < nob; ++ob) items.push_back(BatchItem{t, (int32_t)i, ob});
+            for (int n = 0; n < (int)d.nst; ++n) items.push_back(BatchItem{t, (int32_t)i, n});
         for (int k = 0; k < 4; ++k) {
             StageArgs a;
             stage_buffers(b, i, k, &a.in, &a.base, &a.out);
             a.mode = 1;
             a.nst = d.nst;
-            a.ld = d.ld;
+            a.ldp = d.ldp;
             a.first = k == 0;
             sp[k].push_back(make_params(H, a, sh, plan));
             KbSys ks;
             ks.in = (const double *)a.in;
             ks.out = (double *)a.out;
-            ks.ldr = 2 * d.ld;
+            ks.ldo = 2 * d.ldp;
             ks.ncols = 2 * d.nst;
             ks.atoms = H.gather_items;
             ks.idx = H.kb_idx;
@@ -206,9 +205,11 @@ static int check_systems(int32_t nsys, const rsg_system_desc *sys) {
     for (int32_t i = 0; i < nsys; ++i) {
         const rsg_system_desc &d = sys[i];
         RSG_REQUIRE(d.ham, RSG_EINVAL, "batch: system %d has no Hamiltonian", i);
-        RSG_REQUIRE(d.nst >= 1 && d.ld >= d.nst, RSG_ESHAPE, "batch: system %d needs 1 <= nst <= ld", i);
+        RSG_REQUIRE(d.nst >= 1 && d.ldp >= 1 && d.ldp >= d.ham->g->np, RSG_ESHAPE,
+                    "batch: system %d needs nst >= 1 and ldp >= np", i);
         RSG_REQUIRE(d.psi && ((uintptr_t)d.psi & 15) == 0, RSG_EINVAL, "batch: system %d orbital pointer", i);
         RSG_REQUIRE(d.ham->axis < 0, RSG_EUNSUPPORTED, "batch: system %d has a dipole field (not batched)", i);
+        RSG_REQUIRE(d.ham->g->np < ((int64_t)1 << 27), RSG_EUNSUPPORTED, "batch: system %d has 2^27 points or more", i);
     }
     return RSG_OK;
 }
@@ -217,7 +218,7 @@ extern "C" size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc 
     if (nsys < 1 || !sys) return 0;
     size_t n = 256;
     for (int32_t i = 0; i < nsys; ++i) {
-        if (!sys[i].ham || sys[i].ld < 1 || sys[i].nst < 0) return 0;
+        if (!sys[i].ham || sys[i].ldp < 1 || sys[i].nst < 0) return 0;
         n += sys_bytes(sys[i]);
     }
     return n;
@@ -236,15 +237,12 @@ extern "C" int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *
         auto *b = new rsg_batch_s();
         b->sys.assign(sys, sys + nsys);
         char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        int64_t maxnst = 0;
         for (int32_t i = 0; i < nsys; ++i) {
-            const Ham &H = *sys[i].ham;
-            const size_t bb = rnd((size_t)H.g->np * (size_t)sys[i].ld * 16);
+            const size_t bb = rnd((size_t)sys[i].nst * (size_t)sys[i].ldp * 16);
             b->w1.push_back(base);
             b->w2.push_back(base + bb);
             b->D.push_back(base + 2 * bb);
             base += sys_bytes(sys[i]);
-            maxnst = std::max(maxnst, sys[i].nst);
         }
         // zero the work buffers once, so timing runs never read garbage
         const hipError_t e = hipMemsetAsync(ws, 0, ws_bytes, s);
@@ -253,8 +251,8 @@ extern "C" int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *
             delete b;
             return RSG_EHIP;
         }
-        b->tile = default_shape(*sys[0].ham->g, maxnst >= 4 ? 4 : maxnst, 0);
-        b->tile.ZC = 0;
+        b->tile = TileShape{1, 32, 8, 0};
+        b->tile.PD = 2;
         const int r = build_tables(*b, s);
         if (r) {
             delete b;

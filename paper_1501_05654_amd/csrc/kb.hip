@@ -11,7 +11,9 @@
 //   gather : D^T[cols x 4] = psi^T[cols x |S_a|] * P[|S_a| x 4]
 //   scatter: Y[|S_a| x cols] += P[|S_a| x 4] * F[4 x cols],  F = c E D
 //
-// where cols are the 2*nst real columns of the interleaved complex batch.
+// where cols are the 2*nst real columns (re and im of each orbital).  The
+// batch is orbital-major: real column col of point r sits at
+// (col / 2) * ldo + 2 r + col % 2 (in reals), ldo = 2 ldp.
 // Both run on v_mfma_{f64,f32}_16x16x4: the gather puts 16 columns on M,
 // 4 support points on K and the 4 projectors on N (zero-padded to 16); the
 // scatter puts 16 support points on M, the 4 projectors on K and 16
@@ -61,7 +63,7 @@ __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
 constexpr int GW = 16;  // waves per gather workgroup
 constexpr int GU = 4;   // groups in flight per wave
 template <class Tin, class Tc>
-__device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t ldr, int64_t ncols,
+__device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t ldo, int64_t ncols,
                                             const int4 at, int a, int ct,
                                             const int32_t *__restrict__ idx,
                                             const Tc *__restrict__ p, Tc h3, Tc *__restrict__ D,
@@ -71,6 +73,7 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
     const int lo = l & 15, hi = l >> 4;
     const int64_t col = (int64_t)ct * 16 + lo;
     const bool cok = col < ncols;
+    const Tin *inc = in + (cok ? (col >> 1) * ldo + (col & 1) : 0);
     V acc = {0, 0, 0, 0};
     const int ngroups = at.y >> 2;
     int gq = w;
@@ -85,13 +88,13 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
             bv[u] = lo < 4 ? p[e[u] * 4 + lo] : (Tc)0;
         }
 #pragma unroll
-        for (int u = 0; u < GU; ++u) av[u] = cok ? (Tc)in[(int64_t)ix[u] * ldr + col] : (Tc)0;
+        for (int u = 0; u < GU; ++u) av[u] = cok ? (Tc)inc[2 * (int64_t)ix[u]] : (Tc)0;
 #pragma unroll
         for (int u = 0; u < GU; ++u) acc = mfma16(av[u], bv[u], acc);
     }
     for (; gq < ngroups; gq += GW) {
         const int64_t e = (int64_t)at.x + 4 * gq + hi;
-        const Tc av = cok ? (Tc)in[(int64_t)idx[e] * ldr + col] : (Tc)0;
+        const Tc av = cok ? (Tc)inc[2 * (int64_t)idx[e]] : (Tc)0;
         const Tc bv = lo < 4 ? p[e * 4 + lo] : (Tc)0;
         acc = mfma16(av, bv, acc);
     }
@@ -112,18 +115,18 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
 
 // blockIdx.x = atom, blockIdx.y = tile of 16 real columns.
 template <class Tin, class Tc>
-__global__ void __launch_bounds__(GW * 64) k_kb_gather(const Tin *__restrict__ in, int64_t ldr,
+__global__ void __launch_bounds__(GW * 64) k_kb_gather(const Tin *__restrict__ in, int64_t ldo,
                                                        int64_t ncols, const int4 *__restrict__ atoms,
                                                        const int32_t *__restrict__ idx,
                                                        const Tc *__restrict__ p, Tc h3,
                                                        Tc *__restrict__ D) {
     __shared__ Tc red[GW][64][4];
-    gather_tile<Tin, Tc>(in, ldr, ncols, atoms[blockIdx.x], blockIdx.x, blockIdx.y, idx, p, h3, D, red);
+    gather_tile<Tin, Tc>(in, ldo, ncols, atoms[blockIdx.x], blockIdx.x, blockIdx.y, idx, p, h3, D, red);
 }
 
 // Scatter for one (16-entry support tile, 16-column tile), one wave.
 template <class Tout, class Tc>
-__device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldr, int64_t ncols,
+__device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldo, int64_t ncols,
                                              const int2 itm, const int4 at, int ct,
                                              const int32_t *__restrict__ idx,
                                              const Tc *__restrict__ p,
@@ -149,7 +152,7 @@ __device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldr
     for (int r = 0; r < 4; ++r) {
         const int64_t e = (int64_t)itm.y + acc_row(Tc(0), hi, r);
         if (e < end && col < ncols) {
-            Tout *dst = out + (int64_t)idx[e] * ldr + col;
+            Tout *dst = out + (col >> 1) * ldo + 2 * (int64_t)idx[e] + (col & 1);
             *dst = (Tout)((double)*dst + (double)acc[r]);
         }
     }
@@ -157,7 +160,7 @@ __device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldr
 
 // One wave per (16-entry support tile, 16-column tile).
 template <class Tout, class Tc>
-__global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int64_t ldr, int64_t ncols,
+__global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int64_t ldo, int64_t ncols,
                                                     const int2 *__restrict__ items, int32_t nitems,
                                                     const int4 *__restrict__ atoms,
                                                     const int32_t *__restrict__ idx,
@@ -168,7 +171,7 @@ __global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int6
     const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (item >= nitems) return;
     const int2 itm = items[item];  // {atom, first entry}
-    scatter_tile<Tout, Tc>(out, ldr, ncols, itm, atoms[itm.x], blockIdx.y, idx, p, E, D, cre, cim);
+    scatter_tile<Tout, Tc>(out, ldo, ncols, itm, atoms[itm.x], blockIdx.y, idx, p, E, D, cre, cim);
 }
 
 // Batched forms over many systems (FP64): item {system, atom, column tile}
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(GW * 64) k_kb_gather_batch(const KbSys *__rest
     __shared__ double red[GW][64][4];
     const int4 it = items[blockIdx.x];
     const KbSys &s = sys[it.x];
-    gather_tile<double, double>(s.in, s.ldr, s.ncols, s.atoms[it.y], it.y, it.z, s.idx, s.p, s.h3, s.D,
+    gather_tile<double, double>(s.in, s.ldo, s.ncols, s.atoms[it.y], it.y, it.z, s.idx, s.p, s.h3, s.D,
                                 red);
 }
 
@@ -189,7 +192,7 @@ __global__ void __launch_bounds__(256) k_kb_scatter_batch(const KbSys *__restric
     if (item >= nitems) return;
     const int4 it = items[item];
     const KbSys &s = sys[it.x];
-    scatter_tile<double, double>(s.out, s.ldr, s.ncols, make_int2(it.y, it.z), s.atoms[it.y], it.w, s.idx,
+    scatter_tile<double, double>(s.out, s.ldo, s.ncols, make_int2(it.y, it.z), s.atoms[it.y], it.w, s.idx,
                                  s.p, s.E, s.D, cre, cim);
 }
 
@@ -199,7 +202,7 @@ size_t kb_workspace_bytes(const Ham &H, int64_t nst) {
     return (size_t)H.natoms * 4 * 2 * (size_t)nst * sizeof(double);
 }
 
-int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ld,
+int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ldp,
                      void *D, hipStream_t s) {
     if (H.natoms == 0 || nst == 0) return RSG_OK;
     const int64_t ncols = 2 * nst;
@@ -207,15 +210,15 @@ int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_
     const double h3 = H.g->h * H.g->h * H.g->h;
     if (compute == 0) {
         if (in_t != 0) return RSG_EUNSUPPORTED;
-        k_kb_gather<double, double><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ld, ncols,
+        k_kb_gather<double, double><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ldp, ncols,
                                                         H.gather_items, H.kb_idx, H.kb_p, h3,
                                                         (double *)D);
     } else if (in_t == 0) {
-        k_kb_gather<double, float><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ld, ncols,
+        k_kb_gather<double, float><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ldp, ncols,
                                                        H.gather_items, H.kb_idx, H.kb_p32,
                                                        (float)h3, (float *)D);
     } else {
-        k_kb_gather<float, float><<<grid, GW * 64, 0, s>>>((const float *)in, 2 * ld, ncols,
+        k_kb_gather<float, float><<<grid, GW * 64, 0, s>>>((const float *)in, 2 * ldp, ncols,
                                                       H.gather_items, H.kb_idx, H.kb_p32,
                                                       (float)h3, (float *)D);
     }
@@ -223,7 +226,7 @@ int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_
     return RSG_OK;
 }
 
-int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ld,
+int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ldp,
                       const void *D, double cre, double cim, hipStream_t s) {
     if (H.natoms == 0 || nst == 0) return RSG_OK;
     const int64_t ncols = 2 * nst;
@@ -234,15 +237,15 @@ int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t n
         if (compute == 0) {
             if (out_t != 0) return RSG_EUNSUPPORTED;
             k_kb_scatter<double, double><<<grid, 256, 0, s>>>(
-                (double *)out, 2 * ld, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
+                (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
                 H.kb_p, H.kb_E, (const double *)D, cre, cim);
         } else if (out_t == 0) {
             k_kb_scatter<double, float><<<grid, 256, 0, s>>>(
-                (double *)out, 2 * ld, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
+                (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
                 H.kb_p32, H.kb_E, (const float *)D, cre, cim);
         } else {
             k_kb_scatter<float, float><<<grid, 256, 0, s>>>(
-                (float *)out, 2 * ld, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
+                (float *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
                 H.kb_p32, H.kb_E, (const float *)D, cre, cim);
         }
         RSG_CHECK_HIP(hipGetLastError());

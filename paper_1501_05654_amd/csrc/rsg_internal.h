@@ -52,18 +52,18 @@ int guarded(F &&f) {
 
 // ----------------------------------------------------------- launch plan --
 
-// Tile shape of the z-marching stencil: B orbitals x TX x TY points per
-// workgroup, marching along z in chunks of at most ZC planes.
-// PD is the software-pipeline depth of the FP64 kernel (planes prefetched
-// ahead, 1..3).  PT > 0 groups tiles into PT x PT patches that share one
-// z-range and are launched consecutively, so the workgroups of a patch march
-// in step and read each other's halos from L2.  The launch plan depends on
-// (TX, TY, ZC, PT).
+// Tile shape of the z-marching stencil: B orbitals (1 in this build) x TX x
+// TY columns per workgroup, marching along z in chunks of at most ZC planes.
+// PD is the software-pipeline depth (planes in flight: 1..2; 0 selects the
+// lean march).  PT = 1 launches the tiles of a z-chunk in Morton order;
+// PT > 1 groups tiles into PT x PT patches that share one z-range and are
+// launched consecutively.  BO is the block order (0: orbital fastest,
+// 1: orbital slowest).  The launch plan depends on (TX, TY, ZC, PT).
 struct TileShape {
     int B, TX, TY, ZC;
     int PD = 1;
     int PT = 0;
-    int BO = 0;  // block order: 0 = orbital batch fastest, 1 = batch slowest
+    int BO = 0;  // block order: 0 = orbital fastest, 1 = orbital slowest
     bool operator<(const TileShape &o) const {
         if (B != o.B) return B < o.B;
         if (TX != o.TX) return TX < o.TX;
@@ -137,13 +137,15 @@ template <> struct cpx<float> { using type = float2; };
 // Stencil stage: out = [base +] c * (kin Lap + V + field x_axis)(in).
 // mode 0: out = H in (no base, c = 1).  mode 1: out = base + c H in.
 // in_t / out_t: 0 = complex128, 1 = complex64.  compute: 0 = FP64, 1 = FP32.
+// All operands are orbital-major with ldp complex values between orbitals;
+// base is always complex128.
 struct StageArgs {
     const void *in = nullptr;
     const void *base = nullptr;
     void *out = nullptr;
     int in_t = 0, out_t = 0, compute = 0, mode = 0;
     bool first = false;  // base == in (first Horner stage)
-    int64_t nst = 0, ld = 0;
+    int64_t nst = 0, ldp = 0;
     double field = 0;
     const double *field_dev = nullptr;
     double cre = 1, cim = 0;
@@ -159,20 +161,19 @@ struct KParams {
     const double *zeros;
     const void *V;
     const double *field_dev;
-    int64_t nst, ld;
+    int64_t nst, ldp, np;
     double kin_h2;
     double field;
     double h;
     double off[3];
     double cre, cim;
-    int32_t nob;
     int32_t nitems;
     int32_t batch_slowest;
     int32_t ny, nz;
     int32_t axis;
 };
 // One work item of the batched stencil: tile (tx, ty, z0, z1) of system sys,
-// orbital batch ob.
+// orbital ob.
 struct BatchItem {
     int4 tile;
     int32_t sys, ob;
@@ -187,20 +188,21 @@ int stencil_batch_grid(const TileShape &shape, bool first);
 TileShape default_shape(const Grid &g, int64_t nst, int compute);
 std::vector<TileShape> tile_candidates(int compute);
 
-// KB projectors.  gather: D[a][i][col] = h^3 sum_e p[e][i] in[idx[e]][col]
-// (col over the 2*nst real columns); scatter: out[idx[e]][col] +=
-// sum_i p[e][i] (c E_i D[a][i][.])[col].
-int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ld,
+// KB projectors.  gather: D[a][i][col] = h^3 sum_e p[e][i] in(idx[e], col)
+// (col over the 2*nst real columns: re and im of each orbital); scatter:
+// out(idx[e], col) += sum_i p[e][i] (c E_i D[a][i][.])[col].  Operands are
+// orbital-major with ldp complex values between orbitals.
+int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ldp,
                      void *D, hipStream_t s);
-int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ld,
+int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ldp,
                       const void *D, double cre, double cim, hipStream_t s);
 size_t kb_workspace_bytes(const Ham &H, int64_t nst);
 
 // Per-system projector parameters of one stage of the batched path (FP64).
 struct KbSys {
-    const double *in;   // gather input (interleaved complex as doubles)
+    const double *in;   // gather input (complex as pairs of doubles)
     double *out;        // scatter output
-    int64_t ldr, ncols; // 2*ld, 2*nst
+    int64_t ldo, ncols; // 2*ldp (doubles between orbitals), 2*nst
     const int4 *atoms;  // {offset, padded length, length, atom}
     const int32_t *idx;
     const double *p;
@@ -214,18 +216,18 @@ int launch_kb_scatter_batch(const KbSys *sys, const int4 *items, int32_t nitems,
 
 // Reductions: partial sums per block then a fixed-order final pass.
 // kind 0: <a|b> (complex out [2*nst]); 1: |a|^2 (out [nst]);
-// 2: x_axis |a|^2 (out [nst]); all scaled by h^3.
+// 2: x_axis |a|^2 (out [nst]); all scaled by h^3.  Operands orbital-major.
 size_t reduce_workspace_bytes(const Grid &g, int64_t nst);
 int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const double2 *b,
-                  int64_t nst, int64_t ld, double *out, void *ws, size_t ws_bytes, hipStream_t s);
+                  int64_t nst, int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s);
 
 // Pointwise helpers.
-int launch_axpby_list(const Grid &g, int64_t nst, int64_t ld, int nterms, const double2 *const *src,
+int launch_axpby_list(const Grid &g, int64_t nst, int64_t ldp, int nterms, const double2 *const *src,
                       const double2 *coef, double2 *dst, hipStream_t s);
 int launch_mul_axis(const Grid &g, int axis, const double2 *src, double2 *dst, int64_t nst,
-                    int64_t ld, hipStream_t s);
+                    int64_t ldp, hipStream_t s);
 int launch_cross_dots(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
-                      const double2 *pair_coef, int64_t nst, int64_t ld, double *out, void *ws,
+                      const double2 *pair_coef, int64_t nst, int64_t ldp, double *out, void *ws,
                       size_t ws_bytes, hipStream_t s);
 int launch_accumulate(const double *src, double *dst, hipStream_t s);
 

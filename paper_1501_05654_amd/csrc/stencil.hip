@@ -10,21 +10,25 @@
 // order is this library's choice.  The separable projectors are added by the
 // projector kernels after this one.
 //
-// Data layout: an orbital batch is [np][ld] complex, orbital index fastest,
-// points in compact order (z-major, y, x).  Mapping onto CDNA4:
-//   - one workgroup owns a TX x TY tile of (x, y) columns and B orbitals, and
+// Data layout: an orbital batch is orbital-major, [nst][ldp] complex:
+// orbital n holds its values at n*ldp + i for compact point i (z-major, y,
+// x), so every orbital is one contiguous field and every grid row of it is
+// contiguous.  Mapping onto CDNA4:
+//   - one workgroup owns a TX x TY tile of (x, y) columns of one orbital and
 //     marches along z over the tile's z-extent (or a chunk of it);
-//   - each thread keeps its own column's 9 planes (z-4..z+4) in registers,
-//     so every orbital value is read from memory once per workgroup for the
-//     z taps;
+//   - a thread owns one column and keeps its complex value on the planes
+//     z-4..z+4 in registers (z taps), plus the planes in flight;
 //   - the current plane, with a 4-point x/y halo, is staged in LDS for the
-//     x and y taps; halo values come from neighbouring tiles through L2;
-//   - lanes run over orbitals first, so a wave reads B*16 contiguous bytes
-//     per point, and consecutive points of a row are contiguous;
-//   - the next plane and the next halo are fetched into registers before the
-//     current plane is computed (one plane of prefetch);
+//     x and y taps; the halo comes from the neighbouring tiles through L2;
+//   - x runs fastest over the threads, so a wave's loads are runs of TX
+//     consecutive 16-byte values;
+//   - loads of later planes are issued before the current plane is computed
+//     (software pipeline, depth PD);
 //   - workgroup ids are remapped so that each XCD (own L2) receives a
-//     contiguous range of tiles.
+//     contiguous range of the launch order.
+// A tile per workgroup covers many more points than a point-major layout
+// with the orbitals of a point side by side would allow in the same
+// registers, so far fewer halo values are read per output.
 #include "rsg_internal.h"
 
 #include <algorithm>
@@ -53,188 +57,25 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + local;
 }
 
-// Block order.  Batch fastest: the orbital batches of a tile run together,
-// so the whole ld-orbital row of each point is read at about the same time
-// (DRAM row locality).  Batch slowest: each XCD sweeps a band of tiles of one
-// batch, so neighbouring tiles can find each other's halos in L2.
-__device__ __forceinline__ void block_item(const KParams &a, int blk, int *ob, int *item) {
+// Block order.  Orbital slowest (BO = 1): each XCD sweeps the tiles of one
+// orbital at a time, so neighbouring tiles march together and find each
+// other's halos in L2.  Orbital fastest (BO = 0): the orbitals of one tile
+// march together and share V and the row table in L2.
+__device__ __forceinline__ void block_item(const KParams &a, int blk, int *n, int *item) {
     if (a.batch_slowest) {
-        *ob = blk / a.nitems;
-        *item = blk - *ob * a.nitems;
+        *n = blk / a.nitems;
+        *item = blk - *n * a.nitems;
     } else {
-        *item = blk / a.nob;
-        *ob = blk - *item * a.nob;
+        *item = blk / (int)a.nst;
+        *n = blk - *item * (int)a.nst;
     }
 }
 
-__device__ __forceinline__ int64_t point_index(const KParams &a, int x, int y, int z) {
-    if (y < 0 || y >= a.ny || z < 0 || z >= a.nz) return -1;
-    const int2 r = a.rows[z * a.ny + y];
-    const int x0 = r.y & 0xffff, x1 = (r.y >> 16) & 0xffff;
-    if (x < x0 || x >= x1) return -1;
-    return (int64_t)r.x + x;
-}
-
-__device__ __forceinline__ void store_c(double2 *p, double r, double i) { *p = make_double2(r, i); }
-__device__ __forceinline__ void store_c(float2 *p, double r, double i) {
-    *p = make_float2((float)r, (float)i);
-}
-__device__ __forceinline__ void store_c(double2 *p, float r, float i) {
-    *p = make_double2((double)r, (double)i);
-}
-__device__ __forceinline__ void store_c(float2 *p, float r, float i) { *p = make_float2(r, i); }
-
-template <class Tin, class Tc>
-__device__ __forceinline__ typename CT<Tc>::c2 fetch(const Tin *in, int64_t idx, int64_t ld,
-                                                     int64_t s, bool ok) {
-    using C2 = typename CT<Tc>::c2;
-    if (!ok || idx < 0) return C2{(Tc)0, (Tc)0};
-    const Tin v = in[idx * ld + s];
-    return C2{(Tc)v.x, (Tc)v.y};
-}
-
-// Complex-lane variant (one complex value per lane), used by the mixed
-// path: FP32 arithmetic on complex64 or complex128 input.
-template <int B, int TX, int TY, class Tin, class Tc, int MODE, class Tout>
-__global__ void __launch_bounds__(B * TX * TY) k_stencil_c(KParams a) {
-    using C2 = typename CT<Tc>::c2;
-    constexpr int NT = B * TX * TY;
-    constexpr int LX = TX + 8, LY = TY + 8;
-    constexpr int NHP = 8 * TX + 8 * TY;  // halo points of one plane
-    constexpr int NH = NHP * B;
-    constexpr int HPT = (NH + NT - 1) / NT;
-    __shared__ C2 tile[LY * LX * B];
-
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // block order: see k_stencil_r
-    int ob, item;
-    block_item(a, blk, &ob, &item);
-    const int4 it = a.items[item];
-    const int t = threadIdx.x;
-    const int o = t % B, lx = (t / B) % TX, ly = t / (B * TX);
-    const int x = it.x * TX + lx, y = it.y * TY + ly;
-    const int64_t s = (int64_t)ob * B + o;
-    const bool sok = s < a.nst;
-    const Tin *in = static_cast<const Tin *>(a.in);
-
-    // Halo assignment (fixed for the whole march): value j = t + k*NT is
-    // orbital j % B of halo point j / B.  Points 0..8TX-1 are the y halo rows
-    // (x fastest), the rest the x halo columns (4 left, 4 right per row).
-    int hl[HPT], hx[HPT], hy[HPT];
-    int64_t hs[HPT];
-    bool hok[HPT];
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) {
-        const int j = t + k * NT;
-        const int oh = j % B, hp = j / B;
-        int lxl, lyl;
-        if (hp < 8 * TX) {
-            const int yh = hp / TX;
-            lxl = hp % TX + 4;
-            lyl = yh < 4 ? yh : TY + yh;
-        } else {
-            const int q = hp - 8 * TX;
-            const int c = q % 8;
-            lyl = q / 8 + 4;
-            lxl = c < 4 ? c : TX + c;
-        }
-        hl[k] = (lyl * LX + lxl) * B + oh;
-        hx[k] = it.x * TX + lxl - 4;
-        hy[k] = it.y * TY + lyl - 4;
-        hs[k] = (int64_t)ob * B + oh;
-        hok[k] = j < NH && hs[k] < a.nst;
-    }
-
-    const int z0 = it.z, z1 = it.w;
-    C2 q[9];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) q[k] = fetch<Tin, Tc>(in, point_index(a, x, y, z0 - 4 + k), a.ld, s, sok);
-    C2 nxt = fetch<Tin, Tc>(in, point_index(a, x, y, z0 + 4), a.ld, s, sok);
-    C2 hv[HPT];
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) hv[k] = fetch<Tin, Tc>(in, point_index(a, hx[k], hy[k], z0), a.ld, hs[k], hok[k]);
-
-    const double E = a.field_dev ? *a.field_dev : a.field;
-    const Tc kin_h2 = (Tc)a.kin_h2;
-    const Tc *Vp = static_cast<const Tc *>(a.V);
-    const int own_l = ((ly + 4) * LX + lx + 4) * B + o;
-
-    for (int z = z0; z < z1; ++z) {
-        q[8] = nxt;
-        tile[own_l] = q[4];
-#pragma unroll
-        for (int k = 0; k < HPT; ++k)
-            if (t + k * NT < NH) tile[hl[k]] = hv[k];
-        __syncthreads();
-        if (z + 1 < z1) {
-            nxt = fetch<Tin, Tc>(in, point_index(a, x, y, z + 5), a.ld, s, sok);
-#pragma unroll
-            for (int k = 0; k < HPT; ++k)
-                hv[k] = fetch<Tin, Tc>(in, point_index(a, hx[k], hy[k], z + 1), a.ld, hs[k], hok[k]);
-        }
-        const int64_t idx = point_index(a, x, y, z);
-        if (idx >= 0 && sok) {
-            const C2 cc = q[4];
-            const C2 xm1 = tile[own_l - B], xp1 = tile[own_l + B];
-            const C2 xm2 = tile[own_l - 2 * B], xp2 = tile[own_l + 2 * B];
-            const C2 xm3 = tile[own_l - 3 * B], xp3 = tile[own_l + 3 * B];
-            const C2 xm4 = tile[own_l - 4 * B], xp4 = tile[own_l + 4 * B];
-            constexpr int YS = LX * B;
-            const C2 ym1 = tile[own_l - YS], yp1 = tile[own_l + YS];
-            const C2 ym2 = tile[own_l - 2 * YS], yp2 = tile[own_l + 2 * YS];
-            const C2 ym3 = tile[own_l - 3 * YS], yp3 = tile[own_l + 3 * YS];
-            const C2 ym4 = tile[own_l - 4 * YS], yp4 = tile[own_l + 4 * YS];
-            C2 lap;
-            lap.x = (Tc)3 * FD<Tc>::c0 * cc.x +
-                    FD<Tc>::c1 * ((xm1.x + xp1.x) + (ym1.x + yp1.x) + (q[3].x + q[5].x)) +
-                    FD<Tc>::c2 * ((xm2.x + xp2.x) + (ym2.x + yp2.x) + (q[2].x + q[6].x)) +
-                    FD<Tc>::c3 * ((xm3.x + xp3.x) + (ym3.x + yp3.x) + (q[1].x + q[7].x)) +
-                    FD<Tc>::c4 * ((xm4.x + xp4.x) + (ym4.x + yp4.x) + (q[0].x + q[8].x));
-            lap.y = (Tc)3 * FD<Tc>::c0 * cc.y +
-                    FD<Tc>::c1 * ((xm1.y + xp1.y) + (ym1.y + yp1.y) + (q[3].y + q[5].y)) +
-                    FD<Tc>::c2 * ((xm2.y + xp2.y) + (ym2.y + yp2.y) + (q[2].y + q[6].y)) +
-                    FD<Tc>::c3 * ((xm3.y + xp3.y) + (ym3.y + yp3.y) + (q[1].y + q[7].y)) +
-                    FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (q[0].y + q[8].y));
-            Tc vloc = Vp ? Vp[idx] : (Tc)0;
-            if (a.axis >= 0) {
-                const int c = a.axis == 0 ? x : (a.axis == 1 ? y : z);
-                vloc += (Tc)(E * (a.h * ((double)c - a.off[a.axis])));
-            }
-            const Tc hr = kin_h2 * lap.x + vloc * cc.x;
-            const Tc hi = kin_h2 * lap.y + vloc * cc.y;
-            Tout *out = static_cast<Tout *>(a.out);
-            if (MODE == 0) {
-                store_c(out + idx * a.ld + s, hr, hi);
-            } else {
-                const double2 bb = static_cast<const double2 *>(a.base)[idx * a.ld + s];
-                const double r = bb.x + (a.cre * (double)hr - a.cim * (double)hi);
-                const double i = bb.y + (a.cre * (double)hi + a.cim * (double)hr);
-                store_c(out + idx * a.ld + s, r, i);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 8; ++k) q[k] = q[k + 1];
-    }
-}
-
-// Real-lane variant for FP64: lanes run over the 2*nst real columns of the
-// interleaved batch (re and im of an orbital in adjacent lanes), so a thread
-// carries one double per plane instead of a complex pair; the Horner
-// epilogue gets the partner component with one xor-1 lane shuffle.
-//
-// Software pipeline over z, depth D: at step z (output plane z) a thread
-//   - issues the row-table reads for the loads of step z+1,
-//   - issues the data loads of plane z+4+D (own column, entering the
-//     register queue D steps later), of the halo of plane z+D, and the V and
-//     base values of plane z+D, all from row entries read one step earlier,
-//   - computes plane z from data that arrived during earlier steps.
-// No load is waited on in the step that issues it, and no data load waits on
-// a row-table read of the same step.  FIRST: base == in, whose value at the
-// point is the centre tap.
 // Branch-free row lookup: an out-of-box row reads the empty sentinel entry
 // that follows the table.  Loads are never masked after they return (the
 // compiler would place the select where the load is issued and wait there);
-// a masked-off lane loads from a location that holds the neutral value.
+// a masked-off lane issues its load at an out-of-range offset, which the
+// buffer hardware answers with zero.
 __device__ __forceinline__ int2 row_of(const KParams &a, int y, int z) {
     const bool v = y >= 0 && y < a.ny && z >= 0 && z < a.nz;
     return a.rows[v ? z * a.ny + y : a.ny * a.nz];
@@ -244,114 +85,195 @@ __device__ __forceinline__ int idx_in_row(int2 r, int x) {
     return (x >= x0 && x < x1) ? r.x + x : -1;
 }
 
+// Buffer loads and stores (CDNA): a per-workgroup resource (base address,
+// size in bytes) in scalar registers and a 32-bit byte offset per lane.  An
+// offset at or beyond the size reads zero and drops a store, in hardware, so
+// masked-off lanes need no select and no second address register.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v2i_t __attribute__((ext_vector_type(2)));
+constexpr unsigned OOB = 0x80000000u;    // byte offset beyond every buffer used here
+constexpr int RSRC_WORD3 = 0x00020000;   // resource format word of the gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, RSRC_WORD3);
+}
+template <class T>
+__device__ __forceinline__ unsigned boff(int idx) {
+    return idx >= 0 ? (unsigned)idx * (unsigned)sizeof(T) : OOB;
+}
+
+template <class T> struct BL;
+template <> struct BL<double2> {
+    static __device__ __forceinline__ double2 ld(__amdgpu_buffer_rsrc_t r, unsigned o) {
+        return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)o, 0, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned o, double2 v) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i_t, v), r, (int)o, 0, 0);
+    }
+};
+template <> struct BL<float2> {
+    static __device__ __forceinline__ float2 ld(__amdgpu_buffer_rsrc_t r, unsigned o) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)o, 0, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned o, float2 v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i_t, v), r, (int)o, 0, 0);
+    }
+};
+template <> struct BL<double> {
+    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned o) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)o, 0, 0));
+    }
+};
+template <> struct BL<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned o) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)o, 0, 0));
+    }
+};
+
+template <class Tc, class Tin>
+__device__ __forceinline__ typename CT<Tc>::c2 load_c(__amdgpu_buffer_rsrc_t r, unsigned o) {
+    const Tin v = BL<Tin>::ld(r, o);
+    return typename CT<Tc>::c2{(Tc)v.x, (Tc)v.y};
+}
+
+__device__ __forceinline__ void store_c(__amdgpu_buffer_rsrc_t r, unsigned o, double2 *, double re, double im) {
+    BL<double2>::st(r, o, make_double2(re, im));
+}
+__device__ __forceinline__ void store_c(__amdgpu_buffer_rsrc_t r, unsigned o, float2 *, double re, double im) {
+    BL<float2>::st(r, o, make_float2((float)re, (float)im));
+}
+
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
 
-// One work item of the FP64 kernel: tile it = (tx, ty, z0, z1), orbital
-// batch ob, with the shared-memory plane `tile` of the calling workgroup.
-template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
-__device__ __forceinline__ void march_r(const KParams &a, const int4 it, const int ob, double *tile) {
-    constexpr int NT = RB * TX * TY;
-    constexpr int LX = TX + 8;
-    constexpr int NHP = 8 * TX + 8 * TY;
-    constexpr int NH = NHP * RB;
-    constexpr int HPT = (NH + NT - 1) / NT;
-    constexpr int YS = LX * RB;
-    // Register rings, all indexed by compile-time constants after unrolling:
-    //   col[Q]  own-column values of planes z-4 .. z+4+D (loads land in place),
-    //   oid[Q]  own compact index of the same planes,
-    //   hal[D]: halo of planes z .. z+D-1,
-    //   vr[D+1], br[D+1]: V and base, loaded into the slot consumed last step
-    //     so that a new load never targets a register still being read,
-    //   rfr[2], rhl[2]: row entries read one step before the loads using them.
-    constexpr int Q = D == 1 ? 10 : 12;  // >= 9 + D, and keeps the unroll period at 10 or 12
-    constexpr int VD = D + 1;
-    constexpr int P = clcm(clcm(clcm(Q, D), VD), 2);  // unroll period of the z loop
-    const int t = threadIdx.x;
-    const int c = t % RB, lx = (t / RB) % TX, ly = t / (RB * TX);
-    const int x = it.x * TX + lx, y = it.y * TY + ly;
-    const int ncols = (int)(2 * a.nst);
-    const int col = ob * RB + c;
-    const bool cok = col < ncols;
-    const int64_t ldr = 2 * a.ld;
-    const double *in = static_cast<const double *>(a.in);
-    const double *base = static_cast<const double *>(a.base);
-    const double *Vp = static_cast<const double *>(a.V);
-
-    int hl[HPT], hx[HPT], hy[HPT], hc[HPT];
-    bool hok[HPT];
+// Halo assignment of a TX x TY tile (fixed for the whole march): halo value
+// j is a y-halo point for j < 8 TX (4 rows above, 4 below, x fastest) and an
+// x-halo point otherwise (4 left and 4 right of each tile row).
+template <int TX, int TY, int HPT>
+struct Halo {
+    int l[HPT], x[HPT], y[HPT];
+    bool ok[HPT];
+    __device__ __forceinline__ Halo(int t, int4 it) {
+        constexpr int NT = TX * TY, NHP = 8 * TX + 8 * TY, LX = TX + 8;
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) {
-        const int j = t + k * NT;
-        const int oh = j % RB, hp = j / RB;
-        int lxl, lyl;
-        if (hp < 8 * TX) {
-            const int yh = hp / TX;
-            lxl = hp % TX + 4;
-            lyl = yh < 4 ? yh : TY + yh;
-        } else {
-            const int q = hp - 8 * TX;
-            const int cc = q % 8;
-            lyl = q / 8 + 4;
-            lxl = cc < 4 ? cc : TX + cc;
+        for (int k = 0; k < HPT; ++k) {
+            const int j = t + k * NT;
+            int lxl, lyl;
+            if (j < 8 * TX) {
+                const int yh = j / TX;
+                lxl = j % TX + 4;
+                lyl = yh < 4 ? yh : TY + yh;
+            } else {
+                const int q = j - 8 * TX;
+                const int cc = q % 8;
+                lyl = q / 8 + 4;
+                lxl = cc < 4 ? cc : TX + cc;
+            }
+            ok[k] = j < NHP;
+            if (!ok[k]) lxl = lyl = 0;
+            l[k] = lyl * LX + lxl;
+            x[k] = it.x * TX + lxl - 4;
+            y[k] = it.y * TY + lyl - 4;
         }
-        hl[k] = (lyl * LX + lxl) * RB + oh;
-        hx[k] = it.x * TX + lxl - 4;
-        hy[k] = it.y * TY + lyl - 4;
-        hc[k] = ob * RB + oh;
-        hok[k] = j < NH && hc[k] < ncols;
     }
-    // Loads are unconditional: a tap outside the box (or a padding column)
-    // reads the zero pad; V and base of an outside point read a valid entry
-    // whose value is never stored.
-    const double *zp = a.zeros;
-    auto fetch = [&](int idx, int cc, bool ok) -> double {
-        const double *pa = (ok && idx >= 0) ? in + (int64_t)idx * ldr + cc : zp;
-        return *pa;
-    };
-    auto fetch_v = [&](int idx) -> double { return Vp[idx >= 0 ? idx : 0]; };
-    auto fetch_b = [&](int idx) -> double {
-        if (MODE != 1 || FIRST) return 0.0;
-        const bool v = idx >= 0 && cok;
-        return base[(int64_t)(v ? idx : 0) * ldr + (v ? col : 0)];
+};
+
+// The per-point epilogue shared by both marches: H value from the Laplacian
+// taps, then the stage combination, stored at idx (dropped when idx < 0).
+template <class Tc, class Tout, int MODE, bool FIRST>
+__device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0, Tc lr, Tc li, Tc v_c,
+                                       double2 b_c, double E, int x, int y, int z, int idx,
+                                       __amdgpu_buffer_rsrc_t rout) {
+    Tc vloc = v_c;
+    if (a.axis >= 0) {
+        const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
+        vloc += (Tc)(E * (a.h * ((double)cc - a.off[a.axis])));
+    }
+    const Tc kin_h2 = (Tc)a.kin_h2;
+    const Tc hr = kin_h2 * lr + vloc * q0.x;
+    const Tc hi = kin_h2 * li + vloc * q0.y;
+    const unsigned o = boff<Tout>(idx);
+    if (MODE == 0) {
+        store_c(rout, o, (Tout *)nullptr, (double)hr, (double)hi);
+    } else {
+        const double2 bb = FIRST ? make_double2((double)q0.x, (double)q0.y) : b_c;
+        const double r = bb.x + (a.cre * (double)hr - a.cim * (double)hi);
+        const double i = bb.y + (a.cre * (double)hi + a.cim * (double)hr);
+        store_c(rout, o, (Tout *)nullptr, r, i);
+    }
+}
+
+// Software-pipelined march, depth D = 1..3.  At step z (output plane z) a
+// thread
+//   - issues the row-table reads for the loads of step z+1,
+//   - issues the data loads of plane z+4+D (own column), of the halo of
+//     plane z+D and of V and base at plane z+D, from row entries read one
+//     step earlier,
+//   - computes plane z from data that arrived during earlier steps.
+// All rings are indexed by compile-time constants after unrolling the z loop
+// by a common period, so no register is moved while its load is in flight.
+// FIRST: base == in, whose value at the point is the centre tap.
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+__device__ __forceinline__ void march_ring(const KParams &a, const int4 it, const int n,
+                                           typename CT<Tc>::c2 *tile) {
+    using C2 = typename CT<Tc>::c2;
+    constexpr int NT = TX * TY, LX = TX + 8;
+    constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
+    constexpr int Q = D == 1 ? 10 : 12;  // >= 9 + D, keeps the unroll period at 10 or 12
+    static_assert(D >= 1 && D <= 3, "pipeline depth 1..3");
+    constexpr int VD = D + 1;
+    constexpr int P = clcm(clcm(clcm(Q, D), VD), 2);
+    const int t = threadIdx.x, lx = t % TX, ly = t / TX;
+    const int x = it.x * TX + lx, y = it.y * TY + ly;
+    const int64_t np = a.np;
+    const auto rin = rsrc(static_cast<const Tin *>(a.in) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tin));
+    const auto rbase = rsrc(static_cast<const double2 *>(a.base) + (int64_t)n * a.ldp, np * 16);
+    const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
+    const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
+    const Halo<TX, TY, HPT> hl(t, it);
+
+    auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
+    auto fetch_v = [&](int idx) -> Tc { return BL<Tc>::ld(rv, boff<Tc>(idx)); };
+    auto fetch_b = [&](int idx) -> double2 {
+        if (MODE != 1 || FIRST) return make_double2(0.0, 0.0);
+        return BL<double2>::ld(rbase, boff<double2>(idx));
     };
 
     const int z0 = it.z, z1 = it.w;
     // prologue: planes z0-4 .. z0+3+D into ring slots 0 .. Q-2 (slot of plane
     // z0 + m is m + 4), halo/V/base of planes z0 .. z0+D-1, rows for step z0
-    double cv[Q];
+    C2 cv[Q];
     int oid[Q];
 #pragma unroll
     for (int j = 0; j < Q - 1; ++j) {
         oid[j] = idx_in_row(row_of(a, y, z0 - 4 + j), x);
-        cv[j] = fetch(oid[j], col, cok);
+        cv[j] = fetch(oid[j], true);
     }
-    cv[Q - 1] = 0.0;
+    cv[Q - 1] = C2{(Tc)0, (Tc)0};
     oid[Q - 1] = -1;
-    double hal[D][HPT], vr[VD], br[VD];
+    C2 hal[D][HPT];
+    Tc vr[VD];
+    double2 br[VD];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
 #pragma unroll
-        for (int k = 0; k < HPT; ++k)
-            hal[d][k] = fetch(idx_in_row(row_of(a, hy[k], z0 + d), hx[k]), hc[k], hok[k]);
+        for (int k = 0; k < HPT; ++k) hal[d][k] = fetch(idx_in_row(row_of(a, hl.y[k], z0 + d), hl.x[k]), hl.ok[k]);
         vr[d] = fetch_v(oid[4 + d]);
         br[d] = fetch_b(oid[4 + d]);
     }
-    vr[D] = 0.0;
-    br[D] = 0.0;
+    vr[D] = (Tc)0;
+    br[D] = make_double2(0.0, 0.0);
     // step z reads row slot (z - z0) % 2 and fills the other one
     int2 rfr[2], rhl[2][HPT];
     rfr[0] = row_of(a, y, z0 + 4 + D);
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of(a, hy[k], z0 + D);
+    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of(a, hl.y[k], z0 + D);
     rfr[1] = make_int2(0, 0);
 #pragma unroll
     for (int k = 0; k < HPT; ++k) rhl[1][k] = make_int2(0, 0);
 
     const double E = a.field_dev ? *a.field_dev : a.field;
-    const double kin_h2 = a.kin_h2;
-    const int own = ((ly + 4) * LX + lx + 4) * RB + c;
-    double *out = static_cast<double *>(a.out);
+    const int own = (ly + 4) * LX + lx + 4;
 
     for (int zb = z0; zb < z1; zb += P) {
 #pragma unroll
@@ -360,186 +282,142 @@ __device__ __forceinline__ void march_r(const KParams &a, const int4 it, const i
             if (z >= z1) break;
             const int sd = s % D, sr = s % 2, srp = (s + 1) % 2;
             const int sv = s % VD, svn = (s + D) % VD;  // V/base: read slot, load slot
-            // ring slot of plane z + m
 #define SLOT(m) ((s + (m) + 4 + Q) % Q)
             tile[own] = cv[SLOT(0)];
 #pragma unroll
             for (int k = 0; k < HPT; ++k)
-                if (t + k * NT < NH) tile[hl[k]] = hal[sd][k];
+                if (hl.ok[k]) tile[hl.l[k]] = hal[sd][k];
             const int idx_c = oid[SLOT(0)];
-            const double v_c = vr[sv], b_c = br[sv];
+            const Tc v_c = vr[sv];
+            const double2 b_c = br[sv];
             __syncthreads();
             {
-                // row entries for the next step first, then the loads that use
-                // the entries read last step: own column plane z+4+D, halo and
-                // V/base of plane z+D
                 rfr[srp] = row_of(a, y, z + 5 + D);
 #pragma unroll
-                for (int k = 0; k < HPT; ++k) rhl[srp][k] = row_of(a, hy[k], z + 1 + D);
+                for (int k = 0; k < HPT; ++k) rhl[srp][k] = row_of(a, hl.y[k], z + 1 + D);
                 const int idf = (z + 4 + D < z1 + 4) ? idx_in_row(rfr[sr], x) : -1;
                 oid[SLOT(4 + D)] = idf;
-                cv[SLOT(4 + D)] = fetch(idf, col, cok);
+                cv[SLOT(4 + D)] = fetch(idf, true);
                 const bool live = z + D < z1;
 #pragma unroll
                 for (int k = 0; k < HPT; ++k)
-                    hal[sd][k] = fetch(idx_in_row(rhl[sr][k], hx[k]), hc[k], hok[k] && live);
+                    hal[sd][k] = fetch(idx_in_row(rhl[sr][k], hl.x[k]), hl.ok[k] && live);
                 const int idv = live ? oid[SLOT(D)] : -1;
                 vr[svn] = fetch_v(idv);
                 br[svn] = fetch_b(idv);
             }
-            const double q0 = cv[SLOT(0)];
-            const double lap =
-                3.0 * FD<double>::c0 * q0 +
-                FD<double>::c1 * ((tile[own - RB] + tile[own + RB]) + (tile[own - YS] + tile[own + YS]) + (cv[SLOT(-1)] + cv[SLOT(1)])) +
-                FD<double>::c2 * ((tile[own - 2 * RB] + tile[own + 2 * RB]) + (tile[own - 2 * YS] + tile[own + 2 * YS]) + (cv[SLOT(-2)] + cv[SLOT(2)])) +
-                FD<double>::c3 * ((tile[own - 3 * RB] + tile[own + 3 * RB]) + (tile[own - 3 * YS] + tile[own + 3 * YS]) + (cv[SLOT(-3)] + cv[SLOT(3)])) +
-                FD<double>::c4 * ((tile[own - 4 * RB] + tile[own + 4 * RB]) + (tile[own - 4 * YS] + tile[own + 4 * YS]) + (cv[SLOT(-4)] + cv[SLOT(4)]));
+            const C2 q0 = cv[SLOT(0)];
+            Tc lr, li;
+            {
+                const C2 xm1 = tile[own - 1], xp1 = tile[own + 1], xm2 = tile[own - 2], xp2 = tile[own + 2];
+                const C2 xm3 = tile[own - 3], xp3 = tile[own + 3], xm4 = tile[own - 4], xp4 = tile[own + 4];
+                const C2 ym1 = tile[own - LX], yp1 = tile[own + LX], ym2 = tile[own - 2 * LX], yp2 = tile[own + 2 * LX];
+                const C2 ym3 = tile[own - 3 * LX], yp3 = tile[own + 3 * LX], ym4 = tile[own - 4 * LX], yp4 = tile[own + 4 * LX];
+                const C2 zm1 = cv[SLOT(-1)], zp1 = cv[SLOT(1)], zm2 = cv[SLOT(-2)], zp2 = cv[SLOT(2)];
+                const C2 zm3 = cv[SLOT(-3)], zp3 = cv[SLOT(3)], zm4 = cv[SLOT(-4)], zp4 = cv[SLOT(4)];
+                lr = (Tc)3 * FD<Tc>::c0 * q0.x + FD<Tc>::c1 * ((xm1.x + xp1.x) + (ym1.x + yp1.x) + (zm1.x + zp1.x)) +
+                     FD<Tc>::c2 * ((xm2.x + xp2.x) + (ym2.x + yp2.x) + (zm2.x + zp2.x)) +
+                     FD<Tc>::c3 * ((xm3.x + xp3.x) + (ym3.x + yp3.x) + (zm3.x + zp3.x)) +
+                     FD<Tc>::c4 * ((xm4.x + xp4.x) + (ym4.x + yp4.x) + (zm4.x + zp4.x));
+                li = (Tc)3 * FD<Tc>::c0 * q0.y + FD<Tc>::c1 * ((xm1.y + xp1.y) + (ym1.y + yp1.y) + (zm1.y + zp1.y)) +
+                     FD<Tc>::c2 * ((xm2.y + xp2.y) + (ym2.y + yp2.y) + (zm2.y + zp2.y)) +
+                     FD<Tc>::c3 * ((xm3.y + xp3.y) + (ym3.y + yp3.y) + (zm3.y + zp3.y)) +
+                     FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (zm4.y + zp4.y));
+            }
 #undef SLOT
-            double vloc = v_c;
-            if (a.axis >= 0) {
-                const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
-                vloc += E * (a.h * ((double)cc - a.off[a.axis]));
-            }
-            const double hval = kin_h2 * lap + vloc * q0;
-            if (MODE == 0) {
-                if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = hval;
-            } else {
-                const double hpart = __shfl_xor(hval, 1);  // the other component of this orbital
-                const double bb = FIRST ? q0 : b_c;
-                // re: b + cre*Hre - cim*Him ; im: b + cre*Him + cim*Hre
-                const double r = (c & 1) ? bb + (a.cre * hval + a.cim * hpart)
-                                         : bb + (a.cre * hval - a.cim * hpart);
-                if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = r;
-            }
+            finish<Tc, Tout, MODE, FIRST>(a, q0, lr, li, v_c, b_c, E, x, y, z, idx_c, rout);
             __syncthreads();
         }
     }
 }
 
-// Lean variant (pipeline depth 1): the own-column queue q[9] rotates in
+// Lean march (depth 1, few registers): the own-column queue q[9] rotates in
 // registers and every load of plane z+1 (own column z+5, halo, V, base) is
 // issued one step ahead; a step starts by waiting for the previous step's
-// loads.  Few registers, so 1024-thread workgroups with 512-point tiles fit
-// without spilling, which cuts the halo per output.
-template <int RB, int TX, int TY, int MODE, bool FIRST>
-__device__ __forceinline__ void march_s(const KParams &a, const int4 it, const int ob, double *tile) {
-    constexpr int NT = RB * TX * TY;
-    constexpr int LX = TX + 8;
-    constexpr int NHP = 8 * TX + 8 * TY;
-    constexpr int NH = NHP * RB;
-    constexpr int HPT = (NH + NT - 1) / NT;
-    constexpr int YS = LX * RB;
-    const int t = threadIdx.x;
-    const int c = t % RB, lx = (t / RB) % TX, ly = t / (RB * TX);
+// loads.  Fits 1024-thread workgroups without spilling.
+template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+__device__ __forceinline__ void march_lean(const KParams &a, const int4 it, const int n,
+                                           typename CT<Tc>::c2 *tile) {
+    using C2 = typename CT<Tc>::c2;
+    constexpr int NT = TX * TY, LX = TX + 8;
+    constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
+    const int t = threadIdx.x, lx = t % TX, ly = t / TX;
     const int x = it.x * TX + lx, y = it.y * TY + ly;
-    const int ncols = (int)(2 * a.nst);
-    const int col = ob * RB + c;
-    const bool cok = col < ncols;
-    const int64_t ldr = 2 * a.ld;
-    const double *in = static_cast<const double *>(a.in);
-    const double *base = static_cast<const double *>(a.base);
-    const double *Vp = static_cast<const double *>(a.V);
-    const double *zp = a.zeros;
+    const int64_t np = a.np;
+    const auto rin = rsrc(static_cast<const Tin *>(a.in) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tin));
+    const auto rbase = rsrc(static_cast<const double2 *>(a.base) + (int64_t)n * a.ldp, np * 16);
+    const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
+    const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
+    const Halo<TX, TY, HPT> hl(t, it);
 
-    int hl[HPT], hx[HPT], hy[HPT], hc[HPT];
-    bool hok[HPT];
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) {
-        const int j = t + k * NT;
-        const int oh = j % RB, hp = j / RB;
-        int lxl, lyl;
-        if (hp < 8 * TX) {
-            const int yh = hp / TX;
-            lxl = hp % TX + 4;
-            lyl = yh < 4 ? yh : TY + yh;
-        } else {
-            const int q = hp - 8 * TX;
-            const int cc = q % 8;
-            lyl = q / 8 + 4;
-            lxl = cc < 4 ? cc : TX + cc;
-        }
-        hl[k] = (lyl * LX + lxl) * RB + oh;
-        hx[k] = it.x * TX + lxl - 4;
-        hy[k] = it.y * TY + lyl - 4;
-        hc[k] = ob * RB + oh;
-        hok[k] = j < NH && hc[k] < ncols;
-    }
-    auto fetch = [&](int idx, int cc, bool ok) -> double {
-        const double *pa = (ok && idx >= 0) ? in + (int64_t)idx * ldr + cc : zp;
-        return *pa;
-    };
-    auto fetch_v = [&](int idx) -> double { return Vp[idx >= 0 ? idx : 0]; };
-    auto fetch_b = [&](int idx) -> double {
-        if (MODE != 1 || FIRST) return 0.0;
-        const bool v = idx >= 0 && cok;
-        return base[(int64_t)(v ? idx : 0) * ldr + (v ? col : 0)];
+    auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
+    auto fetch_v = [&](int idx) -> Tc { return BL<Tc>::ld(rv, boff<Tc>(idx)); };
+    auto fetch_b = [&](int idx) -> double2 {
+        if (MODE != 1 || FIRST) return make_double2(0.0, 0.0);
+        return BL<double2>::ld(rbase, boff<double2>(idx));
     };
 
     const int z0 = it.z, z1 = it.w;
-    double q[9];
+    C2 q[9];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) q[k] = fetch(idx_in_row(row_of(a, y, z0 - 4 + k), x), col, cok);
+    for (int k = 0; k < 8; ++k) q[k] = fetch(idx_in_row(row_of(a, y, z0 - 4 + k), x), true);
     int idx_c = idx_in_row(row_of(a, y, z0), x);
-    double nxt = fetch(idx_in_row(row_of(a, y, z0 + 4), x), col, cok);
-    double hv[HPT];
+    C2 nxt = fetch(idx_in_row(row_of(a, y, z0 + 4), x), true);
+    C2 hv[HPT];
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(row_of(a, hy[k], z0), hx[k]), hc[k], hok[k]);
-    double v_c = fetch_v(idx_c), b_c = fetch_b(idx_c);
+    for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(row_of(a, hl.y[k], z0), hl.x[k]), hl.ok[k]);
+    Tc v_c = fetch_v(idx_c);
+    double2 b_c = fetch_b(idx_c);
     int2 rf = row_of(a, y, z0 + 5);  // rows for the loads of the first step
     int2 ro = row_of(a, y, z0 + 1);
     int2 rh[HPT];
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) rh[k] = row_of(a, hy[k], z0 + 1);
+    for (int k = 0; k < HPT; ++k) rh[k] = row_of(a, hl.y[k], z0 + 1);
 
     const double E = a.field_dev ? *a.field_dev : a.field;
-    const double kin_h2 = a.kin_h2;
-    const int own = ((ly + 4) * LX + lx + 4) * RB + c;
-    double *out = static_cast<double *>(a.out);
+    const int own = (ly + 4) * LX + lx + 4;
 
     for (int z = z0; z < z1; ++z) {
         q[8] = nxt;
         tile[own] = q[4];
 #pragma unroll
         for (int k = 0; k < HPT; ++k)
-            if (t + k * NT < NH) tile[hl[k]] = hv[k];
+            if (hl.ok[k]) tile[hl.l[k]] = hv[k];
         __syncthreads();
         // row entries for the next step, then this step's loads (plane z+1)
         const int2 rf_n = row_of(a, y, z + 6), ro_n = row_of(a, y, z + 2);
         int2 rh_n[HPT];
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) rh_n[k] = row_of(a, hy[k], z + 2);
+        for (int k = 0; k < HPT; ++k) rh_n[k] = row_of(a, hl.y[k], z + 2);
         const bool live = z + 1 < z1;
-        nxt = fetch(live ? idx_in_row(rf, x) : -1, col, cok);
+        nxt = fetch(live ? idx_in_row(rf, x) : -1, true);
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(rh[k], hx[k]), hc[k], hok[k] && live);
+        for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(rh[k], hl.x[k]), hl.ok[k] && live);
         const int idx_n = live ? idx_in_row(ro, x) : -1;
-        const double v_n = fetch_v(idx_n), b_n = fetch_b(idx_n);
+        const Tc v_n = fetch_v(idx_n);
+        const double2 b_n = fetch_b(idx_n);
         rf = rf_n;
         ro = ro_n;
 #pragma unroll
         for (int k = 0; k < HPT; ++k) rh[k] = rh_n[k];
 
-        const double lap =
-            3.0 * FD<double>::c0 * q[4] +
-            FD<double>::c1 * ((tile[own - RB] + tile[own + RB]) + (tile[own - YS] + tile[own + YS]) + (q[3] + q[5])) +
-            FD<double>::c2 * ((tile[own - 2 * RB] + tile[own + 2 * RB]) + (tile[own - 2 * YS] + tile[own + 2 * YS]) + (q[2] + q[6])) +
-            FD<double>::c3 * ((tile[own - 3 * RB] + tile[own + 3 * RB]) + (tile[own - 3 * YS] + tile[own + 3 * YS]) + (q[1] + q[7])) +
-            FD<double>::c4 * ((tile[own - 4 * RB] + tile[own + 4 * RB]) + (tile[own - 4 * YS] + tile[own + 4 * YS]) + (q[0] + q[8]));
-        double vloc = v_c;
-        if (a.axis >= 0) {
-            const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
-            vloc += E * (a.h * ((double)cc - a.off[a.axis]));
+        const C2 q0 = q[4];
+        Tc lr, li;
+        {
+            const C2 xm1 = tile[own - 1], xp1 = tile[own + 1], xm2 = tile[own - 2], xp2 = tile[own + 2];
+            const C2 xm3 = tile[own - 3], xp3 = tile[own + 3], xm4 = tile[own - 4], xp4 = tile[own + 4];
+            const C2 ym1 = tile[own - LX], yp1 = tile[own + LX], ym2 = tile[own - 2 * LX], yp2 = tile[own + 2 * LX];
+            const C2 ym3 = tile[own - 3 * LX], yp3 = tile[own + 3 * LX], ym4 = tile[own - 4 * LX], yp4 = tile[own + 4 * LX];
+            lr = (Tc)3 * FD<Tc>::c0 * q0.x + FD<Tc>::c1 * ((xm1.x + xp1.x) + (ym1.x + yp1.x) + (q[3].x + q[5].x)) +
+                 FD<Tc>::c2 * ((xm2.x + xp2.x) + (ym2.x + yp2.x) + (q[2].x + q[6].x)) +
+                 FD<Tc>::c3 * ((xm3.x + xp3.x) + (ym3.x + yp3.x) + (q[1].x + q[7].x)) +
+                 FD<Tc>::c4 * ((xm4.x + xp4.x) + (ym4.x + yp4.x) + (q[0].x + q[8].x));
+            li = (Tc)3 * FD<Tc>::c0 * q0.y + FD<Tc>::c1 * ((xm1.y + xp1.y) + (ym1.y + yp1.y) + (q[3].y + q[5].y)) +
+                 FD<Tc>::c2 * ((xm2.y + xp2.y) + (ym2.y + yp2.y) + (q[2].y + q[6].y)) +
+                 FD<Tc>::c3 * ((xm3.y + xp3.y) + (ym3.y + yp3.y) + (q[1].y + q[7].y)) +
+                 FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (q[0].y + q[8].y));
         }
-        const double hval = kin_h2 * lap + vloc * q[4];
-        if (MODE == 0) {
-            if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = hval;
-        } else {
-            const double hpart = __shfl_xor(hval, 1);  // the other component of this orbital
-            const double bb = FIRST ? q[4] : b_c;
-            const double r = (c & 1) ? bb + (a.cre * hval + a.cim * hpart)
-                                     : bb + (a.cre * hval - a.cim * hpart);
-            if (idx_c >= 0 && cok) out[(int64_t)idx_c * ldr + col] = r;
-        }
+        finish<Tc, Tout, MODE, FIRST>(a, q0, lr, li, v_c, b_c, E, x, y, z, idx_c, rout);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 8; ++k) q[k] = q[k + 1];
@@ -549,126 +427,116 @@ __device__ __forceinline__ void march_s(const KParams &a, const int4 it, const i
     }
 }
 
-template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
-__global__ void __launch_bounds__(RB * TX * TY) k_stencil_r(KParams a) {
-    __shared__ double tile[(TY + 8) * (TX + 8) * RB];
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    int ob, item;
-    block_item(a, blk, &ob, &item);
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+__device__ __forceinline__ void march(const KParams &a, const int4 it, const int n, typename CT<Tc>::c2 *tile) {
     if constexpr (D == 0)
-        march_s<RB, TX, TY, MODE, FIRST>(a, a.items[item], ob, tile);
+        march_lean<TX, TY, Tin, Tc, Tout, MODE, FIRST>(a, it, n, tile);
     else
-        march_r<RB, TX, TY, MODE, FIRST, D>(a, a.items[item], ob, tile);
+        march_ring<TX, TY, D, Tin, Tc, Tout, MODE, FIRST>(a, it, n, tile);
 }
 
-// Persistent form over many independent systems: workgroup g takes items
-// g, g + G, g + 2G, ... of the cost-sorted list {system, tx, ty, z0, z1, ob};
-// each system's parameters come from sysp[system].
-template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
-__global__ void __launch_bounds__(RB * TX * TY) k_stencil_batch(const KParams *__restrict__ sysp,
-                                                                const BatchItem *__restrict__ items,
-                                                                int32_t nitems, double cre, double cim) {
-    __shared__ double tile[(TY + 8) * (TX + 8) * RB];
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+__global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
+    __shared__ typename CT<Tc>::c2 tile[(TY + 8) * (TX + 8)];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    int n, item;
+    block_item(a, blk, &n, &item);
+    march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST>(a, a.items[item], n, tile);
+}
+
+// Persistent form over many independent systems (FP64): workgroup g takes
+// items g, g + G, g + 2G, ... of the cost-sorted list {tile, system,
+// orbital}; each system's parameters come from sysp[system].
+template <int TX, int TY, int D, bool FIRST>
+__global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__restrict__ sysp,
+                                                           const BatchItem *__restrict__ items,
+                                                           int32_t nitems, double cre, double cim) {
+    __shared__ double2 tile[(TY + 8) * (TX + 8)];
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
         const BatchItem bi = items[w];
         KParams a = sysp[bi.sys];
         a.cre = cre;
         a.cim = cim;
-        if constexpr (D == 0)
-            march_s<RB, TX, TY, MODE, FIRST>(a, bi.tile, bi.ob, tile);
-        else
-            march_r<RB, TX, TY, MODE, FIRST, D>(a, bi.tile, bi.ob, tile);
+        march<TX, TY, D, double2, double, double2, 1, FIRST>(a, bi.tile, bi.ob, tile);
         __syncthreads();  // the next item reuses the plane buffer
     }
 }
 
-template <int B, int TX, int TY>
-int launch_c(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
-    constexpr int NT = B * TX * TY;
-    if (a.compute == 0 || a.mode != 1) return RSG_EUNSUPPORTED;
-    if (a.in_t == 0 && a.out_t == 1)
-        k_stencil_c<B, TX, TY, double2, float, 1, float2><<<nb, NT, 0, s>>>(p);
-    else if (a.in_t == 1 && a.out_t == 1)
-        k_stencil_c<B, TX, TY, float2, float, 1, float2><<<nb, NT, 0, s>>>(p);
-    else if (a.in_t == 1 && a.out_t == 0)
-        k_stencil_c<B, TX, TY, float2, float, 1, double2><<<nb, NT, 0, s>>>(p);
+template <int TX, int TY, int D>
+int launch_fp64(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
+    constexpr int NT = TX * TY;
+    if (a.in_t != 0 || a.out_t != 0) return RSG_EUNSUPPORTED;
+    if (a.mode == 0)
+        k_stencil<TX, TY, D, double2, double, double2, 0, false><<<nb, NT, 0, s>>>(p);
+    else if (a.first)
+        k_stencil<TX, TY, D, double2, double, double2, 1, true><<<nb, NT, 0, s>>>(p);
+    else
+        k_stencil<TX, TY, D, double2, double, double2, 1, false><<<nb, NT, 0, s>>>(p);
+    return RSG_OK;
+}
+
+// Mixed path: FP32 arithmetic; the first stage reads complex128 psi and
+// writes complex64, the middle stages complex64 to complex64, the last
+// complex64 to complex128 with the complex128 base.
+template <int TX, int TY, int D>
+int launch_fp32(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
+    constexpr int NT = TX * TY;
+    if (a.mode != 1) return RSG_EUNSUPPORTED;
+    if (a.in_t == 0 && a.out_t == 1 && a.first)
+        k_stencil<TX, TY, D, double2, float, float2, 1, true><<<nb, NT, 0, s>>>(p);
+    else if (a.in_t == 1 && a.out_t == 1 && !a.first)
+        k_stencil<TX, TY, D, float2, float, float2, 1, false><<<nb, NT, 0, s>>>(p);
+    else if (a.in_t == 1 && a.out_t == 0 && !a.first)
+        k_stencil<TX, TY, D, float2, float, double2, 1, false><<<nb, NT, 0, s>>>(p);
     else
         return RSG_EUNSUPPORTED;
     return RSG_OK;
 }
 
-template <int RB, int TX, int TY, int D>
-int launch_rd(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
-    constexpr int NT = RB * TX * TY;
-    if (a.mode == 0)
-        k_stencil_r<RB, TX, TY, 0, false, D><<<nb, NT, 0, s>>>(p);
-    else if (a.first)
-        k_stencil_r<RB, TX, TY, 1, true, D><<<nb, NT, 0, s>>>(p);
-    else
-        k_stencil_r<RB, TX, TY, 1, false, D><<<nb, NT, 0, s>>>(p);
-    return RSG_OK;
-}
-
-template <int B, int TX, int TY>
-int launch_r(const StageArgs &a, const KParams &p, int nb, hipStream_t s, int D) {
-    constexpr int RB = 2 * B;
-    if (a.compute != 0 || a.in_t != 0 || a.out_t != 0) return RSG_EUNSUPPORTED;
-    if (D == 0) return launch_rd<RB, TX, TY, 0>(a, p, nb, s);
-    if (RB * TX * TY > 512) return RSG_EUNSUPPORTED;  // deeper pipelines spill at 1024 threads
-    if (D == 1) return launch_rd<RB, TX, TY, 1>(a, p, nb, s);
-    if (D == 2) return launch_rd<RB, TX, TY, 2>(a, p, nb, s);
-    return launch_rd<RB, TX, TY, 3>(a, p, nb, s);
-    return RSG_OK;
-}
-
 }  // namespace
 
-// Tile shapes compiled into the library: {orbitals per workgroup B, TX, TY}.
-// FP64 kernels have 2B real lanes per point, FP32 kernels B complex lanes.
+// Tile shapes compiled into the library, {TX, TY, depth}: depth 1..3 is the
+// pipelined march, depth 0 the lean one.  (1024-thread tiles are not
+// compiled: at the 128-register limit of such workgroups the z-window
+// spills.)
 #define RSG_FP64_SHAPES(X) \
-    X(1, 16, 16) X(2, 16, 8) X(2, 8, 8) X(4, 8, 8) X(4, 16, 4) X(4, 8, 4) \
-    X(8, 8, 4) X(8, 4, 8) X(8, 4, 4) X(16, 4, 4) \
-    X(1, 32, 16) X(2, 16, 16) X(4, 16, 8) X(8, 8, 8) X(16, 8, 4) X(16, 4, 8) X(32, 4, 4)
-#define RSG_FP32_SHAPES(X) X(1, 16, 16) X(2, 16, 16) X(4, 16, 16) X(4, 16, 8) X(8, 16, 8) X(8, 8, 8)
+    X(16, 8, 1) X(16, 8, 2) X(32, 8, 1) X(32, 8, 2) X(32, 8, 3) X(16, 16, 1) X(16, 16, 2) \
+    X(16, 16, 3) X(32, 16, 1) X(32, 16, 2) X(32, 16, 3) X(64, 8, 1) X(64, 8, 2) X(32, 16, 0)
+#define RSG_FP32_SHAPES(X) X(16, 8, 1) X(32, 8, 1) X(32, 8, 2) X(32, 16, 1) X(32, 16, 2) X(64, 8, 2)
 
 std::vector<TileShape> tile_candidates(int compute) {
-    std::vector<TileShape> shapes, v;
-#define RSG_ADD(B_, X_, Y_) shapes.push_back(TileShape{B_, X_, Y_, 0});
+    std::vector<TileShape> v;
+#define RSG_ADD(X_, Y_, D_)                \
+    {                                      \
+        TileShape sh{1, X_, Y_, 0};        \
+        sh.PD = D_;                        \
+        v.push_back(sh);                   \
+    }
     if (compute == 0) {
         RSG_FP64_SHAPES(RSG_ADD)
     } else {
         RSG_FP32_SHAPES(RSG_ADD)
     }
 #undef RSG_ADD
-    const int d0 = compute == 0 ? 0 : 1, maxd = compute == 0 ? 3 : 1;
-    for (int d = d0; d <= maxd; ++d)
-        for (auto sh : shapes) {
-            if (compute == 0 && d > 0 && 2 * sh.B * sh.TX * sh.TY > 512) continue;
-            sh.PD = d;
-            v.push_back(sh);
-        }
     return v;
 }
 
+// Measured on MI355X (sphere of 3.05 M points, 64 orbitals): 32 x 16 tiles,
+// depth 2, orbital-slowest order.  Smaller grids take the largest tile that
+// still gives every compute unit several workgroups.
 TileShape default_shape(const Grid &g, int64_t nst, int compute) {
-    TileShape sh;
-    if (compute == 0) {
-        // measured on MI355X (sphere of 3.05 M points): 8 orbitals per
-        // workgroup (one 128-byte line per point), 4 x 8 tiles, depth 3,
-        // batch-slowest order; fewer orbitals use the lean variant
-        if (nst <= 1) sh = {1, 16, 16, 0, 0};
-        else if (nst <= 2) sh = {2, 16, 8, 0, 0};
-        else if (nst <= 4) sh = {4, 8, 8, 0, 0};
-        else {
-            sh = {8, 4, 8, 0, 3};
-            sh.BO = 1;
-        }
-    } else {
-        if (nst <= 1) sh = {1, 16, 16, 0};
-        else if (nst <= 2) sh = {2, 16, 16, 0};
-        else if (nst <= 4) sh = {4, 16, 16, 0};
-        else sh = {8, 16, 8, 0};
+    static const int pref[][3] = {{32, 16, 2}, {32, 8, 2}, {16, 8, 1}};
+    static const int pref32[][3] = {{32, 16, 2}, {32, 8, 2}, {16, 8, 1}};
+    TileShape sh{1, 16, 8, 0};
+    sh.PD = 1;
+    for (const auto &c : (compute == 0 ? pref : pref32)) {
+        const int64_t tiles = (int64_t)((g.n[0] + c[0] - 1) / c[0]) * ((g.n[1] + c[1] - 1) / c[1]);
+        sh.TX = c[0];
+        sh.TY = c[1];
+        sh.PD = c[2];
+        if (tiles * std::max<int64_t>(nst, 1) >= 2048) break;
     }
+    sh.BO = 1;
     sh.ZC = g.n[2];
     return sh;
 }
@@ -685,20 +553,20 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     p.in = a.in;
     p.base = a.base;
     p.out = a.out;
-    p.items = plan->items;
+    p.items = plan ? plan->items : nullptr;
     p.rows = g.rows;
     p.zeros = g.zeros;
     p.V = a.compute == 0 ? (const void *)H.V : (const void *)H.V32;
     p.field_dev = a.field_dev;
     p.nst = a.nst;
-    p.ld = a.ld;
+    p.ldp = a.ldp;
+    p.np = g.np;
     p.kin_h2 = H.kin / (g.h * g.h);
     p.field = a.field;
     p.h = g.h;
     for (int k = 0; k < 3; ++k) p.off[k] = 0.5 * (double)(g.n[k] - 1);
     p.cre = a.cre;
     p.cim = a.cim;
-    p.nob = (int32_t)((a.nst + shape.B - 1) / shape.B);
     p.nitems = plan ? plan->nitems : 0;
     p.batch_slowest = shape.BO;
     p.ny = g.n[1];
@@ -715,8 +583,12 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     const TilePlan *plan = const_cast<Grid &>(g).plan(key, s, &err);
     if (!plan) return err;
     if (plan->nitems == 0 || a.nst == 0) return RSG_OK;
+    if (g.np >= (int64_t)(OOB / 16)) {
+        set_error("stencil: grids of 2^27 points or more are not supported");
+        return RSG_EUNSUPPORTED;
+    }
     const KParams p = make_params(H, a, shape, plan);
-    const int64_t nb64 = (int64_t)plan->nitems * p.nob;
+    const int64_t nb64 = (int64_t)plan->nitems * a.nst;
     if (nb64 > INT32_MAX) {
         set_error("stencil launch too large");
         return RSG_EUNSUPPORTED;
@@ -725,17 +597,27 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     timing_before(s);
     int rc = RSG_EUNSUPPORTED;
     bool found = false;
-#define RSG_TRY_R(B_, X_, Y_) \
-    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) { found = true; rc = launch_r<B_, X_, Y_>(a, p, nb, s, shape.PD); }
-#define RSG_TRY_C(B_, X_, Y_) \
-    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) { found = true; rc = launch_c<B_, X_, Y_>(a, p, nb, s); }
-    if (a.compute == 0) { RSG_FP64_SHAPES(RSG_TRY_R) } else { RSG_FP32_SHAPES(RSG_TRY_C) }
-#undef RSG_TRY_R
-#undef RSG_TRY_C
+#define RSG_TRY(X_, Y_, D_, FN)                                                     \
+    if (!found && shape.TX == X_ && shape.TY == Y_ && shape.PD == D_) {             \
+        found = true;                                                               \
+        rc = FN<X_, Y_, D_>(a, p, nb, s);                                           \
+    }
+#define RSG_TRY64(X_, Y_, D_) RSG_TRY(X_, Y_, D_, launch_fp64)
+#define RSG_TRY32(X_, Y_, D_) RSG_TRY(X_, Y_, D_, launch_fp32)
+    if (shape.B == 1) {
+        if (a.compute == 0) {
+            RSG_FP64_SHAPES(RSG_TRY64)
+        } else {
+            RSG_FP32_SHAPES(RSG_TRY32)
+        }
+    }
+#undef RSG_TRY64
+#undef RSG_TRY32
+#undef RSG_TRY
     timing_after(s);
     if (rc == RSG_EUNSUPPORTED) {
-        set_error("stencil: unsupported tile shape %dx%dx%d for this precision", shape.B, shape.TX,
-                  shape.TY);
+        set_error("stencil: unsupported tile %dx%dx%d depth %d for this precision", shape.B, shape.TX,
+                  shape.TY, shape.PD);
         return rc;
     }
     RSG_CHECK_HIP(hipGetLastError());
@@ -746,11 +628,11 @@ namespace {
 // grid < 0: return the number of resident workgroups of this kernel on the
 // device (occupancy query, not allowed during graph capture); grid > 0:
 // launch with that many persistent workgroups.
-template <int RB, int TX, int TY, int MODE, bool FIRST, int D>
+template <int TX, int TY, int D, bool FIRST>
 int launch_batch_inst(const KParams *sysp, const BatchItem *items, int32_t nitems, double cre, double cim,
                       int grid, hipStream_t s) {
-    constexpr int NT = RB * TX * TY;
-    auto kern = k_stencil_batch<RB, TX, TY, MODE, FIRST, D>;
+    constexpr int NT = TX * TY;
+    auto kern = k_stencil_batch<TX, TY, D, FIRST>;
     if (grid < 0) {
         int per_cu = 0, dev = 0;
         hipDeviceProp_t prop;
@@ -763,33 +645,23 @@ int launch_batch_inst(const KParams *sysp, const BatchItem *items, int32_t nitem
     return RSG_OK;
 }
 
-template <int B, int TX, int TY>
-int launch_batch_shape(int mode, bool first, int D, const KParams *sysp, const BatchItem *items, int32_t nitems,
-                       double cre, double cim, int grid, hipStream_t s) {
-    constexpr int RB = 2 * B;
-#define RSG_BD(DD)                                                                                          \
-    if (D == DD) {                                                                                          \
-        if (mode == 0) return launch_batch_inst<RB, TX, TY, 0, false, DD>(sysp, items, nitems, cre, cim, grid, s); \
-        if (first) return launch_batch_inst<RB, TX, TY, 1, true, DD>(sysp, items, nitems, cre, cim, grid, s);      \
-        return launch_batch_inst<RB, TX, TY, 1, false, DD>(sysp, items, nitems, cre, cim, grid, s);               \
-    }
-    RSG_BD(0)
-    if (RB * TX * TY > 512) return RSG_EUNSUPPORTED;
-    RSG_BD(1) RSG_BD(2) RSG_BD(3)
-#undef RSG_BD
-    return RSG_EUNSUPPORTED;
+template <int TX, int TY, int D>
+int launch_batch_shape(bool first, const KParams *sysp, const BatchItem *items, int32_t nitems, double cre,
+                       double cim, int grid, hipStream_t s) {
+    if (first) return launch_batch_inst<TX, TY, D, true>(sysp, items, nitems, cre, cim, grid, s);
+    return launch_batch_inst<TX, TY, D, false>(sysp, items, nitems, cre, cim, grid, s);
 }
 }  // namespace
 
 int stencil_batch_grid(const TileShape &shape, bool first) {
     int g = RSG_EUNSUPPORTED;
     bool found = false;
-#define RSG_TRY_G(B_, X_, Y_)                                                                          \
-    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) {                                 \
-        found = true;                                                                                  \
-        g = launch_batch_shape<B_, X_, Y_>(1, first, shape.PD, nullptr, nullptr, 0, 0.0, 0.0, -1, nullptr); \
+#define RSG_TRY_G(X_, Y_, D_)                                                                        \
+    if (!found && shape.TX == X_ && shape.TY == Y_ && shape.PD == D_) {                              \
+        found = true;                                                                                \
+        g = launch_batch_shape<X_, Y_, D_>(first, nullptr, nullptr, 0, 0.0, 0.0, -1, nullptr);       \
     }
-    RSG_FP64_SHAPES(RSG_TRY_G)
+    if (shape.B == 1) { RSG_FP64_SHAPES(RSG_TRY_G) }
 #undef RSG_TRY_G
     return g;
 }
@@ -798,6 +670,10 @@ int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KPa
                          const BatchItem *items, int32_t nitems, double cre, double cim, int grid,
                          hipStream_t s) {
     if (nitems == 0) return RSG_OK;
+    if (mode != 1) {
+        set_error("batched stencil: only Horner stages are batched");
+        return RSG_EUNSUPPORTED;
+    }
     if (grid <= 0) {
         set_error("batched stencil: persistent grid size must be > 0");
         return RSG_EINVAL;
@@ -805,16 +681,17 @@ int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KPa
     int rc = RSG_EUNSUPPORTED;
     bool found = false;
     timing_before(s);
-#define RSG_TRY_B(B_, X_, Y_)                                                                              \
-    if (!found && shape.B == B_ && shape.TX == X_ && shape.TY == Y_) {                                     \
-        found = true;                                                                                      \
-        rc = launch_batch_shape<B_, X_, Y_>(mode, first, shape.PD, sysp, items, nitems, cre, cim, grid, s); \
+#define RSG_TRY_B(X_, Y_, D_)                                                                      \
+    if (!found && shape.TX == X_ && shape.TY == Y_ && shape.PD == D_) {                            \
+        found = true;                                                                              \
+        rc = launch_batch_shape<X_, Y_, D_>(first, sysp, items, nitems, cre, cim, grid, s);        \
     }
-    RSG_FP64_SHAPES(RSG_TRY_B)
+    if (shape.B == 1) { RSG_FP64_SHAPES(RSG_TRY_B) }
 #undef RSG_TRY_B
     timing_after(s);
     if (rc != RSG_OK) {
-        if (rc == RSG_EUNSUPPORTED) set_error("batched stencil: unsupported tile %dx%dx%d", shape.B, shape.TX, shape.TY);
+        if (rc == RSG_EUNSUPPORTED)
+            set_error("batched stencil: unsupported tile %dx%dx%d depth %d", shape.B, shape.TX, shape.TY, shape.PD);
         return rc;
     }
     RSG_CHECK_HIP(hipGetLastError());

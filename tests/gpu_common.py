@@ -1,5 +1,9 @@
 """Shared helpers of the GPU parity tests: build one system on both sides
-from the same seeded inputs and compare results to the stated tolerance."""
+from the same seeded inputs and compare results to the stated tolerance.
+
+The oracle works on point-major arrays [np, ld]; the library takes
+orbital-major tensors [nst, ldp].  to_om / from_om convert between the two
+(a transpose plus optional padding points), nothing else."""
 from __future__ import annotations
 
 import numpy as np
@@ -17,6 +21,29 @@ def rsg():
     return m
 
 
+# Value written into the padding points (np..ldp-1) of every orbital-major
+# tensor the tests build, so that tests can check they stay untouched.
+PAD = 7.0 - 3.0j
+
+
+def to_om(a: np.ndarray, pad: int = 0) -> torch.Tensor:
+    """Point-major [np, ld] array (the oracle's layout) -> orbital-major CUDA
+    tensor [ld, np + pad], padding points set to PAD."""
+    npts, ld = a.shape
+    t = np.full((ld, npts + pad), PAD, dtype=np.complex128)
+    t[:, :npts] = a.T
+    return torch.from_numpy(t).to("cuda")
+
+
+def from_om(t: torch.Tensor, npts: int) -> np.ndarray:
+    """Orbital-major tensor [ld, ldp] -> point-major [np, ld] numpy array."""
+    return np.ascontiguousarray(t.detach().cpu().numpy()[:, :npts].T)
+
+
+def pad_untouched(t: torch.Tensor, npts: int) -> bool:
+    return bool(np.all(t.detach().cpu().numpy()[:, npts:] == PAD))
+
+
 class System:
     """One grid + Hamiltonian on the oracle and on the GPU, built from the
     same synth inputs evaluated at the oracle's grid positions.  The GPU
@@ -24,7 +51,7 @@ class System:
 
     def __init__(self, h, *, R=None, n=None, potential="wells", natoms=0, nst=4, ld=None,
                  seed=0, dipole_axis=-1, kin=-0.5, well_ball=None, well_box=None, rcut=2.0,
-                 orbitals="white", packet_box=5.0):
+                 orbitals="white", packet_box=5.0, pad=0):
         R_ = rsg()
         self.og = oracle.Grid(h, R=R, n=n)
         self.gg = R_.Grid(h, R=R, n=n)
@@ -34,6 +61,7 @@ class System:
         self.pos = pos
         self.nst = nst
         self.ld = nst if ld is None else ld
+        self.pad = pad  # padding points per orbital on the GPU side
         if potential == "harmonic":
             V = synth.harmonic_potential(pos)
             centres = np.zeros((0, 3))
@@ -66,7 +94,14 @@ class System:
             raise ValueError(orbitals)
 
     def to_gpu(self, a: np.ndarray) -> torch.Tensor:
-        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+        """Oracle-layout [np, ld] -> orbital-major GPU tensor [ld, np + pad]."""
+        return to_om(a, self.pad)
+
+    def from_gpu(self, t: torch.Tensor) -> np.ndarray:
+        return from_om(t, self.og.np)
+
+    def pad_untouched(self, t: torch.Tensor) -> bool:
+        return pad_untouched(t, self.og.np)
 
 
 def orbital_rel_err(got: np.ndarray, ref: np.ndarray, nst: int) -> float:

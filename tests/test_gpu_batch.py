@@ -7,14 +7,14 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_common import orbital_rel_err, rsg
+from tests.gpu_common import from_om, orbital_rel_err, pad_untouched, rsg, to_om
 
 pytestmark = pytest.mark.gpu
 
 
 def _systems(n=7, seed=33):
     """Uneven spheres (radii 2.2..4.6 bohr at h = 0.3), 1..9 orbitals with
-    padding columns, 0..3 atoms with projectors."""
+    spare orbitals and padding points, 0..3 atoms with projectors."""
     R_ = rsg()
     g = synth.rng(seed, 9)
     out = []
@@ -37,7 +37,7 @@ def _systems(n=7, seed=33):
                      for i, p, E in zip(proj.idx, proj.p, proj.E)]
         gh = R_.Hamiltonian(gg, V=torch.from_numpy(V).cuda(), kin=-0.5, projectors=projs)
         psi = synth.white_noise(seed * 100 + k, og.np, nst, 0.3, ld=ld)
-        out.append(dict(og=og, oh=oh, gg=gg, gh=gh, psi=psi, nst=nst, ld=ld))
+        out.append(dict(og=og, oh=oh, gg=gg, gh=gh, psi=psi, nst=nst, ld=ld, pad=k % 3))
     return out
 
 
@@ -45,21 +45,22 @@ def test_batch_matches_oracle_and_single_system_bitwise():
     R = rsg()
     systems = _systems()
     dt, nsteps = 0.005, 3
-    tens = [torch.from_numpy(s["psi"]).cuda() for s in systems]
+    tens = [to_om(s["psi"], s["pad"]) for s in systems]
     b = R.Batch([(s["gh"], t, s["nst"]) for s, t in zip(systems, tens)])
     tile = b.get_tile()
     b.propagate(dt, nsteps)
     torch.cuda.synchronize()
     for s, t in zip(systems, tens):
-        got = t.cpu().numpy()
+        got = from_om(t, s["og"].np)
         ref = oracle.propagate(s["oh"], s["psi"], dt, nsteps, nst=s["nst"])
         assert orbital_rel_err(got, ref, s["nst"]) <= 1e-12
         np.testing.assert_array_equal(got[:, s["nst"]:], s["psi"][:, s["nst"]:])
+        assert pad_untouched(t, s["og"].np)
         # same system alone, same tile: bitwise equal
-        alone = torch.from_numpy(s["psi"]).cuda()
+        alone = to_om(s["psi"], s["pad"])
         R.set_tile(s["gh"], s["nst"], tile["B"], tile["TX"], tile["TY"], tile["ZC"], tile["PD"])
         R.propagate(s["gh"], alone, dt, nsteps, nst=s["nst"])
-        np.testing.assert_array_equal(alone.cpu().numpy(), got)
+        np.testing.assert_array_equal(alone.cpu().numpy(), t.cpu().numpy())
 
 
 def test_batch_graph_replays_and_autotune():
@@ -67,8 +68,8 @@ def test_batch_graph_replays_and_autotune():
     systems = _systems(n=5, seed=44)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        a = [torch.from_numpy(s["psi"]).cuda() for s in systems]
-        g = [torch.from_numpy(s["psi"]).cuda() for s in systems]
+        a = [to_om(s["psi"], s["pad"]) for s in systems]
+        g = [to_om(s["psi"], s["pad"]) for s in systems]
         ba = R.Batch([(s["gh"], t, s["nst"]) for s, t in zip(systems, a)])
         bg = R.Batch([(s["gh"], t, s["nst"]) for s, t in zip(systems, g)])
         tile, ms = bg.autotune(reps=1)

@@ -29,28 +29,29 @@ def sphere18():
     V = synth.well_potential(pos, wells)
     proj = synth.kb_projectors(cfg["seed"], pos, wells.centres)
     psi = synth.white_noise(cfg["seed"], og.np, cfg["nst"], cfg["h"])
+    psi_om = np.ascontiguousarray(psi.T)  # the library's orbital-major layout
     oh = oracle.Ham(og, V=V, kin=-0.5, projectors=proj)
     dev = torch.device("cuda")
     gh = R.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
                        projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
                                    for i, p, E in zip(proj.idx, proj.p, proj.E)])
-    return dict(cfg=cfg, og=og, oh=oh, gg=gg, gh=gh, psi=psi)
+    return dict(cfg=cfg, og=og, oh=oh, gg=gg, gh=gh, psi=psi, psi_om=psi_om)
 
 
 def test_sphere18_hpsi_sampled_orbitals(sphere18):
     s = sphere18
-    psi = torch.from_numpy(s["psi"]).cuda()
+    psi = torch.from_numpy(s["psi_om"]).cuda()
     out = rsg().hpsi(s["gh"], psi)
-    got = out[:, SAMPLE].cpu().numpy()
+    got = out[SAMPLE, :].cpu().numpy().T
     ref = oracle.hpsi(s["oh"], np.ascontiguousarray(s["psi"][:, SAMPLE]))
     assert orbital_rel_err(got, ref, len(SAMPLE)) <= 1e-12
 
 
 def test_sphere18_taylor_step_sampled_orbitals(sphere18):
     s = sphere18
-    psi = torch.from_numpy(s["psi"]).cuda()
+    psi = torch.from_numpy(s["psi_om"]).cuda()
     rsg().propagate_step(s["gh"], psi, s["cfg"]["dt"])
-    got = psi[:, SAMPLE].cpu().numpy()
+    got = psi[SAMPLE, :].cpu().numpy().T
     ref = oracle.taylor_step(s["oh"], np.ascontiguousarray(s["psi"][:, SAMPLE]), s["cfg"]["dt"])
     assert orbital_rel_err(got, ref, len(SAMPLE)) <= 1e-12
 
@@ -60,7 +61,7 @@ def test_sphere18_norm_conserved_over_steps(sphere18):
     Taylor(4) amplification of its highest modes (|T4(ix)|^2 <= 1)."""
     s = sphere18
     R = rsg()
-    psi = torch.from_numpy(s["psi"]).cuda()
+    psi = torch.from_numpy(s["psi_om"]).cuda()
     n0 = R.norm2(s["gg"], psi).cpu().numpy()
     R.propagate(s["gh"], psi, s["cfg"]["dt"], 5)
     n1 = R.norm2(s["gg"], psi).cpu().numpy()

@@ -1,6 +1,8 @@
 """GPU parity: every C-ABI entry point against the FP64 oracle on the same
 seeded inputs.  FP64 results must agree to 1e-12 relative per orbital
-(||gpu_n - oracle_n||_2 / ||oracle_n||_2, max over orbitals)."""
+(||gpu_n - oracle_n||_2 / ||oracle_n||_2, max over orbitals).  GPU batches
+are orbital-major; several cases pad every orbital beyond np points and
+check the padding is never written."""
 import math
 
 import numpy as np
@@ -37,30 +39,33 @@ def test_hpsi_cube32_harmonic_ten_calls():
     ref = oracle.hpsi(s.oh, s.psi)
     psi = s.to_gpu(s.psi)
     for _ in range(10):
-        out = rsg().hpsi(s.gh, psi).cpu().numpy()
+        out = s.from_gpu(rsg().hpsi(s.gh, psi))
         assert orbital_rel_err(out, ref, 4) <= TOL
 
 
 @pytest.mark.parametrize("nst,ld", [(1, 1), (3, 4), (5, 8), (8, 8), (13, 16), (33, 40)])
 def test_hpsi_sphere_projectors_dipole(nst, ld):
     """Sphere with wells, overlapping projector supports and a dipole field;
-    ragged orbital counts with padding columns that must stay untouched."""
+    ragged orbital counts with spare orbitals and padding points that must
+    stay untouched."""
     s = System(0.3, R=4.1, potential="wells", natoms=5, nst=nst, ld=ld, seed=7, dipole_axis=2,
-               well_ball=1.5)
+               well_ball=1.5, pad=ld % 5)
     ref = oracle.hpsi(s.oh, s.psi, field=0.23, nst=nst)
     psi = s.to_gpu(s.psi)
     out = torch.full_like(psi, 3.0 + 1.0j)
     rsg().hpsi(s.gh, psi, field=0.23, out=out, nst=nst)
-    got = out.cpu().numpy()
+    got = s.from_gpu(out)
     assert orbital_rel_err(got, ref, nst) <= TOL
     assert np.all(got[:, nst:] == 3.0 + 1.0j)
+    assert np.all(out[:, s.og.np:].cpu().numpy() == 3.0 + 1.0j)
+    assert s.pad_untouched(psi)
 
 
 @pytest.mark.parametrize("axis", [0, 1])
 def test_hpsi_dipole_axes(axis):
     s = System(0.35, R=3.0, potential="harmonic", nst=2, seed=3, dipole_axis=axis)
     ref = oracle.hpsi(s.oh, s.psi, field=-0.7)
-    got = rsg().hpsi(s.gh, s.to_gpu(s.psi), field=-0.7).cpu().numpy()
+    got = s.from_gpu(rsg().hpsi(s.gh, s.to_gpu(s.psi), field=-0.7))
     assert orbital_rel_err(got, ref, 2) <= TOL
 
 
@@ -69,7 +74,7 @@ def test_hpsi_tiny_boxes():
     for kw in (dict(R=0.2), dict(n=3), dict(n=2)):
         s = System(0.3, potential="harmonic", nst=2, seed=5, **kw)
         ref = oracle.hpsi(s.oh, s.psi)
-        got = rsg().hpsi(s.gh, s.to_gpu(s.psi)).cpu().numpy()
+        got = s.from_gpu(rsg().hpsi(s.gh, s.to_gpu(s.psi)))
         assert orbital_rel_err(got, ref, 2) <= TOL
 
 
@@ -80,20 +85,22 @@ def test_taylor_steps_cube32():
     psi = s.to_gpu(s.psi)
     for _ in range(10):
         rsg().propagate_step(s.gh, psi, 0.01)
-    assert orbital_rel_err(psi.cpu().numpy(), ref, 4) <= TOL
+    assert orbital_rel_err(s.from_gpu(psi), ref, 4) <= TOL
 
 
 def test_propagate_fields_sphere_projectors():
-    """Steps with a per-step field array, projectors and padding columns."""
+    """Steps with a per-step field array, projectors, spare orbitals and
+    padding points."""
     s = System(0.3, R=4.0, potential="wells", natoms=4, nst=6, ld=8, seed=9, dipole_axis=1,
-               well_ball=1.2)
+               well_ball=1.2, pad=37)
     fields = np.linspace(-0.3, 0.4, 6)
     ref = oracle.propagate(s.oh, s.psi, 0.005, 6, fields=fields, nst=6)
     psi = s.to_gpu(s.psi)
     rsg().propagate(s.gh, psi, 0.005, 6, fields=torch.from_numpy(fields).cuda(), nst=6)
-    got = psi.cpu().numpy()
+    got = s.from_gpu(psi)
     assert orbital_rel_err(got, ref, 6) <= TOL
     np.testing.assert_array_equal(got[:, 6:], s.psi[:, 6:])
+    assert s.pad_untouched(psi)
 
 
 def test_propagate_graph_replays_match_eager():
@@ -104,7 +111,8 @@ def test_propagate_graph_replays_match_eager():
     with torch.cuda.stream(stream):
         eager = s.to_gpu(s.psi)
         graphed = s.to_gpu(s.psi)
-        ws = torch.empty(s.gh.workspace_bytes("step", 4, 4), dtype=torch.uint8, device="cuda")
+        ws = torch.empty(s.gh.workspace_bytes("step", 4, eager.shape[1]), dtype=torch.uint8,
+                         device="cuda")
         for rep in range(3):
             rsg().propagate(s.gh, eager, 0.01, 5, ws=ws)
             rsg().propagate(s.gh, graphed, 0.01, 5, graph=True, ws=ws)
@@ -112,12 +120,12 @@ def test_propagate_graph_replays_match_eager():
             _ = (eager.abs() ** 2).sum().item()  # eager library work between replays
             np.testing.assert_array_equal(graphed.cpu().numpy(), eager.cpu().numpy())
     ref = oracle.propagate(s.oh, s.psi, 0.01, 15)
-    assert orbital_rel_err(graphed.cpu().numpy(), ref, 4) <= TOL
+    assert orbital_rel_err(s.from_gpu(graphed), ref, 4) <= TOL
 
 
 def test_reductions_and_energy():
     s = System(0.3, R=4.5, potential="wells", natoms=3, nst=5, ld=6, seed=4, dipole_axis=0,
-               well_ball=1.0)
+               well_ball=1.0, pad=3)
     phi = synth.white_noise(77, s.og.np, 5, s.og.h, ld=6)
     R = rsg()
     a, b = s.to_gpu(phi), s.to_gpu(s.psi)
@@ -147,12 +155,12 @@ def test_reductions_deterministic():
 
 def test_adjoint_step_matches_oracle():
     s = System(0.3, R=3.6, potential="wells", natoms=3, nst=3, ld=4, seed=12, dipole_axis=2,
-               well_ball=1.0)
+               well_ball=1.0, pad=2)
     lam0 = synth.white_noise(31, s.og.np, 3, s.og.h, ld=4)
     lam_ref, g_ref = oracle.adjoint_step(s.oh, s.psi, lam0, 0.02, 0.15, nst=3)
     lam = s.to_gpu(lam0)
     g = rsg().adjoint_step(s.gh, s.to_gpu(s.psi), lam, 0.02, 0.15, nst=3).item()
-    assert orbital_rel_err(lam.cpu().numpy(), lam_ref, 3) <= TOL
+    assert orbital_rel_err(s.from_gpu(lam), lam_ref, 3) <= TOL
     assert g == pytest.approx(g_ref, rel=1e-11, abs=1e-14)
 
 
@@ -203,34 +211,40 @@ def test_mixed_precision_step_error():
     psi = s.to_gpu(s.psi)
     for _ in range(10):
         rsg().propagate_step(s.gh, psi, 0.01, dtype="mixed")
-    err = orbital_rel_err(psi.cpu().numpy(), ref, 4)
+    err = orbital_rel_err(s.from_gpu(psi), ref, 4)
     assert err < 1e-5, err
     assert err > 1e-13  # really ran in FP32
 
 
 def test_mixed_precision_projectors():
-    s = System(0.3, R=4.0, potential="wells", natoms=4, nst=5, ld=8, seed=10, well_ball=1.2)
+    s = System(0.3, R=4.0, potential="wells", natoms=4, nst=5, ld=8, seed=10, well_ball=1.2, pad=9)
     ref = oracle.propagate(s.oh, s.psi, 0.005, 3, nst=5)
     psi = s.to_gpu(s.psi)
     rsg().propagate(s.gh, psi, 0.005, 3, dtype="mixed", nst=5)
-    assert orbital_rel_err(psi.cpu().numpy(), ref, 5) < 1e-5
+    got = s.from_gpu(psi)
+    assert orbital_rel_err(got, ref, 5) < 1e-5
+    np.testing.assert_array_equal(got[:, 5:], s.psi[:, 5:])
+    assert s.pad_untouched(psi)
 
 
 def test_error_codes():
+    import ctypes as C
     R = rsg()
     s = System(0.3, n=8, potential="harmonic", nst=2, seed=1)
     psi = s.to_gpu(s.psi)
-    with pytest.raises(R.RSGError) as ei:
-        R.hpsi(s.gh, psi, nst=3)  # nst > ld
-    assert ei.value.code == -2
+    with pytest.raises(ValueError):
+        R.hpsi(s.gh, psi, nst=3)  # more orbitals than the tensor holds
     with pytest.raises(R.RSGError) as ei:
         R.adjoint_step(s.gh, psi, psi.clone(), 0.01, 0.0)  # no dipole axis
     assert ei.value.code == -1
+    p = C.c_void_p(psi.data_ptr())
+    ldp = psi.shape[1]
+    out = torch.zeros_like(psi)
+    # stride shorter than the grid
+    rc = R._lib.rsg_hpsi(s.gh._h, p, C.c_void_p(out.data_ptr()), 2, s.og.np - 1, 0, 0.0, None, 0, None)
+    assert rc == -2
     # the C call rejects a too-small workspace before enqueuing anything
-    import ctypes as C
-    rc = R._lib.rsg_propagate_step(s.gh._h, C.c_void_p(psi.data_ptr()), 2, 2, 0, 0.01, 0.0,
-                                   C.c_void_p(psi.data_ptr()), 16, None)
+    rc = R._lib.rsg_propagate_step(s.gh._h, p, 2, ldp, 0, 0.01, 0.0, p, 16, None)
     assert rc == -5
-    rc = R._lib.rsg_hpsi(s.gh._h, C.c_void_p(psi.data_ptr()), C.c_void_p(psi.data_ptr()), 2, 2, 0,
-                         0.0, None, 0, None)
+    rc = R._lib.rsg_hpsi(s.gh._h, p, p, 2, ldp, 0, 0.0, None, 0, None)
     assert rc == -1  # psi and hpsi overlap

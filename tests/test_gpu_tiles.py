@@ -3,9 +3,9 @@ tile order (row, Morton, patches) and block order, gives the oracle's
 H psi and Taylor(4) step to the FP64 bar; the mixed-precision tiles agree
 with each other to FP32 rounding of the same arithmetic.
 
-The grid is a small sphere with ragged rows and a ragged orbital batch
-(13 of 16 columns), so partial tiles in x, y, z and a partial orbital batch
-occur for every shape."""
+The grid is a small sphere with ragged rows, 13 of 16 orbitals in use and
+padding points after every orbital, so partial tiles in x, y and z occur
+for every shape and spare orbitals and padding must stay untouched."""
 import numpy as np
 import pytest
 import torch
@@ -17,13 +17,13 @@ pytestmark = pytest.mark.gpu
 
 ZCS = (0, 4)        # whole z-range, and chunks of 4 planes (several per tile)
 PTS = (0, 1, 2)     # row order, Morton order, 2 x 2 patches
-BOS = (0, 1)        # orbital batch fastest / slowest
+BOS = (0, 1)        # orbital fastest / slowest
 
 
 @pytest.fixture(scope="module")
 def sys_():
     return System(0.3, R=3.1, potential="wells", natoms=2, nst=13, ld=16, seed=71,
-                  dipole_axis=2, rcut=1.2)
+                  dipole_axis=2, rcut=1.2, pad=5)
 
 
 def _variants(dtype):
@@ -51,18 +51,19 @@ def test_every_fp64_tile_matches_oracle(sys_):
     for t in _variants("c128"):
         _set(R, s, t, "c128")
         assert R.get_tile(s.gh, s.nst) == t
-        y = R.hpsi(s.gh, psi, field=field, nst=s.nst).cpu().numpy()
+        y = s.from_gpu(R.hpsi(s.gh, psi, field=field, nst=s.nst))
         e = orbital_rel_err(y, ref_h, s.nst)
         assert e <= 1e-12, (t, e)
         assert not np.any(y[:, s.nst:]), t
         x = psi.clone()
         R.propagate_step(s.gh, x, dt, field=field, nst=s.nst)
-        xs = x.cpu().numpy()
+        xs = s.from_gpu(x)
+        assert s.pad_untouched(x), t
         e = orbital_rel_err(xs, ref_s, s.nst)
         assert e <= 1e-12, (t, e)
         np.testing.assert_array_equal(xs[:, s.nst:], s.psi[:, s.nst:])
         n += 1
-    assert n >= 100
+    assert n >= 150
 
 
 def test_every_mixed_tile_agrees(sys_):
@@ -76,7 +77,7 @@ def test_every_mixed_tile_agrees(sys_):
         _set(R, s, t, "mixed")
         x = psi.clone()
         R.propagate_step(s.gh, x, dt, dtype="mixed", nst=s.nst)
-        xs = x.cpu().numpy()
+        xs = s.from_gpu(x)
         # FP32 Hamiltonian: error of FP32 rounding of a step of size dt |H|
         assert orbital_rel_err(xs, ref_s, s.nst) <= 2e-6, t
         if first is None:
