@@ -120,8 +120,10 @@ def bench_sphere(args):
     dt = cfg["dt"]
     tile = None
     if args.tile:
-        B, TX, TY, ZC, PD, PT, BO = (int(v) for v in args.tile.split(","))
-        rsg.set_tile(gh, nst, B, TX, TY, ZC, PD, PT, BO)
+        vals = [int(v) for v in args.tile.split(",")]
+        B, TX, TY, ZC, PD, PT, BO = vals[:7]
+        ZM = vals[7] if len(vals) > 7 else 0
+        rsg.set_tile(gh, nst, B, TX, TY, ZC, PD, PT, BO, ZM)
         tile = rsg.get_tile(gh, nst)
     elif not args.no_autotune:
         tile, tile_ms = rsg.autotune(gh, psi, reps=2)
@@ -408,7 +410,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape instead of timing the candidates")
     ap.add_argument("--tile", default="",
-                    help="B,TX,TY,ZC,PD,PT,BO: use this stencil tile instead of autotuning")
+                    help="B,TX,TY,ZC,PD,PT,BO[,ZM]: use this stencil tile instead of autotuning")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -249,13 +249,19 @@ int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld
 
 /* Tile of the z-marching stencil kernel: B orbitals (1) x TX x TY grid
  * columns per workgroup, marching along z in chunks of ZC planes (0 = whole
- * box), with PD planes in flight (1..3: pipelined march; 0: lean march).
+ * box), with PD planes in flight (1..2: pipelined march; 0: lean march).
  * PT = 1 launches the tiles of each z-chunk in Morton (Z-curve) order;
  * PT >= 2 launches them in PT x PT patches that share a z-range, so that
- * neighbouring workgroups march together; 0 = row order.  BO = 0 launches the orbitals of a tile
- * together, BO = 1 sweeps all tiles of one orbital before the next. */
+ * neighbouring workgroups march together; 0 = row order.  BO = 0 launches
+ * the orbitals of a tile together, BO = 1 sweeps all tiles of one orbital
+ * before the next, BO = G in 2..64 sweeps the tiles with G orbitals of each
+ * tile side by side.  ZM = 0 marches each tile upward from its lowest plane;
+ * ZM = 1 marches every tile outward from the box's centre plane (upward
+ * above it, downward below it), longest tiles first within a z-chunk, so
+ * that workgroups resident together cover neighbouring tiles at the same
+ * plane. */
 typedef struct {
-    int32_t B, TX, TY, ZC, PD, PT, BO;
+    int32_t B, TX, TY, ZC, PD, PT, BO, ZM;
 } rsg_tile;
 
 /* Compiled tile shapes for a dtype (ZC = 0).  Writes up to max entries and
@@ -268,8 +274,9 @@ int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_tile *t);
 int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
 
 /* Time one Horner stage on psi (device [nst][ldp], left unchanged) for every
- * compiled tile shape and several z-chunk lengths with HIP events (best of
- * reps launches after a warm-up launch), keep the fastest for (nst, dtype)
+ * compiled tile shape, z-chunk lengths {whole, 64, 32}, PT {0, 1}, BO {0, 1,
+ * 2, 4} and ZM {0, 1} with HIP events (best of reps launches after a warm-up launch), keep the
+ * fastest for (nst, dtype)
  * and return it in *best and its time in *best_ms (either may be NULL).
  * ws: RSG_OP_STEP bytes.  Synchronises the stream. */
 int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, void *ws,

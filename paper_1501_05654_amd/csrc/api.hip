@@ -206,10 +206,11 @@ size_t step_ws(const Ham &H, int64_t nst, int64_t ldp, int32_t dtype) {
 }
 
 // Taylor(4) in Horner form: y4 = psi, y_{k-1} = psi + (-i dt / k) H y_k,
-// psi <- y0.  Work buffers alternate; the last stage writes psi in place
-// (each output point reads only its own psi value).
-int step_impl(const Ham &H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
-              double field, const double *field_dev, void *ws, size_t ws_bytes, hipStream_t s) {
+// psi_out <- y0.  Work buffers alternate; every stage reads its base from
+// psi and only the last one writes psi_out, which may be psi itself (each
+// output point reads only its own psi value).
+int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t ldp, int32_t dtype,
+              double dt, double field, const double *field_dev, void *ws, size_t ws_bytes, hipStream_t s) {
     const size_t e = dtype == RSG_C128 ? 16 : 8;
     Carve c(ws, ws_bytes);
     void *w1 = c.take(batch_bytes(nst, ldp, e));
@@ -225,7 +226,7 @@ int step_impl(const Ham &H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, 
     if ((rc = stage_impl(H, psi, 0, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 4.0, field, field_dev, D, s))) return rc;
     if ((rc = stage_impl(H, w1, wt, psi, w2, wt, cmp, nst, ldp, 0.0, -dt / 3.0, field, field_dev, D, s))) return rc;
     if ((rc = stage_impl(H, w2, wt, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 2.0, field, field_dev, D, s))) return rc;
-    return stage_impl(H, w1, wt, psi, psi, 0, cmp, nst, ldp, 0.0, -dt, field, field_dev, D, s);
+    return stage_impl(H, w1, wt, psi, psi_out, 0, cmp, nst, ldp, 0.0, -dt, field, field_dev, D, s);
 }
 
 size_t adjoint_ws(const Ham &H, int64_t nst, int64_t ldp) {
@@ -267,17 +268,15 @@ int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int
     double2 pc[16];
     for (int l = 0; l < 4; ++l)
         for (int m = 0; m < 4; ++m) pc[4 * l + m] = (l + m <= 3) ? a[l + m + 1] : make_double2(0, 0);
-    const double2 *mup[4] = {(const double2 *)mu[0], (const double2 *)mu[1], (const double2 *)mu[2],
-                             (const double2 *)mu[3]};
+    const double2 *mup[5] = {(const double2 *)mu[0], (const double2 *)mu[1], (const double2 *)mu[2],
+                             (const double2 *)mu[3], (const double2 *)mu[4]};
     const double2 *nup[4] = {(const double2 *)nu[0], (const double2 *)nu[1], (const double2 *)nu[2],
                              (const double2 *)nu[3]};
-    if ((rc = launch_cross_dots(*H.g, H.axis, mup, nup, pc, nst, ldp, g_dev, R, rb, s))) return rc;
-    // lambda_n = sum_k conj(a_k) mu_k
+    // lambda_n = sum_k conj(a_k) mu_k, written over mu_0 = lambda by the same
+    // pass that forms the pair sums
     double2 ca[5];
     for (int k = 0; k < 5; ++k) ca[k] = make_double2(a[k].x, -a[k].y);
-    const double2 *src[5] = {(const double2 *)mu[0], (const double2 *)mu[1], (const double2 *)mu[2],
-                             (const double2 *)mu[3], (const double2 *)mu[4]};
-    return launch_axpby_list(*H.g, nst, ldp, 5, src, ca, (double2 *)lambda, s);
+    return launch_adjoint_pass(*H.g, H.axis, mup, nup, pc, ca, (double2 *)lambda, nst, ldp, g_dev, R, rb, s);
 }
 
 // Graph cache key for rsg_propagate.
@@ -513,7 +512,7 @@ extern "C" int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t l
     RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ldp, dtype) - 256 || nst == 0, RSG_ENOMEM,
                 "rsg_propagate_step: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ldp, dtype));
     if (nst == 0 || H->g->np == 0) return RSG_OK;
-    return step_impl(*H, psi, nst, ldp, dtype, dt, field, nullptr, ws, ws_bytes, (hipStream_t)stream);
+    return step_impl(*H, psi, psi, nst, ldp, dtype, dt, field, nullptr, ws, ws_bytes, (hipStream_t)stream);
 }
 
 extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
@@ -530,7 +529,7 @@ extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, i
     hipStream_t s = (hipStream_t)stream;
     auto run = [&]() -> int {
         for (int64_t n = 0; n < nsteps; ++n) {
-            const int r = step_impl(*H, psi, nst, ldp, dtype, dt, 0.0, fields_dev ? fields_dev + n : nullptr,
+            const int r = step_impl(*H, psi, psi, nst, ldp, dtype, dt, 0.0, fields_dev ? fields_dev + n : nullptr,
                                     ws, ws_bytes, s);
             if (r) return r;
         }
@@ -710,7 +709,7 @@ extern "C" int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t 
     if ((rc = rsg_laser_field(coef, ncoef, T, dt, 0, nsteps, fields, stream))) return rc;
     if (ckpt_dev) RSG_CHECK_HIP(hipMemcpyAsync(ckpt_dev, psi, bb, hipMemcpyDeviceToDevice, s));
     for (int64_t n = 0; n < nsteps; ++n) {
-        if ((rc = step_impl(*H, psi, nst, ldp, RSG_C128, dt, 0.0, fields + n, sws, rest, s))) return rc;
+        if ((rc = step_impl(*H, psi, psi, nst, ldp, RSG_C128, dt, 0.0, fields + n, sws, rest, s))) return rc;
         if (ckpt_dev && (n + 1) % ckpt_every == 0)
             RSG_CHECK_HIP(hipMemcpyAsync((char *)ckpt_dev + (size_t)((n + 1) / ckpt_every) * bb, psi, bb,
                                          hipMemcpyDeviceToDevice, s));
@@ -753,17 +752,16 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t s0 = seg * ckpt_every, s1 = std::min(nsteps, s0 + ckpt_every);
-        // states[k] = psi_{s0 + k}, k = 0 .. s1 - s0 - 1
-        RSG_CHECK_HIP(hipMemcpyAsync(states, (const char *)ckpt_dev + (size_t)seg * bb, bb,
-                                     hipMemcpyDeviceToDevice, s));
-        for (int64_t k = 1; k < s1 - s0; ++k) {
-            RSG_CHECK_HIP(hipMemcpyAsync(states + k * bbr, states + (k - 1) * bbr, bb, hipMemcpyDeviceToDevice, s));
-            if ((rc = step_impl(*H, states + k * bbr, nst, ldp, RSG_C128, dt, 0.0, fields + s0 + k - 1, sws, rest, s)))
+        // st(k) = psi_{s0 + k}, k = 0 .. s1 - s0 - 1: the checkpoint, then
+        // states recomputed out of place from it
+        const char *ck = (const char *)ckpt_dev + (size_t)seg * bb;
+        auto st = [&](int64_t k) -> const char * { return k == 0 ? ck : states + k * bbr; };
+        for (int64_t k = 1; k < s1 - s0; ++k)
+            if ((rc = step_impl(*H, st(k - 1), states + k * bbr, nst, ldp, RSG_C128, dt, 0.0,
+                                fields + s0 + k - 1, sws, rest, s)))
                 return rc;
-        }
         for (int64_t n = s1 - 1; n >= s0; --n) {
-            if ((rc = adjoint_impl(*H, states + (n - s0) * bbr, lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws,
-                                   rest, s)))
+            if ((rc = adjoint_impl(*H, st(n - s0), lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws, rest, s)))
                 return rc;
         }
     }
@@ -778,7 +776,7 @@ extern "C" int rsg_tile_candidates(int32_t dtype, rsg_tile *out, int32_t max, in
     RSG_REQUIRE(count && (max <= 0 || out), RSG_EINVAL, "rsg_tile_candidates: null output");
     const auto v = tile_candidates(tile_compute(dtype));
     *count = (int32_t)v.size();
-    for (int32_t k = 0; k < max && k < (int32_t)v.size(); ++k) out[k] = rsg_tile{v[k].B, v[k].TX, v[k].TY, 0, v[k].PD, 0, 0};
+    for (int32_t k = 0; k < max && k < (int32_t)v.size(); ++k) out[k] = rsg_tile{v[k].B, v[k].TX, v[k].TY, 0, v[k].PD, 0, 0, 0};
     return RSG_OK;
 }
 
@@ -794,11 +792,13 @@ extern "C" int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_t
     RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_set_tile: %dx%dx%d (depth %d) is not a compiled tile shape", t->B,
                 t->TX, t->TY, t->PD);
     RSG_REQUIRE(t->PT >= 0 && t->PT <= 64, RSG_EINVAL, "rsg_set_tile: PT must be in 0..64");
-    RSG_REQUIRE(t->BO == 0 || t->BO == 1, RSG_EINVAL, "rsg_set_tile: BO must be 0 or 1");
+    RSG_REQUIRE(t->BO >= 0 && t->BO <= 64, RSG_EINVAL, "rsg_set_tile: BO must be in 0..64");
+    RSG_REQUIRE(t->ZM == 0 || t->ZM == 1, RSG_EINVAL, "rsg_set_tile: ZM must be 0 or 1");
     TileShape sh{t->B, t->TX, t->TY, t->ZC};
     sh.PD = pd;
     sh.PT = t->PT;
     sh.BO = t->BO;
+    sh.ZM = t->ZM;
     H->tiles[std::make_pair(nst, tile_compute(dtype))] = sh;
     drop_graphs(H);
     return RSG_OK;
@@ -809,13 +809,13 @@ extern "C" int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t
     RSG_REQUIRE(H && t, RSG_EINVAL, "rsg_get_tile: null argument");
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_get_tile: bad dtype");
     const TileShape s = H->tile_for(nst, tile_compute(dtype));
-    *t = rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, s.PT, s.BO};
+    *t = rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, s.PT, s.BO, s.ZM};
     return RSG_OK;
 }
 
 // Times one Horner stage (out = psi + c H psi into the workspace, psi
-// untouched) for every compiled tile shape and z-chunk length, keeps the
-// fastest for (nst, dtype) and reports it.
+// untouched) for every compiled tile shape, z-chunk length, tile order,
+// block order and z-march, keeps the fastest for (nst, dtype) and reports it.
 extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype,
                             void *ws, size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms,
                             void *stream) {
@@ -839,6 +839,8 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         for (int z : {64, 32})
             if (z < H->g->n[2]) zcs.push_back(z);
         const std::vector<int> pts = {0, 1};
+        const std::vector<int> bos = {0, 1, 2, 4};
+        const int nzp = (int)(zcs.size() * pts.size()), nvar = nzp * (int)bos.size() * 2;  // x BO x ZM
         hipEvent_t e0, e1;
         RSG_CHECK_HIP(hipEventCreate(&e0));
         RSG_CHECK_HIP(hipEventCreate(&e1));
@@ -846,12 +848,13 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         TileShape bs = default_shape(*H->g, nst, cmp);
         int err = RSG_OK;
         for (const auto &cand : tile_candidates(cmp)) {
-            for (int zpi = 0; zpi < (int)(zcs.size() * pts.size() * 2); ++zpi) {
+            for (int zpi = 0; zpi < nvar; ++zpi) {
                 const int zc = zcs[zpi % zcs.size()];
                 TileShape sh = cand;
                 sh.ZC = zc > 0 ? zc : H->g->n[2];
                 sh.PT = pts[(zpi / zcs.size()) % pts.size()];
-                sh.BO = zpi / (int)(zcs.size() * pts.size());
+                sh.BO = bos[(zpi / nzp) % bos.size()];
+                sh.ZM = zpi / (nzp * (int)bos.size());
                 if (!H->g->plan(sh, s, &err)) break;
                 StageArgs a;
                 a.in = psi;
@@ -888,7 +891,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         if (rc) return rc;
         H->tiles[std::make_pair(nst, cmp)] = bs;
         drop_graphs(H);
-        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, bs.PT, bs.BO};
+        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, bs.PT, bs.BO, bs.ZM};
         if (best_ms) *best_ms = bt;
         return RSG_OK;
     });

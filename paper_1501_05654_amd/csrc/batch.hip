@@ -98,7 +98,7 @@ int build_tables(Batch &b, hipStream_t s) {
         TileShape sh = b.tile;
         sh.PT = 0;
         sh.BO = 0;
-        sh.ZC = sh.ZC > 0 ? sh.ZC : H.g->n[2];
+        sh.ZC = sh.ZC > 0 ? sh.ZC : H.g->n[2];  // ZM as chosen for the batch
         const TilePlan *plan = H.g->plan(sh, s, &err);
         if (!plan) return err;
         // copy the plan's items back to the host to expand them per orbital
@@ -276,15 +276,17 @@ extern "C" int rsg_batch_set_tile(rsg_batch_t b, const rsg_tile *t, void *stream
     for (const auto &c : tile_candidates(0)) ok = ok || (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == t->PD);
     RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_batch_set_tile: not a compiled FP64 tile");
     RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "rsg_batch_set_tile: ZC must be >= 0");
+    RSG_REQUIRE(t->ZM == 0 || t->ZM == 1, RSG_EINVAL, "rsg_batch_set_tile: ZM must be 0 or 1");
     b->tile = TileShape{t->B, t->TX, t->TY, t->ZC};
     b->tile.PD = t->PD;
+    b->tile.ZM = t->ZM;
     return guarded([&]() { return build_tables(*b, (hipStream_t)stream); });
 }
 
 extern "C" int rsg_batch_get_tile(rsg_batch_t b, rsg_tile *t) {
     clear_error();
     RSG_REQUIRE(b && t, RSG_EINVAL, "rsg_batch_get_tile: null argument");
-    *t = rsg_tile{b->tile.B, b->tile.TX, b->tile.TY, b->tile.ZC, b->tile.PD, 0, 0};
+    *t = rsg_tile{b->tile.B, b->tile.TX, b->tile.TY, b->tile.ZC, b->tile.PD, 0, 0, b->tile.ZM};
     return RSG_OK;
 }
 
@@ -300,9 +302,10 @@ extern "C" int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, d
         TileShape bs = b->tile;
         int rc = RSG_OK;
         for (const auto &cand : tile_candidates(0)) {
-            for (int zc : {0, 32}) {
+            for (int zv = 0; zv < 4; ++zv) {
                 b->tile = cand;
-                b->tile.ZC = zc;
+                b->tile.ZC = (zv & 1) ? 32 : 0;
+                b->tile.ZM = zv >> 1;
                 if ((rc = build_tables(*b, s))) break;
                 double tmin = 1e300;
                 for (int r = 0; r <= reps; ++r) {
@@ -331,7 +334,7 @@ extern "C" int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, d
         const int r2 = build_tables(*b, s);
         if (rc) return rc;
         if (r2) return r2;
-        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, 0, 0};
+        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, 0, 0, bs.ZM};
         if (best_ms) *best_ms = bt;
         return RSG_OK;
     });

@@ -10,6 +10,7 @@
 #include "rsg_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 
@@ -101,16 +102,25 @@ Grid::~Grid() {
 }
 
 // Work items for one tile shape: every (tx, ty) tile that holds box points,
-// with its z-extent split into chunks of at most ZC planes.  PT = 0: items
-// are ordered z-chunk major, then ty, then tx.  PT = 1: z-chunk major, then
-// the Morton (Z-curve) order of (tx, ty).  PT >= 2: patches,
-// tiles are grouped into PT x PT patches; all tiles of a patch march over the
-// patch's common z-extent, and items are ordered patch-major, then chunk,
-// then tile, so that a patch's workgroups are launched together.
+// with its z-extent split into chunks of at most ZC planes.  Within a chunk
+// the tiles follow row order (PT = 0: ty, then tx) or the Morton (Z-curve)
+// order of (tx, ty) (PT = 1).
+//   ZM = 0: chunks start at each tile's lowest plane and march upward; items
+//     are ordered chunk-major.
+//   ZM = 1: chunks are aligned to the box's centre plane zc = nz / 2; planes
+//     >= zc march upward from zc, planes < zc downward from zc - 1, chunk by
+//     chunk outward (up-chunk j, then down-chunk j), and within a chunk the
+//     tiles with the most planes come first.  Tiles resident together then
+//     start on the same plane and advance together, so neighbours read each
+//     other's planes from L2 while they are still there.
+//   PT >= 2 (with ZM = 0): tiles are grouped into PT x PT patches; all tiles
+//     of a patch march over the patch's common z-extent, and items are ordered
+//     patch-major, then chunk, then tile.
 const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
     TileShape key{0, s.TX, s.TY, s.ZC};
     key.PD = 0;
     key.PT = s.PT;
+    key.ZM = s.ZM;
     auto it = plans.find(key);
     if (it != plans.end()) return &it->second;
     const int nx = n[0], ny = n[1], nz = n[2];
@@ -128,44 +138,51 @@ const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
                 zhi[k] = std::max(zhi[k], z);
             }
         }
-    std::vector<int4> items;
+    // non-empty tiles in the order used inside a z-chunk
+    std::vector<int> order;
+    for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx)
+            if (zhi[(size_t)ty * ntx + tx] >= zlo[(size_t)ty * ntx + tx]) order.push_back(ty * ntx + tx);
     if (s.PT == 1) {
-        // Morton (Z-curve) order of the tiles within each z-chunk: launch
-        // neighbours are spatial neighbours in both x and y
         auto spread = [](uint32_t v) {
             uint64_t r = 0;
             for (int b = 0; b < 16; ++b) r |= (uint64_t)((v >> b) & 1u) << (2 * b);
             return r;
         };
-        std::vector<std::pair<uint64_t, int>> order;
-        for (int ty = 0; ty < nty; ++ty)
-            for (int tx = 0; tx < ntx; ++tx)
-                if (zhi[(size_t)ty * ntx + tx] >= zlo[(size_t)ty * ntx + tx])
-                    order.emplace_back(spread((uint32_t)tx) | (spread((uint32_t)ty) << 1), ty * ntx + tx);
-        std::sort(order.begin(), order.end());
+        auto key_of = [&](int k) { return spread((uint32_t)(k % ntx)) | (spread((uint32_t)(k / ntx)) << 1); };
+        std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return key_of(p) < key_of(q); });
+    }
+    std::vector<int4> items;
+    if (s.ZM == 1) {
+        const int zc = nz / 2, L = s.ZC;
+        const int nup = (nz - zc + L - 1) / L, ndn = (zc + L - 1) / L;
+        for (int j = 0; j < std::max(nup, ndn); ++j)
+            for (int half = 0; half < 2; ++half) {
+                std::vector<int4> chunk;
+                for (const int k : order) {
+                    const int tx = k % ntx, ty = k / ntx;
+                    if (half == 0) {
+                        const int a = std::max(zlo[k], zc + j * L), b = std::min(zhi[k] + 1, zc + (j + 1) * L);
+                        if (a < b) chunk.push_back(make_int4(tx, ty, a, b));
+                    } else {
+                        const int hi = std::min(zhi[k], zc - 1 - j * L), lo = std::max(zlo[k], zc - (j + 1) * L);
+                        if (hi >= lo) chunk.push_back(make_int4(tx, ty, hi, lo - 1));
+                    }
+                }
+                std::stable_sort(chunk.begin(), chunk.end(), [](const int4 &p, const int4 &q) {
+                    return std::abs(p.w - p.z) > std::abs(q.w - q.z);
+                });
+                items.insert(items.end(), chunk.begin(), chunk.end());
+            }
+    } else if (s.PT <= 1) {
         int maxchunks = 0;
-        for (size_t k = 0; k < zlo.size(); ++k)
-            if (zhi[k] >= zlo[k]) maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);
+        for (const int k : order) maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);
         for (int c = 0; c < maxchunks; ++c)
-            for (const auto &o : order) {
-                const int k = o.second, tx = k % ntx, ty = k / ntx;
+            for (const int k : order) {
                 const int z0 = zlo[k] + c * s.ZC;
                 if (z0 > zhi[k]) continue;
-                items.push_back(make_int4(tx, ty, z0, std::min(zhi[k] + 1, z0 + s.ZC)));
+                items.push_back(make_int4(k % ntx, k / ntx, z0, std::min(zhi[k] + 1, z0 + s.ZC)));
             }
-    } else if (s.PT <= 0) {
-        int maxchunks = 0;
-        for (size_t k = 0; k < zlo.size(); ++k)
-            if (zhi[k] >= zlo[k]) maxchunks = std::max(maxchunks, (zhi[k] - zlo[k] + s.ZC) / s.ZC);
-        for (int c = 0; c < maxchunks; ++c)
-            for (int ty = 0; ty < nty; ++ty)
-                for (int tx = 0; tx < ntx; ++tx) {
-                    const size_t k = (size_t)ty * ntx + tx;
-                    if (zhi[k] < zlo[k]) continue;
-                    const int z0 = zlo[k] + c * s.ZC;
-                    if (z0 > zhi[k]) continue;
-                    items.push_back(make_int4(tx, ty, z0, std::min(zhi[k] + 1, z0 + s.ZC)));
-                }
     } else {
         const int npx = (ntx + s.PT - 1) / s.PT, npy = (nty + s.PT - 1) / s.PT;
         for (int py = 0; py < npy; ++py)

@@ -118,11 +118,15 @@ __global__ void __launch_bounds__(RB) k_reduce_final(const double *part, int64_t
     }
 }
 
-// Adjoint pair sums: per orbital, sum_r sum_{l+m<=3} coef[l][m] conj(mu_l) x nu_m.
+// Adjoint pass: per orbital, the pair sum sum_r sum_{l+m<=3} coef[l][m]
+// conj(mu_l) x nu_m, and the new costate lam = sum_k ca[k] mu_k (k = 0..4)
+// written at the same point in the same pass.
 struct XArgs {
-    const double2 *mu[4];
+    const double2 *mu[5];
     const double2 *nu[4];
     double2 coef[4][4];
+    double2 ca[5];
+    double2 *lam;
     const int32_t *ijk;
     int64_t np, nst, ldp, chunk;
     double h, off;
@@ -130,7 +134,7 @@ struct XArgs {
     double *part;
 };
 
-__global__ void __launch_bounds__(RB) k_cross_partial(XArgs r) {
+__global__ void __launch_bounds__(RB) k_adjoint_pass(XArgs r) {
     __shared__ double red[RB / 64][2];
     const int64_t n = blockIdx.y;
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
@@ -139,9 +143,11 @@ __global__ void __launch_bounds__(RB) k_cross_partial(XArgs r) {
     for (int64_t p = p0 + threadIdx.x; p < p1; p += RB) {
         const int64_t e = n * r.ldp + p;
         const double xc = r.h * ((double)r.ijk[3 * p + r.axis] - r.off);
-        double2 nu[4];
+        double2 nu[4], mu[5];
 #pragma unroll
         for (int m = 0; m < 4; ++m) nu[m] = r.nu[m][e];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) mu[l] = r.mu[l][e];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             double wr = 0.0, wi = 0.0;  // w_l = sum_m coef[l][m] nu_m
@@ -150,10 +156,16 @@ __global__ void __launch_bounds__(RB) k_cross_partial(XArgs r) {
                 wr += r.coef[l][m].x * nu[m].x - r.coef[l][m].y * nu[m].y;
                 wi += r.coef[l][m].x * nu[m].y + r.coef[l][m].y * nu[m].x;
             }
-            const double2 mu = r.mu[l][e];
-            re += xc * (mu.x * wr + mu.y * wi);
-            im += xc * (mu.x * wi - mu.y * wr);
+            re += xc * (mu[l].x * wr + mu[l].y * wi);
+            im += xc * (mu[l].x * wi - mu[l].y * wr);
         }
+        double lr = 0.0, li = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            lr += r.ca[k].x * mu[k].x - r.ca[k].y * mu[k].y;
+            li += r.ca[k].x * mu[k].y + r.ca[k].y * mu[k].x;
+        }
+        r.lam[e] = make_double2(lr, li);
     }
     block_sum(re, im, red);
     if (threadIdx.x == 0) {
@@ -172,31 +184,13 @@ __global__ void k_two_re_sum(const double *per, int64_t nst, double *dst) {
 }
 
 struct PwArgs {
-    const double2 *src[5];
-    double2 coef[5];
+    const double2 *src[1];
     double2 *dst;
     const int32_t *ijk;
     int64_t np, nst, ldp;
     double h, off;
-    int32_t axis, nterms;
+    int32_t axis;
 };
-
-// dst = sum_k coef_k src_k (complex coefficients), over the first np points
-// of orbital blockIdx.y.
-__global__ void k_lincomb(PwArgs a) {
-    const int64_t base = (int64_t)blockIdx.y * a.ldp;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.np;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = base + p;
-        double re = 0.0, im = 0.0;
-        for (int k = 0; k < a.nterms; ++k) {
-            const double2 v = a.src[k][e];
-            re += a.coef[k].x * v.x - a.coef[k].y * v.y;
-            im += a.coef[k].x * v.y + a.coef[k].y * v.x;
-        }
-        a.dst[e] = make_double2(re, im);
-    }
-}
 
 // dst = x_axis * src.
 __global__ void k_mul_axis(PwArgs a) {
@@ -262,9 +256,9 @@ int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const dou
     return RSG_OK;
 }
 
-int launch_cross_dots(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
-                      const double2 *pair_coef, int64_t nst, int64_t ldp, double *out, void *ws,
-                      size_t ws_bytes, hipStream_t s) {
+int launch_adjoint_pass(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
+                        const double2 *pair_coef, const double2 *lam_coef, double2 *lam, int64_t nst,
+                        int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s) {
     if (ws_bytes < reduce_workspace_bytes(g, nst)) {
         set_error("adjoint reduction workspace too small");
         return RSG_ENOMEM;
@@ -275,11 +269,15 @@ int launch_cross_dots(const Grid &g, int axis, const double2 *const *mu, const d
     }
     const int64_t nblk = reduce_blocks(g.np);
     XArgs r;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
         r.mu[k] = mu[k];
+        r.ca[k] = lam_coef[k];
+    }
+    for (int k = 0; k < 4; ++k) {
         r.nu[k] = nu[k];
         for (int m = 0; m < 4; ++m) r.coef[k][m] = pair_coef[4 * k + m];
     }
+    r.lam = lam;
     r.ijk = g.ijk;
     r.np = g.np;
     r.nst = nst;
@@ -291,32 +289,10 @@ int launch_cross_dots(const Grid &g, int axis, const double2 *const *mu, const d
     r.part = (double *)ws;
     double *per = r.part + nblk * nst * 2;
     const dim3 grid((unsigned)nblk, (unsigned)nst);
-    k_cross_partial<<<grid, RB, 0, s>>>(r);
+    k_adjoint_pass<<<grid, RB, 0, s>>>(r);
     const double h3 = g.h * g.h * g.h;
     k_reduce_final<<<(unsigned)nst, RB, 0, s>>>(r.part, nblk, nst, 2, h3, per);
     k_two_re_sum<<<1, 64, 0, s>>>(per, nst, out);
-    RSG_CHECK_HIP(hipGetLastError());
-    return RSG_OK;
-}
-
-int launch_axpby_list(const Grid &g, int64_t nst, int64_t ldp, int nterms, const double2 *const *src,
-                      const double2 *coef, double2 *dst, hipStream_t s) {
-    if (nst == 0 || g.np == 0) return RSG_OK;
-    if (nst > 65535) {
-        set_error("pointwise: at most 65535 orbitals per call");
-        return RSG_EUNSUPPORTED;
-    }
-    PwArgs a;
-    for (int k = 0; k < nterms; ++k) {
-        a.src[k] = src[k];
-        a.coef[k] = coef[k];
-    }
-    a.nterms = nterms;
-    a.dst = dst;
-    a.np = g.np;
-    a.nst = nst;
-    a.ldp = ldp;
-    k_lincomb<<<pw_grid(g.np, nst), 256, 0, s>>>(a);
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }

@@ -58,12 +58,15 @@ int guarded(F &&f) {
 // lean march).  PT = 1 launches the tiles of a z-chunk in Morton order;
 // PT > 1 groups tiles into PT x PT patches that share one z-range and are
 // launched consecutively.  BO is the block order (0: orbital fastest,
-// 1: orbital slowest).  The launch plan depends on (TX, TY, ZC, PT).
+// 1: orbital slowest).  ZM = 1 marches from the box's centre plane outward
+// (upward above it, downward below it) with the longest tiles of each
+// z-chunk first.  The launch plan depends on (TX, TY, ZC, PT, ZM).
 struct TileShape {
     int B, TX, TY, ZC;
     int PD = 1;
     int PT = 0;
-    int BO = 0;  // block order: 0 = orbital fastest, 1 = orbital slowest
+    int BO = 0;  // block order: 0 = orbital fastest, 1 = orbital slowest, G >= 2 = groups of G orbitals
+    int ZM = 0;  // z-march: 0 = upward from each tile's lowest plane, 1 = outward from the centre
     bool operator<(const TileShape &o) const {
         if (B != o.B) return B < o.B;
         if (TX != o.TX) return TX < o.TX;
@@ -71,12 +74,14 @@ struct TileShape {
         if (ZC != o.ZC) return ZC < o.ZC;
         if (PD != o.PD) return PD < o.PD;
         if (PT != o.PT) return PT < o.PT;
-        return BO < o.BO;
+        if (BO != o.BO) return BO < o.BO;
+        return ZM < o.ZM;
     }
 };
 
-// Work items of one tile shape on one grid: (tx, ty, z0, z1) per item,
-// items ordered z-chunk major, then ty, then tx.
+// Work items of one tile shape on one grid: (tx, ty, zs, ze) per item: the
+// tile marches over planes zs, zs + dir, ... up to ze exclusive, dir = +1 if
+// ze > zs, else -1.
 struct TilePlan {
     int4 *items = nullptr;  // device
     int32_t nitems = 0;
@@ -168,7 +173,7 @@ struct KParams {
     double off[3];
     double cre, cim;
     int32_t nitems;
-    int32_t batch_slowest;
+    int32_t block_order;
     int32_t ny, nz;
     int32_t axis;
 };
@@ -222,13 +227,15 @@ int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const dou
                   int64_t nst, int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s);
 
 // Pointwise helpers.
-int launch_axpby_list(const Grid &g, int64_t nst, int64_t ldp, int nterms, const double2 *const *src,
-                      const double2 *coef, double2 *dst, hipStream_t s);
 int launch_mul_axis(const Grid &g, int axis, const double2 *src, double2 *dst, int64_t nst,
                     int64_t ldp, hipStream_t s);
-int launch_cross_dots(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
-                      const double2 *pair_coef, int64_t nst, int64_t ldp, double *out, void *ws,
-                      size_t ws_bytes, hipStream_t s);
+// One pass of the discrete adjoint over mu_0..mu_4 (H^k lambda_{n+1}) and
+// nu_0..nu_3 (H^m psi_n): *out = 2 Re sum_n h^3 sum_r sum_{l+m<=3}
+// pair_coef[4l+m] conj(mu_l) x_axis nu_m, and lam = sum_k lam_coef[k] mu_k
+// (lam may be mu_0: each point is read before it is written).
+int launch_adjoint_pass(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
+                        const double2 *pair_coef, const double2 *lam_coef, double2 *lam, int64_t nst,
+                        int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s);
 int launch_accumulate(const double *src, double *dst, hipStream_t s);
 
 // Kernel timing hooks around stencil launches.

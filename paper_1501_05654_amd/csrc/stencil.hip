@@ -19,7 +19,8 @@
 //   - a thread owns one column and keeps its complex value on the planes
 //     z-4..z+4 in registers (z taps), plus the planes in flight;
 //   - the current plane, with a 4-point x/y halo, is staged in LDS for the
-//     x and y taps; the halo comes from the neighbouring tiles through L2;
+//     x and y taps (two plane buffers used in turn, so one barrier per plane
+//     suffices); the halo comes from the neighbouring tiles through L2;
 //   - x runs fastest over the threads, so a wave's loads are runs of TX
 //     consecutive 16-byte values;
 //   - loads of later planes are issued before the current plane is computed
@@ -59,15 +60,25 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 // Block order.  Orbital slowest (BO = 1): each XCD sweeps the tiles of one
 // orbital at a time, so neighbouring tiles march together and find each
-// other's halos in L2.  Orbital fastest (BO = 0): the orbitals of one tile
-// march together and share V and the row table in L2.
+// other's halos and shared row-boundary lines in L2.  Orbital fastest
+// (BO = 0): the orbitals of one tile march together and share V and the row
+// table in L2.  BO = G >= 2: orbitals in groups of G, each group sweeping
+// the tiles with its G orbitals of a tile side by side (V read once per
+// group from HBM, neighbouring tiles still resident together).
 __device__ __forceinline__ void block_item(const KParams &a, int blk, int *n, int *item) {
-    if (a.batch_slowest) {
+    const int nst = (int)a.nst;
+    if (a.block_order == 0) {
+        *item = blk / nst;
+        *n = blk - *item * nst;
+    } else if (a.block_order == 1) {
         *n = blk / a.nitems;
         *item = blk - *n * a.nitems;
     } else {
-        *item = blk / (int)a.nst;
-        *n = blk - *item * (int)a.nst;
+        const int G = a.block_order, per = a.nitems * G;
+        const int g = blk / per, r = blk - g * per;
+        const int gs = min(G, nst - g * G);  // orbitals in this group
+        *item = r / gs;
+        *n = g * G + (r - *item * gs);
     }
 }
 
@@ -94,8 +105,17 @@ typedef int v2i_t __attribute__((ext_vector_type(2)));
 constexpr unsigned OOB = 0x80000000u;    // byte offset beyond every buffer used here
 constexpr int RSRC_WORD3 = 0x00020000;   // resource format word of the gfx9 family
 
+// Every operand base and size is the same for all lanes of a workgroup;
+// reading them through the first lane tells the compiler so, which keeps
+// the resource in scalar registers instead of a per-lane loop around each
+// buffer instruction.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, RSRC_WORD3);
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    const int nb = __builtin_amdgcn_readfirstlane((int)bytes);
+    void *q = (void *)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, nb, RSRC_WORD3);
 }
 template <class T>
 __device__ __forceinline__ unsigned boff(int idx) {
@@ -203,26 +223,33 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
     }
 }
 
-// Software-pipelined march, depth D = 1..3.  At step z (output plane z) a
-// thread
-//   - issues the row-table reads for the loads of step z+1,
-//   - issues the data loads of plane z+4+D (own column), of the halo of
-//     plane z+D and of V and base at plane z+D, from row entries read one
-//     step earlier,
-//   - computes plane z from data that arrived during earlier steps.
-// All rings are indexed by compile-time constants after unrolling the z loop
-// by a common period, so no register is moved while its load is in flight.
-// FIRST: base == in, whose value at the point is the centre tap.
+// Software-pipelined march, depth D = 1..2, over the item's planes zs, zs +
+// dir, ... (dir = +1 upward, -1 downward; the stencil is symmetric in z).
+// At step k (output plane z = zs + dir k) a thread
+//   - issues the row-table reads for the loads of step k+1,
+//   - issues the data loads of plane k+4+D (own column), of the halo of plane
+//     k+HA and of V and base at plane k+D, from row entries read one step
+//     earlier,
+//   - computes plane k from data that arrived during earlier steps.
+// HA = 4+D when each thread carries one halo value (the halo of a plane is
+// then loaded in the same step as the plane's own columns, by this and by
+// the neighbouring workgroups, while the lines are in L2), else HA = D.
+// All rings are indexed by compile-time constants after unrolling the step
+// loop by a common period, so no register is moved while its load is in
+// flight.  FIRST: base == in, whose value at the point is the centre tap.
 template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
 __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile) {
     using C2 = typename CT<Tc>::c2;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
-    constexpr int Q = D == 1 ? 10 : 12;  // >= 9 + D, keeps the unroll period at 10 or 12
-    static_assert(D >= 1 && D <= 3, "pipeline depth 1..3");
-    constexpr int VD = D + 1;
-    constexpr int P = clcm(clcm(clcm(Q, D), VD), 2);
+    static_assert(D >= 1 && D <= 2, "pipeline depth 1..2");
+    constexpr int Q = D == 1 ? 10 : 12;        // own-column ring, >= 9 + D
+    constexpr int HA = HPT == 1 ? 4 + D : D;   // planes ahead at which the halo is loaded
+    constexpr int HQ = HA;                     // halo ring slots
+    constexpr int VD = D + 1;                  // V / base ring slots
+    constexpr int P = clcm(clcm(clcm(clcm(Q, D), VD), 2), HQ);
+    constexpr int PLANE = (TY + 8) * LX;       // one plane buffer; tile holds two
     const int t = threadIdx.x, lx = t % TX, ly = t / TX;
     const int x = it.x * TX + lx, y = it.y * TY + ly;
     const int64_t np = a.np;
@@ -239,35 +266,41 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
 
-    const int z0 = it.z, z1 = it.w;
-    // prologue: planes z0-4 .. z0+3+D into ring slots 0 .. Q-2 (slot of plane
-    // z0 + m is m + 4), halo/V/base of planes z0 .. z0+D-1, rows for step z0
+    const int zs = it.z, dir = it.w > it.z ? 1 : -1;
+    const int nk = (it.w - it.z) * dir;  // planes to compute
+    // prologue: planes k = -4 .. 3+D into ring slots 0 .. Q-2 (slot of plane
+    // k is k + 4), halo of planes 0 .. HA-1, V/base of planes 0 .. D-1, rows
+    // for step 0
     C2 cv[Q];
     int oid[Q];
 #pragma unroll
     for (int j = 0; j < Q - 1; ++j) {
-        oid[j] = idx_in_row(row_of(a, y, z0 - 4 + j), x);
+        oid[j] = idx_in_row(row_of(a, y, zs + dir * (j - 4)), x);
         cv[j] = fetch(oid[j], true);
     }
     cv[Q - 1] = C2{(Tc)0, (Tc)0};
     oid[Q - 1] = -1;
-    C2 hal[D][HPT];
+    C2 hal[HQ][HPT];
+#pragma unroll
+    for (int d = 0; d < HQ; ++d)
+#pragma unroll
+        for (int k = 0; k < HPT; ++k)
+            hal[d][k] = d < HA ? fetch(idx_in_row(row_of(a, hl.y[k], zs + dir * d), hl.x[k]), hl.ok[k] && d < nk)
+                               : C2{(Tc)0, (Tc)0};
     Tc vr[VD];
     double2 br[VD];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-#pragma unroll
-        for (int k = 0; k < HPT; ++k) hal[d][k] = fetch(idx_in_row(row_of(a, hl.y[k], z0 + d), hl.x[k]), hl.ok[k]);
         vr[d] = fetch_v(oid[4 + d]);
         br[d] = fetch_b(oid[4 + d]);
     }
     vr[D] = (Tc)0;
     br[D] = make_double2(0.0, 0.0);
-    // step z reads row slot (z - z0) % 2 and fills the other one
+    // step k reads row slot k % 2 and fills the other one
     int2 rfr[2], rhl[2][HPT];
-    rfr[0] = row_of(a, y, z0 + 4 + D);
+    rfr[0] = row_of(a, y, zs + dir * (4 + D));
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of(a, hl.y[k], z0 + D);
+    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of(a, hl.y[k], zs + dir * HA);
     rfr[1] = make_int2(0, 0);
 #pragma unroll
     for (int k = 0; k < HPT; ++k) rhl[1][k] = make_int2(0, 0);
@@ -275,44 +308,50 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     const double E = a.field_dev ? *a.field_dev : a.field;
     const int own = (ly + 4) * LX + lx + 4;
 
-    for (int zb = z0; zb < z1; zb += P) {
+    for (int kb = 0; kb < nk; kb += P) {
 #pragma unroll
         for (int s = 0; s < P; ++s) {
-            const int z = zb + s;
-            if (z >= z1) break;
-            const int sd = s % D, sr = s % 2, srp = (s + 1) % 2;
+            const int k = kb + s;
+            if (k >= nk) break;
+            const int z = zs + dir * k;
+            const int sh = s % HQ, sr = s % 2, srp = (s + 1) % 2;
+            const int shl = (s + HA) % HQ;              // halo slot of plane k + HA
             const int sv = s % VD, svn = (s + D) % VD;  // V/base: read slot, load slot
+            // ring slot of plane k + m
 #define SLOT(m) ((s + (m) + 4 + Q) % Q)
-            tile[own] = cv[SLOT(0)];
+            C2 *const pl = tile + (s % 2) * PLANE;  // plane buffer of this step
+            pl[own] = cv[SLOT(0)];
 #pragma unroll
-            for (int k = 0; k < HPT; ++k)
-                if (hl.ok[k]) tile[hl.l[k]] = hal[sd][k];
+            for (int j = 0; j < HPT; ++j)
+                if (hl.ok[j]) pl[hl.l[j]] = hal[sh][j];
             const int idx_c = oid[SLOT(0)];
             const Tc v_c = vr[sv];
             const double2 b_c = br[sv];
             __syncthreads();
             {
-                rfr[srp] = row_of(a, y, z + 5 + D);
+                // row entries for the next step first, then the loads that use
+                // the entries read last step
+                rfr[srp] = row_of(a, y, z + dir * (5 + D));
 #pragma unroll
-                for (int k = 0; k < HPT; ++k) rhl[srp][k] = row_of(a, hl.y[k], z + 1 + D);
-                const int idf = (z + 4 + D < z1 + 4) ? idx_in_row(rfr[sr], x) : -1;
+                for (int j = 0; j < HPT; ++j) rhl[srp][j] = row_of(a, hl.y[j], z + dir * (1 + HA));
+                const int idf = (k + 4 + D < nk + 4) ? idx_in_row(rfr[sr], x) : -1;
                 oid[SLOT(4 + D)] = idf;
                 cv[SLOT(4 + D)] = fetch(idf, true);
-                const bool live = z + D < z1;
+                const bool hlive = k + HA < nk;
 #pragma unroll
-                for (int k = 0; k < HPT; ++k)
-                    hal[sd][k] = fetch(idx_in_row(rhl[sr][k], hl.x[k]), hl.ok[k] && live);
-                const int idv = live ? oid[SLOT(D)] : -1;
+                for (int j = 0; j < HPT; ++j)
+                    hal[shl][j] = fetch(idx_in_row(rhl[sr][j], hl.x[j]), hl.ok[j] && hlive);
+                const int idv = k + D < nk ? oid[SLOT(D)] : -1;
                 vr[svn] = fetch_v(idv);
                 br[svn] = fetch_b(idv);
             }
             const C2 q0 = cv[SLOT(0)];
             Tc lr, li;
             {
-                const C2 xm1 = tile[own - 1], xp1 = tile[own + 1], xm2 = tile[own - 2], xp2 = tile[own + 2];
-                const C2 xm3 = tile[own - 3], xp3 = tile[own + 3], xm4 = tile[own - 4], xp4 = tile[own + 4];
-                const C2 ym1 = tile[own - LX], yp1 = tile[own + LX], ym2 = tile[own - 2 * LX], yp2 = tile[own + 2 * LX];
-                const C2 ym3 = tile[own - 3 * LX], yp3 = tile[own + 3 * LX], ym4 = tile[own - 4 * LX], yp4 = tile[own + 4 * LX];
+                const C2 xm1 = pl[own - 1], xp1 = pl[own + 1], xm2 = pl[own - 2], xp2 = pl[own + 2];
+                const C2 xm3 = pl[own - 3], xp3 = pl[own + 3], xm4 = pl[own - 4], xp4 = pl[own + 4];
+                const C2 ym1 = pl[own - LX], yp1 = pl[own + LX], ym2 = pl[own - 2 * LX], yp2 = pl[own + 2 * LX];
+                const C2 ym3 = pl[own - 3 * LX], yp3 = pl[own + 3 * LX], ym4 = pl[own - 4 * LX], yp4 = pl[own + 4 * LX];
                 const C2 zm1 = cv[SLOT(-1)], zp1 = cv[SLOT(1)], zm2 = cv[SLOT(-2)], zp2 = cv[SLOT(2)];
                 const C2 zm3 = cv[SLOT(-3)], zp3 = cv[SLOT(3)], zm4 = cv[SLOT(-4)], zp4 = cv[SLOT(4)];
                 lr = (Tc)3 * FD<Tc>::c0 * q0.x + FD<Tc>::c1 * ((xm1.x + xp1.x) + (ym1.x + yp1.x) + (zm1.x + zp1.x)) +
@@ -326,21 +365,24 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
             }
 #undef SLOT
             finish<Tc, Tout, MODE, FIRST>(a, q0, lr, li, v_c, b_c, E, x, y, z, idx_c, rout);
-            __syncthreads();
+            // no barrier here: the next step writes the other plane buffer,
+            // and every wave has finished reading it once all have passed
+            // this step's barrier
         }
     }
 }
 
 // Lean march (depth 1, few registers): the own-column queue q[9] rotates in
-// registers and every load of plane z+1 (own column z+5, halo, V, base) is
+// registers and every load of plane k+1 (own column k+5, halo, V, base) is
 // issued one step ahead; a step starts by waiting for the previous step's
-// loads.  Fits 1024-thread workgroups without spilling.
+// loads.  Planes run zs, zs + dir, ... as in the pipelined march.
 template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST>
 __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile) {
     using C2 = typename CT<Tc>::c2;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
+    constexpr int PLANE = (TY + 8) * LX;  // one plane buffer; tile holds two
     const int t = threadIdx.x, lx = t % TX, ly = t / TX;
     const int x = it.x * TX + lx, y = it.y * TY + ly;
     const int64_t np = a.np;
@@ -357,57 +399,60 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
 
-    const int z0 = it.z, z1 = it.w;
+    const int zs = it.z, dir = it.w > it.z ? 1 : -1;
+    const int nk = (it.w - it.z) * dir;
     C2 q[9];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) q[k] = fetch(idx_in_row(row_of(a, y, z0 - 4 + k), x), true);
-    int idx_c = idx_in_row(row_of(a, y, z0), x);
-    C2 nxt = fetch(idx_in_row(row_of(a, y, z0 + 4), x), true);
+    for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(row_of(a, y, zs + dir * (j - 4)), x), true);
+    int idx_c = idx_in_row(row_of(a, y, zs), x);
+    C2 nxt = fetch(idx_in_row(row_of(a, y, zs + dir * 4), x), true);
     C2 hv[HPT];
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(row_of(a, hl.y[k], z0), hl.x[k]), hl.ok[k]);
+    for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
     Tc v_c = fetch_v(idx_c);
     double2 b_c = fetch_b(idx_c);
-    int2 rf = row_of(a, y, z0 + 5);  // rows for the loads of the first step
-    int2 ro = row_of(a, y, z0 + 1);
+    int2 rf = row_of(a, y, zs + dir * 5);  // rows for the loads of the first step
+    int2 ro = row_of(a, y, zs + dir);
     int2 rh[HPT];
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) rh[k] = row_of(a, hl.y[k], z0 + 1);
+    for (int j = 0; j < HPT; ++j) rh[j] = row_of(a, hl.y[j], zs + dir);
 
     const double E = a.field_dev ? *a.field_dev : a.field;
     const int own = (ly + 4) * LX + lx + 4;
 
-    for (int z = z0; z < z1; ++z) {
+    for (int k = 0; k < nk; ++k) {
+        const int z = zs + dir * k;
+        C2 *const pl = tile + (k & 1) * PLANE;  // plane buffer of this step
         q[8] = nxt;
-        tile[own] = q[4];
+        pl[own] = q[4];
 #pragma unroll
-        for (int k = 0; k < HPT; ++k)
-            if (hl.ok[k]) tile[hl.l[k]] = hv[k];
+        for (int j = 0; j < HPT; ++j)
+            if (hl.ok[j]) pl[hl.l[j]] = hv[j];
         __syncthreads();
-        // row entries for the next step, then this step's loads (plane z+1)
-        const int2 rf_n = row_of(a, y, z + 6), ro_n = row_of(a, y, z + 2);
+        // row entries for the next step, then this step's loads (plane k+1)
+        const int2 rf_n = row_of(a, y, z + dir * 6), ro_n = row_of(a, y, z + dir * 2);
         int2 rh_n[HPT];
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) rh_n[k] = row_of(a, hl.y[k], z + 2);
-        const bool live = z + 1 < z1;
+        for (int j = 0; j < HPT; ++j) rh_n[j] = row_of(a, hl.y[j], z + dir * 2);
+        const bool live = k + 1 < nk;
         nxt = fetch(live ? idx_in_row(rf, x) : -1, true);
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) hv[k] = fetch(idx_in_row(rh[k], hl.x[k]), hl.ok[k] && live);
+        for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(rh[j], hl.x[j]), hl.ok[j] && live);
         const int idx_n = live ? idx_in_row(ro, x) : -1;
         const Tc v_n = fetch_v(idx_n);
         const double2 b_n = fetch_b(idx_n);
         rf = rf_n;
         ro = ro_n;
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) rh[k] = rh_n[k];
+        for (int j = 0; j < HPT; ++j) rh[j] = rh_n[j];
 
         const C2 q0 = q[4];
         Tc lr, li;
         {
-            const C2 xm1 = tile[own - 1], xp1 = tile[own + 1], xm2 = tile[own - 2], xp2 = tile[own + 2];
-            const C2 xm3 = tile[own - 3], xp3 = tile[own + 3], xm4 = tile[own - 4], xp4 = tile[own + 4];
-            const C2 ym1 = tile[own - LX], yp1 = tile[own + LX], ym2 = tile[own - 2 * LX], yp2 = tile[own + 2 * LX];
-            const C2 ym3 = tile[own - 3 * LX], yp3 = tile[own + 3 * LX], ym4 = tile[own - 4 * LX], yp4 = tile[own + 4 * LX];
+            const C2 xm1 = pl[own - 1], xp1 = pl[own + 1], xm2 = pl[own - 2], xp2 = pl[own + 2];
+            const C2 xm3 = pl[own - 3], xp3 = pl[own + 3], xm4 = pl[own - 4], xp4 = pl[own + 4];
+            const C2 ym1 = pl[own - LX], yp1 = pl[own + LX], ym2 = pl[own - 2 * LX], yp2 = pl[own + 2 * LX];
+            const C2 ym3 = pl[own - 3 * LX], yp3 = pl[own + 3 * LX], ym4 = pl[own - 4 * LX], yp4 = pl[own + 4 * LX];
             lr = (Tc)3 * FD<Tc>::c0 * q0.x + FD<Tc>::c1 * ((xm1.x + xp1.x) + (ym1.x + yp1.x) + (q[3].x + q[5].x)) +
                  FD<Tc>::c2 * ((xm2.x + xp2.x) + (ym2.x + yp2.x) + (q[2].x + q[6].x)) +
                  FD<Tc>::c3 * ((xm3.x + xp3.x) + (ym3.x + yp3.x) + (q[1].x + q[7].x)) +
@@ -418,9 +463,8 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
                  FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (q[0].y + q[8].y));
         }
         finish<Tc, Tout, MODE, FIRST>(a, q0, lr, li, v_c, b_c, E, x, y, z, idx_c, rout);
-        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 8; ++k) q[k] = q[k + 1];
+        for (int j = 0; j < 8; ++j) q[j] = q[j + 1];
         idx_c = idx_n;
         v_c = v_n;
         b_c = b_n;
@@ -437,10 +481,14 @@ __device__ __forceinline__ void march(const KParams &a, const int4 it, const int
 
 template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
 __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
-    __shared__ typename CT<Tc>::c2 tile[(TY + 8) * (TX + 8)];
+    __shared__ typename CT<Tc>::c2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     int n, item;
     block_item(a, blk, &n, &item);
+    // uniform by construction; saying so keeps the buffer resources in
+    // scalar registers (no per-lane loop around each buffer instruction)
+    n = __builtin_amdgcn_readfirstlane(n);
+    item = __builtin_amdgcn_readfirstlane(item);
     march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST>(a, a.items[item], n, tile);
 }
 
@@ -451,13 +499,13 @@ template <int TX, int TY, int D, bool FIRST>
 __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__restrict__ sysp,
                                                            const BatchItem *__restrict__ items,
                                                            int32_t nitems, double cre, double cim) {
-    __shared__ double2 tile[(TY + 8) * (TX + 8)];
+    __shared__ double2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
         const BatchItem bi = items[w];
-        KParams a = sysp[bi.sys];
+        KParams a = sysp[__builtin_amdgcn_readfirstlane(bi.sys)];
         a.cre = cre;
         a.cim = cim;
-        march<TX, TY, D, double2, double, double2, 1, FIRST>(a, bi.tile, bi.ob, tile);
+        march<TX, TY, D, double2, double, double2, 1, FIRST>(a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile);
         __syncthreads();  // the next item reuses the plane buffer
     }
 }
@@ -495,13 +543,12 @@ int launch_fp32(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
 
 }  // namespace
 
-// Tile shapes compiled into the library, {TX, TY, depth}: depth 1..3 is the
-// pipelined march, depth 0 the lean one.  (1024-thread tiles are not
-// compiled: at the 128-register limit of such workgroups the z-window
-// spills.)
+// Tile shapes compiled into the library, {TX, TY, depth}: depth 1..2 is the
+// pipelined march, depth 0 the lean one.  (Deeper pipelines and 1024-thread
+// tiles are not compiled: their rings spill past the register limit.)
 #define RSG_FP64_SHAPES(X) \
-    X(16, 8, 1) X(16, 8, 2) X(32, 8, 1) X(32, 8, 2) X(32, 8, 3) X(16, 16, 1) X(16, 16, 2) \
-    X(16, 16, 3) X(32, 16, 1) X(32, 16, 2) X(32, 16, 3) X(64, 8, 1) X(64, 8, 2) X(32, 16, 0)
+    X(16, 8, 1) X(16, 8, 2) X(32, 8, 1) X(32, 8, 2) X(16, 16, 1) X(16, 16, 2) \
+    X(32, 16, 1) X(32, 16, 2) X(64, 8, 1) X(64, 8, 2) X(32, 16, 0)
 #define RSG_FP32_SHAPES(X) X(16, 8, 1) X(32, 8, 1) X(32, 8, 2) X(32, 16, 1) X(32, 16, 2) X(64, 8, 2)
 
 std::vector<TileShape> tile_candidates(int compute) {
@@ -568,7 +615,7 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     p.cre = a.cre;
     p.cim = a.cim;
     p.nitems = plan ? plan->nitems : 0;
-    p.batch_slowest = shape.BO;
+    p.block_order = shape.BO;
     p.ny = g.n[1];
     p.nz = g.n[2];
     p.axis = H.axis;

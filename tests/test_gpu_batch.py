@@ -58,7 +58,8 @@ def test_batch_matches_oracle_and_single_system_bitwise():
         assert pad_untouched(t, s["og"].np)
         # same system alone, same tile: bitwise equal
         alone = to_om(s["psi"], s["pad"])
-        R.set_tile(s["gh"], s["nst"], tile["B"], tile["TX"], tile["TY"], tile["ZC"], tile["PD"])
+        R.set_tile(s["gh"], s["nst"], tile["B"], tile["TX"], tile["TY"], tile["ZC"], tile["PD"],
+                   ZM=tile["ZM"])
         R.propagate(s["gh"], alone, dt, nsteps, nst=s["nst"])
         np.testing.assert_array_equal(alone.cpu().numpy(), t.cpu().numpy())
 
@@ -74,7 +75,7 @@ def test_batch_graph_replays_and_autotune():
         bg = R.Batch([(s["gh"], t, s["nst"]) for s, t in zip(systems, g)])
         tile, ms = bg.autotune(reps=1)
         assert ms > 0
-        ba.set_tile(tile["B"], tile["TX"], tile["TY"], tile["ZC"], tile["PD"])
+        ba.set_tile(tile["B"], tile["TX"], tile["TY"], tile["ZC"], tile["PD"], tile["ZM"])
         for rep in range(3):
             ba.propagate(0.01, 2)
             bg.propagate(0.01, 2, graph=True)

@@ -1,5 +1,6 @@
 """Every compiled stencil tile the autotuner may pick, with every z-chunking,
-tile order (row, Morton, patches) and block order, gives the oracle's
+tile order (row, Morton, patches), block order and z-march direction (upward,
+or outward from the centre plane), gives the oracle's
 H psi and Taylor(4) step to the FP64 bar; the mixed-precision tiles agree
 with each other to FP32 rounding of the same arithmetic.
 
@@ -17,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 ZCS = (0, 4)        # whole z-range, and chunks of 4 planes (several per tile)
 PTS = (0, 1, 2)     # row order, Morton order, 2 x 2 patches
-BOS = (0, 1)        # orbital fastest / slowest
+BOS = (0, 1, 3)     # orbital fastest / slowest / groups of 3 (13 = 4 x 3 + 1)
+ZMS = (0, 1)        # upward from each tile's lowest plane / outward from the centre plane
 
 
 @pytest.fixture(scope="module")
@@ -32,12 +34,15 @@ def _variants(dtype):
         for zc in ZCS:
             for pt in PTS:
                 for bo in BOS:
-                    yield dict(t, ZC=zc, PT=pt, BO=bo)
+                    for zm in ZMS:
+                        if zm == 1 and pt >= 2:
+                            continue  # patches apply to the upward march only
+                        yield dict(t, ZC=zc, PT=pt, BO=bo, ZM=zm)
 
 
 def _set(R, s, t, dtype):
     R.set_tile(s.gh, s.nst, t["B"], t["TX"], t["TY"], t["ZC"], t["PD"], t["PT"], t["BO"],
-               dtype=dtype)
+               t["ZM"], dtype=dtype)
 
 
 def test_every_fp64_tile_matches_oracle(sys_):
