@@ -64,9 +64,20 @@ def build_sphere_inputs(cfg, positions):
     return V, proj
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, seconds: float):
     """The FP64 oracle on the host: one Taylor(4) step over the full grid on
-    a sample of the orbitals sized to take about `seconds`."""
+    a sample of the orbitals sized to take about `seconds` with every host
+    thread, then the same for one orbital on a single thread."""
     import oracle
     import synth
     t0 = time.perf_counter()
@@ -74,6 +85,7 @@ def cpu_baseline(cfg, seconds: float):
     V, proj = build_sphere_inputs(cfg, og.positions())
     oh = oracle.Ham(og, V=V, kin=-0.5, projectors=proj)
     psi1 = synth.white_noise(cfg["seed"], og.np, 1, cfg["h"])
+    cores = oracle.max_threads()
     t = time.perf_counter()
     oracle.hpsi(oh, psi1)
     per_orb_h = time.perf_counter() - t
@@ -82,14 +94,23 @@ def cpu_baseline(cfg, seconds: float):
     t = time.perf_counter()
     oracle.taylor_step(oh, psi, cfg["dt"])
     el = time.perf_counter() - t
-    log(f"cpu baseline: {n_orb} orbitals, {el:.1f} s (setup {t - t0:.1f} s)")
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.taylor_step(oh, psi1, cfg["dt"])
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    log(f"cpu baseline: {n_orb} orbitals, {el:.1f} s on {cores} threads; 1 orbital, {el1:.1f} s on 1 thread "
+        f"(setup {t - t0:.1f} s)")
     return {
         "value": og.np * n_orb * 4 / el,
         "unit": UNIT,
-        "cores": oracle.max_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"1 Taylor(4) step (4 H applications) over all {og.np} points for "
                   f"{n_orb} of the {cfg['nst']} orbitals, FP64 C oracle, OpenMP over points",
+        "single_thread_value": og.np * 4 / el1,
+        "single_thread_sample": "1 Taylor(4) step over all points for 1 orbital on 1 thread",
+        "cpu_model": cpu_model(),
     }
 
 
@@ -396,13 +417,85 @@ def bench_control(args):
     }
 
 
+def bench_cube32(args):
+    """The 32^3 harmonic cube (h = 0.3, V = r^2/2, 4 white-noise orbitals):
+    10 H*psi calls followed by 10 Taylor(4) steps at dt = 0.01 (50 H
+    applications), captured once as a HIP graph and replayed K times.  The
+    orbitals (2 MiB) stay in L2/MALL, so the rate is cache-resident, not an
+    HBM figure; checked against the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1501_05654_amd as rsg
+    import synth
+
+    cfg = dict(synth.WORKLOADS["cube32_ho"])
+    n, h, nst, dt = cfg["n"], cfg["h"], cfg["nst"], cfg["dt"]
+    torch.cuda.set_device(0)
+    gg, og = rsg.Grid(h, n=n), oracle.Grid(h, n=n)
+    V = synth.harmonic_potential(og.positions())
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).cuda(), kin=-0.5)
+    oh = oracle.Ham(og, V=V, kin=-0.5)
+    psi0 = synth.white_noise(cfg["seed"], og.np, nst, h)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        psi = torch.from_numpy(psi0).cuda().t().contiguous()
+        hp = torch.zeros_like(psi)
+        ws = torch.empty(gh.workspace_bytes("step", nst, psi.shape[1]), dtype=torch.uint8, device="cuda")
+
+        def seq():
+            for _ in range(cfg["hpsi_calls"]):
+                rsg.hpsi(gh, psi, out=hp)
+            for _ in range(cfg["steps"]):
+                rsg.propagate_step(gh, psi, dt, ws=ws)
+
+        tile, _ = rsg.autotune(gh, psi, reps=3)
+        seq()  # plans and tiles exist before capture
+        torch.cuda.synchronize()
+        # parity of one sequence against the oracle
+        ref_h = oracle.hpsi(oh, psi0)
+        ref_s = oracle.propagate(oh, psi0, dt, cfg["steps"])
+        err_h = float(np.max(np.linalg.norm(hp.cpu().numpy().T - ref_h, axis=0) / np.linalg.norm(ref_h, axis=0)))
+        err_s = float(np.max(np.linalg.norm(psi.cpu().numpy().T - ref_s, axis=0) / np.linalg.norm(ref_s, axis=0)))
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            seq()
+        for _ in range(max(args.warmup, 1)):
+            graph.replay()
+        torch.cuda.synchronize()
+        reps = max(args.steps, 1)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+    napp = cfg["hpsi_calls"] + 4 * cfg["steps"]
+    npo = og.np * nst
+    alg = cfg["hpsi_calls"] * (32 * npo + 8 * og.np) + cfg["steps"] * (176 * npo + 32 * og.np)
+    return {
+        "metric": METRIC, "value": npo * napp / el, "unit": UNIT, "n_gpus": 1, "steps": reps,
+        "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "cube32_ho", "np": og.np, "nst": nst, "h_bohr": h, "tile": tile,
+                   "sequence": "10 hpsi + 10 Taylor(4) steps in one HIP graph (one step of this "
+                               "line = one replay of the sequence)"},
+        "roofline": {"bound": "hbm", "achieved": alg / el / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / el / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "note": "2 MiB of orbitals stay in L2/MALL: algorithmic bytes over wall time of the "
+                             "whole graph, not an HBM measurement"},
+        "parity": {"hpsi_rel_err_max": err_h, "taylor10_rel_err_max": err_s},
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sphere18_wells",
-                    choices=["sphere18_wells", "batch256", "cube32_mixed", "cube96_control"])
+                    choices=["sphere18_wells", "batch256", "cube32_mixed", "cube96_control", "cube32_ho"])
     ap.add_argument("--nsys", type=int, default=0, help="batch256: use only the first N systems")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
@@ -424,6 +517,8 @@ def main():
         out = bench_mixed(args)
     elif args.workload == "cube96_control":
         out = bench_control(args)
+    elif args.workload == "cube32_ho":
+        out = bench_cube32(args)
     else:
         out, cfg = bench_sphere(args)
         out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)

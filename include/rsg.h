@@ -140,6 +140,18 @@ int rsg_ham_create(rsg_grid_t g, const double *vloc_dev, double kin, int32_t dip
                    int32_t natoms, const rsg_proj_desc *proj, rsg_ham_t *out);
 int rsg_ham_destroy(rsg_ham_t H);
 
+/* Mask boundary absorber (section "Photoemission", eq. (mask_split) and the
+ * outgoing-flow propagation after it): with a mask set, every Taylor(4)
+ * step of this Hamiltonian (rsg_propagate_step, rsg_propagate) ends with
+ * psi <- M(r) psi, the part (1 - M) psi leaving the simulation box.
+ * mask_dev: device [np] float64, real values (normally in [0, 1]); the
+ * handle copies it.  NULL removes the mask.  The multiply is fused into the
+ * last Horner stage and its projector scatter.  The charge that leaves is
+ * the drop of rsg_norm2 across a step.  rsg_adjoint_step, the control entry
+ * points and rsg_batch_create reject a masked Hamiltonian
+ * (RSG_EUNSUPPORTED).  Errors: RSG_EINVAL, RSG_EHIP. */
+int rsg_ham_set_mask(rsg_ham_t H, const double *mask_dev);
+
 /* Scratch device bytes an operation needs for a batch of nst orbitals with
  * orbital stride ldp (0 when the arguments are invalid). */
 size_t rsg_workspace_bytes(rsg_ham_t H, int32_t op, int64_t nst, int64_t ldp, int32_t dtype);
@@ -275,10 +287,10 @@ int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
 
 /* Time one Horner stage on psi (device [nst][ldp], left unchanged) for every
  * compiled tile shape, z-chunk lengths {whole, 64, 32}, PT {0, 1}, BO {0, 1,
- * 2, 4} and ZM {0, 1} with HIP events (best of reps launches after a warm-up launch), keep the
- * fastest for (nst, dtype)
- * and return it in *best and its time in *best_ms (either may be NULL).
- * ws: RSG_OP_STEP bytes.  Synchronises the stream. */
+ * 2, 4} and ZM {0, 1} with HIP events (best of reps launches after a warm-up
+ * launch), re-time the six fastest with 3 reps launches each, keep the
+ * fastest for (nst, dtype) and return it in *best and its time in *best_ms
+ * (either may be NULL).  ws: RSG_OP_STEP bytes.  Synchronises the stream. */
 int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, void *ws,
                  size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
 
@@ -300,8 +312,8 @@ size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc *sys);
 /* Group nsys independent systems (the group of states of section
  * "Parallelization, optimizations and graphics processing units", extended
  * across systems) so that each stage of a Taylor(4) step of all of them runs
- * as one persistent stencil launch over a cost-sorted list of (system, tile,
- * z-range, orbital) items, with one projector gather launch and one
+ * as one persistent stencil launch over a list of (system, tile, z-range,
+ * orbital) items (largest systems first), with one projector gather launch and one
  * scatter launch per colour.  ws (rsg_batch_workspace_bytes) holds the work
  * buffers and must outlive the batch, as must every Hamiltonian and orbital
  * array named in sys.  Results are bitwise equal to propagating each system

@@ -55,6 +55,7 @@ def lib():
         L.or_energy.argtypes = [vp, vp, dbl, vp, i64, i64, vp]
         L.or_taylor_step.argtypes = [vp, vp, dbl, dbl, vp, i64, i64]
         L.or_propagate.argtypes = [vp, vp, dbl, i64, vp, vp, i64, i64]
+        L.or_propagate_masked.argtypes = [vp, vp, dbl, i64, vp, vp, vp, i64, i64, vp]
         L.or_laser_field.restype = dbl
         L.or_laser_field.argtypes = [vp, i32, dbl, dbl]
         L.or_dipole_target.restype = dbl
@@ -64,12 +65,18 @@ def lib():
         L.or_adjoint_step.argtypes = [vp, vp, dbl, dbl, vp, vp, i64, i64, vp]
         L.or_control_gradient.argtypes = [vp, vp, dbl, i64, vp, i32, vp, i64, i64, vp, vp, vp]
         L.or_max_threads.restype = i32
+        L.or_set_threads.argtypes = [i32]
         _lib = L
     return _lib
 
 
 def max_threads() -> int:
     return int(lib().or_max_threads())
+
+
+def set_threads(n: int):
+    """OpenMP thread count of the oracle's loops (timing only)."""
+    lib().or_set_threads(int(n))
 
 
 def _p(a):
@@ -203,6 +210,23 @@ def propagate(ham: Ham, psi, dt: float, nsteps: int, fields=None, nst: int | Non
     lib().or_propagate(C.byref(ham.grid._s), C.byref(ham._s), float(dt), int(nsteps), _p(f),
                        _p(psi), nst, psi.shape[1])
     return psi
+
+
+def propagate_masked(ham: Ham, psi, dt: float, nsteps: int, mask, fields=None,
+                     nst: int | None = None):
+    """nsteps steps of psi <- M U(dt) psi (mask boundary absorber, section
+    "Photoemission", eq. (mask_split)).  Returns (psi, removed) with removed[n]
+    the charge orbital n lost through the mask over all steps."""
+    psi = _c(psi).copy()
+    nst = psi.shape[1] if nst is None else nst
+    f = None if fields is None else np.ascontiguousarray(fields, dtype=np.float64)
+    m = np.ascontiguousarray(mask, dtype=np.float64)
+    if m.shape != (ham.grid.np,):
+        raise ValueError("mask must have one value per grid point")
+    removed = np.zeros(nst)
+    lib().or_propagate_masked(C.byref(ham.grid._s), C.byref(ham._s), float(dt), int(nsteps), _p(f),
+                              _p(m), _p(psi), nst, psi.shape[1], _p(removed))
+    return psi, removed
 
 
 def laser_field(coef, T: float, t: float) -> float:

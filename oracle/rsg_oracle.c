@@ -36,7 +36,10 @@
  *    field whose parameters are Fourier coefficients of its amplitude).
  *  - Discrete evolution operator U(dt) applied recursively (section
  *    "Photoemission"); realised as the 4th-order Taylor expansion of
- *    exp(-i dt H), with H evaluated at the step midpoint.
+ *    exp(-i dt H), with H evaluated at the step midpoint.  The same section's
+ *    mask boundary absorber multiplies each propagated orbital by a real mask
+ *    M(r) after every step (eq. (mask_split)); M itself is an input (the
+ *    paper gives no formula for it).
  *  - Optimal-control gradient, eq. (qoctgradient), with the costate
  *    propagated backwards by the adjoint of the forward propagator.  The
  *    oracle computes the exact gradient of the time-discretised target
@@ -286,6 +289,33 @@ void or_propagate(const or_grid *g, const or_ham *H, double dt, int64_t nsteps,
         taylor4(g, H, fields ? fields[n] : 0.0, -I * dt, psi, nst, ld);
 }
 
+/* Mask boundary absorber (section "Photoemission", eq. (mask_split) and the
+   outgoing-flow propagation that follows it): after every step the orbital
+   keeps only its bounded part, psi <- M(r) U(dt) psi, and the part
+   (1 - M) U(dt) psi leaves the simulation box.  removed[s] accumulates, per
+   orbital, the charge that leaves the box: the norm before the mask minus
+   the norm after it, h^3 sum_r (|U psi|^2 - |M U psi|^2).  M is real. */
+void or_propagate_masked(const or_grid *g, const or_ham *H, double dt, int64_t nsteps,
+                         const double *fields, const double *mask, cplx *psi, int64_t nst,
+                         int64_t ld, double *removed) {
+    const double h3 = g->h * g->h * g->h;
+    for (int64_t s = 0; s < nst; ++s) removed[s] = 0.0;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        taylor4(g, H, fields ? fields[n] : 0.0, -I * dt, psi, nst, ld);
+        for (int64_t s = 0; s < nst; ++s) {
+            double before = 0.0, after = 0.0;
+            for (int64_t p = 0; p < g->np; ++p) {
+                const cplx u = psi[p * ld + s];
+                before += creal(u) * creal(u) + cimag(u) * cimag(u);
+                const cplx m = mask[p] * u;
+                after += creal(m) * creal(m) + cimag(m) * cimag(m);
+                psi[p * ld + s] = m;
+            }
+            removed[s] += h3 * (before - after);
+        }
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Optimal control                                                          */
 /* ---------------------------------------------------------------------- */
@@ -417,5 +447,15 @@ int32_t or_max_threads(void) {
     return (int32_t)omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Thread count for the OpenMP loops (timing only; results do not depend on
+   it: every output point and every reduction is computed in a fixed order). */
+void or_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads((int)n);
+#else
+    (void)n;
 #endif
 }

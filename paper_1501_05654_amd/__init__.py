@@ -51,6 +51,7 @@ def _load():
         "rsg_grid_destroy": (C.c_int, [vp]),
         "rsg_ham_create": (C.c_int, [vp, vp, dbl, i32, i32, vp, vp]),
         "rsg_ham_destroy": (C.c_int, [vp]),
+        "rsg_ham_set_mask": (C.c_int, [vp, vp]),
         "rsg_workspace_bytes": (sz, [vp, i32, i64, i64, i32]),
         "rsg_hpsi": (C.c_int, [vp, vp, vp, i64, i64, i32, dbl, vp, sz, vp]),
         "rsg_propagate_step": (C.c_int, [vp, vp, i64, i64, i32, dbl, dbl, vp, sz, vp]),
@@ -196,6 +197,16 @@ class Hamiltonian:
                                    descs, C.byref(self._h)))
         torch.cuda.synchronize()
         self.natoms = len(projectors)
+
+    def set_mask(self, mask: torch.Tensor | None):
+        """Absorber mask M(r) (CUDA float64 [np]) applied after every Taylor
+        step, psi <- M psi; None removes it.  The library copies it."""
+        if mask is not None:
+            mask = mask.to(torch.float64).contiguous()
+            if not mask.is_cuda or mask.numel() != self.grid.np:
+                raise ValueError("mask must be a CUDA float64 tensor with np entries")
+            torch.cuda.synchronize()
+        _check(_lib.rsg_ham_set_mask(self._h, _ptr(mask)))
 
     def workspace_bytes(self, op: str, nst: int, ldp: int, dtype: int = C128) -> int:
         return int(_lib.rsg_workspace_bytes(self._h, _OP[op], nst, ldp, dtype))

@@ -3,8 +3,9 @@
 // The paper's basic object is a group of states rather than one state
 // (section "Parallelization, optimizations and graphics processing units");
 // here the group extends across systems: every stage of a Taylor(4) step of
-// every system runs as one persistent stencil launch over a cost-sorted list
-// of (system, tile, z-range, orbital) items, preceded by one projector
+// every system runs as one persistent stencil launch over a list of
+// (system, tile, z-range, orbital) items (largest systems first, each
+// sweeping its tiles orbital by orbital), preceded by one projector
 // gather launch and followed by one scatter launch per colour, all systems at
 // once.  A step sequence can be captured once into a HIP graph and replayed.
 // Each output point is computed by the same arithmetic as the single-system
@@ -92,6 +93,15 @@ int build_tables(Batch &b, hipStream_t s) {
     std::vector<KParams> sp[4];
     std::vector<KbSys> kb[4];
     int err = RSG_OK;
+    // stencil items: systems with the most work first (the small ones fill
+    // the tail of the persistent grid), each system sweeping its tiles one
+    // orbital at a time so that neighbouring tiles are resident together
+    std::vector<size_t> by_work(b.sys.size());
+    for (size_t i = 0; i < by_work.size(); ++i) by_work[i] = i;
+    std::stable_sort(by_work.begin(), by_work.end(), [&](size_t p, size_t q) {
+        return b.sys[p].ham->g->np * b.sys[p].nst > b.sys[q].ham->g->np * b.sys[q].nst;
+    });
+    std::vector<std::vector<BatchItem>> sys_items(b.sys.size());
     for (size_t i = 0; i < b.sys.size(); ++i) {
         const rsg_system_desc &d = b.sys[i];
         Ham &H = *d.ham;
@@ -105,8 +115,8 @@ int build_tables(Batch &b, hipStream_t s) {
         std::vector<int4> pit(plan->nitems);
         if (plan->nitems)
             RSG_CHECK_HIP(hipMemcpy(pit.data(), plan->items, sizeof(int4) * plan->nitems, hipMemcpyDeviceToHost));
-        for (const int4 &t : pit)
-            for (int n = 0; n < (int)d.nst; ++n) items.push_back(BatchItem{t, (int32_t)i, n});
+        for (int n = 0; n < (int)d.nst; ++n)
+            for (const int4 &t : pit) sys_items[i].push_back(BatchItem{t, (int32_t)i, n});
         for (int k = 0; k < 4; ++k) {
             StageArgs a;
             stage_buffers(b, i, k, &a.in, &a.base, &a.out);
@@ -144,11 +154,7 @@ int build_tables(Batch &b, hipStream_t s) {
             }
         }
     }
-    // longest items first: with a fixed stride over the list, every
-    // workgroup gets a similar total amount of z-marching
-    std::stable_sort(items.begin(), items.end(), [](const BatchItem &x, const BatchItem &y) {
-        return (x.tile.w - x.tile.z) > (y.tile.w - y.tile.z);
-    });
+    for (const size_t i : by_work) items.insert(items.end(), sys_items[i].begin(), sys_items[i].end());
     int rc;
     b.grid_first = stencil_batch_grid(b.tile, true);
     b.grid_rest = stencil_batch_grid(b.tile, false);
@@ -209,6 +215,7 @@ static int check_systems(int32_t nsys, const rsg_system_desc *sys) {
                     "batch: system %d needs nst >= 1 and ldp >= np", i);
         RSG_REQUIRE(d.psi && ((uintptr_t)d.psi & 15) == 0, RSG_EINVAL, "batch: system %d orbital pointer", i);
         RSG_REQUIRE(d.ham->axis < 0, RSG_EUNSUPPORTED, "batch: system %d has a dipole field (not batched)", i);
+        RSG_REQUIRE(!d.ham->mask, RSG_EUNSUPPORTED, "batch: system %d has an absorber mask (not batched)", i);
         RSG_REQUIRE(d.ham->g->np < ((int64_t)1 << 27), RSG_EUNSUPPORTED, "batch: system %d has 2^27 points or more", i);
     }
     return RSG_OK;

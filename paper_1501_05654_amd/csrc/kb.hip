@@ -131,7 +131,8 @@ __device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldo
                                              const int32_t *__restrict__ idx,
                                              const Tc *__restrict__ p,
                                              const double *__restrict__ E,
-                                             const Tc *__restrict__ D, double cre, double cim) {
+                                             const Tc *__restrict__ D, double cre, double cim,
+                                             const double *__restrict__ mask) {
     using V = typename V4<Tc>::type;
     const int l = threadIdx.x & 63;
     const int lo = l & 15, hi = l >> 4;
@@ -152,8 +153,10 @@ __device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldo
     for (int r = 0; r < 4; ++r) {
         const int64_t e = (int64_t)itm.y + acc_row(Tc(0), hi, r);
         if (e < end && col < ncols) {
-            Tout *dst = out + (col >> 1) * ldo + 2 * (int64_t)idx[e] + (col & 1);
-            *dst = (Tout)((double)*dst + (double)acc[r]);
+            const int64_t pt = idx[e];
+            Tout *dst = out + (col >> 1) * ldo + 2 * pt + (col & 1);
+            const double add = mask ? mask[pt] * (double)acc[r] : (double)acc[r];
+            *dst = (Tout)((double)*dst + add);
         }
     }
 }
@@ -167,11 +170,11 @@ __global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int6
                                                     const Tc *__restrict__ p,
                                                     const double *__restrict__ E,
                                                     const Tc *__restrict__ D, double cre,
-                                                    double cim) {
+                                                    double cim, const double *__restrict__ mask) {
     const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (item >= nitems) return;
     const int2 itm = items[item];  // {atom, first entry}
-    scatter_tile<Tout, Tc>(out, ldo, ncols, itm, atoms[itm.x], blockIdx.y, idx, p, E, D, cre, cim);
+    scatter_tile<Tout, Tc>(out, ldo, ncols, itm, atoms[itm.x], blockIdx.y, idx, p, E, D, cre, cim, mask);
 }
 
 // Batched forms over many systems (FP64): item {system, atom, column tile}
@@ -193,7 +196,7 @@ __global__ void __launch_bounds__(256) k_kb_scatter_batch(const KbSys *__restric
     const int4 it = items[item];
     const KbSys &s = sys[it.x];
     scatter_tile<double, double>(s.out, s.ldo, s.ncols, make_int2(it.y, it.z), s.atoms[it.y], it.w, s.idx,
-                                 s.p, s.E, s.D, cre, cim);
+                                 s.p, s.E, s.D, cre, cim, nullptr);
 }
 
 }  // namespace
@@ -227,7 +230,7 @@ int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_
 }
 
 int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ldp,
-                      const void *D, double cre, double cim, hipStream_t s) {
+                      const void *D, double cre, double cim, const double *mask, hipStream_t s) {
     if (H.natoms == 0 || nst == 0) return RSG_OK;
     const int64_t ncols = 2 * nst;
     for (size_t c = 0; c < H.scatter_items.size(); ++c) {
@@ -238,15 +241,15 @@ int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t n
             if (out_t != 0) return RSG_EUNSUPPORTED;
             k_kb_scatter<double, double><<<grid, 256, 0, s>>>(
                 (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
-                H.kb_p, H.kb_E, (const double *)D, cre, cim);
+                H.kb_p, H.kb_E, (const double *)D, cre, cim, mask);
         } else if (out_t == 0) {
             k_kb_scatter<double, float><<<grid, 256, 0, s>>>(
                 (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
-                H.kb_p32, H.kb_E, (const float *)D, cre, cim);
+                H.kb_p32, H.kb_E, (const float *)D, cre, cim, mask);
         } else {
             k_kb_scatter<float, float><<<grid, 256, 0, s>>>(
                 (float *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
-                H.kb_p32, H.kb_E, (const float *)D, cre, cim);
+                H.kb_p32, H.kb_E, (const float *)D, cre, cim, mask);
         }
         RSG_CHECK_HIP(hipGetLastError());
     }

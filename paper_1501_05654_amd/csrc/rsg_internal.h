@@ -113,6 +113,7 @@ struct Ham {
     int32_t axis = -1;
     double *V = nullptr;     // device [np] or null
     float *V32 = nullptr;    // device [np] FP32 copy or null
+    double *mask = nullptr;  // device [np] absorber mask applied after every step, or null
     // projectors, padded per atom to a multiple of 16 support entries
     int32_t natoms = 0;
     int32_t *kb_idx = nullptr;   // device [total_padded]
@@ -150,6 +151,7 @@ struct StageArgs {
     void *out = nullptr;
     int in_t = 0, out_t = 0, compute = 0, mode = 0;
     bool first = false;  // base == in (first Horner stage)
+    const double *mask = nullptr;  // mode 1: out = mask * (base + c H in)
     int64_t nst = 0, ldp = 0;
     double field = 0;
     const double *field_dev = nullptr;
@@ -166,6 +168,7 @@ struct KParams {
     const double *zeros;
     const void *V;
     const double *field_dev;
+    const double *mask;
     int64_t nst, ldp, np;
     double kin_h2;
     double field;
@@ -195,12 +198,13 @@ std::vector<TileShape> tile_candidates(int compute);
 
 // KB projectors.  gather: D[a][i][col] = h^3 sum_e p[e][i] in(idx[e], col)
 // (col over the 2*nst real columns: re and im of each orbital); scatter:
-// out(idx[e], col) += sum_i p[e][i] (c E_i D[a][i][.])[col].  Operands are
-// orbital-major with ldp complex values between orbitals.
+// out(idx[e], col) += sum_i p[e][i] (c E_i D[a][i][.])[col], times mask(idx[e])
+// when a mask is given.  Operands are orbital-major with ldp complex values
+// between orbitals.
 int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ldp,
                      void *D, hipStream_t s);
 int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ldp,
-                      const void *D, double cre, double cim, hipStream_t s);
+                      const void *D, double cre, double cim, const double *mask, hipStream_t s);
 size_t kb_workspace_bytes(const Ham &H, int64_t nst);
 
 // Per-system projector parameters of one stage of the batched path (FP64).

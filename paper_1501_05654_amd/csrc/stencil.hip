@@ -199,10 +199,11 @@ struct Halo {
 };
 
 // The per-point epilogue shared by both marches: H value from the Laplacian
-// taps, then the stage combination, stored at idx (dropped when idx < 0).
-template <class Tc, class Tout, int MODE, bool FIRST>
+// taps, then the stage combination (times the absorber mask m_c when MASK),
+// stored at idx (dropped when idx < 0).
+template <class Tc, class Tout, int MODE, bool FIRST, bool MASK>
 __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0, Tc lr, Tc li, Tc v_c,
-                                       double2 b_c, double E, int x, int y, int z, int idx,
+                                       double2 b_c, double m_c, double E, int x, int y, int z, int idx,
                                        __amdgpu_buffer_rsrc_t rout) {
     Tc vloc = v_c;
     if (a.axis >= 0) {
@@ -217,8 +218,12 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
         store_c(rout, o, (Tout *)nullptr, (double)hr, (double)hi);
     } else {
         const double2 bb = FIRST ? make_double2((double)q0.x, (double)q0.y) : b_c;
-        const double r = bb.x + (a.cre * (double)hr - a.cim * (double)hi);
-        const double i = bb.y + (a.cre * (double)hi + a.cim * (double)hr);
+        double r = bb.x + (a.cre * (double)hr - a.cim * (double)hi);
+        double i = bb.y + (a.cre * (double)hi + a.cim * (double)hr);
+        if (MASK) {
+            r *= m_c;
+            i *= m_c;
+        }
         store_c(rout, o, (Tout *)nullptr, r, i);
     }
 }
@@ -237,7 +242,7 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
 // All rings are indexed by compile-time constants after unrolling the step
 // loop by a common period, so no register is moved while its load is in
 // flight.  FIRST: base == in, whose value at the point is the centre tap.
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK>
 __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile) {
     using C2 = typename CT<Tc>::c2;
@@ -257,6 +262,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     const auto rbase = rsrc(static_cast<const double2 *>(a.base) + (int64_t)n * a.ldp, np * 16);
     const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
     const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
+    const auto rm = rsrc(MASK ? a.mask : a.V, MASK ? np * 8 : 0);
     const Halo<TX, TY, HPT> hl(t, it);
 
     auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
@@ -265,6 +271,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
         if (MODE != 1 || FIRST) return make_double2(0.0, 0.0);
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
+    auto fetch_m = [&](int idx) -> double { return MASK ? BL<double>::ld(rm, boff<double>(idx)) : 1.0; };
 
     const int zs = it.z, dir = it.w > it.z ? 1 : -1;
     const int nk = (it.w - it.z) * dir;  // planes to compute
@@ -289,13 +296,16 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                                : C2{(Tc)0, (Tc)0};
     Tc vr[VD];
     double2 br[VD];
+    double mr[VD];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         vr[d] = fetch_v(oid[4 + d]);
         br[d] = fetch_b(oid[4 + d]);
+        mr[d] = fetch_m(oid[4 + d]);
     }
     vr[D] = (Tc)0;
     br[D] = make_double2(0.0, 0.0);
+    mr[D] = 0.0;
     // step k reads row slot k % 2 and fills the other one
     int2 rfr[2], rhl[2][HPT];
     rfr[0] = row_of(a, y, zs + dir * (4 + D));
@@ -327,6 +337,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
             const int idx_c = oid[SLOT(0)];
             const Tc v_c = vr[sv];
             const double2 b_c = br[sv];
+            const double m_c = mr[sv];
             __syncthreads();
             {
                 // row entries for the next step first, then the loads that use
@@ -344,6 +355,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                 const int idv = k + D < nk ? oid[SLOT(D)] : -1;
                 vr[svn] = fetch_v(idv);
                 br[svn] = fetch_b(idv);
+                mr[svn] = fetch_m(idv);
             }
             const C2 q0 = cv[SLOT(0)];
             Tc lr, li;
@@ -364,7 +376,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                      FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (zm4.y + zp4.y));
             }
 #undef SLOT
-            finish<Tc, Tout, MODE, FIRST>(a, q0, lr, li, v_c, b_c, E, x, y, z, idx_c, rout);
+            finish<Tc, Tout, MODE, FIRST, MASK>(a, q0, lr, li, v_c, b_c, m_c, E, x, y, z, idx_c, rout);
             // no barrier here: the next step writes the other plane buffer,
             // and every wave has finished reading it once all have passed
             // this step's barrier
@@ -376,7 +388,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
 // registers and every load of plane k+1 (own column k+5, halo, V, base) is
 // issued one step ahead; a step starts by waiting for the previous step's
 // loads.  Planes run zs, zs + dir, ... as in the pipelined march.
-template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK>
 __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile) {
     using C2 = typename CT<Tc>::c2;
@@ -390,6 +402,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     const auto rbase = rsrc(static_cast<const double2 *>(a.base) + (int64_t)n * a.ldp, np * 16);
     const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
     const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
+    const auto rm = rsrc(MASK ? a.mask : a.V, MASK ? np * 8 : 0);
     const Halo<TX, TY, HPT> hl(t, it);
 
     auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
@@ -398,6 +411,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
         if (MODE != 1 || FIRST) return make_double2(0.0, 0.0);
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
+    auto fetch_m = [&](int idx) -> double { return MASK ? BL<double>::ld(rm, boff<double>(idx)) : 1.0; };
 
     const int zs = it.z, dir = it.w > it.z ? 1 : -1;
     const int nk = (it.w - it.z) * dir;
@@ -411,6 +425,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
     Tc v_c = fetch_v(idx_c);
     double2 b_c = fetch_b(idx_c);
+    double m_c = fetch_m(idx_c);
     int2 rf = row_of(a, y, zs + dir * 5);  // rows for the loads of the first step
     int2 ro = row_of(a, y, zs + dir);
     int2 rh[HPT];
@@ -441,6 +456,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
         const int idx_n = live ? idx_in_row(ro, x) : -1;
         const Tc v_n = fetch_v(idx_n);
         const double2 b_n = fetch_b(idx_n);
+        const double m_n = fetch_m(idx_n);
         rf = rf_n;
         ro = ro_n;
 #pragma unroll
@@ -462,24 +478,25 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
                  FD<Tc>::c3 * ((xm3.y + xp3.y) + (ym3.y + yp3.y) + (q[1].y + q[7].y)) +
                  FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (q[0].y + q[8].y));
         }
-        finish<Tc, Tout, MODE, FIRST>(a, q0, lr, li, v_c, b_c, E, x, y, z, idx_c, rout);
+        finish<Tc, Tout, MODE, FIRST, MASK>(a, q0, lr, li, v_c, b_c, m_c, E, x, y, z, idx_c, rout);
 #pragma unroll
         for (int j = 0; j < 8; ++j) q[j] = q[j + 1];
         idx_c = idx_n;
         v_c = v_n;
         b_c = b_n;
+        m_c = m_n;
     }
 }
 
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK>
 __device__ __forceinline__ void march(const KParams &a, const int4 it, const int n, typename CT<Tc>::c2 *tile) {
     if constexpr (D == 0)
-        march_lean<TX, TY, Tin, Tc, Tout, MODE, FIRST>(a, it, n, tile);
+        march_lean<TX, TY, Tin, Tc, Tout, MODE, FIRST, MASK>(a, it, n, tile);
     else
-        march_ring<TX, TY, D, Tin, Tc, Tout, MODE, FIRST>(a, it, n, tile);
+        march_ring<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK>(a, it, n, tile);
 }
 
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST>
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK = false>
 __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     __shared__ typename CT<Tc>::c2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -489,23 +506,27 @@ __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     // scalar registers (no per-lane loop around each buffer instruction)
     n = __builtin_amdgcn_readfirstlane(n);
     item = __builtin_amdgcn_readfirstlane(item);
-    march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST>(a, a.items[item], n, tile);
+    march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK>(a, a.items[item], n, tile);
 }
 
-// Persistent form over many independent systems (FP64): workgroup g takes
-// items g, g + G, g + 2G, ... of the cost-sorted list {tile, system,
-// orbital}; each system's parameters come from sysp[system].
+// Persistent form over many independent systems (FP64): in round r the G
+// workgroups take items r G .. r G + G - 1 of the list {tile, system,
+// orbital}, remapped so that each XCD takes a contiguous run of them
+// (neighbouring tiles share that XCD's L2); each system's parameters come
+// from sysp[system].
 template <int TX, int TY, int D, bool FIRST>
 __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__restrict__ sysp,
                                                            const BatchItem *__restrict__ items,
                                                            int32_t nitems, double cre, double cim) {
     __shared__ double2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
-    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const int slot = xcd_remap(blockIdx.x, gridDim.x);
+    for (int w = slot; w < nitems; w += gridDim.x) {
         const BatchItem bi = items[w];
         KParams a = sysp[__builtin_amdgcn_readfirstlane(bi.sys)];
         a.cre = cre;
         a.cim = cim;
-        march<TX, TY, D, double2, double, double2, 1, FIRST>(a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile);
+        march<TX, TY, D, double2, double, double2, 1, FIRST, false>(a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob),
+                                                                 tile);
         __syncthreads();  // the next item reuses the plane buffer
     }
 }
@@ -518,6 +539,8 @@ int launch_fp64(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
         k_stencil<TX, TY, D, double2, double, double2, 0, false><<<nb, NT, 0, s>>>(p);
     else if (a.first)
         k_stencil<TX, TY, D, double2, double, double2, 1, true><<<nb, NT, 0, s>>>(p);
+    else if (a.mask)
+        k_stencil<TX, TY, D, double2, double, double2, 1, false, true><<<nb, NT, 0, s>>>(p);
     else
         k_stencil<TX, TY, D, double2, double, double2, 1, false><<<nb, NT, 0, s>>>(p);
     return RSG_OK;
@@ -534,6 +557,8 @@ int launch_fp32(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
         k_stencil<TX, TY, D, double2, float, float2, 1, true><<<nb, NT, 0, s>>>(p);
     else if (a.in_t == 1 && a.out_t == 1 && !a.first)
         k_stencil<TX, TY, D, float2, float, float2, 1, false><<<nb, NT, 0, s>>>(p);
+    else if (a.in_t == 1 && a.out_t == 0 && !a.first && a.mask)
+        k_stencil<TX, TY, D, float2, float, double2, 1, false, true><<<nb, NT, 0, s>>>(p);
     else if (a.in_t == 1 && a.out_t == 0 && !a.first)
         k_stencil<TX, TY, D, float2, float, double2, 1, false><<<nb, NT, 0, s>>>(p);
     else
@@ -547,8 +572,8 @@ int launch_fp32(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
 // pipelined march, depth 0 the lean one.  (Deeper pipelines and 1024-thread
 // tiles are not compiled: their rings spill past the register limit.)
 #define RSG_FP64_SHAPES(X) \
-    X(16, 8, 1) X(16, 8, 2) X(32, 8, 1) X(32, 8, 2) X(16, 16, 1) X(16, 16, 2) \
-    X(32, 16, 1) X(32, 16, 2) X(64, 8, 1) X(64, 8, 2) X(32, 16, 0)
+    X(8, 8, 1) X(8, 8, 2) X(16, 8, 1) X(16, 8, 2) X(32, 8, 1) X(32, 8, 2) X(16, 16, 1) \
+    X(16, 16, 2) X(32, 16, 1) X(32, 16, 2) X(64, 8, 1) X(64, 8, 2) X(32, 16, 0)
 #define RSG_FP32_SHAPES(X) X(16, 8, 1) X(32, 8, 1) X(32, 8, 2) X(32, 16, 1) X(32, 16, 2) X(64, 8, 2)
 
 std::vector<TileShape> tile_candidates(int compute) {
@@ -570,7 +595,8 @@ std::vector<TileShape> tile_candidates(int compute) {
 
 // Measured on MI355X (sphere of 3.05 M points, 64 orbitals): 32 x 16 tiles,
 // depth 2, orbital-slowest order.  Smaller grids take the largest tile that
-// still gives every compute unit several workgroups.
+// still gives every compute unit several workgroups, and z-chunks when even
+// the smallest tile does not.
 TileShape default_shape(const Grid &g, int64_t nst, int compute) {
     static const int pref[][3] = {{32, 16, 2}, {32, 8, 2}, {16, 8, 1}};
     static const int pref32[][3] = {{32, 16, 2}, {32, 8, 2}, {16, 8, 1}};
@@ -585,6 +611,11 @@ TileShape default_shape(const Grid &g, int64_t nst, int compute) {
     }
     sh.BO = 1;
     sh.ZC = g.n[2];
+    // a grid with too few tiles to give every compute unit a few workgroups
+    // is also split along z (each chunk re-reads only 8 planes)
+    const int64_t tiles = (int64_t)((g.n[0] + sh.TX - 1) / sh.TX) * ((g.n[1] + sh.TY - 1) / sh.TY);
+    const int64_t wgs = tiles * std::max<int64_t>(nst, 1);
+    if (wgs < 1024) sh.ZC = std::max<int>(8, (int)((int64_t)g.n[2] * wgs / 1024));
     return sh;
 }
 
@@ -605,6 +636,7 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     p.zeros = g.zeros;
     p.V = a.compute == 0 ? (const void *)H.V : (const void *)H.V32;
     p.field_dev = a.field_dev;
+    p.mask = a.mask;
     p.nst = a.nst;
     p.ldp = a.ldp;
     p.np = g.np;

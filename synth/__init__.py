@@ -213,6 +213,15 @@ def kb_projectors(seed: int, pos: np.ndarray, centres: np.ndarray,
     return out
 
 
+def radial_mask(pos: np.ndarray, R: float, width: float) -> np.ndarray:
+    """Real mask M(r) for the boundary absorber: 1 inside |r| <= R - width,
+    cos^2 ramp to 0 at |r| = R, 0 beyond.  The paper leaves the mask's form
+    open; this smooth radial ramp is the input used here."""
+    r = np.linalg.norm(pos, axis=1)
+    t = np.clip((r - (R - width)) / width, 0.0, 1.0)
+    return np.where(t >= 1.0, 0.0, np.cos(0.5 * np.pi * t) ** 2)
+
+
 def laser_coefficients(seed: int, ncoef: int, sigma: float = 0.005) -> np.ndarray:
     """Sine-series coefficients c_k ~ N(0, sigma^2) of the control field."""
     return rng(seed, _P_LASER).normal(0.0, sigma, size=ncoef)

@@ -248,3 +248,53 @@ def test_error_codes():
     assert rc == -5
     rc = R._lib.rsg_hpsi(s.gh._h, p, p, 2, ldp, 0, 0.0, None, 0, None)
     assert rc == -1  # psi and hpsi overlap
+
+
+def test_mask_absorber_matches_oracle():
+    """psi <- M U(dt) psi after every step (mask boundary absorber): FP64 parity
+    with projectors, a per-step field, spare orbitals and padding points;
+    graph replay equal to eager; the FP32 path within its rounding; removing
+    the mask restores the plain step; the adjoint rejects a masked H."""
+    R = rsg()
+    s = System(0.3, R=4.0, potential="wells", natoms=4, nst=5, ld=6, seed=21, dipole_axis=2,
+               well_ball=1.2, pad=7)
+    M = synth.radial_mask(s.pos, 3.6, 1.4)
+    assert np.any(M == 0.0) and np.any((M > 0) & (M < 1))
+    fields = np.linspace(0.2, -0.1, 4)
+    ref, removed = oracle.propagate_masked(s.oh, s.psi, 0.005, 4, M, fields=fields, nst=5)
+    s.gh.set_mask(torch.from_numpy(M).cuda())
+    f = torch.from_numpy(fields).cuda()
+    psi = s.to_gpu(s.psi)
+    n0 = R.norm2(s.gg, psi, nst=5).cpu().numpy()
+    R.propagate(s.gh, psi, 0.005, 4, fields=f, nst=5)
+    got = s.from_gpu(psi)
+    assert orbital_rel_err(got, ref, 5) <= TOL
+    np.testing.assert_array_equal(got[:, 5:], s.psi[:, 5:])
+    assert s.pad_untouched(psi)
+    assert np.all(got[M == 0.0, :5] == 0)
+    n1 = R.norm2(s.gg, psi, nst=5).cpu().numpy()
+    np.testing.assert_allclose(n0 - n1, oracle.norm2(s.og, s.psi, nst=5) - oracle.norm2(s.og, ref, nst=5),
+                               rtol=1e-10)
+    assert np.all(removed > 0)
+    # graph capture of the masked steps
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = s.to_gpu(s.psi)
+        for _ in range(2):
+            g.copy_(s.to_gpu(s.psi))
+            R.propagate(s.gh, g, 0.005, 4, fields=f, nst=5, graph=True)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.cpu().numpy(), psi.cpu().numpy())
+    # mixed precision with the mask
+    m = s.to_gpu(s.psi)
+    R.propagate(s.gh, m, 0.005, 4, fields=f, nst=5, dtype="mixed")
+    assert orbital_rel_err(s.from_gpu(m), ref, 5) < 1e-5
+    with pytest.raises(R.RSGError) as ei:
+        R.adjoint_step(s.gh, psi, psi.clone(), 0.01, 0.0, nst=5)
+    assert ei.value.code == -6
+    # removing the mask restores the plain step
+    s.gh.set_mask(None)
+    p = s.to_gpu(s.psi)
+    R.propagate_step(s.gh, p, 0.005, field=0.2, nst=5)
+    plain = oracle.taylor_step(s.oh, s.psi, 0.005, field=0.2, nst=5)
+    assert orbital_rel_err(s.from_gpu(p), plain, 5) <= TOL
