@@ -338,6 +338,54 @@ int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, double *best
 int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_graph, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Grid-to-memory maps                                                 */
+/* ------------------------------------------------------------------ */
+
+/* Section "Parallelization, optimizations and graphics processing units",
+ * figures gridmaps and gpu_laplacian: a grid function is a linear array and
+ * the order in which grid points are stored in it is free.  A map is such an
+ * order together with the neighbour table of the 25-point star stencil in
+ * it, for a generic (gather-form) finite-difference Laplacian that works
+ * with any order.  Kinds:
+ *   RSG_MAP_STANDARD  the compact order (z, then y, then x fastest);
+ *   RSG_MAP_BRICKS    the tight box cut into param^3 bricks, bricks in the
+ *                     compact order of their corner, points inside a brick in
+ *                     compact order;
+ *   RSG_MAP_HILBERT   ascending 3D Hilbert index of the box coordinates
+ *                     (x, y, z) on the enclosing 2^b cube, from the
+ *                     axes-to-transpose transform of Skilling (AIP Conf.
+ *                     Proc. 707, 2004), x the most significant axis of each
+ *                     level.
+ * The map holds a device table of 24 int32 per point (96 B/pt). */
+typedef struct rsg_map_s *rsg_map_t;
+enum { RSG_MAP_STANDARD = 0, RSG_MAP_BRICKS = 1, RSG_MAP_HILBERT = 2 };
+
+/* Builds the order and the neighbour table on the host from the grid's row
+ * table and uploads the table; param = brick edge (1..64) for
+ * RSG_MAP_BRICKS, ignored otherwise.  The grid must outlive the map.
+ * Errors: RSG_EINVAL (null argument, unknown kind, bad brick edge),
+ * RSG_ENOMEM, RSG_EHIP. */
+int rsg_map_create(rsg_grid_t g, int32_t kind, int32_t param, rsg_map_t *out);
+int rsg_map_destroy(rsg_map_t m);
+
+/* order_host[i] = compact index of the i-th point in map order (host
+ * [np] int32, caller-owned).  A grid function f in compact order is
+ * f[order] in map order. */
+int rsg_map_order(rsg_map_t m, int32_t *order_host);
+
+/* out = scale * sum over the 25 stencil taps of c_|m| psi(r + m h e_axis)
+ * (the 8th-order star of rsg_hpsi's kinetic term, psi = 0 outside the box),
+ * with psi and out both in map order and in the point-major batch layout
+ * [np][ld] complex128 (orbital fastest, nst <= ld).  kin * Lap_h is
+ * scale = kin / h^2.  Columns nst..ld-1 of out are not written; psi and out
+ * must not overlap.  One thread per (point, orbital); consecutive
+ * workgroups are kept on one XCD so that points close in the map share that
+ * XCD's L2.  Errors: RSG_EINVAL, RSG_ESHAPE (nst < 1 or ld < nst),
+ * RSG_EHIP. */
+int rsg_map_laplacian(rsg_map_t m, const void *psi, void *out, int64_t nst, int64_t ld, double scale,
+                      void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Misc                                                                */
 /* ------------------------------------------------------------------ */
 

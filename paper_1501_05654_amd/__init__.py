@@ -24,11 +24,13 @@ __all__ = [
     "energy", "dipole_expectation", "adjoint_step", "laser_field", "laser_grad",
     "control_forward", "control_backward", "OptimalControlJ", "copy", "kernel_timing",
     "C128", "MIXED", "LIB_PATH", "autotune", "set_tile", "get_tile", "tile_candidates", "Batch",
+    "GridMap", "MAP_STANDARD", "MAP_BRICKS", "MAP_HILBERT",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsg.so")
 
 C128, MIXED = 0, 1
+MAP_STANDARD, MAP_BRICKS, MAP_HILBERT = 0, 1, 2
 _OP = {"hpsi": 0, "step": 1, "reduce": 2, "energy": 3, "adjoint": 4}
 
 
@@ -85,6 +87,10 @@ def _load():
         "rsg_batch_get_tile": (C.c_int, [vp, vp]),
         "rsg_batch_autotune": (C.c_int, [vp, i32, vp, vp, vp]),
         "rsg_batch_propagate": (C.c_int, [vp, dbl, i64, i32, vp]),
+        "rsg_map_create": (C.c_int, [vp, i32, i32, vp]),
+        "rsg_map_destroy": (C.c_int, [vp]),
+        "rsg_map_order": (C.c_int, [vp, vp]),
+        "rsg_map_laplacian": (C.c_int, [vp, vp, vp, i64, i64, dbl, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -215,6 +221,44 @@ class Hamiltonian:
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None:
             _lib.rsg_ham_destroy(h)
+            self._h = None
+
+
+class GridMap:
+    """An order of the grid's points in memory (standard rows, param^3
+    bricks or the 3D Hilbert curve) with the neighbour table of the 25-point
+    stencil in that order.  Batches here are point-major [np, ld]
+    complex128 (orbital fastest), in map order."""
+
+    def __init__(self, grid: Grid, kind: int = MAP_STANDARD, param: int = 0):
+        self.grid, self.kind, self.param = grid, int(kind), int(param)
+        self._h = C.c_void_p()
+        _check(_lib.rsg_map_create(grid._h, self.kind, self.param, C.byref(self._h)))
+
+    def order(self) -> np.ndarray:
+        """order[i] = compact index of the i-th point in map order."""
+        out = np.empty(self.grid.np, dtype=np.int32)
+        _check(_lib.rsg_map_order(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def laplacian(self, psi: torch.Tensor, out: torch.Tensor | None = None, nst: int | None = None,
+                  scale: float = 1.0) -> torch.Tensor:
+        """out[:, :nst] = scale * (8th-order star stencil sum) of psi[:, :nst]."""
+        if not (psi.is_cuda and psi.dtype == torch.complex128 and psi.dim() == 2 and psi.is_contiguous()
+                and psi.shape[0] == self.grid.np):
+            raise ValueError("psi must be a contiguous CUDA complex128 tensor [np, ld]")
+        out = torch.zeros_like(psi) if out is None else out
+        if not (out.is_cuda and out.dtype == psi.dtype and out.shape == psi.shape and out.is_contiguous()):
+            raise ValueError("out must match psi")
+        n = psi.shape[1] if nst is None else int(nst)
+        _check(_lib.rsg_map_laplacian(self._h, _ptr(psi), _ptr(out), n, psi.shape[1], float(scale),
+                                      _stream()))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rsg_map_destroy(h)
             self._h = None
 
 

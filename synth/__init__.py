@@ -33,6 +33,13 @@ import numpy as np
 WORKLOADS = {
     # 32^3 cube, harmonic potential, 4 white-noise orbitals, no projectors:
     # 10 H*psi applications + 10 Taylor(4) steps.
+    # Grid-to-memory map study: spheres of 5.0e5 points (R = 9.85, h = 0.2)
+    # and 3.05e6 points (R = 18, h = 0.2), point-major batches of 1..64
+    # white-noise orbitals; standard, 4^3 / 8^3 brick and Hilbert orders.
+    "sphere500k_gridmap": dict(shape="sphere", spheres=((9.85, 0.2), (18.0, 0.2)),
+                               nst_list=(1, 4, 16, 64), seed=6,
+                               maps=(("standard", 0, 0), ("bricks4", 1, 4), ("bricks8", 1, 8),
+                                     ("hilbert", 2, 0))),
     "cube32_ho": dict(shape="cube", n=32, h=0.3, nst=4, potential="harmonic",
                       natoms=0, kb=False, steps=10, hpsi_calls=10, dt=0.01,
                       seed=1, orbitals="white"),
