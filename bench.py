@@ -37,9 +37,10 @@ def stencil_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(workload: str):
+def read_traffic(workload: str, tile=None):
     """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, if it was taken on the current stencil source."""
+    summary, if it was taken on the current stencil source and with the
+    tile shape in use."""
     p = os.path.join(ROOT, "profiles", f"traffic_stencil_{workload}.txt")
     if not os.path.exists(p):
         return None
@@ -50,6 +51,10 @@ def read_traffic(workload: str):
             kv[k.strip()] = v.strip()
     if kv.get("stencil_source_sha256") != stencil_source_hash():
         return None
+    if tile is not None:
+        key = ",".join(str(tile[k]) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM"))
+        if kv.get("tile") != key:
+            return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -148,7 +153,9 @@ def bench_sphere(args):
         tile = rsg.get_tile(gh, nst)
     elif not args.no_autotune:
         tile, tile_ms = rsg.autotune(gh, psi, reps=2)
-        log(f"autotuned tile {tile}: {tile_ms:.3f} ms per stage")
+        log(f"autotuned tile {tile}: {tile_ms:.3f} ms of stencil work per step")
+    if tile is None:
+        tile = rsg.get_tile(gh, nst)
     log(f"warmup {args.warmup} steps")
     rsg.propagate(gh, psi, dt, args.warmup, ws=ws)
     torch.cuda.synchronize()
@@ -167,7 +174,7 @@ def bench_sphere(args):
     # write (48 B); each stage reads V once (8 B per point)
     stage_bytes = (npts * nst * (32 + 3 * 48) + 4 * 8 * npts) / 4.0
     achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
-    traffic = read_traffic(args.workload)
+    traffic = read_traffic(args.workload, tile)
     norms = rsg.norm2(gg, psi).cpu().numpy()
     # plain device copy of 1 GiB: achievable copy bandwidth, and the
     # reference kernel for scaling the HBM byte counters

@@ -285,12 +285,17 @@ int rsg_tile_candidates(int32_t dtype, rsg_tile *out, int32_t max, int32_t *coun
 int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_tile *t);
 int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
 
-/* Time one Horner stage on psi (device [nst][ldp], left unchanged) for every
- * compiled tile shape, z-chunk lengths {whole, 64, 32}, PT {0, 1}, BO {0, 1,
- * 2, 4} and ZM {0, 1} with HIP events (best of reps launches after a warm-up
- * launch), re-time the six fastest with 3 reps launches each, keep the
- * fastest for (nst, dtype) and return it in *best and its time in *best_ms
- * (either may be NULL).  ws: RSG_OP_STEP bytes.  Synchronises the stream. */
+/* Tile autotuner for the Taylor(4) step on psi (device [nst][ldp], left
+ * unchanged).  Phase 1 times one of the later Horner stages (reads a work
+ * buffer and psi, writes the other work buffer) for every compiled tile
+ * shape, z-chunk lengths {whole, 64, 32, and 16, 8 when the batch has few
+ * tiles}, PT {0, 1}, BO {0, 1, 2, 4} and ZM {0, 1} with HIP events (best of
+ * reps launches after a warm-up launch).  Phase 2 re-times the six fastest
+ * on the stencil work of a whole step (the first stage plus three later
+ * ones, 3 reps launches each), keeps the fastest for (nst, dtype) and
+ * returns it in *best and that step time in *best_ms (either may be NULL).
+ * ws: RSG_OP_STEP bytes (both work buffers are used).  Synchronises the
+ * stream. */
 int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, void *ws,
                  size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
 

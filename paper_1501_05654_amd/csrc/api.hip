@@ -853,6 +853,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
     const int wt = cmp;  // work-buffer type: complex64 for the mixed path
     Carve c(ws, ws_bytes);
     void *w1 = c.take(batch_bytes(nst, ldp, cmp ? 8 : 16));
+    void *w2 = c.take(batch_bytes(nst, ldp, cmp ? 8 : 16));
     if (!c.ok) {
         set_error("rsg_autotune: workspace carve failed");
         return RSG_ENOMEM;
@@ -872,20 +873,35 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         hipEvent_t e0, e1;
         RSG_CHECK_HIP(hipEventCreate(&e0));
         RSG_CHECK_HIP(hipEventCreate(&e1));
-        StageArgs a;
-        a.in = psi;
-        a.base = psi;
-        a.out = w1;
-        a.in_t = 0;
-        a.out_t = wt;
-        a.compute = cmp;
-        a.mode = 1;
-        a.nst = nst;
-        a.ldp = ldp;
-        a.cim = -1e-3;
+        // the two kinds of Horner stage of a step: the first (reads psi
+        // once, its centre tap is the base) and the others (read a work
+        // buffer and psi, write the other work buffer)
+        StageArgs first;
+        first.in = psi;
+        first.base = psi;
+        first.out = w1;
+        first.in_t = 0;
+        first.out_t = wt;
+        first.compute = cmp;
+        first.mode = 1;
+        first.first = true;
+        first.nst = nst;
+        first.ldp = ldp;
+        first.cim = -1e-3;
+        StageArgs rest = first;
+        rest.in = w1;
+        rest.in_t = wt;
+        rest.out = w2;
+        rest.first = false;
         int err = RSG_OK;
+        // the work buffer read by the other stages holds a real stage output
+        if ((rc = launch_stencil(*H, first, default_shape(*H->g, nst, cmp), s))) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
         // best of n launches of one stage with shape sh (after a warm-up)
-        auto time_shape = [&](const TileShape &sh, int n, double *tmin) -> int {
+        auto time_stage = [&](const StageArgs &a, const TileShape &sh, int n, double *tmin) -> int {
             *tmin = 1e300;
             for (int r = 0; r <= n; ++r) {
                 RSG_CHECK_HIP(hipEventRecord(e0, s));
@@ -898,6 +914,18 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
                 if (r > 0) *tmin = std::min(*tmin, (double)ms);
             }
             return RSG_OK;
+        };
+        // phase 1 ranks by one of the other stages; phase 2 by the stencil
+        // time of a whole step, first + 3 others
+        auto time_shape = [&](const TileShape &sh, int n, double *t) -> int {
+            return time_stage(rest, sh, n, t);
+        };
+        auto time_step = [&](const TileShape &sh, int n, double *t) -> int {
+            double t1 = 0, t2 = 0;
+            int q = time_stage(first, sh, n, &t1);
+            if (!q) q = time_stage(rest, sh, n, &t2);
+            *t = t1 + 3.0 * t2;
+            return q;
         };
         // phase 1: every candidate, reps launches each
         std::vector<std::pair<double, TileShape>> timed;
@@ -928,7 +956,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
             const size_t keep = std::min<size_t>(6, timed.size());
             for (size_t k = 0; k < keep && !rc; ++k) {
                 double t = 0;
-                if ((rc = time_shape(timed[k].second, 3 * reps, &t))) break;
+                if ((rc = time_step(timed[k].second, 3 * reps, &t))) break;
                 if (t < bt) {
                     bt = t;
                     bs = timed[k].second;
