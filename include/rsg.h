@@ -343,6 +343,43 @@ int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, double *best
 int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_graph, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Shifted-Hamiltonian solves                                          */
+/* ------------------------------------------------------------------ */
+
+/* Section "The Sternheimer formulation of linear-response", eq.
+ * (sternheimer): each Sternheimer iteration
+ * solves (H - eps_n +- omega + i eta) x_n = b_n for every occupied orbital;
+ * the paper uses conjugate gradients for a real shift and the quasi-minimal
+ * residual method (Freund and Nachtigal, Numer. Math. 60, 315 (1991)) for a
+ * complex one.  Here sigma_n stands for the whole shift -eps_n +- omega +
+ * i eta and the operator is the Hamiltonian without field, so A_n = H +
+ * sigma_n is complex symmetric and QMR needs one H application per
+ * iteration. */
+enum { RSG_SOLVE_CG = 0, RSG_SOLVE_QMR = 1 };
+
+/* Workspace bytes of rsg_shifted_solve (6 batch buffers for QMR, 3 for CG,
+ * the projector buffer, partial sums and per-orbital state); 0 on bad
+ * arguments. */
+size_t rsg_solve_workspace_bytes(rsg_ham_t H, int32_t method, int64_t nst, int64_t ldp);
+
+/* Solves (H + sigma_n) x_n = b_n for n < nst.  shift: host [2*nst], re and
+ * im of sigma_n (CG: im must be 0).  b, x: device orbital-major [nst][ldp]
+ * complex128; x holds the initial guess on entry and the solution on exit;
+ * b and x must not overlap.  Orbital n stops when ||b - A x|| <= tol ||b||
+ * (the recurrence residual; ||b|| = 0 counts as 1), after maxiter
+ * iterations or at a breakdown of the recurrence; all orbitals iterate
+ * together and a stopped orbital is left untouched.  The host reads the
+ * stop flags every check_every iterations (one synchronisation each) and
+ * returns when all have stopped.  Outputs (host, [nst], each may be NULL):
+ * iters, rel_res = ||r|| / ||b||, status = 0 converged, 1 iteration limit,
+ * 2 breakdown.  ws: rsg_solve_workspace_bytes.  Synchronises the stream.
+ * Errors: RSG_EINVAL (method, shift, tol, overlap), RSG_ESHAPE (nst
+ * outside 1..65535, ldp < np), RSG_ENOMEM (workspace), RSG_EHIP. */
+int rsg_shifted_solve(rsg_ham_t H, const double *shift, const void *b, void *x, int64_t nst, int64_t ldp,
+                      int32_t method, double tol, int32_t maxiter, int32_t check_every, int32_t *iters,
+                      double *rel_res, int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Grid-to-memory maps                                                 */
 /* ------------------------------------------------------------------ */
 

@@ -24,7 +24,7 @@ __all__ = [
     "energy", "dipole_expectation", "adjoint_step", "laser_field", "laser_grad",
     "control_forward", "control_backward", "OptimalControlJ", "copy", "kernel_timing",
     "C128", "MIXED", "LIB_PATH", "autotune", "set_tile", "get_tile", "tile_candidates", "Batch",
-    "GridMap", "MAP_STANDARD", "MAP_BRICKS", "MAP_HILBERT",
+    "GridMap", "MAP_STANDARD", "MAP_BRICKS", "MAP_HILBERT", "shifted_solve",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsg.so")
@@ -87,6 +87,9 @@ def _load():
         "rsg_batch_get_tile": (C.c_int, [vp, vp]),
         "rsg_batch_autotune": (C.c_int, [vp, i32, vp, vp, vp]),
         "rsg_batch_propagate": (C.c_int, [vp, dbl, i64, i32, vp]),
+        "rsg_solve_workspace_bytes": (sz, [vp, i32, i64, i64]),
+        "rsg_shifted_solve": (C.c_int, [vp, vp, vp, vp, i64, i64, i32, dbl, i32, i32, vp, vp, vp, vp, sz,
+                                        vp]),
         "rsg_map_create": (C.c_int, [vp, i32, i32, vp]),
         "rsg_map_destroy": (C.c_int, [vp]),
         "rsg_map_order": (C.c_int, [vp, vp]),
@@ -222,6 +225,40 @@ class Hamiltonian:
         if h is not None and h.value and _lib is not None:
             _lib.rsg_ham_destroy(h)
             self._h = None
+
+
+def shifted_solve(ham: Hamiltonian, b: torch.Tensor, shift, x: torch.Tensor | None = None,
+                  method: str = "qmr", tol: float = 1e-10, maxiter: int = 1000, check_every: int = 10,
+                  nst: int | None = None, ws: torch.Tensor | None = None):
+    """Solve (H + shift[n]) x_n = b_n for each orbital (orbital-major
+    [nst, ldp] complex128).  method "qmr" (complex shifts) or "cg" (real
+    shifts).  x (initial guess, default zeros) is updated in place and
+    returned with per-orbital iterations, relative residuals and status
+    (0 converged, 1 iteration limit, 2 breakdown)."""
+    _batch(b, "b", ham.grid.np)
+    x = torch.zeros_like(b) if x is None else _batch(x, "x", ham.grid.np)
+    if x.shape != b.shape:
+        raise ValueError("x must have the shape of b")
+    n = _nst(b, nst)
+    sh = np.asarray(shift, dtype=np.complex128).reshape(-1)
+    if sh.size == 1:
+        sh = np.full(n, sh[0])
+    if sh.size < n:
+        raise ValueError(f"need {n} shifts, got {sh.size}")
+    host = np.ascontiguousarray(np.stack([sh[:n].real, sh[:n].imag], axis=1).reshape(-1))
+    m = {"cg": 0, "qmr": 1}[method]
+    need = int(_lib.rsg_solve_workspace_bytes(ham._h, m, n, b.shape[1]))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, b.device)
+    iters = np.zeros(n, dtype=np.int32)
+    res = np.zeros(n, dtype=np.float64)
+    status = np.zeros(n, dtype=np.int32)
+    vp = C.c_void_p
+    _check(_lib.rsg_shifted_solve(ham._h, host.ctypes.data_as(vp), _ptr(b), _ptr(x), n, b.shape[1], m,
+                                  float(tol), int(maxiter), int(check_every), iters.ctypes.data_as(vp),
+                                  res.ctypes.data_as(vp), status.ctypes.data_as(vp), _ptr(ws), ws.numel(),
+                                  _stream()))
+    return x, {"iters": iters, "rel_res": res, "status": status}
 
 
 class GridMap:

@@ -111,39 +111,7 @@ unsigned nblocks_for(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
 }
 
-// Bump allocator over a caller-provided workspace (256-byte aligned pieces).
-struct Carve {
-    char *base;
-    size_t cap, used = 0;
-    bool ok = true;
-    Carve(void *p, size_t n) : base((char *)p), cap(n) {}
-    void *take(size_t n) {
-        const size_t a = (used + 255) & ~(size_t)255;
-        if (a + n > cap || (!base && n)) {
-            ok = false;
-            return nullptr;
-        }
-        used = a + n;
-        return base + a;
-    }
-    // everything that is left (aligned); *n receives its size
-    void *take_rest(size_t *n) {
-        const size_t a = (used + 255) & ~(size_t)255;
-        if (!base || a >= cap) {
-            ok = false;
-            *n = 0;
-            return nullptr;
-        }
-        *n = cap - a;
-        used = cap;
-        return base + a;
-    }
-};
-
-size_t rounded(size_t n) { return (n + 255) & ~(size_t)255; }
-
-// Bytes of an orbital-major batch of nst orbitals with stride ldp.
-size_t batch_bytes(int64_t nst, int64_t ldp, size_t elem) { return (size_t)nst * (size_t)ldp * elem; }
+}  // namespace
 
 int check_batch(const Ham *H, const void *p, int64_t nst, int64_t ldp, const char *who) {
     RSG_REQUIRE(H, RSG_EINVAL, "%s: null Hamiltonian", who);
@@ -174,6 +142,8 @@ int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ldp,
     if (rc) return rc;
     return launch_kb_scatter(H, out, 0, 0, nst, ldp, D, 1.0, 0.0, nullptr, s);
 }
+
+namespace {
 
 // One Horner stage: out = base + c H(in).
 int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *out, int out_t,

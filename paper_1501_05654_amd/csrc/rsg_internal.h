@@ -223,6 +223,47 @@ int launch_kb_gather_batch(const KbSys *sys, const int4 *items, int32_t nitems, 
 int launch_kb_scatter_batch(const KbSys *sys, const int4 *items, int32_t nitems, double cre, double cim,
                             hipStream_t s);
 
+// Bump allocator over a caller-provided workspace (256-byte aligned pieces).
+struct Carve {
+    char *base;
+    size_t cap, used = 0;
+    bool ok = true;
+    Carve(void *p, size_t n) : base((char *)p), cap(n) {}
+    void *take(size_t n) {
+        const size_t a = (used + 255) & ~(size_t)255;
+        if (a + n > cap || (!base && n)) {
+            ok = false;
+            return nullptr;
+        }
+        used = a + n;
+        return base + a;
+    }
+    // everything that is left (aligned); *n receives its size
+    void *take_rest(size_t *n) {
+        const size_t a = (used + 255) & ~(size_t)255;
+        if (!base || a >= cap) {
+            ok = false;
+            *n = 0;
+            return nullptr;
+        }
+        *n = cap - a;
+        used = cap;
+        return base + a;
+    }
+};
+
+inline size_t rounded(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Bytes of an orbital-major batch of nst orbitals with stride ldp.
+inline size_t batch_bytes(int64_t nst, int64_t ldp, size_t elem) { return (size_t)nst * (size_t)ldp * elem; }
+
+// Argument checks shared by the entry points that take an orbital-major
+// batch [nst][ldp] (RSG_EINVAL / RSG_ESHAPE with a message).
+int check_batch(const Ham *H, const void *p, int64_t nst, int64_t ldp, const char *who);
+// out = H(in) for an FP64 orbital-major batch; D: kb_workspace_bytes(H, nst).
+int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ldp, double field,
+              const double *field_dev, void *D, hipStream_t s);
+
 // Reductions: partial sums per block then a fixed-order final pass.
 // kind 0: <a|b> (complex out [2*nst]); 1: |a|^2 (out [nst]);
 // 2: x_axis |a|^2 (out [nst]); all scaled by h^3.  Operands orbital-major.

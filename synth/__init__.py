@@ -33,6 +33,13 @@ import numpy as np
 WORKLOADS = {
     # 32^3 cube, harmonic potential, 4 white-noise orbitals, no projectors:
     # 10 H*psi applications + 10 Taylor(4) steps.
+    # Shifted solves (Sternheimer step): sphere R = 9.85 bohr at h = 0.2
+    # (500,199 points), 16 white-noise right-hand sides, 4 wells with
+    # projectors, shifts sigma_n = -eps_n + omega + i eta with eps_n ~
+    # U(-0.6, -0.1) Ha, omega = 0.3 Ha, eta = 0.1 Ha; QMR to 1e-8.
+    "sphere500k_qmr": dict(shape="sphere", R=9.85, h=0.2, nst=16, natoms=4, well_ball=4.0,
+                           omega=0.3, eta=0.1, eps_lo=-0.6, eps_hi=-0.1, tol=1e-8,
+                           maxiter=4000, seed=7),
     # Grid-to-memory map study: spheres of 5.0e5 points (R = 9.85, h = 0.2)
     # and 3.05e6 points (R = 18, h = 0.2), point-major batches of 1..64
     # white-noise orbitals; standard, 4^3 / 8^3 brick and Hilbert orders.
