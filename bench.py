@@ -319,6 +319,7 @@ def bench_mixed(args):
     marks = [m for m in (1, 10, 100, 1000) if m <= nsteps]
     report = {}
     timing = {}
+    kms = []
     for name, psi0 in (("white_noise", synth.white_noise(cfg["seed"], gg.np, nst, h)),
                        ("ho_low_states", synth.ho_low_states(pos, nst))):
         mixed = torch.from_numpy(psi0).cuda().t().contiguous()  # orbital-major
@@ -328,9 +329,12 @@ def bench_mixed(args):
         for m in marks:
             torch.cuda.synchronize()
             t = time.perf_counter()
-            rsg.propagate(gh, mixed, dt, m - prev, dtype="mixed")
-            torch.cuda.synchronize()
+            with rsg.kernel_timing() as kt:
+                rsg.propagate(gh, mixed, dt, m - prev, dtype="mixed")
+                torch.cuda.synchronize()
             tm += time.perf_counter() - t
+            if name == "white_noise" and kt.count:
+                kms.append((kt.mean_ms, kt.count))
             t = time.perf_counter()
             rsg.propagate(gh, full, dt, m - prev)
             torch.cuda.synchronize()
@@ -349,12 +353,23 @@ def bench_mixed(args):
         report[name] = rows
         timing[name] = {"mixed_ms_per_step": tm * 1e3 / nsteps, "fp64_ms_per_step": tf * 1e3 / nsteps}
     tot = gg.np * nst
+    # mixed Horner stages per step: read complex128 psi and complex64 work
+    # buffers, write complex64 (last stage complex128): 128 B/pt.orb per step,
+    # 32 per launch, plus the FP32 potential (4 B/pt)
+    cnt = sum(c for _, c in kms)
+    mean_ms = sum(m * c for m, c in kms) / cnt if cnt else None
+    mix_gbs = (32 * tot + 4 * gg.np) / (mean_ms * 1e-3) / 1e9 if mean_ms else None
     return {
         "metric": "mixed-precision orbital error vs the FP64 path", "value":
             report["white_noise"][-1]["orbital_rel_err_max"], "unit": "relative 2-norm",
         "n_gpus": 1, "steps": nsteps, "warmup": 0, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 H / f64 accumulation", "data": "synthetic",
         "config": {"workload": "cube32_mixed", "np": gg.np, "nst": nst, "dt": dt},
+        "roofline": {"bound": "hbm", "achieved": mix_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": mix_gbs / HBM_PEAK_GBS if mix_gbs else None, "traffic": None,
+                     "kernel": "k_stencil mixed (FP32 arithmetic, Horner stage)", "kernel_mean_ms": mean_ms,
+                     "launches_timed": cnt,
+                     "note": "2 MiB of orbitals stay in L2/MALL: a latency figure, not an HBM one"},
         "errors": report, "timing": timing,
         "mixed_value_pt_orb_H_per_s": tot * 4 * nsteps / (timing["white_noise"]["mixed_ms_per_step"] * nsteps * 1e-3),
         "cpu_baseline": None,
@@ -396,6 +411,18 @@ def bench_control(args):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     fwd, bwd = t1 - t0, t2 - t1
+    # a second, untimed backward sweep with a HIP-event pair around every
+    # stencil launch (the events would otherwise count in the ratio)
+    with rsg.kernel_timing() as kt:
+        rsg.control_backward(gh, psi, dt, nsteps, coef, ck, store)
+        torch.cuda.synchronize()
+    # stencil launches of the backward sweep: per step 4 Horner stages of the
+    # checkpoint recompute (44 B/pt.orb on average) and 7 H applications of
+    # the adjoint step (32 B/pt.orb), each also reading V (8 B/pt)
+    per_launch = (4 * 44 + 7 * 32) / 11.0 * gg.np * nst + 8 * gg.np
+    st_gbs = per_launch / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
+    # the whole sweep: 560 B/pt.orb + 88 B/pt per step (recompute, 7 H, adjoint pass)
+    sweep_gbs = (560 * gg.np * nst + 88 * gg.np) * nsteps / bwd / 1e9
     # central difference along a random unit direction d: (J(c+eps d) - J(c-eps d)) / 2 eps
     d = torch.from_numpy(synth.random_unit(cfg["seed"], cfg["ncoef"])).cuda()
     eps = 1e-4 * float(coef.abs().max())
@@ -411,6 +438,11 @@ def bench_control(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "cube96_control", "np": gg.np, "nst": nst, "dt": dt, "ncoef": cfg["ncoef"],
                    "checkpoint_every": ck},
+        "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": st_gbs / HBM_PEAK_GBS if st_gbs else None, "traffic": None,
+                     "kernel": "k_stencil in the backward sweep (Horner recompute and H-only launches)",
+                     "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
+                     "sweep_algorithmic_GBs": sweep_gbs},
         "forward_s": fwd, "gradient_s": bwd, "J": J.item(),
         "forward_value_pt_orb_H_per_s": gg.np * nst * 4 * nsteps / fwd,
         "directional_derivative": ad, "central_fd": fd, "fd_rel_err": abs(ad - fd) / max(abs(fd), 1e-300),
@@ -477,6 +509,86 @@ def bench_cube32(args):
                      "frac": alg / el / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "note": "2 MiB of orbitals stay in L2/MALL: algorithmic bytes over wall time of the "
                              "whole graph, not an HBM measurement"},
+        "cpu_baseline": None,
+    }
+
+
+def bench_cs(args):
+    """Complex scaling.  (1) H_theta applications (kinetic prefactor
+    -1/2 e^{-2 i theta}, continued wells potential) to 64 orbitals on the
+    3.05 M-point sphere, beside plain H applications, K calls each; the
+    roofline is that of the complex-scaled stencil (32 B/pt.orb + 16 B/pt
+    for V and V_im).  (2) The harmonic oscillator continued to
+    e^{2 i theta} r^2/2 on a 48^3 cube at h = 0.3: the eigenvalues nearest
+    4 targets by inverse iteration, against the exact levels 1.5 .. 4.5."""
+    import numpy as np
+    import torch
+
+    import paper_1501_05654_amd as rsg
+    import synth
+
+    cfg = dict(synth.WORKLOADS["sphere18_cs"])
+    torch.cuda.set_device(0)
+    th, nst = cfg["theta"], cfg["nst"]
+    gg = rsg.Grid(cfg["h"], R=cfg["R"])
+    pos = gg.positions()
+    wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
+    vz = synth.well_potential_scaled(pos, wells, th)
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(vz.real.copy()).cuda(), kin=-0.5)
+    psi = torch.from_numpy(synth.white_noise(cfg["seed"], gg.np, nst, cfg["h"])).cuda().t().contiguous()
+    out = torch.empty_like(psi)
+    rsg.autotune(gh, psi, reps=2)
+    reps = max(args.steps, 1)
+
+    def timed():
+        for _ in range(max(args.warmup, 1)):
+            rsg.hpsi(gh, psi, out=out)
+        torch.cuda.synchronize()
+        with rsg.kernel_timing() as kt:
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rsg.hpsi(gh, psi, out=out)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / reps
+        return el, kt.mean_ms
+
+    el_plain, k_plain = timed()
+    gh.set_complex_scaling(th, torch.from_numpy(vz.imag.copy()).cuda())
+    el_cs, k_cs = timed()
+    npo = gg.np * nst
+    alg = 32 * npo + 16 * gg.np
+    log(f"H {el_plain * 1e3:.3f} ms, H_theta {el_cs * 1e3:.3f} ms (stencil {k_plain:.3f} / {k_cs:.3f} ms)")
+    del psi, out
+    # (2) scaled oscillator
+    n, h = cfg["cube_n"], cfg["cube_h"]
+    gc = rsg.Grid(h, n=n)
+    r2 = (gc.positions() ** 2).sum(axis=1)
+    hc = rsg.Hamiltonian(gc, V=torch.from_numpy(np.cos(2 * th) * r2 / 2).cuda(), kin=-0.5)
+    hc.set_complex_scaling(th, torch.from_numpy(np.sin(2 * th) * r2 / 2).cuda())
+    targets = np.array(cfg["targets"])
+    start = torch.from_numpy(synth.white_noise(cfg["seed"] + 1, gc.np, len(targets), h)).cuda().t().contiguous()
+    t0 = time.perf_counter()
+    lam, outer = rsg.cs_eigs(hc, start, targets, max_outer=60, tol=1e-12, qmr_maxiter=20000, qmr_tol=1e-11)
+    el_eig = time.perf_counter() - t0
+    exact = np.array([1.5, 2.5, 3.5, 4.5])
+    log(f"scaled oscillator levels {lam} in {el_eig:.2f} s")
+    return {
+        "metric": "H_theta grid-pt·orbital applications/s", "value": npo / el_cs, "unit": "pt·orb·H/s",
+        "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": el_cs * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sphere18_cs", "np": gg.np, "nst": nst, "theta": th,
+                   "potential": "16 wells continued to r e^{i theta}, no projectors",
+                   "step": "one H_theta application to the batch"},
+        "roofline": {"bound": "hbm", "achieved": alg / (k_cs * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / (k_cs * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stencil complex-scaled (H application)", "kernel_mean_ms": k_cs,
+                     "algorithmic_bytes": "32 B/pt·orb + 16 B/pt"},
+        "plain_H_value": npo / el_plain, "plain_H_stencil_ms": k_plain,
+        "scaled_oscillator": {"grid": f"cube {n}^3, h = {h}", "targets": list(targets),
+                              "eigenvalues": [[float(z.real), float(z.imag)] for z in lam],
+                              "max_abs_err_vs_exact_levels": float(np.max(np.abs(lam - exact))),
+                              "max_abs_imag": float(np.max(np.abs(lam.imag))),
+                              "outer_iterations": int(outer.max()), "seconds": el_eig},
         "cpu_baseline": None,
     }
 
@@ -665,7 +777,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sphere18_wells",
                     choices=["sphere18_wells", "batch256", "cube32_mixed", "cube96_control", "cube32_ho",
-                             "sphere500k_gridmap", "sphere500k_qmr"])
+                             "sphere500k_gridmap", "sphere500k_qmr", "sphere18_cs"])
     ap.add_argument("--nsys", type=int, default=0, help="batch256: use only the first N systems")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
@@ -693,6 +805,8 @@ def main():
         out = bench_gridmap(args)
     elif args.workload == "sphere500k_qmr":
         out = bench_solve(args)
+    elif args.workload == "sphere18_cs":
+        out = bench_cs(args)
     else:
         out, cfg = bench_sphere(args)
         out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)

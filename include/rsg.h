@@ -343,6 +343,47 @@ int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, double *best
 int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_graph, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Complex scaling                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Section "Complex scaling and resonances": under r -> r e^{i theta} the
+ * Hamiltonian becomes H_theta = kin e^{-2 i theta} Lap_h + v(r e^{i theta}),
+ * symmetric but not Hermitian; bound-state energies stay put, the continuum
+ * rotates by -2 theta and resonances appear as eigenvalues eps - i Gamma/2.
+ * After this call every H application of the handle (rsg_hpsi,
+ * rsg_propagate_step, rsg_propagate, rsg_energy, rsg_shifted_solve with QMR)
+ * uses kin e^{-2 i theta} and the local potential V + i V_im, where V is
+ * the real part given at creation (the caller evaluates the continued
+ * potential) and vim_dev (device [np] float64, copied; NULL = 0) its
+ * imaginary part.  theta = 0 with vim_dev = NULL restores the Hermitian
+ * operator.  Only the FP64 path is complex-scaled (RSG_C64_MIXED returns
+ * RSG_EUNSUPPORTED).  Errors: RSG_EINVAL (theta not finite), RSG_EUNSUPPORTED
+ * (the handle has projectors or an absorber mask; the adjoint, control,
+ * batch and CG entry points reject a complex-scaled handle), RSG_EHIP. */
+int rsg_ham_set_complex_scaling(rsg_ham_t H, double theta, const double *vim_dev);
+
+/* Bilinear form without conjugation, out_dev[2n], out_dev[2n+1] = re, im of
+ * h^3 sum_r a_n(r) b_n(r) (the matrix elements of complex scaling).  Same
+ * arguments and errors as rsg_dot. */
+int rsg_bilinear(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ldp, double *out_dev,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Eigenvalues of the (complex-scaled) Hamiltonian nearest the targets
+ * z_n (host [2*nst], re and im), one per orbital, by shifted inverse
+ * iteration: psi_n <- (H - z_n)^{-1} psi_n with rsg_shifted_solve (QMR,
+ * qmr_tol, qmr_maxiter), normalised to h^3 psi^T psi = 1, lambda_n = h^3
+ * psi_n^T H psi_n, until every lambda changes by at most tol max(1,
+ * |lambda|) or after max_outer iterations.  psi: device [nst][ldp]
+ * complex128, start vectors in, eigenvectors out.  lambda: host [2*nst]
+ * out; outer_iters: host [nst] or NULL.  ws: rsg_cs_eigs_workspace_bytes.
+ * Synchronises the stream.  Errors: RSG_EINVAL (targets, tolerances, a
+ * start vector of zero bilinear norm), RSG_ESHAPE, RSG_ENOMEM, RSG_EHIP. */
+size_t rsg_cs_eigs_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp);
+int rsg_cs_eigs(rsg_ham_t H, const double *target, void *psi, int64_t nst, int64_t ldp, int32_t max_outer,
+                double tol, int32_t qmr_maxiter, double qmr_tol, double *lambda, int32_t *outer_iters, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Shifted-Hamiltonian solves                                          */
 /* ------------------------------------------------------------------ */
 
@@ -352,9 +393,9 @@ int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_gr
  * the paper uses conjugate gradients for a real shift and the quasi-minimal
  * residual method (Freund and Nachtigal, Numer. Math. 60, 315 (1991)) for a
  * complex one.  Here sigma_n stands for the whole shift -eps_n +- omega +
- * i eta and the operator is the Hamiltonian without field, so A_n = H +
- * sigma_n is complex symmetric and QMR needs one H application per
- * iteration. */
+ * i eta and the operator is the Hamiltonian without field (complex-scaled
+ * or not), so A_n = H + sigma_n is complex symmetric and QMR needs one H
+ * application per iteration; CG needs a Hermitian H. */
 enum { RSG_SOLVE_CG = 0, RSG_SOLVE_QMR = 1 };
 
 /* Workspace bytes of rsg_shifted_solve (6 batch buffers for QMR, 3 for CG,

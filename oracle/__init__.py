@@ -91,7 +91,8 @@ class _GridS(C.Structure):
 class _HamS(C.Structure):
     _fields_ = [("V", C.c_void_p), ("kin", C.c_double), ("dipole_axis", C.c_int32),
                 ("natoms", C.c_int32), ("kb_off", C.c_void_p), ("kb_idx", C.c_void_p),
-                ("kb_p", C.c_void_p), ("kb_E", C.c_void_p)]
+                ("kb_p", C.c_void_p), ("kb_E", C.c_void_p), ("kin_im", C.c_double),
+                ("V_im", C.c_void_p)]
 
 
 class Grid:
@@ -127,13 +128,22 @@ class Grid:
 
 
 class Ham:
-    """H = kin * Laplacian + V + field * x_axis + separable projectors."""
+    """H = kin * Laplacian + V + field * x_axis + separable projectors.
+
+    Complex scaling (section "Complex scaling and resonances"): theta != 0
+    makes the kinetic prefactor kin e^{-2 i theta}; V_im is the imaginary
+    part of the continued local potential v(r e^{i theta}) (V its real
+    part)."""
 
     def __init__(self, grid: Grid, V=None, kin: float = -0.5, dipole_axis: int = -1,
-                 projectors=None):
+                 projectors=None, theta: float = 0.0, V_im=None):
         self.grid = grid
         self.V = None if V is None else np.ascontiguousarray(V, dtype=np.float64)
-        self.kin = float(kin)
+        self.V_im = None if V_im is None else np.ascontiguousarray(V_im, dtype=np.float64)
+        self.theta = float(theta)
+        kc = complex(kin) * np.exp(-2j * self.theta) if self.theta != 0.0 else complex(kin)
+        self.kin = float(kc.real)
+        self.kin_im = float(kc.imag)
         self.dipole_axis = int(dipole_axis)
         na = 0 if projectors is None else projectors.natoms
         if na:
@@ -149,7 +159,8 @@ class Ham:
             self.kb_E = np.zeros(4)
         self._s = _HamS(None if self.V is None else self.V.ctypes.data, self.kin,
                         self.dipole_axis, na, self.kb_off.ctypes.data, self.kb_idx.ctypes.data,
-                        self.kb_p.ctypes.data, self.kb_E.ctypes.data)
+                        self.kb_p.ctypes.data, self.kb_E.ctypes.data, self.kin_im,
+                        None if self.V_im is None else self.V_im.ctypes.data)
 
 
 def _c(psi):

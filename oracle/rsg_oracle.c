@@ -44,6 +44,11 @@
  *    propagated backwards by the adjoint of the forward propagator.  The
  *    oracle computes the exact gradient of the time-discretised target
  *    (discrete adjoint); the continuous formula is its dt -> 0 limit.
+ *  - Complex scaling r -> r e^{i theta} (section "Complex scaling and
+ *    resonances"): the kinetic prefactor becomes kin e^{-2 i theta} and the
+ *    local potential its analytic continuation v(r e^{i theta}), whose real
+ *    and imaginary parts are inputs; the operator stays symmetric (not
+ *    Hermitian), and its matrix elements take no complex conjugation.
  */
 #include <complex.h>
 #include <math.h>
@@ -73,6 +78,8 @@ typedef struct {
     const int32_t *kb_idx;   /* compact indices of every support S_a */
     const double *kb_p;      /* [entries][4] projector values */
     const double *kb_E;      /* [natoms][4] projector energies */
+    double kin_im;           /* imaginary part of the kinetic prefactor (complex scaling) */
+    const double *V_im;      /* [np] imaginary part of the local potential, or NULL */
 } or_ham;
 
 /* ---------------------------------------------------------------------- */
@@ -163,7 +170,8 @@ static const double FD8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0,
      (H psi)(r) = kin/h^2 sum_axes sum_{m=-4..4} c_|m| psi(r + m h e_axis)
                 + (V(r) + field * x_axis(r)) psi(r)
                 + sum_a sum_i p_i^a(r) E_i^a [h^3 sum_{r' in S_a} p_i^a(r') psi(r')]
-   for the first nst of ld columns; columns nst..ld-1 of out are untouched. */
+   for the first nst of ld columns; columns nst..ld-1 of out are untouched.
+   Complex-scaled: kin -> kin + i kin_im and V -> V + i V_im. */
 void or_hpsi(const or_grid *g, const or_ham *H, double field,
              const cplx *psi, int64_t nst, int64_t ld, cplx *out) {
     const double inv_h2 = 1.0 / (g->h * g->h);
@@ -172,6 +180,9 @@ void or_hpsi(const or_grid *g, const or_ham *H, double field,
         const int32_t *c = g->ijk + 3 * p;
         double vloc = H->V ? H->V[p] : 0.0;
         if (H->dipole_axis >= 0) vloc += field * coord(g, p, H->dipole_axis);
+        const int cs = H->kin_im != 0.0 || H->V_im != NULL;
+        const cplx kin_c = H->kin + I * H->kin_im;
+        const cplx vloc_c = vloc + I * (H->V_im ? H->V_im[p] : 0.0);
         for (int64_t s = 0; s < nst; ++s) {
             cplx lap = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -182,7 +193,10 @@ void or_hpsi(const or_grid *g, const or_ham *H, double field,
                     if (j >= 0) lap += FD8[m < 0 ? -m : m] * psi[j * ld + s];
                 }
             }
-            out[p * ld + s] = H->kin * inv_h2 * lap + vloc * psi[p * ld + s];
+            if (cs)
+                out[p * ld + s] = kin_c * inv_h2 * lap + vloc_c * psi[p * ld + s];
+            else
+                out[p * ld + s] = H->kin * inv_h2 * lap + vloc * psi[p * ld + s];
         }
     }
     /* non-local part, atom by atom in order */

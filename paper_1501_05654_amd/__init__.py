@@ -24,7 +24,7 @@ __all__ = [
     "energy", "dipole_expectation", "adjoint_step", "laser_field", "laser_grad",
     "control_forward", "control_backward", "OptimalControlJ", "copy", "kernel_timing",
     "C128", "MIXED", "LIB_PATH", "autotune", "set_tile", "get_tile", "tile_candidates", "Batch",
-    "GridMap", "MAP_STANDARD", "MAP_BRICKS", "MAP_HILBERT", "shifted_solve",
+    "GridMap", "MAP_STANDARD", "MAP_BRICKS", "MAP_HILBERT", "shifted_solve", "bilinear", "cs_eigs",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsg.so")
@@ -87,6 +87,10 @@ def _load():
         "rsg_batch_get_tile": (C.c_int, [vp, vp]),
         "rsg_batch_autotune": (C.c_int, [vp, i32, vp, vp, vp]),
         "rsg_batch_propagate": (C.c_int, [vp, dbl, i64, i32, vp]),
+        "rsg_ham_set_complex_scaling": (C.c_int, [vp, dbl, vp]),
+        "rsg_bilinear": (C.c_int, [vp, vp, vp, i64, i64, vp, vp, sz, vp]),
+        "rsg_cs_eigs_workspace_bytes": (sz, [vp, i64, i64]),
+        "rsg_cs_eigs": (C.c_int, [vp, vp, vp, i64, i64, i32, dbl, i32, dbl, vp, vp, vp, sz, vp]),
         "rsg_solve_workspace_bytes": (sz, [vp, i32, i64, i64]),
         "rsg_shifted_solve": (C.c_int, [vp, vp, vp, vp, i64, i64, i32, dbl, i32, i32, vp, vp, vp, vp, sz,
                                         vp]),
@@ -217,6 +221,18 @@ class Hamiltonian:
             torch.cuda.synchronize()
         _check(_lib.rsg_ham_set_mask(self._h, _ptr(mask)))
 
+    def set_complex_scaling(self, theta: float, V_im: torch.Tensor | None = None):
+        """Complex scaling r -> r e^{i theta}: kinetic prefactor kin
+        e^{-2 i theta} and imaginary potential V_im (CUDA float64 [np], the
+        imaginary part of the continued potential; the real part is the V
+        given at creation).  theta = 0 and V_im = None undo it."""
+        if V_im is not None:
+            V_im = V_im.to(torch.float64).contiguous()
+            if not V_im.is_cuda or V_im.numel() != self.grid.np:
+                raise ValueError("V_im must be a CUDA float64 tensor with np entries")
+            torch.cuda.synchronize()
+        _check(_lib.rsg_ham_set_complex_scaling(self._h, float(theta), _ptr(V_im)))
+
     def workspace_bytes(self, op: str, nst: int, ldp: int, dtype: int = C128) -> int:
         return int(_lib.rsg_workspace_bytes(self._h, _OP[op], nst, ldp, dtype))
 
@@ -225,6 +241,46 @@ class Hamiltonian:
         if h is not None and h.value and _lib is not None:
             _lib.rsg_ham_destroy(h)
             self._h = None
+
+
+def bilinear(grid: Grid | Hamiltonian, a: torch.Tensor, b: torch.Tensor,
+             nst: int | None = None) -> torch.Tensor:
+    """h^3 sum a_n b_n per orbital, no conjugation -> complex128 CUDA [nst]."""
+    grid = _grid_of(grid)
+    _batch(a, "a", grid.np)
+    _batch(b, "b", grid.np)
+    if a.shape != b.shape:
+        raise ValueError("a and b must have the same shape")
+    n = _nst(a, nst)
+    out = torch.empty(2 * n, dtype=torch.float64, device=a.device)
+    ws = _reduce_ws(grid, n, a.device)
+    _check(_lib.rsg_bilinear(grid._h, _ptr(a), _ptr(b), n, a.shape[1], _ptr(out), _ptr(ws),
+                             ws.numel(), _stream()))
+    return torch.view_as_complex(out.view(n, 2))
+
+
+def cs_eigs(ham: Hamiltonian, psi: torch.Tensor, targets, max_outer: int = 50, tol: float = 1e-12,
+            qmr_maxiter: int = 5000, qmr_tol: float = 1e-12, nst: int | None = None):
+    """Eigenvalues nearest targets[n] by shifted inverse iteration (QMR
+    inner solves); psi (start vectors, orbital-major) is overwritten with
+    the eigenvectors, normalised to h^3 psi^T psi = 1.  Returns (lambda
+    complex numpy [nst], outer iterations)."""
+    _batch(psi, "psi", ham.grid.np)
+    n = _nst(psi, nst)
+    z = np.asarray(targets, dtype=np.complex128).reshape(-1)
+    if z.size == 1:
+        z = np.full(n, z[0])
+    if z.size < n:
+        raise ValueError(f"need {n} targets")
+    zt = np.ascontiguousarray(np.stack([z[:n].real, z[:n].imag], axis=1).reshape(-1))
+    lam = np.zeros(2 * n)
+    its = np.zeros(n, dtype=np.int32)
+    ws = _ws(_lib.rsg_cs_eigs_workspace_bytes(ham._h, n, psi.shape[1]), psi.device)
+    vp = C.c_void_p
+    _check(_lib.rsg_cs_eigs(ham._h, zt.ctypes.data_as(vp), _ptr(psi), n, psi.shape[1], int(max_outer), float(tol),
+                            int(qmr_maxiter), float(qmr_tol), lam.ctypes.data_as(vp), its.ctypes.data_as(vp),
+                            _ptr(ws), ws.numel(), _stream()))
+    return lam[0::2] + 1j * lam[1::2], its
 
 
 def shifted_solve(ham: Hamiltonian, b: torch.Tensor, shift, x: torch.Tensor | None = None,

@@ -67,6 +67,7 @@ void timing_after(hipStream_t s) {
 Ham::~Ham() {
     if (V) (void)hipFree(V);
     if (mask) (void)hipFree(mask);
+    if (vim) (void)hipFree(vim);
     if (V32) (void)hipFree(V32);
     if (kb_idx) (void)hipFree(kb_idx);
     if (kb_p) (void)hipFree(kb_p);
@@ -442,9 +443,33 @@ extern "C" int rsg_ham_destroy(rsg_ham_t H) {
     return RSG_OK;
 }
 
+extern "C" int rsg_ham_set_complex_scaling(rsg_ham_t H, double theta, const double *vim_dev) {
+    clear_error();
+    RSG_REQUIRE(H, RSG_EINVAL, "rsg_ham_set_complex_scaling: null Hamiltonian");
+    RSG_REQUIRE(std::isfinite(theta), RSG_EINVAL, "rsg_ham_set_complex_scaling: theta not finite");
+    const bool on = theta != 0 || vim_dev;
+    RSG_REQUIRE(!on || H->natoms == 0, RSG_EUNSUPPORTED,
+                "rsg_ham_set_complex_scaling: projectors are not complex-scaled in this library");
+    RSG_REQUIRE(!on || !H->mask, RSG_EUNSUPPORTED,
+                "rsg_ham_set_complex_scaling: a complex-scaled Hamiltonian takes no absorber mask");
+    drop_graphs(H);  // captured steps hold the old kernels
+    H->cs_theta = theta;
+    if (!vim_dev) {
+        if (H->vim) RSG_CHECK_HIP(hipFree(H->vim));
+        H->vim = nullptr;
+        return RSG_OK;
+    }
+    const int64_t np = H->g->np;
+    if (!H->vim && np > 0) RSG_CHECK_HIP(hipMalloc(&H->vim, sizeof(double) * np));
+    if (np > 0) RSG_CHECK_HIP(hipMemcpy(H->vim, vim_dev, sizeof(double) * np, hipMemcpyDeviceToDevice));
+    return RSG_OK;
+}
+
 extern "C" int rsg_ham_set_mask(rsg_ham_t H, const double *mask_dev) {
     clear_error();
     RSG_REQUIRE(H, RSG_EINVAL, "rsg_ham_set_mask: null Hamiltonian");
+    RSG_REQUIRE(!mask_dev || !H->complex_scaled(), RSG_EUNSUPPORTED,
+                "rsg_ham_set_mask: a complex-scaled Hamiltonian takes no absorber mask");
     drop_graphs(H);  // captured steps hold the old mask (or none)
     if (!mask_dev) {
         if (H->mask) RSG_CHECK_HIP(hipFree(H->mask));
@@ -498,6 +523,8 @@ extern "C" int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t l
     int rc = check_batch(H, psi, nst, ldp, "rsg_propagate_step");
     if (rc) return rc;
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_propagate_step: bad dtype %d", dtype);
+    RSG_REQUIRE(dtype == RSG_C128 || !H->complex_scaled(), RSG_EUNSUPPORTED,
+                "rsg_propagate_step: a complex-scaled Hamiltonian needs RSG_C128");
     RSG_REQUIRE(std::isfinite(dt) && std::isfinite(field), RSG_EINVAL, "rsg_propagate_step: dt/field not finite");
     RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ldp, dtype) - 256 || nst == 0, RSG_ENOMEM,
                 "rsg_propagate_step: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ldp, dtype));
@@ -512,6 +539,8 @@ extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, i
     int rc = check_batch(H, psi, nst, ldp, "rsg_propagate");
     if (rc) return rc;
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_propagate: bad dtype %d", dtype);
+    RSG_REQUIRE(dtype == RSG_C128 || !H->complex_scaled(), RSG_EUNSUPPORTED,
+                "rsg_propagate: a complex-scaled Hamiltonian needs RSG_C128");
     RSG_REQUIRE(nsteps >= 0 && std::isfinite(dt), RSG_EINVAL, "rsg_propagate: bad nsteps/dt");
     RSG_REQUIRE(ws_bytes >= step_ws(*H, nst, ldp, dtype) - 256 || nst == 0, RSG_ENOMEM,
                 "rsg_propagate: workspace too small (%zu < %zu)", ws_bytes, step_ws(*H, nst, ldp, dtype));
@@ -592,6 +621,17 @@ extern "C" int rsg_dot(rsg_grid_t g, const void *a, const void *b, int64_t nst, 
                          (hipStream_t)stream);
 }
 
+extern "C" int rsg_bilinear(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ldp, double *out,
+                            void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = check_reduce(g, a, nst, ldp, out, "rsg_bilinear");
+    if (rc) return rc;
+    RSG_REQUIRE(nst == 0 || b, RSG_EINVAL, "rsg_bilinear: null pointer");
+    RSG_REQUIRE(((uintptr_t)b & 15) == 0, RSG_EINVAL, "rsg_bilinear: pointer not 16-byte aligned");
+    return launch_reduce(*g, 3, 0, (const double2 *)a, (const double2 *)b, nst, ldp, out, ws, ws_bytes,
+                         (hipStream_t)stream);
+}
+
 extern "C" int rsg_norm2(rsg_grid_t g, const void *a, int64_t nst, int64_t ldp, double *out, void *ws,
                          size_t ws_bytes, void *stream) {
     clear_error();
@@ -641,6 +681,8 @@ extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, in
     if (rc) return rc;
     RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "rsg_adjoint_step: Hamiltonian has no dipole axis");
     RSG_REQUIRE(!H->mask, RSG_EUNSUPPORTED, "rsg_adjoint_step: the adjoint of a masked step is not built");
+    RSG_REQUIRE(!H->complex_scaled(), RSG_EUNSUPPORTED,
+                "rsg_adjoint_step: the adjoint assumes a Hermitian Hamiltonian (no complex scaling)");
     RSG_REQUIRE(g_dev, RSG_EINVAL, "rsg_adjoint_step: null gradient output");
     RSG_REQUIRE(ws_bytes >= adjoint_ws(*H, nst, ldp) - 256, RSG_ENOMEM,
                 "rsg_adjoint_step: workspace too small (%zu < %zu)", ws_bytes, adjoint_ws(*H, nst, ldp));
@@ -668,6 +710,8 @@ static int check_control(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp,
     if (rc) return rc;
     RSG_REQUIRE(H->axis >= 0, RSG_EINVAL, "%s: Hamiltonian has no dipole axis", who);
     RSG_REQUIRE(!H->mask, RSG_EUNSUPPORTED, "%s: the adjoint of a masked step is not built", who);
+    RSG_REQUIRE(!H->complex_scaled(), RSG_EUNSUPPORTED,
+                "%s: the adjoint assumes a Hermitian Hamiltonian (no complex scaling)", who);
     RSG_REQUIRE(nst > 0 && nsteps > 0 && dt > 0 && std::isfinite(dt), RSG_EINVAL, "%s: need nst, nsteps, dt > 0", who);
     RSG_REQUIRE(ncoef >= 0 && (ncoef == 0 || coef), RSG_EINVAL, "%s: bad coefficient array", who);
     RSG_REQUIRE(ckpt >= 1, RSG_EINVAL, "%s: ckpt_every must be >= 1", who);

@@ -216,6 +216,8 @@ static int check_systems(int32_t nsys, const rsg_system_desc *sys) {
         RSG_REQUIRE(d.psi && ((uintptr_t)d.psi & 15) == 0, RSG_EINVAL, "batch: system %d orbital pointer", i);
         RSG_REQUIRE(d.ham->axis < 0, RSG_EUNSUPPORTED, "batch: system %d has a dipole field (not batched)", i);
         RSG_REQUIRE(!d.ham->mask, RSG_EUNSUPPORTED, "batch: system %d has an absorber mask (not batched)", i);
+        RSG_REQUIRE(!d.ham->complex_scaled(), RSG_EUNSUPPORTED, "batch: system %d is complex-scaled (not batched)",
+                    i);
         RSG_REQUIRE(d.ham->g->np < ((int64_t)1 << 27), RSG_EUNSUPPORTED, "batch: system %d has 2^27 points or more", i);
     }
     return RSG_OK;

@@ -60,7 +60,8 @@ struct RArgs {
     double *part;
 };
 
-// KIND 0: conj(a) b; 1: |a|^2; 2: x_axis |a|^2.  blockIdx.x = point chunk,
+// KIND 0: conj(a) b; 1: |a|^2; 2: x_axis |a|^2; 3: a b (no conjugation, the
+// bilinear form of complex scaling).  blockIdx.x = point chunk,
 // blockIdx.y = orbital.
 template <int KIND>
 __global__ void __launch_bounds__(RB) k_reduce_partial(RArgs r) {
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(RB) k_reduce_partial(RArgs r) {
     const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
     const int64_t p1 = min(r.np, p0 + r.chunk);
     const double2 *a = r.a + n * r.ldp;
-    const double2 *b = KIND == 0 ? r.b + n * r.ldp : nullptr;
+    const double2 *b = (KIND == 0 || KIND == 3) ? r.b + n * r.ldp : nullptr;
     double re = 0.0, im = 0.0;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += RB) {
         const double2 va = a[p];
@@ -77,6 +78,10 @@ __global__ void __launch_bounds__(RB) k_reduce_partial(RArgs r) {
             const double2 vb = b[p];
             re += va.x * vb.x + va.y * vb.y;
             im += va.x * vb.y - va.y * vb.x;
+        } else if (KIND == 3) {
+            const double2 vb = b[p];
+            re += va.x * vb.x - va.y * vb.y;
+            im += va.x * vb.y + va.y * vb.x;
         } else if (KIND == 1) {
             re += va.x * va.x + va.y * va.y;
         } else {
@@ -249,9 +254,10 @@ int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const dou
     const dim3 grid((unsigned)nblk, (unsigned)nst);
     if (kind == 0) k_reduce_partial<0><<<grid, RB, 0, s>>>(r);
     else if (kind == 1) k_reduce_partial<1><<<grid, RB, 0, s>>>(r);
+    else if (kind == 3) k_reduce_partial<3><<<grid, RB, 0, s>>>(r);
     else k_reduce_partial<2><<<grid, RB, 0, s>>>(r);
     const double h3 = g.h * g.h * g.h;
-    k_reduce_final<<<(unsigned)nst, RB, 0, s>>>(r.part, nblk, nst, kind == 0 ? 2 : 1, h3, out);
+    k_reduce_final<<<(unsigned)nst, RB, 0, s>>>(r.part, nblk, nst, (kind == 0 || kind == 3) ? 2 : 1, h3, out);
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }

@@ -114,6 +114,11 @@ struct Ham {
     double *V = nullptr;     // device [np] or null
     float *V32 = nullptr;    // device [np] FP32 copy or null
     double *mask = nullptr;  // device [np] absorber mask applied after every step, or null
+    // complex scaling r -> r e^{i theta}: kinetic prefactor kin e^{-2 i theta}
+    // and an imaginary part of the local potential (device [np] or null)
+    double cs_theta = 0;
+    double *vim = nullptr;
+    bool complex_scaled() const { return cs_theta != 0 || vim != nullptr; }
     // projectors, padded per atom to a multiple of 16 support entries
     int32_t natoms = 0;
     int32_t *kb_idx = nullptr;   // device [total_padded]
@@ -169,8 +174,10 @@ struct KParams {
     const void *V;
     const double *field_dev;
     const double *mask;
+    const double *Vim;  // imaginary part of the local potential (complex scaling) or null
     int64_t nst, ldp, np;
     double kin_h2;
+    double kin_h2_im;   // imaginary part of the kinetic prefactor over h^2 (complex scaling)
     double field;
     double h;
     double off[3];
@@ -266,7 +273,8 @@ int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ldp,
 
 // Reductions: partial sums per block then a fixed-order final pass.
 // kind 0: <a|b> (complex out [2*nst]); 1: |a|^2 (out [nst]);
-// 2: x_axis |a|^2 (out [nst]); all scaled by h^3.  Operands orbital-major.
+// 2: x_axis |a|^2 (out [nst]); 3: sum a b without conjugation (complex out
+// [2*nst]); all scaled by h^3.  Operands orbital-major.
 size_t reduce_workspace_bytes(const Grid &g, int64_t nst);
 int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const double2 *b,
                   int64_t nst, int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s);

@@ -6,7 +6,8 @@
 // conjugate gradients for a real shift and the quasi-minimal residual method
 // (Freund and Nachtigal, Numer. Math. 60, 315 (1991)) for a complex one.
 // The Hamiltonian of this library is real symmetric (real potential, real
-// projectors, a real field), so A = H + sigma is complex symmetric, A^T = A:
+// projectors, a real field), or complex symmetric once complex-scaled, so
+// A = H + sigma is complex symmetric, A^T = A:
 // the two-sided Lanczos process of QMR then needs only A, its left vectors
 // equal the right ones under the bilinear form u^T v (no conjugation), and
 // one H application per iteration suffices.
@@ -437,6 +438,8 @@ extern "C" int rsg_shifted_solve(rsg_ham_t H, const double *shift, const void *b
     RSG_REQUIRE(shift, RSG_EINVAL, "rsg_shifted_solve: null shift");
     RSG_REQUIRE(tol >= 0 && std::isfinite(tol) && maxiter >= 0 && check_every >= 1, RSG_EINVAL,
                 "rsg_shifted_solve: need tol >= 0, maxiter >= 0, check_every >= 1");
+    RSG_REQUIRE(method == RSG_SOLVE_QMR || !H->complex_scaled(), RSG_EINVAL,
+                "rsg_shifted_solve: conjugate gradients need a Hermitian Hamiltonian (no complex scaling)");
     for (int64_t n = 0; n < nst; ++n) {
         RSG_REQUIRE(std::isfinite(shift[2 * n]) && std::isfinite(shift[2 * n + 1]), RSG_EINVAL,
                     "rsg_shifted_solve: shift %lld is not finite", (long long)n);

@@ -33,6 +33,7 @@
 #include "rsg_internal.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace rsg {
 
@@ -201,18 +202,26 @@ struct Halo {
 // The per-point epilogue shared by both marches: H value from the Laplacian
 // taps, then the stage combination (times the absorber mask m_c when MASK),
 // stored at idx (dropped when idx < 0).
-template <class Tc, class Tout, int MODE, bool FIRST, bool MASK>
+template <class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
 __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0, Tc lr, Tc li, Tc v_c,
-                                       double2 b_c, double m_c, double E, int x, int y, int z, int idx,
-                                       __amdgpu_buffer_rsrc_t rout) {
+                                       Tc vi_c, double2 b_c, double m_c, double E, int x, int y, int z,
+                                       int idx, __amdgpu_buffer_rsrc_t rout) {
     Tc vloc = v_c;
     if (a.axis >= 0) {
         const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
         vloc += (Tc)(E * (a.h * ((double)cc - a.off[a.axis])));
     }
     const Tc kin_h2 = (Tc)a.kin_h2;
-    const Tc hr = kin_h2 * lr + vloc * q0.x;
-    const Tc hi = kin_h2 * li + vloc * q0.y;
+    Tc hr, hi;
+    if constexpr (CS) {
+        // complex kinetic prefactor and complex local potential
+        const Tc ki = (Tc)a.kin_h2_im;
+        hr = kin_h2 * lr - ki * li + vloc * q0.x - vi_c * q0.y;
+        hi = kin_h2 * li + ki * lr + vloc * q0.y + vi_c * q0.x;
+    } else {
+        hr = kin_h2 * lr + vloc * q0.x;
+        hi = kin_h2 * li + vloc * q0.y;
+    }
     const unsigned o = boff<Tout>(idx);
     if (MODE == 0) {
         store_c(rout, o, (Tout *)nullptr, (double)hr, (double)hi);
@@ -242,7 +251,7 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
 // All rings are indexed by compile-time constants after unrolling the step
 // loop by a common period, so no register is moved while its load is in
 // flight.  FIRST: base == in, whose value at the point is the centre tap.
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK>
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
 __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile) {
     using C2 = typename CT<Tc>::c2;
@@ -263,6 +272,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
     const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
     const auto rm = rsrc(MASK ? a.mask : a.V, MASK ? np * 8 : 0);
+    const auto rvi = rsrc(CS ? a.Vim : a.V, CS && a.Vim ? np * 8 : 0);
     const Halo<TX, TY, HPT> hl(t, it);
 
     auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
@@ -272,6 +282,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
     auto fetch_m = [&](int idx) -> double { return MASK ? BL<double>::ld(rm, boff<double>(idx)) : 1.0; };
+    auto fetch_vi = [&](int idx) -> Tc { return CS ? (Tc)BL<double>::ld(rvi, boff<double>(idx)) : (Tc)0; };
 
     const int zs = it.z, dir = it.w > it.z ? 1 : -1;
     const int nk = (it.w - it.z) * dir;  // planes to compute
@@ -294,16 +305,18 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
         for (int k = 0; k < HPT; ++k)
             hal[d][k] = d < HA ? fetch(idx_in_row(row_of(a, hl.y[k], zs + dir * d), hl.x[k]), hl.ok[k] && d < nk)
                                : C2{(Tc)0, (Tc)0};
-    Tc vr[VD];
+    Tc vr[VD], vir[VD];
     double2 br[VD];
     double mr[VD];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         vr[d] = fetch_v(oid[4 + d]);
+        vir[d] = fetch_vi(oid[4 + d]);
         br[d] = fetch_b(oid[4 + d]);
         mr[d] = fetch_m(oid[4 + d]);
     }
     vr[D] = (Tc)0;
+    vir[D] = (Tc)0;
     br[D] = make_double2(0.0, 0.0);
     mr[D] = 0.0;
     // step k reads row slot k % 2 and fills the other one
@@ -336,6 +349,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                 if (hl.ok[j]) pl[hl.l[j]] = hal[sh][j];
             const int idx_c = oid[SLOT(0)];
             const Tc v_c = vr[sv];
+            const Tc vi_c = vir[sv];
             const double2 b_c = br[sv];
             const double m_c = mr[sv];
             __syncthreads();
@@ -354,6 +368,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                     hal[shl][j] = fetch(idx_in_row(rhl[sr][j], hl.x[j]), hl.ok[j] && hlive);
                 const int idv = k + D < nk ? oid[SLOT(D)] : -1;
                 vr[svn] = fetch_v(idv);
+                vir[svn] = fetch_vi(idv);
                 br[svn] = fetch_b(idv);
                 mr[svn] = fetch_m(idv);
             }
@@ -376,7 +391,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                      FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (zm4.y + zp4.y));
             }
 #undef SLOT
-            finish<Tc, Tout, MODE, FIRST, MASK>(a, q0, lr, li, v_c, b_c, m_c, E, x, y, z, idx_c, rout);
+            finish<Tc, Tout, MODE, FIRST, MASK, CS>(a, q0, lr, li, v_c, vi_c, b_c, m_c, E, x, y, z, idx_c, rout);
             // no barrier here: the next step writes the other plane buffer,
             // and every wave has finished reading it once all have passed
             // this step's barrier
@@ -388,7 +403,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
 // registers and every load of plane k+1 (own column k+5, halo, V, base) is
 // issued one step ahead; a step starts by waiting for the previous step's
 // loads.  Planes run zs, zs + dir, ... as in the pipelined march.
-template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK>
+template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
 __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile) {
     using C2 = typename CT<Tc>::c2;
@@ -403,6 +418,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
     const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
     const auto rm = rsrc(MASK ? a.mask : a.V, MASK ? np * 8 : 0);
+    const auto rvi = rsrc(CS ? a.Vim : a.V, CS && a.Vim ? np * 8 : 0);
     const Halo<TX, TY, HPT> hl(t, it);
 
     auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
@@ -412,6 +428,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
     auto fetch_m = [&](int idx) -> double { return MASK ? BL<double>::ld(rm, boff<double>(idx)) : 1.0; };
+    auto fetch_vi = [&](int idx) -> Tc { return CS ? (Tc)BL<double>::ld(rvi, boff<double>(idx)) : (Tc)0; };
 
     const int zs = it.z, dir = it.w > it.z ? 1 : -1;
     const int nk = (it.w - it.z) * dir;
@@ -424,6 +441,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
 #pragma unroll
     for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
     Tc v_c = fetch_v(idx_c);
+    Tc vi_c = fetch_vi(idx_c);
     double2 b_c = fetch_b(idx_c);
     double m_c = fetch_m(idx_c);
     int2 rf = row_of(a, y, zs + dir * 5);  // rows for the loads of the first step
@@ -455,6 +473,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
         for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(rh[j], hl.x[j]), hl.ok[j] && live);
         const int idx_n = live ? idx_in_row(ro, x) : -1;
         const Tc v_n = fetch_v(idx_n);
+        const Tc vi_n = fetch_vi(idx_n);
         const double2 b_n = fetch_b(idx_n);
         const double m_n = fetch_m(idx_n);
         rf = rf_n;
@@ -478,25 +497,27 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
                  FD<Tc>::c3 * ((xm3.y + xp3.y) + (ym3.y + yp3.y) + (q[1].y + q[7].y)) +
                  FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (q[0].y + q[8].y));
         }
-        finish<Tc, Tout, MODE, FIRST, MASK>(a, q0, lr, li, v_c, b_c, m_c, E, x, y, z, idx_c, rout);
+        finish<Tc, Tout, MODE, FIRST, MASK, CS>(a, q0, lr, li, v_c, vi_c, b_c, m_c, E, x, y, z, idx_c, rout);
 #pragma unroll
         for (int j = 0; j < 8; ++j) q[j] = q[j + 1];
         idx_c = idx_n;
         v_c = v_n;
+        vi_c = vi_n;
         b_c = b_n;
         m_c = m_n;
     }
 }
 
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK>
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
 __device__ __forceinline__ void march(const KParams &a, const int4 it, const int n, typename CT<Tc>::c2 *tile) {
     if constexpr (D == 0)
-        march_lean<TX, TY, Tin, Tc, Tout, MODE, FIRST, MASK>(a, it, n, tile);
+        march_lean<TX, TY, Tin, Tc, Tout, MODE, FIRST, MASK, CS>(a, it, n, tile);
     else
-        march_ring<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK>(a, it, n, tile);
+        march_ring<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK, CS>(a, it, n, tile);
 }
 
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK = false>
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK = false,
+          bool CS = false>
 __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     __shared__ typename CT<Tc>::c2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -506,7 +527,7 @@ __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     // scalar registers (no per-lane loop around each buffer instruction)
     n = __builtin_amdgcn_readfirstlane(n);
     item = __builtin_amdgcn_readfirstlane(item);
-    march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK>(a, a.items[item], n, tile);
+    march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK, CS>(a, a.items[item], n, tile);
 }
 
 // Persistent form over many independent systems (FP64): in round r the G
@@ -525,10 +546,25 @@ __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__rest
         KParams a = sysp[__builtin_amdgcn_readfirstlane(bi.sys)];
         a.cre = cre;
         a.cim = cim;
-        march<TX, TY, D, double2, double, double2, 1, FIRST, false>(a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob),
-                                                                 tile);
+        march<TX, TY, D, double2, double, double2, 1, FIRST, false, false>(
+            a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile);
         __syncthreads();  // the next item reuses the plane buffer
     }
+}
+
+// Complex-scaled Hamiltonians use the depth-1 pipelined march; other tile
+// shapes are mapped to these (see launch_stencil).
+template <int TX, int TY, int D>
+int launch_fp64_cs(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
+    constexpr int NT = TX * TY;
+    if (a.in_t != 0 || a.out_t != 0 || a.mask) return RSG_EUNSUPPORTED;
+    if (a.mode == 0)
+        k_stencil<TX, TY, D, double2, double, double2, 0, false, false, true><<<nb, NT, 0, s>>>(p);
+    else if (a.first)
+        k_stencil<TX, TY, D, double2, double, double2, 1, true, false, true><<<nb, NT, 0, s>>>(p);
+    else
+        k_stencil<TX, TY, D, double2, double, double2, 1, false, false, true><<<nb, NT, 0, s>>>(p);
+    return RSG_OK;
 }
 
 template <int TX, int TY, int D>
@@ -575,6 +611,7 @@ int launch_fp32(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
     X(8, 8, 1) X(8, 8, 2) X(16, 8, 1) X(16, 8, 2) X(32, 8, 1) X(32, 8, 2) X(16, 16, 1) \
     X(16, 16, 2) X(32, 16, 1) X(32, 16, 2) X(64, 8, 1) X(64, 8, 2) X(32, 16, 0)
 #define RSG_FP32_SHAPES(X) X(16, 8, 1) X(32, 8, 1) X(32, 8, 2) X(32, 16, 1) X(32, 16, 2) X(64, 8, 2)
+#define RSG_CS_SHAPES(X) X(8, 8, 1) X(16, 8, 1) X(16, 16, 1) X(32, 16, 1)
 
 std::vector<TileShape> tile_candidates(int compute) {
     std::vector<TileShape> v;
@@ -640,7 +677,15 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     p.nst = a.nst;
     p.ldp = a.ldp;
     p.np = g.np;
-    p.kin_h2 = H.kin / (g.h * g.h);
+    p.Vim = H.vim;
+    if (H.cs_theta != 0) {
+        // kin e^{-2 i theta}
+        p.kin_h2 = H.kin * std::cos(2.0 * H.cs_theta) / (g.h * g.h);
+        p.kin_h2_im = -H.kin * std::sin(2.0 * H.cs_theta) / (g.h * g.h);
+    } else {
+        p.kin_h2 = H.kin / (g.h * g.h);
+        p.kin_h2_im = 0.0;
+    }
     p.field = a.field;
     p.h = g.h;
     for (int k = 0; k < 3; ++k) p.off[k] = 0.5 * (double)(g.n[k] - 1);
@@ -654,9 +699,27 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     return p;
 }
 
-int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s) {
+int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &tile, hipStream_t s) {
     const Grid &g = *H.g;
     int err = RSG_OK;
+    const bool cs = H.complex_scaled();
+    TileShape shape = tile;
+    if (cs) {
+        if (a.compute != 0) {
+            set_error("stencil: a complex-scaled Hamiltonian needs the FP64 path");
+            return RSG_EUNSUPPORTED;
+        }
+        // complex-scaled kernels exist for a few depth-1 shapes; others map to 16 x 8
+        bool have = false;
+#define RSG_CS_HAVE(X_, Y_, D_) have = have || (shape.TX == X_ && shape.TY == Y_ && shape.PD == D_);
+        RSG_CS_SHAPES(RSG_CS_HAVE)
+#undef RSG_CS_HAVE
+        if (!have) {
+            shape.TX = 16;
+            shape.TY = 8;
+            shape.PD = 1;
+        }
+    }
     TileShape key = shape;
     if (key.ZC <= 0) key.ZC = g.n[2];
     const TilePlan *plan = const_cast<Grid &>(g).plan(key, s, &err);
@@ -683,8 +746,11 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     }
 #define RSG_TRY64(X_, Y_, D_) RSG_TRY(X_, Y_, D_, launch_fp64)
 #define RSG_TRY32(X_, Y_, D_) RSG_TRY(X_, Y_, D_, launch_fp32)
+#define RSG_TRYCS(X_, Y_, D_) RSG_TRY(X_, Y_, D_, launch_fp64_cs)
     if (shape.B == 1) {
-        if (a.compute == 0) {
+        if (cs) {
+            RSG_CS_SHAPES(RSG_TRYCS)
+        } else if (a.compute == 0) {
             RSG_FP64_SHAPES(RSG_TRY64)
         } else {
             RSG_FP32_SHAPES(RSG_TRY32)
@@ -692,6 +758,7 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
     }
 #undef RSG_TRY64
 #undef RSG_TRY32
+#undef RSG_TRYCS
 #undef RSG_TRY
     timing_after(s);
     if (rc == RSG_EUNSUPPORTED) {

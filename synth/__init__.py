@@ -40,6 +40,12 @@ WORKLOADS = {
     "sphere500k_qmr": dict(shape="sphere", R=9.85, h=0.2, nst=16, natoms=4, well_ball=4.0,
                            omega=0.3, eta=0.1, eps_lo=-0.6, eps_hi=-0.1, tol=1e-8,
                            maxiter=4000, seed=7),
+    # Complex scaling: H_theta applications on the sphere18 grid (64
+    # orbitals, its 16 wells continued to r e^{i theta}, no projectors), and
+    # the levels of the harmonic oscillator continued to e^{2 i theta} r^2/2
+    # on a 48^3 cube at h = 0.3 by inverse iteration from 4 targets.
+    "sphere18_cs": dict(R=18.0, h=0.2, nst=64, natoms=16, well_ball=12.0, seed=2, theta=0.3,
+                        cube_n=48, cube_h=0.3, targets=(1.45, 2.45, 3.45, 4.45)),
     # Grid-to-memory map study: spheres of 5.0e5 points (R = 9.85, h = 0.2)
     # and 3.05e6 points (R = 18, h = 0.2), point-major batches of 1..64
     # white-noise orbitals; standard, 4^3 / 8^3 brick and Hilbert orders.
@@ -225,6 +231,16 @@ def kb_projectors(seed: int, pos: np.ndarray, centres: np.ndarray,
         out.p.append(np.ascontiguousarray(pv))
         out.E.append(g.uniform(0.5, 2.0, size=4))
     return out
+
+
+def well_potential_scaled(pos: np.ndarray, wells: Wells, theta: float) -> np.ndarray:
+    """The wells' potential continued to r e^{i theta} (complex scaling about
+    the origin): -sum_a D_a exp(-sum_k (x_k e^{i theta} - R_ak)^2 / (2 w_a^2))."""
+    z = pos * np.exp(1j * theta)
+    v = np.zeros(pos.shape[0], dtype=np.complex128)
+    for c, d, w in zip(wells.centres, wells.depth, wells.width):
+        v -= d * np.exp(-((z - c) ** 2).sum(axis=1) / (2.0 * w * w))
+    return v
 
 
 def radial_mask(pos: np.ndarray, R: float, width: float) -> np.ndarray:
