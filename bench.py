@@ -568,7 +568,7 @@ def bench_cs(args):
     targets = np.array(cfg["targets"])
     start = torch.from_numpy(synth.white_noise(cfg["seed"] + 1, gc.np, len(targets), h)).cuda().t().contiguous()
     t0 = time.perf_counter()
-    lam, outer = rsg.cs_eigs(hc, start, targets, max_outer=60, tol=1e-12, qmr_maxiter=20000, qmr_tol=1e-11)
+    lam, outer = rsg.cs_eigs(hc, start, targets, max_outer=60, tol=1e-10, qmr_maxiter=20000, qmr_tol=1e-11)
     el_eig = time.perf_counter() - t0
     exact = np.array([1.5, 2.5, 3.5, 4.5])
     log(f"scaled oscillator levels {lam} in {el_eig:.2f} s")
