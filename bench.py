@@ -38,27 +38,28 @@ def stencil_source_hash() -> str:
 
 
 def read_traffic(workload: str, tile=None):
-    """HBM bytes per stencil launch from the committed rocprofv3 counter
-    summary, if it was taken on the current stencil source and with the
-    tile shape in use."""
-    p = os.path.join(ROOT, "profiles", f"traffic_stencil_{workload}.txt")
-    if not os.path.exists(p):
-        return None
-    kv = {}
-    for line in open(p):
-        if ":" in line and not line.lstrip().startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("stencil_source_sha256") != stencil_source_hash():
-        return None
+    """HBM bytes per stencil launch from a committed rocprofv3 counter
+    summary (profiles/traffic_stencil_<workload>*.txt) taken on the current
+    stencil source and with the tile shape in use; None if there is none."""
+    import glob
+    key = None
     if tile is not None:
         key = ",".join(str(tile[k]) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM"))
-        if kv.get("tile") != key:
-            return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    for p in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_stencil_{workload}*.txt"))):
+        kv = {}
+        for line in open(p):
+            if ":" in line and not line.lstrip().startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("stencil_source_sha256") != stencil_source_hash():
+            continue
+        if key is not None and kv.get("tile") != key:
+            continue
+        try:
+            return float(kv["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def build_sphere_inputs(cfg, positions):
