@@ -67,3 +67,25 @@ def test_sphere18_norm_conserved_over_steps(sphere18):
     n1 = R.norm2(s["gg"], psi).cpu().numpy()
     assert np.all(n1 <= n0 * (1 + 1e-12))
     assert np.all(n1 > 0.5 * n0)
+
+
+def test_sphere18_complex_scaled_sampled_orbitals(sphere18):
+    """The complex-scaling workload at full size: the 16 wells continued to
+    r e^{i theta} (theta = 0.3, no projectors), 64 orbitals in one launch;
+    H_theta psi and one step on sampled orbitals against the oracle."""
+    s = sphere18
+    R = rsg()
+    cfg = synth.WORKLOADS["sphere18_cs"]
+    th = cfg["theta"]
+    wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
+    vz = synth.well_potential_scaled(s["og"].positions(), wells, th)
+    oh = oracle.Ham(s["og"], V=vz.real.copy(), V_im=vz.imag.copy(), kin=-0.5, theta=th)
+    gh = R.Hamiltonian(s["gg"], V=torch.from_numpy(vz.real.copy()).cuda(), kin=-0.5)
+    gh.set_complex_scaling(th, torch.from_numpy(vz.imag.copy()).cuda())
+    psi = torch.from_numpy(s["psi_om"]).cuda()
+    sub = np.ascontiguousarray(s["psi"][:, SAMPLE])
+    got = R.hpsi(gh, psi)[SAMPLE, :].cpu().numpy().T
+    assert orbital_rel_err(got, oracle.hpsi(oh, sub), len(SAMPLE)) <= 1e-12
+    R.propagate_step(gh, psi, 0.005)
+    got = psi[SAMPLE, :].cpu().numpy().T
+    assert orbital_rel_err(got, oracle.taylor_step(oh, sub, 0.005), len(SAMPLE)) <= 1e-12
