@@ -31,6 +31,8 @@ struct Batch {
     int32_t nitems = 0;
     int4 *gitems = nullptr;
     int32_t ngitems = 0;
+    int2 *sumitems = nullptr;  // projector chunk sums {system, block of 256 D entries}
+    int32_t nsumitems = 0;
     std::vector<int4 *> sitems;  // scatter items per colour
     std::vector<int32_t> nsitems;
     std::map<std::tuple<double, int64_t, hipStream_t>, hipGraphExec_t> graphs;
@@ -43,6 +45,9 @@ struct Batch {
         }
         if (items) (void)hipFree(items);
         if (gitems) (void)hipFree(gitems);
+        if (sumitems) (void)hipFree(sumitems);
+        sumitems = nullptr;
+        nsumitems = 0;
         for (auto *p : sitems)
             if (p) (void)hipFree(p);
         items = nullptr;
@@ -89,6 +94,7 @@ int build_tables(Batch &b, hipStream_t s) {
     b.free_tables();
     std::vector<BatchItem> items;
     std::vector<int4> gitems;
+    std::vector<int2> sumitems;
     std::vector<std::vector<int4>> sitems;
     std::vector<KParams> sp[4];
     std::vector<KbSys> kb[4];
@@ -135,12 +141,21 @@ int build_tables(Batch &b, hipStream_t s) {
             ks.p = H.kb_p;
             ks.E = H.kb_E;
             ks.D = (double *)b.D[i];
+            ks.nchunk = gather_chunks(H, d.nst);
+            ks.natoms = H.natoms;
+            ks.P = ks.nchunk > 1 ? (double *)((char *)b.D[i] + gather_partials_offset(H, d.nst)) : nullptr;
             ks.h3 = H.g->h * H.g->h * H.g->h;
             kb[k].push_back(ks);
         }
         const int nct = (int)((2 * d.nst + 15) / 16);
+        const int nchunk = gather_chunks(H, d.nst);
         for (int a = 0; a < H.natoms; ++a)
-            for (int ct = 0; ct < nct; ++ct) gitems.push_back(make_int4((int)i, a, ct, 0));
+            for (int ct = 0; ct < nct; ++ct)
+                for (int ch = 0; ch < nchunk; ++ch) gitems.push_back(make_int4((int)i, a, ct, ch));
+        if (nchunk > 1) {
+            const int64_t nd = (int64_t)H.natoms * 4 * 2 * d.nst;
+            for (int64_t blk = 0; blk < (nd + 255) / 256; ++blk) sumitems.push_back(make_int2((int)i, (int)blk));
+        }
         if (H.natoms > 0) {
             // host copy of this system's scatter lists, per colour
             for (size_t c = 0; c < H.scatter_items.size(); ++c) {
@@ -165,8 +180,10 @@ int build_tables(Batch &b, hipStream_t s) {
     }
     if ((rc = upload(&b.items, items, s))) return rc;
     if ((rc = upload(&b.gitems, gitems, s))) return rc;
+    if ((rc = upload(&b.sumitems, sumitems, s))) return rc;
     b.nitems = (int32_t)items.size();
     b.ngitems = (int32_t)gitems.size();
+    b.nsumitems = (int32_t)sumitems.size();
     for (auto &v : sitems) {
         int4 *dptr = nullptr;
         if ((rc = upload(&dptr, v, s))) return rc;
@@ -181,6 +198,7 @@ int stage_launches(const Batch &b, int k, double dt, hipStream_t s) {
     const double cim = -dt / (double)(4 - k);  // c = -i dt / (4 - k): stages k = 0..3 use 1/4, 1/3, 1/2, 1
     int rc;
     if ((rc = launch_kb_gather_batch(b.kb[k], b.gitems, b.ngitems, s))) return rc;
+    if ((rc = launch_kb_gather_sum_batch(b.kb[k], b.sumitems, b.nsumitems, s))) return rc;
     if ((rc = launch_stencil_batch(b.tile, 1, k == 0, b.sp[k], b.items, b.nitems, 0.0, cim,
                                    k == 0 ? b.grid_first : b.grid_rest, s)))
         return rc;

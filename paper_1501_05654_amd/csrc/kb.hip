@@ -32,6 +32,8 @@
 // without atomics.
 #include "rsg_internal.h"
 
+#include <algorithm>
+
 namespace rsg {
 
 namespace {
@@ -54,12 +56,16 @@ __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Gather for one (atom, 16-column tile): the GW waves of the workgroup split
-// the support in groups of 4 entries (wave w takes groups w, w+GW, ...; each
-// wave accumulates its groups in ascending order) and the partial products
-// are added in wave order, so the result does not depend on timing.  The
-// group loop issues the index loads of GU groups, then their data loads,
-// then the MFMAs, so GU gathers are in flight per wave.
+// Gather for one (atom, 16-column tile, support chunk): the support of 4-entry
+// groups is cut into nchunk contiguous chunks; the GW waves of the workgroup
+// split its chunk (wave w takes groups w, w+GW, ... of the chunk; each wave
+// accumulates its groups in ascending order) and the partial products are
+// added in wave order.  With one chunk the result goes to D scaled by h^3;
+// with several, each chunk's sum goes to the partial buffer P and
+// k_kb_gather_sum adds the chunks in order.  Either way the result does not
+// depend on timing.  The group loop issues the index loads of GU groups,
+// then their data loads, then the MFMAs, so GU gathers are in flight per
+// wave.
 constexpr int GW = 16;  // waves per gather workgroup
 constexpr int GU = 4;   // groups in flight per wave
 template <class Tin, class Tc>
@@ -67,7 +73,8 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
                                             const int4 at, int a, int ct,
                                             const int32_t *__restrict__ idx,
                                             const Tc *__restrict__ p, Tc h3, Tc *__restrict__ D,
-                                            Tc (*red)[64][4]) {
+                                            Tc (*red)[64][4], int chunk = 0, int nchunk = 1,
+                                            Tc *__restrict__ P = nullptr) {
     using V = typename V4<Tc>::type;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int lo = l & 15, hi = l >> 4;
@@ -75,8 +82,11 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
     const bool cok = col < ncols;
     const Tin *inc = in + (cok ? (col >> 1) * ldo + (col & 1) : 0);
     V acc = {0, 0, 0, 0};
-    const int ngroups = at.y >> 2;
-    int gq = w;
+    const int ngall = at.y >> 2;
+    const int per = (ngall + nchunk - 1) / nchunk;
+    const int g0 = min(ngall, chunk * per);
+    const int ngroups = min(ngall, g0 + per);
+    int gq = g0 + w;
     for (; gq + (GU - 1) * GW < ngroups; gq += GU * GW) {
         int64_t e[GU];
         int32_t ix[GU];
@@ -108,21 +118,51 @@ __device__ __forceinline__ void gather_tile(const Tin *__restrict__ in, int64_t 
 #pragma unroll
             for (int k = 1; k < GW; ++k) v += red[k][l][r];
             const int64_t c = (int64_t)ct * 16 + acc_row(Tc(0), hi, r);
-            if (c < ncols) D[((int64_t)a * 4 + lo) * ncols + c] = h3 * v;
+            if (c < ncols) {
+                if (nchunk == 1)
+                    D[((int64_t)a * 4 + lo) * ncols + c] = h3 * v;
+                else
+                    P[(((int64_t)a * 4 + lo) * nchunk + chunk) * ncols + c] = v;
+            }
         }
     }
 }
 
-// blockIdx.x = atom, blockIdx.y = tile of 16 real columns.
+// blockIdx.x = atom, blockIdx.y = tile of 16 real columns, blockIdx.z =
+// support chunk (gridDim.z chunks).
 template <class Tin, class Tc>
 __global__ void __launch_bounds__(GW * 64) k_kb_gather(const Tin *__restrict__ in, int64_t ldo,
                                                        int64_t ncols, const int4 *__restrict__ atoms,
                                                        const int32_t *__restrict__ idx,
                                                        const Tc *__restrict__ p, Tc h3,
-                                                       Tc *__restrict__ D) {
+                                                       Tc *__restrict__ D, Tc *__restrict__ P) {
     __shared__ Tc red[GW][64][4];
-    gather_tile<Tin, Tc>(in, ldo, ncols, atoms[blockIdx.x], blockIdx.x, blockIdx.y, idx, p, h3, D, red);
+    gather_tile<Tin, Tc>(in, ldo, ncols, atoms[blockIdx.x], blockIdx.x, blockIdx.y, idx, p, h3, D, red,
+                         (int)blockIdx.z, (int)gridDim.z, P);
 }
+
+// D[a][i][c] = h3 * sum over chunks k = 0, 1, ... of P[a][i][k][c].
+template <class Tc>
+__global__ void __launch_bounds__(256) k_kb_gather_sum(const Tc *__restrict__ P, Tc *__restrict__ D,
+                                                       int64_t nrows, int nchunk, int64_t ncols, Tc h3) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * ncols) return;
+    const int64_t row = t / ncols, c = t - row * ncols;
+    const Tc *q = P + row * nchunk * ncols + c;
+    // loads of 8 chunks in flight, added in chunk order
+    Tc v = q[0];
+    int k = 1;
+    for (; k + 8 <= nchunk; k += 8) {
+        Tc x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = q[(int64_t)(k + u) * ncols];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    for (; k < nchunk; ++k) v += q[(int64_t)k * ncols];
+    D[row * ncols + c] = h3 * v;
+}
+
 
 // Scatter for one (16-entry support tile, 16-column tile), one wave.
 template <class Tout, class Tc>
@@ -185,7 +225,32 @@ __global__ void __launch_bounds__(GW * 64) k_kb_gather_batch(const KbSys *__rest
     const int4 it = items[blockIdx.x];
     const KbSys &s = sys[it.x];
     gather_tile<double, double>(s.in, s.ldo, s.ncols, s.atoms[it.y], it.y, it.z, s.idx, s.p, s.h3, s.D,
-                                red);
+                                red, it.w, s.nchunk, s.P);
+}
+
+// Same sum as k_kb_gather_sum, one workgroup per {system, block of 256 D
+// entries}.
+__global__ void __launch_bounds__(256) k_kb_gather_sum_batch(const KbSys *__restrict__ sys,
+                                                             const int2 *__restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    const KbSys &s = sys[it.x];
+    const int64_t ncols = s.ncols, nrows = (int64_t)s.natoms * 4;
+    const int64_t t = (int64_t)it.y * 256 + threadIdx.x;
+    if (t >= nrows * ncols) return;
+    const int64_t row = t / ncols, c = t - row * ncols;
+    const int nchunk = s.nchunk;
+    const double *q = s.P + row * nchunk * ncols + c;
+    double v = q[0];
+    int k = 1;
+    for (; k + 8 <= nchunk; k += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = q[(int64_t)(k + u) * ncols];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    for (; k < nchunk; ++k) v += q[(int64_t)k * ncols];
+    s.D[row * ncols + c] = s.h3 * v;
 }
 
 __global__ void __launch_bounds__(256) k_kb_scatter_batch(const KbSys *__restrict__ sys,
@@ -201,29 +266,62 @@ __global__ void __launch_bounds__(256) k_kb_scatter_batch(const KbSys *__restric
 
 }  // namespace
 
+// Support chunks per (atom, column tile): enough workgroups to fill the chip
+// when there are few atoms or few orbitals, each chunk at least 2 GW groups
+// of 4 support entries of the smallest support.
+int gather_chunks(const Ham &H, int64_t nst) {
+    if (H.natoms == 0 || nst == 0) return 1;
+    int64_t min_groups = INT64_MAX;
+    for (int32_t a = 0; a < H.natoms; ++a) min_groups = std::min(min_groups, (H.kb_off[a + 1] - H.kb_off[a]) / 4);
+    const int64_t tiles = (int64_t)H.natoms * ((2 * nst + 15) / 16);
+    const int64_t want = (512 + tiles - 1) / tiles;
+    const int64_t cap = std::max<int64_t>(1, min_groups / (2 * GW));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(want, cap), 64));
+}
+
+size_t gather_partials_offset(const Ham &H, int64_t nst) {
+    const size_t dbytes = (size_t)H.natoms * 4 * 2 * (size_t)nst * sizeof(double);
+    return (dbytes + 255) / 256 * 256;
+}
+
+// D [natoms][4][2 nst] plus, when the support is split, the chunk partials
+// [natoms][4][nchunk][2 nst] behind it (sized for FP64 in every path).
 size_t kb_workspace_bytes(const Ham &H, int64_t nst) {
-    return (size_t)H.natoms * 4 * 2 * (size_t)nst * sizeof(double);
+    const size_t d = (size_t)H.natoms * 4 * 2 * (size_t)nst * sizeof(double);
+    const int nchunk = gather_chunks(H, nst);
+    return nchunk > 1 ? 2 * ((d + 255) / 256 * 256) + (size_t)nchunk * d : d;
 }
 
 int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ldp,
                      void *D, hipStream_t s) {
     if (H.natoms == 0 || nst == 0) return RSG_OK;
     const int64_t ncols = 2 * nst;
-    const dim3 grid((unsigned)H.natoms, (unsigned)((ncols + 15) / 16));
+    const int nchunk = gather_chunks(H, nst);
+    const dim3 grid((unsigned)H.natoms, (unsigned)((ncols + 15) / 16), (unsigned)nchunk);
     const double h3 = H.g->h * H.g->h * H.g->h;
+    // the partials start at the first 256-byte boundary after D (FP64 size)
+    void *P = nchunk > 1 ? (void *)((char *)D + gather_partials_offset(H, nst)) : nullptr;
+    const int64_t nrows = (int64_t)H.natoms * 4;
+    const unsigned sblk = (unsigned)((nrows * ncols + 255) / 256);
     if (compute == 0) {
         if (in_t != 0) return RSG_EUNSUPPORTED;
         k_kb_gather<double, double><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ldp, ncols,
                                                         H.gather_items, H.kb_idx, H.kb_p, h3,
-                                                        (double *)D);
-    } else if (in_t == 0) {
-        k_kb_gather<double, float><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ldp, ncols,
-                                                       H.gather_items, H.kb_idx, H.kb_p32,
-                                                       (float)h3, (float *)D);
+                                                        (double *)D, (double *)P);
+        if (nchunk > 1)
+            k_kb_gather_sum<double><<<sblk, 256, 0, s>>>((const double *)P, (double *)D, nrows, nchunk, ncols, h3);
     } else {
-        k_kb_gather<float, float><<<grid, GW * 64, 0, s>>>((const float *)in, 2 * ldp, ncols,
-                                                      H.gather_items, H.kb_idx, H.kb_p32,
-                                                      (float)h3, (float *)D);
+        if (in_t == 0)
+            k_kb_gather<double, float><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ldp, ncols,
+                                                           H.gather_items, H.kb_idx, H.kb_p32,
+                                                           (float)h3, (float *)D, (float *)P);
+        else
+            k_kb_gather<float, float><<<grid, GW * 64, 0, s>>>((const float *)in, 2 * ldp, ncols,
+                                                          H.gather_items, H.kb_idx, H.kb_p32,
+                                                          (float)h3, (float *)D, (float *)P);
+        if (nchunk > 1)
+            k_kb_gather_sum<float><<<sblk, 256, 0, s>>>((const float *)P, (float *)D, nrows, nchunk, ncols,
+                                                        (float)h3);
     }
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
@@ -259,6 +357,13 @@ int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t n
 int launch_kb_gather_batch(const KbSys *sys, const int4 *items, int32_t nitems, hipStream_t s) {
     if (nitems == 0) return RSG_OK;
     k_kb_gather_batch<<<(unsigned)nitems, GW * 64, 0, s>>>(sys, items);
+    RSG_CHECK_HIP(hipGetLastError());
+    return RSG_OK;
+}
+
+int launch_kb_gather_sum_batch(const KbSys *sys, const int2 *items, int32_t nitems, hipStream_t s) {
+    if (nitems == 0) return RSG_OK;
+    k_kb_gather_sum_batch<<<(unsigned)nitems, 256, 0, s>>>(sys, items);
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }

@@ -224,9 +224,19 @@ struct KbSys {
     const double *p;
     const double *E;
     double *D;          // [natoms][4][ncols]
+    double *P;          // [natoms][4][nchunk][ncols] support-chunk partials (nchunk > 1)
+    int32_t nchunk, natoms;
     double h3;
 };
+// Support chunks of the projector gather for a batch of nst orbitals (the
+// single-system and batched paths use the same split, so they agree bit
+// for bit); the partials live in the projector workspace behind D.
+int gather_chunks(const Ham &H, int64_t nst);
+size_t gather_partials_offset(const Ham &H, int64_t nst);
+// items {system, atom, column tile, chunk}
 int launch_kb_gather_batch(const KbSys *sys, const int4 *items, int32_t nitems, hipStream_t s);
+// items {system, block of 256 D entries}: D = h3 * sum of the chunk partials
+int launch_kb_gather_sum_batch(const KbSys *sys, const int2 *items, int32_t nitems, hipStream_t s);
 int launch_kb_scatter_batch(const KbSys *sys, const int4 *items, int32_t nitems, double cre, double cim,
                             hipStream_t s);
 
