@@ -3,7 +3,6 @@ seeded inputs.  FP64 results must agree to 1e-12 relative per orbital
 (||gpu_n - oracle_n||_2 / ||oracle_n||_2, max over orbitals).  GPU batches
 are orbital-major; several cases pad every orbital beyond np points and
 check the padding is never written."""
-import math
 
 import numpy as np
 import pytest

@@ -9,7 +9,6 @@ padding points after every orbital, so partial tiles in x, y and z occur
 for every shape and spare orbitals and padding must stay untouched."""
 import numpy as np
 import pytest
-import torch
 
 import oracle
 from tests.gpu_common import System, orbital_rel_err, rsg

@@ -13,7 +13,6 @@ matrix elements without conjugation), against facts the section states:
   discretisation error, while a wrong sign of the rotation would move them
   by 1.5 sin(2 theta) off the axis."""
 import numpy as np
-import pytest
 
 import oracle
 
