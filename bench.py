@@ -514,6 +514,69 @@ def bench_cube32(args):
     }
 
 
+def bench_mixed_sphere(args):
+    """Mixed precision on the benchmark system (3.05 M points, 64 orbitals,
+    16 wells with projectors): K Taylor(4) steps with FP32 Hamiltonian
+    arithmetic on complex64 work buffers (FP64 accumulation), timed beside
+    the FP64 path, and the orbital error of the mixed result against the
+    FP64 one after the K steps.  The roofline is the mixed Horner stage's:
+    per step it reads complex128 psi four times and complex64 work buffers
+    three times and writes three complex64 buffers and psi, 128 B/pt.orb,
+    plus the FP32 potential (4 B/pt) per stage."""
+    import numpy as np
+    import torch
+
+    import paper_1501_05654_amd as rsg
+    import synth
+
+    cfg = dict(synth.WORKLOADS["sphere18_wells"])
+    torch.cuda.set_device(0)
+    gg = rsg.Grid(cfg["h"], R=cfg["R"])
+    V, proj = build_sphere_inputs(cfg, gg.positions())
+    dev = torch.device("cuda:0")
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
+                         projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
+                                     for i, p, E in zip(proj.idx, proj.p, proj.E)])
+    nst, dt = cfg["nst"], cfg["dt"]
+    psi0 = torch.from_numpy(synth.white_noise(cfg["seed"], gg.np, nst, cfg["h"])).to(dev).t().contiguous()
+    ws = torch.empty(gh.workspace_bytes("step", nst, psi0.shape[1]), dtype=torch.uint8, device=dev)
+    rsg.autotune(gh, psi0, reps=2)
+    rsg.autotune(gh, psi0, dtype="mixed", reps=2)
+    steps = max(args.steps, 1)
+
+    def run(dtype):
+        psi = psi0.clone()
+        rsg.propagate(gh, psi, dt, max(args.warmup, 1), dtype=dtype, ws=ws)
+        psi.copy_(psi0)
+        torch.cuda.synchronize()
+        with rsg.kernel_timing() as kt:
+            t0 = time.perf_counter()
+            rsg.propagate(gh, psi, dt, steps, dtype=dtype, ws=ws)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        return psi, el, kt.mean_ms
+
+    full, el64, k64 = run("c128")
+    mixed, el32, k32 = run("mixed")
+    err = ((mixed - full).abs().pow(2).sum(1).sqrt() / full.abs().pow(2).sum(1).sqrt()).max().item()
+    npo = gg.np * nst
+    alg = (128 * npo + 16 * gg.np) / 4.0
+    log(f"FP64 {el64 * 1e3 / steps:.3f} ms/step, mixed {el32 * 1e3 / steps:.3f} ms/step, error {err:.2e}")
+    return {
+        "metric": METRIC, "value": npo * 4 * steps / el32, "unit": UNIT, "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": el32 * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 H / f64 accumulation", "data": "synthetic",
+        "config": {"workload": "sphere18_mixed", "np": gg.np, "nst": nst, "natoms": cfg["natoms"], "dt": dt},
+        "roofline": {"bound": "hbm", "achieved": alg / (k32 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stencil mixed (FP32 arithmetic, Horner stage)", "kernel_mean_ms": k32,
+                     "algorithmic_bytes_per_launch": alg},
+        "fp64_value": npo * 4 * steps / el64, "fp64_stencil_ms": k64,
+        "orbital_rel_err_vs_fp64": err,
+        "cpu_baseline": None,
+    }
+
+
 def bench_cs(args):
     """Complex scaling.  (1) H_theta applications (kinetic prefactor
     -1/2 e^{-2 i theta}, continued wells potential) to 64 orbitals on the
@@ -778,7 +841,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sphere18_wells",
                     choices=["sphere18_wells", "batch256", "cube32_mixed", "cube96_control", "cube32_ho",
-                             "sphere500k_gridmap", "sphere500k_qmr", "sphere18_cs"])
+                             "sphere500k_gridmap", "sphere500k_qmr", "sphere18_cs", "sphere18_mixed"])
     ap.add_argument("--nsys", type=int, default=0, help="batch256: use only the first N systems")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
@@ -808,6 +871,8 @@ def main():
         out = bench_solve(args)
     elif args.workload == "sphere18_cs":
         out = bench_cs(args)
+    elif args.workload == "sphere18_mixed":
+        out = bench_mixed_sphere(args)
     else:
         out, cfg = bench_sphere(args)
         out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)

@@ -607,8 +607,10 @@ def get_tile(ham: Hamiltonian, nst: int, dtype="c128") -> dict:
 
 def autotune(ham: Hamiltonian, psi: torch.Tensor, dtype="c128", reps: int = 3,
              nst: int | None = None):
-    """Time every compiled tile shape on one Horner stage of psi and keep the
-    fastest for this (nst, dtype); returns (tile, milliseconds)."""
+    """Time the compiled tile shapes on a later Horner stage of psi, re-time
+    the six fastest on a whole step's stencil work (first stage + three
+    later ones) and keep the fastest for this (nst, dtype); returns (tile,
+    milliseconds of stencil work per step)."""
     _batch(psi, "psi", ham.grid.np)
     n = _nst(psi, nst)
     ws = _ws(ham.workspace_bytes("step", n, psi.shape[1], _dt(dtype)), psi.device)

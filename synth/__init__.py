@@ -40,6 +40,9 @@ WORKLOADS = {
     "sphere500k_qmr": dict(shape="sphere", R=9.85, h=0.2, nst=16, natoms=4, well_ball=4.0,
                            omega=0.3, eta=0.1, eps_lo=-0.6, eps_hi=-0.1, tol=1e-8,
                            maxiter=4000, seed=7),
+    # Mixed precision at the benchmark scale: the sphere18_wells system
+    # propagated with FP32 Hamiltonian arithmetic and complex64 work buffers.
+    "sphere18_mixed": dict(base="sphere18_wells", steps=20),
     # Complex scaling: H_theta applications on the sphere18 grid (64
     # orbitals, its 16 wells continued to r e^{i theta}, no projectors), and
     # the levels of the harmonic oscillator continued to e^{2 i theta} r^2/2
