@@ -27,8 +27,9 @@ CG is the textbook Hermitian method: alpha = r^H r / p^H A p, x += alpha p,
 r -= alpha A p, beta = r'^H r' / r^H r, p = r' + beta p.
 
 Both stop when ||r|| <= tol ||b|| (||b|| = 0 counts as 1), at a breakdown
-(a divisor of modulus below 1e-290, or rho_{i+1} = 0 without convergence)
-or after maxiter iterations.  Status: 0 converged, 1 iteration limit, 2
+(|v^T v| < 1e-13 for the unit-norm Lanczos vector v, any other divisor of
+modulus below 1e-290, or rho_{i+1} = 0 without convergence) or after maxiter
+iterations.  Status: 0 converged, 1 iteration limit, 2
 breakdown.
 """
 from __future__ import annotations
@@ -38,6 +39,7 @@ import numpy as np
 from . import Ham, hpsi
 
 TINY = 1e-290
+DELTA_MIN = 1e-13  # |v^T v| of a unit-norm Lanczos vector below this: breakdown
 
 
 def apply_shifted(ham: Ham, x: np.ndarray, sigma: complex) -> np.ndarray:
@@ -64,7 +66,7 @@ def qmr(ham: Ham, b: np.ndarray, sigma: complex, x0=None, tol: float = 1e-10, ma
     while it < maxiter:
         v = vt / rho
         delta = v @ v
-        if abs(delta) < TINY:
+        if abs(delta) < DELTA_MIN:
             status = 2
             break
         p = v.copy() if p is None else v - (rho * delta / eps) * p

@@ -303,8 +303,12 @@ __device__ __forceinline__ void sum_partials(const double2 *part, int nblk, doub
     for (int k = 0; k < K; ++k) out[k] = red[0][k];
 }
 
-// A scalar is unusable as a divisor (Lanczos breakdown) below this modulus.
+// Breakdown tests.  delta = v^T v of a unit-norm Lanczos vector lies in
+// [0, 1] in modulus; below DELTA_MIN the bilinear form has (nearly)
+// vanished and the recurrence cannot continue.  Other divisors only need
+// to be nonzero.
 constexpr double TINY = 1e-290;
+constexpr double DELTA_MIN = 1e-13;
 
 template <int STEP>
 __global__ void __launch_bounds__(SB) k_sv_scal(SolveState *st, const double2 *part, int nblk) {
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(SB) k_sv_scal(SolveState *st, const double2 *p
             q.gamma = 1.0;
             q.theta = 0.0;
             q.eta = make_double2(-1.0, 0.0);
-            if (std::sqrt(cabs2(q.delta)) < TINY) {
+            if (std::sqrt(cabs2(q.delta)) < DELTA_MIN) {
                 q.active = 0;
                 q.status = 2;
             }
@@ -383,7 +387,7 @@ __global__ void __launch_bounds__(SB) k_sv_scal(SolveState *st, const double2 *p
         if (q.rnorm <= target) {
             q.active = 0;
             q.status = 0;
-        } else if (STEP == SC_RES_QMR && (q.rho <= 0 || std::sqrt(cabs2(q.delta)) < TINY)) {
+        } else if (STEP == SC_RES_QMR && (q.rho <= 0 || std::sqrt(cabs2(q.delta)) < DELTA_MIN)) {
             q.active = 0;
             q.status = 2;
         } else if (q.iters >= q.maxiter) {

@@ -118,6 +118,37 @@ def test_eigenvector_and_trivial_starts(sys_):
     assert np.all(info["iters"] == 0) and np.all(info["status"] == 0)
 
 
+def test_isotropic_rhs_breaks_down_alone(sys_):
+    """One orbital with b^T b = 0 (b = u + i w, u orthogonal to w, equal
+    norms): QMR stops it at once with status 2 and leaves its x untouched,
+    while the other orbitals converge as before."""
+    R = rsg()
+    s, Hd = sys_
+    b = _rhs(s, 12)
+    rng = np.random.default_rng(13)
+    u = rng.standard_normal(s.og.np)
+    w = rng.standard_normal(s.og.np)
+    w -= (w @ u) / (u @ u) * u
+    w *= np.linalg.norm(u) / np.linalg.norm(w)
+    b[:, 2] = u + 1j * w
+    x0 = np.zeros_like(b)
+    x0[:, 2] = 0.25 - 0.5j
+    xg, info = R.shifted_solve(s.gh, s.to_gpu(b), QSHIFTS, x=s.to_gpu(x0), method="qmr", tol=1e-12,
+                               maxiter=3000, nst=s.nst)
+    # the guess for orbital 2 leaves r = b - A x0 not isotropic: clear it
+    xg2, info2 = R.shifted_solve(s.gh, s.to_gpu(b), QSHIFTS, method="qmr", tol=1e-12, maxiter=3000,
+                                 nst=s.nst)
+    assert info2["status"][2] == 2 and info2["iters"][2] == 0
+    x = s.from_gpu(xg2)
+    assert not np.any(x[:, 2])
+    for n in (0, 1, 3, 4):
+        assert info2["status"][n] == 0
+        ref = np.linalg.solve(Hd + QSHIFTS[n] * np.eye(s.og.np), b[:, n])
+        assert np.linalg.norm(x[:, n] - ref) <= 1e-9 * np.linalg.norm(ref)
+    # with a nonzero guess the start residual is not isotropic and QMR runs
+    assert info["status"][2] == 0
+
+
 def test_large_sphere_true_residual():
     """R = 9.85 bohr, h = 0.2 (5.0e5 points), 16 orbitals, 2 wells with
     projectors; complex shifts -eps + omega + i eta: the converged x gives

@@ -90,3 +90,23 @@ def test_trivial_starts(small, method):
     b = (Hd + 2.0 * np.eye(g.np)) @ xe
     x, its, res, st = sv.solve_batch(ham, b[:, None], 2.0, method, x0=xe[:, None], tol=1e-10)
     assert its[0] == 0 and st[0] == 0
+
+
+def test_isotropic_rhs_is_a_qmr_breakdown(small):
+    """b = u + i w with u orthogonal to w and |u| = |w| has b^T b = 0: the
+    bilinear form QMR runs on vanishes at the start, so QMR must stop at
+    once with status 2 (breakdown) and x untouched; CG, which uses the
+    Hermitian product, solves the same system with a real shift."""
+    g, ham, Hd = small
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal(g.np)
+    w = rng.standard_normal(g.np)
+    w -= (w @ u) / (u @ u) * u
+    w *= np.linalg.norm(u) / np.linalg.norm(w)
+    b = (u + 1j * w)[:, None]
+    assert abs(b[:, 0] @ b[:, 0]) < 1e-12 * np.linalg.norm(b) ** 2
+    x, its, res, st = sv.solve_batch(ham, b, 0.5 + 0.2j, "qmr", tol=1e-10)
+    assert st[0] == 2 and its[0] == 0 and not np.any(x)
+    lam0 = np.linalg.eigvalsh(Hd.real)[0]
+    x, its, res, st = sv.solve_batch(ham, b, -lam0 + 1.0, "cg", tol=1e-10, maxiter=2000)
+    assert st[0] == 0
