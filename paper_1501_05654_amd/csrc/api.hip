@@ -879,7 +879,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         // few tiles (small grid, few orbitals): short z-chunks for parallelism
         const int64_t small_tiles = (int64_t)((H->g->n[0] + 15) / 16) * ((H->g->n[1] + 7) / 8) * nst;
         if (small_tiles < 2048)
-            for (int z : {16, 8})
+            for (int z : {16, 8, 4, 2, 1})
                 if (z < H->g->n[2]) zcs.push_back(z);
         const std::vector<int> pts = {0, 1};
         const std::vector<int> bos = {0, 1, 2, 4};

@@ -649,10 +649,11 @@ TileShape default_shape(const Grid &g, int64_t nst, int compute) {
     sh.BO = 1;
     sh.ZC = g.n[2];
     // a grid with too few tiles to give every compute unit a few workgroups
-    // is also split along z (each chunk re-reads only 8 planes)
+    // is also split along z, down to chunks of 2 planes (each chunk re-reads
+    // 8 planes, which such small batches find in cache)
     const int64_t tiles = (int64_t)((g.n[0] + sh.TX - 1) / sh.TX) * ((g.n[1] + sh.TY - 1) / sh.TY);
     const int64_t wgs = tiles * std::max<int64_t>(nst, 1);
-    if (wgs < 1024) sh.ZC = std::max<int>(8, (int)((int64_t)g.n[2] * wgs / 1024));
+    if (wgs < 1024) sh.ZC = std::max<int>(2, (int)((int64_t)g.n[2] * wgs / 1024));
     return sh;
 }
 

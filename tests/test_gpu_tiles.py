@@ -15,7 +15,7 @@ from tests.gpu_common import System, orbital_rel_err, rsg
 
 pytestmark = pytest.mark.gpu
 
-ZCS = (0, 4)        # whole z-range, and chunks of 4 planes (several per tile)
+ZCS = (0, 4, 1)     # whole z-range, chunks of 4 planes (several per tile), single planes
 PTS = (0, 1, 2)     # row order, Morton order, 2 x 2 patches
 BOS = (0, 1, 3)     # orbital fastest / slowest / groups of 3 (13 = 4 x 3 + 1)
 ZMS = (0, 1)        # upward from each tile's lowest plane / outward from the centre plane
@@ -36,6 +36,8 @@ def _variants(dtype):
                     for zm in ZMS:
                         if zm == 1 and pt >= 2:
                             continue  # patches apply to the upward march only
+                        if zc == 1 and pt != 0:
+                            continue  # single planes: row order suffices
                         yield dict(t, ZC=zc, PT=pt, BO=bo, ZM=zm)
 
 
