@@ -87,6 +87,42 @@ def test_taylor_steps_cube32():
     assert orbital_rel_err(s.from_gpu(psi), ref, 4) <= TOL
 
 
+def test_cube32_sequence_autotuned_in_graph():
+    """The 32^3 harmonic system as the benchmark runs it: the autotuner's
+    tile, 10 hpsi calls and 10 Taylor(4) steps captured in one graph.  Two
+    replays, with eager checks between them: each replay's last hpsi output
+    and its final orbitals match the oracle (10 and 20 steps)."""
+    s = System(0.3, n=32, potential="harmonic", nst=4, seed=1)
+    R = rsg()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        psi = s.to_gpu(s.psi)
+        hp = torch.zeros_like(psi)
+        ws = torch.empty(s.gh.workspace_bytes("step", 4, psi.shape[1]), dtype=torch.uint8, device="cuda")
+        R.autotune(s.gh, psi, reps=1)
+
+        def seq():
+            for _ in range(10):
+                R.hpsi(s.gh, psi, out=hp)
+            for _ in range(10):
+                R.propagate_step(s.gh, psi, 0.01, ws=ws)
+
+        # plans exist before capture; the warm-up run is undone
+        seq()
+        psi.copy_(s.to_gpu(s.psi))
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            seq()
+    start = s.psi
+    for rep in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert orbital_rel_err(s.from_gpu(hp), oracle.hpsi(s.oh, start), 4) <= TOL, rep
+        start = oracle.propagate(s.oh, start, 0.01, 10)
+        assert orbital_rel_err(s.from_gpu(psi), start, 4) <= TOL, rep
+
+
 def test_propagate_fields_sphere_projectors():
     """Steps with a per-step field array, projectors, spare orbitals and
     padding points."""
