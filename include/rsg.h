@@ -108,12 +108,34 @@ typedef struct {
  * descriptor, RSG_EHIP on a runtime failure. */
 int rsg_grid_create(const rsg_grid_desc *desc, void *stream, rsg_grid_t *out);
 
-/* np: number of box points; dims: tight bounding box (x, y, z); h. Any
- * output pointer may be NULL. */
+/* The same box with row-aligned storage (a layout choice of this library;
+ * the paper keeps fields as linear arrays over the box points, section
+ * "Parallelization, optimizations and graphics processing units").  The
+ * order of the points is unchanged, but every non-empty (y, z) row owns the
+ * slots of its x-range widened to multiples of align, so that its slot at
+ * x = 0 (mod align) starts a memory line: a stencil tile's row segment then
+ * touches no partly used line at its start.  The extra "dead" slots (at
+ * most 2 (align - 1) per row) hold no point.  align: a power of two in
+ * 1..64 (1 gives rsg_grid_create's compact layout).  Every field on such a
+ * grid has np slots (rsg_grid_info); callers keep zeros in the dead slots
+ * of their inputs (reductions sum every slot), and every stencil output
+ * (rsg_hpsi, the Taylor stages, the adjoint) writes zero there.  Projector
+ * supports must name box points.  Grid-to-memory maps need align 1.
+ * Errors as rsg_grid_create, RSG_EINVAL for a bad align. */
+int rsg_grid_create_aligned(const rsg_grid_desc *desc, int32_t align, void *stream, rsg_grid_t *out);
+
+/* np: slots per field (the number of box points unless the grid is
+ * row-aligned); dims: tight bounding box (x, y, z); h.  Any output pointer
+ * may be NULL. */
 int rsg_grid_info(rsg_grid_t g, int64_t *np, int32_t dims[3], double *h);
 
-/* Host copies: ijk_host [np][3] int32 box coordinates (0 <= ijk < dims),
- * xyz_host [np][3] float64 positions in bohr. */
+/* npoints: box points (np minus the dead slots); align: the grid's row
+ * alignment.  Either pointer may be NULL. */
+int rsg_grid_points(rsg_grid_t g, int64_t *npoints, int32_t *align);
+
+/* Host copies over the np slots: ijk_host [np][3] int32 box coordinates
+ * (0 <= ijk < dims; -1 for a dead slot), xyz_host [np][3] float64 positions
+ * in bohr (0 for a dead slot). */
 int rsg_grid_coords(rsg_grid_t g, int32_t *ijk_host);
 int rsg_grid_positions(rsg_grid_t g, double *xyz_host);
 int rsg_grid_destroy(rsg_grid_t g);
@@ -447,7 +469,7 @@ enum { RSG_MAP_STANDARD = 0, RSG_MAP_BRICKS = 1, RSG_MAP_HILBERT = 2 };
  * table and uploads the table; param = brick edge (1..64) for
  * RSG_MAP_BRICKS, ignored otherwise.  The grid must outlive the map.
  * Errors: RSG_EINVAL (null argument, unknown kind, bad brick edge),
- * RSG_ENOMEM, RSG_EHIP. */
+ * RSG_EUNSUPPORTED (a row-aligned grid), RSG_ENOMEM, RSG_EHIP. */
 int rsg_map_create(rsg_grid_t g, int32_t kind, int32_t param, rsg_map_t *out);
 int rsg_map_destroy(rsg_map_t m);
 

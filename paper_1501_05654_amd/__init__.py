@@ -47,6 +47,8 @@ def _load():
     i32, i64, dbl, vp, sz = C.c_int32, C.c_int64, C.c_double, C.c_void_p, C.c_size_t
     sig = {
         "rsg_grid_create": (C.c_int, [vp, vp, vp]),
+        "rsg_grid_create_aligned": (C.c_int, [vp, i32, vp, vp]),
+        "rsg_grid_points": (C.c_int, [vp, vp, vp]),
         "rsg_grid_info": (C.c_int, [vp, vp, vp, vp]),
         "rsg_grid_coords": (C.c_int, [vp, vp]),
         "rsg_grid_positions": (C.c_int, [vp, vp]),
@@ -144,22 +146,38 @@ class _GridDesc(C.Structure):
 
 
 class Grid:
-    """Uniform grid restricted to a sphere (radius R) or a cube (n per axis)."""
+    """Uniform grid restricted to a sphere (radius R) or a cube (n per axis).
 
-    def __init__(self, h: float, *, R: float | None = None, n: int | None = None):
+    align > 1 (a power of two) gives row-aligned storage: fields have
+    ``np`` slots, of which ``npoints`` hold box points in the same order;
+    the others are dead slots (coordinates -1) that inputs keep at zero.
+    ``live()`` lists the slots of the box points."""
+
+    def __init__(self, h: float, *, R: float | None = None, n: int | None = None, align: int = 1):
         if (R is None) == (n is None):
             raise ValueError("give exactly one of R (sphere) or n (cube)")
         d = _GridDesc(1 if R is not None else 0, int(n or 0), float(R or 0.0), float(h))
         self._h = C.c_void_p()
-        _check(_lib.rsg_grid_create(C.byref(d), _stream(), C.byref(self._h)))
+        _check(_lib.rsg_grid_create_aligned(C.byref(d), int(align), _stream(), C.byref(self._h)))
         np_ = C.c_int64()
         dims = (C.c_int32 * 3)()
         hh = C.c_double()
         _check(_lib.rsg_grid_info(self._h, C.byref(np_), dims, C.byref(hh)))
+        npts = C.c_int64()
+        al = C.c_int32()
+        _check(_lib.rsg_grid_points(self._h, C.byref(npts), C.byref(al)))
         self.np = int(np_.value)
+        self.npoints = int(npts.value)
+        self.align = int(al.value)
         self.dims = tuple(int(x) for x in dims)
         self.h = float(hh.value)
         self.R, self.n = R, n
+
+    def live(self) -> np.ndarray:
+        """Slot of every box point, ascending (all slots when align is 1)."""
+        if self.npoints == self.np:
+            return np.arange(self.np, dtype=np.int64)
+        return np.nonzero(self.coords()[:, 0] >= 0)[0]
 
     def coords(self) -> np.ndarray:
         out = np.empty((self.np, 3), dtype=np.int32)

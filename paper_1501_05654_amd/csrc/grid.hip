@@ -7,6 +7,13 @@
 // inside the box and the compact index of its first point.  Compact order is
 // z-major, then y, then x, so every row is contiguous in memory and a point's
 // index is rows[z*ny + y].base + x.
+//
+// Row-aligned grids (align A > 1, a power of two) keep the same order but
+// give each non-empty row the slots of its x-range widened to multiples of
+// A (base a multiple of A).  A tile's row segment, which starts at a
+// multiple of the tile width, then starts on a memory line.  The extra
+// "dead" slots hold no point: their coordinates read -1, the stencil writes
+// zero there and never reads them.
 #include "rsg_internal.h"
 
 #include <algorithm>
@@ -48,17 +55,22 @@ __global__ void k_row_extent(int shape, int32_t nx, int32_t ny, int32_t nz, int6
     }
 }
 
-// Exclusive scan of the row lengths in one workgroup (fixed order): each
+// Slots a row takes: its x-range [a, a + l) widened to multiples of A.
+__device__ __forceinline__ int64_t row_slots(int32_t a, int32_t l, int32_t A) {
+    return l > 0 ? (int64_t)(((a + l + A - 1) & -A) - (a & -A)) : 0;
+}
+
+// Exclusive scan of the row slot counts in one workgroup (fixed order): each
 // thread sums a contiguous chunk, the 1024 chunk totals are scanned in LDS,
 // then each thread writes its rows.  Writes rows[] and the total.
 __global__ void __launch_bounds__(1024) k_row_scan(const int32_t *x0, const int32_t *len,
-                                                   int64_t nrows, int2 *rows, int64_t *total) {
+                                                   int64_t nrows, int32_t A, int2 *rows, int64_t *total) {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
     const int64_t chunk = (nrows + 1023) / 1024;
     const int64_t r0 = t * chunk, r1 = min(nrows, r0 + chunk);
     int64_t s = 0;
-    for (int64_t r = r0; r < r1; ++r) s += len[r];
+    for (int64_t r = r0; r < r1; ++r) s += row_slots(x0[r], len[r], A);
     part[t] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
@@ -70,8 +82,8 @@ __global__ void __launch_bounds__(1024) k_row_scan(const int32_t *x0, const int3
     int64_t start = t == 0 ? 0 : part[t - 1];
     for (int64_t r = r0; r < r1; ++r) {
         const int32_t a = x0[r], l = len[r];
-        rows[r] = make_int2((int32_t)(start - a), a | ((a + l) << 16));
-        start += l;
+        rows[r] = make_int2((int32_t)(start - (a & -A)), a | ((a + l) << 16));
+        start += row_slots(a, l, A);
     }
     if (t == 1023) *total = part[1023];
 }
@@ -229,8 +241,14 @@ const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
 using namespace rsg;
 
 extern "C" int rsg_grid_create(const rsg_grid_desc *d, void *stream, rsg_grid_t *out) {
+    return rsg_grid_create_aligned(d, 1, stream, out);
+}
+
+extern "C" int rsg_grid_create_aligned(const rsg_grid_desc *d, int32_t align, void *stream, rsg_grid_t *out) {
     clear_error();
     RSG_REQUIRE(d && out, RSG_EINVAL, "rsg_grid_create: null argument");
+    RSG_REQUIRE(align >= 1 && align <= 64 && (align & (align - 1)) == 0, RSG_EINVAL,
+                "rsg_grid_create: align must be a power of two in 1..64");
     RSG_REQUIRE(d->h > 0 && std::isfinite(d->h), RSG_EINVAL, "rsg_grid_create: h must be > 0");
     RSG_REQUIRE(d->shape == RSG_BOX_CUBE || d->shape == RSG_BOX_SPHERE, RSG_EINVAL,
                 "rsg_grid_create: unknown box shape %d", d->shape);
@@ -256,6 +274,7 @@ extern "C" int rsg_grid_create(const rsg_grid_desc *d, void *stream, rsg_grid_t 
         hipStream_t s = (hipStream_t)stream;
         auto *g = new rsg_grid_s();
         g->shape = d->shape;
+        g->align = align;
         g->n[0] = g->n[1] = g->n[2] = nx;
         g->h = d->h;
         const int64_t nrows = (int64_t)nx * nx;
@@ -280,7 +299,7 @@ extern "C" int rsg_grid_create(const rsg_grid_desc *d, void *stream, rsg_grid_t 
         const int bs = 256;
         k_row_extent<<<(unsigned)((nrows + bs - 1) / bs), bs, 0, s>>>(d->shape, nx, nx, nx, Q, M,
                                                                      x0, len);
-        k_row_scan<<<1, 1024, 0, s>>>(x0, len, nrows, g->rows, total);
+        k_row_scan<<<1, 1024, 0, s>>>(x0, len, nrows, align, g->rows, total);
         if ((e = hipGetLastError()) != hipSuccess) return fail(e);
         int64_t np = 0;
         if ((e = hipMemcpyAsync(&np, total, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -299,7 +318,12 @@ extern "C" int rsg_grid_create(const rsg_grid_desc *d, void *stream, rsg_grid_t 
             return RSG_EUNSUPPORTED;
         }
         g->np = np;
+        g->npts = 0;
+        for (const int2 &r : g->rows_host) g->npts += ((r.y >> 16) & 0xffff) - (r.y & 0xffff);
         if ((e = hipMalloc(&g->ijk, sizeof(int32_t) * 3 * (np > 0 ? np : 1))) != hipSuccess)
+            return fail(e);
+        // dead slots of a row-aligned grid keep coordinates -1
+        if (np > g->npts && (e = hipMemsetAsync(g->ijk, 0xff, sizeof(int32_t) * 3 * np, s)) != hipSuccess)
             return fail(e);
         const int64_t work = nrows * nx;
         k_coords<<<(unsigned)((work + bs - 1) / bs), bs, 0, s>>>(g->rows, nx, nx, nrows, g->ijk);
@@ -322,6 +346,14 @@ extern "C" int rsg_grid_info(rsg_grid_t g, int64_t *np, int32_t dims[3], double 
     return RSG_OK;
 }
 
+extern "C" int rsg_grid_points(rsg_grid_t g, int64_t *npoints, int32_t *align) {
+    clear_error();
+    RSG_REQUIRE(g, RSG_EINVAL, "rsg_grid_points: null grid");
+    if (npoints) *npoints = g->npts;
+    if (align) *align = g->align;
+    return RSG_OK;
+}
+
 extern "C" int rsg_grid_coords(rsg_grid_t g, int32_t *ijk_host) {
     clear_error();
     RSG_REQUIRE(g && ijk_host, RSG_EINVAL, "rsg_grid_coords: null argument");
@@ -337,7 +369,8 @@ extern "C" int rsg_grid_positions(rsg_grid_t g, double *xyz) {
         RSG_CHECK_HIP(hipMemcpy(ijk.data(), g->ijk, sizeof(int32_t) * ijk.size(), hipMemcpyDeviceToHost));
         for (int64_t p = 0; p < g->np; ++p)
             for (int a = 0; a < 3; ++a)
-                xyz[3 * p + a] = g->h * ((double)ijk[3 * p + a] - 0.5 * (double)(g->n[a] - 1));
+                xyz[3 * p + a] = ijk[3 * p] < 0 ? 0.0  // dead slot of a row-aligned grid
+                                                : g->h * ((double)ijk[3 * p + a] - 0.5 * (double)(g->n[a] - 1));
         return RSG_OK;
     });
 }

@@ -124,6 +124,7 @@ extern "C" int rsg_map_create(rsg_grid_t g, int32_t kind, int32_t param, rsg_map
     RSG_REQUIRE(kind != RSG_MAP_BRICKS || (param >= 1 && param <= 64), RSG_EINVAL,
                 "rsg_map_create: brick edge must be 1..64 (got %d)", param);
     RSG_REQUIRE(g->np > 0, RSG_EINVAL, "rsg_map_create: empty grid");
+    RSG_REQUIRE(g->align == 1, RSG_EUNSUPPORTED, "rsg_map_create: needs a grid with compact rows (align 1)");
     return guarded([&]() -> int {
         const int64_t np = g->np;
         const int nx = g->n[0], ny = g->n[1], nz = g->n[2];

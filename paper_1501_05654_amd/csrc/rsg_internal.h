@@ -92,10 +92,13 @@ struct TilePlan {
 struct Grid {
     int32_t shape = 0;
     int32_t n[3] = {0, 0, 0};  // tight box x, y, z
-    int64_t np = 0;
+    int64_t np = 0;            // slots per field: box points, plus dead slots when align > 1
+    int64_t npts = 0;          // box points
+    int32_t align = 1;         // row bases are multiples of align (a power of two)
     double h = 0;
     // rows[z*ny + y] = {base, x0 | x1 << 16}: point (x,y,z) is in the box iff
-    // x0 <= x < x1, with compact index base + x.
+    // x0 <= x < x1, with compact index base + x; a non-empty row owns the
+    // slots base + x for x in [x0, x1) widened to multiples of align.
     int2 *rows = nullptr;       // device [ny*nz + 1]; entry ny*nz is an empty row
     double *zeros = nullptr;    // device, 256 zero bytes: target of masked-off loads
     std::vector<int2> rows_host;
@@ -186,6 +189,7 @@ struct KParams {
     int32_t block_order;
     int32_t ny, nz;
     int32_t axis;
+    int32_t align;  // row alignment of the grid (1: compact rows, no dead slots)
 };
 // One work item of the batched stencil: tile (tx, ty, z0, z1) of system sys,
 // orbital ob.

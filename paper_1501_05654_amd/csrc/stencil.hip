@@ -96,6 +96,16 @@ __device__ __forceinline__ int idx_in_row(int2 r, int x) {
     const int x0 = r.y & 0xffff, x1 = (r.y >> 16) & 0xffff;
     return (x >= x0 && x < x1) ? r.x + x : -1;
 }
+// Own-column index for loads and the store: a box point gives its index; a
+// dead slot of a row-aligned grid (inside the row's x-range widened to
+// multiples of align, outside the box) gives -(index) - 2, which every load
+// treats as out of range and the store fills with zero; anything else -1.
+__device__ __forceinline__ int slot_in_row(int2 r, int x, int align) {
+    const int x0 = r.y & 0xffff, x1 = (r.y >> 16) & 0xffff;
+    if (x >= x0 && x < x1) return r.x + x;
+    const int a0 = x0 & -align, a1 = (x1 + align - 1) & -align;
+    return (x0 < x1 && x >= a0 && x < a1) ? -(r.x + x) - 2 : -1;
+}
 
 // Buffer loads and stores (CDNA): a per-workgroup resource (base address,
 // size in bytes) in scalar registers and a 32-bit byte offset per lane.  An
@@ -201,7 +211,8 @@ struct Halo {
 
 // The per-point epilogue shared by both marches: H value from the Laplacian
 // taps, then the stage combination (times the absorber mask m_c when MASK),
-// stored at idx (dropped when idx < 0).
+// stored at idx (dropped when idx = -1; zero at the dead slot -idx - 2 when
+// idx <= -2).
 template <class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
 __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0, Tc lr, Tc li, Tc v_c,
                                        Tc vi_c, double2 b_c, double m_c, double E, int x, int y, int z,
@@ -222,9 +233,10 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
         hr = kin_h2 * lr + vloc * q0.x;
         hi = kin_h2 * li + vloc * q0.y;
     }
-    const unsigned o = boff<Tout>(idx);
+    const bool dead = idx < -1;
+    const unsigned o = boff<Tout>(dead ? -idx - 2 : idx);
     if (MODE == 0) {
-        store_c(rout, o, (Tout *)nullptr, (double)hr, (double)hi);
+        store_c(rout, o, (Tout *)nullptr, dead ? 0.0 : (double)hr, dead ? 0.0 : (double)hi);
     } else {
         const double2 bb = FIRST ? make_double2((double)q0.x, (double)q0.y) : b_c;
         double r = bb.x + (a.cre * (double)hr - a.cim * (double)hi);
@@ -233,7 +245,7 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
             r *= m_c;
             i *= m_c;
         }
-        store_c(rout, o, (Tout *)nullptr, r, i);
+        store_c(rout, o, (Tout *)nullptr, dead ? 0.0 : r, dead ? 0.0 : i);
     }
 }
 
@@ -293,7 +305,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     int oid[Q];
 #pragma unroll
     for (int j = 0; j < Q - 1; ++j) {
-        oid[j] = idx_in_row(row_of(a, y, zs + dir * (j - 4)), x);
+        oid[j] = slot_in_row(row_of(a, y, zs + dir * (j - 4)), x, a.align);
         cv[j] = fetch(oid[j], true);
     }
     cv[Q - 1] = C2{(Tc)0, (Tc)0};
@@ -359,7 +371,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                 rfr[srp] = row_of(a, y, z + dir * (5 + D));
 #pragma unroll
                 for (int j = 0; j < HPT; ++j) rhl[srp][j] = row_of(a, hl.y[j], z + dir * (1 + HA));
-                const int idf = (k + 4 + D < nk + 4) ? idx_in_row(rfr[sr], x) : -1;
+                const int idf = (k + 4 + D < nk + 4) ? slot_in_row(rfr[sr], x, a.align) : -1;
                 oid[SLOT(4 + D)] = idf;
                 cv[SLOT(4 + D)] = fetch(idf, true);
                 const bool hlive = k + HA < nk;
@@ -435,7 +447,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     C2 q[9];
 #pragma unroll
     for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(row_of(a, y, zs + dir * (j - 4)), x), true);
-    int idx_c = idx_in_row(row_of(a, y, zs), x);
+    int idx_c = slot_in_row(row_of(a, y, zs), x, a.align);
     C2 nxt = fetch(idx_in_row(row_of(a, y, zs + dir * 4), x), true);
     C2 hv[HPT];
 #pragma unroll
@@ -471,7 +483,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
         nxt = fetch(live ? idx_in_row(rf, x) : -1, true);
 #pragma unroll
         for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(rh[j], hl.x[j]), hl.ok[j] && live);
-        const int idx_n = live ? idx_in_row(ro, x) : -1;
+        const int idx_n = live ? slot_in_row(ro, x, a.align) : -1;
         const Tc v_n = fetch_v(idx_n);
         const Tc vi_n = fetch_vi(idx_n);
         const double2 b_n = fetch_b(idx_n);
@@ -697,6 +709,7 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     p.ny = g.n[1];
     p.nz = g.n[2];
     p.axis = H.axis;
+    p.align = g.align;
     return p;
 }
 

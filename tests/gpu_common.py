@@ -47,16 +47,20 @@ def pad_untouched(t: torch.Tensor, npts: int) -> bool:
 class System:
     """One grid + Hamiltonian on the oracle and on the GPU, built from the
     same synth inputs evaluated at the oracle's grid positions.  The GPU
-    grid is required to match the oracle grid point for point."""
+    grid is required to match the oracle grid point for point: slot for
+    point with align 1, and on its live slots (in the same order) for a
+    row-aligned grid, whose dead slots the tests fill with zero."""
 
     def __init__(self, h, *, R=None, n=None, potential="wells", natoms=0, nst=4, ld=None,
                  seed=0, dipole_axis=-1, kin=-0.5, well_ball=None, well_box=None, rcut=2.0,
-                 orbitals="white", packet_box=5.0, pad=0):
+                 orbitals="white", packet_box=5.0, pad=0, align=1):
         R_ = rsg()
         self.og = oracle.Grid(h, R=R, n=n)
-        self.gg = R_.Grid(h, R=R, n=n)
-        assert self.gg.np == self.og.np and self.gg.dims == tuple(self.og.dims)
-        np.testing.assert_array_equal(self.gg.coords(), self.og.ijk)
+        self.gg = R_.Grid(h, R=R, n=n, align=align)
+        self.live = self.gg.live()
+        assert self.gg.npoints == self.og.np and self.gg.dims == tuple(self.og.dims)
+        assert align > 1 or self.gg.np == self.og.np
+        np.testing.assert_array_equal(self.gg.coords()[self.live], self.og.ijk)
         pos = self.og.positions()
         self.pos = pos
         self.nst = nst
@@ -81,8 +85,9 @@ class System:
         projs = []
         if self.proj is not None:
             for idx, p, E in zip(self.proj.idx, self.proj.p, self.proj.E):
-                projs.append((torch.from_numpy(idx).to(dev), torch.from_numpy(p).to(dev), E))
-        Vt = None if V is None else torch.from_numpy(V).to(dev)
+                sidx = self.live[idx].astype(np.int32)
+                projs.append((torch.from_numpy(sidx).to(dev), torch.from_numpy(p).to(dev), E))
+        Vt = None if V is None else torch.from_numpy(self.slots(V)).to(dev)
         self.gh = R_.Hamiltonian(self.gg, V=Vt, kin=kin, dipole_axis=dipole_axis, projectors=projs)
         if orbitals == "white":
             self.psi = synth.white_noise(seed + 1000, self.og.np, nst, h, ld=self.ld)
@@ -93,15 +98,34 @@ class System:
         else:
             raise ValueError(orbitals)
 
+    def slots(self, v: np.ndarray) -> np.ndarray:
+        """Per-point array [npoints, ...] -> per-slot array, zero in dead slots."""
+        if self.gg.np == self.og.np:
+            return v
+        out = np.zeros((self.gg.np,) + v.shape[1:], dtype=v.dtype)
+        out[self.live] = v
+        return out
+
     def to_gpu(self, a: np.ndarray) -> torch.Tensor:
-        """Oracle-layout [np, ld] -> orbital-major GPU tensor [ld, np + pad]."""
-        return to_om(a, self.pad)
+        """Oracle-layout [np, ld] -> orbital-major GPU tensor [ld, slots + pad]
+        (dead slots zero)."""
+        return to_om(self.slots(a), self.pad)
 
     def from_gpu(self, t: torch.Tensor) -> np.ndarray:
-        return from_om(t, self.og.np)
+        """Orbital-major GPU tensor -> oracle layout [np, ld] (live slots)."""
+        if self.gg.np == self.og.np:
+            return from_om(t, self.og.np)
+        return np.ascontiguousarray(t.detach().cpu().numpy()[:, self.live].T)
+
+    def dead_values(self, t: torch.Tensor) -> np.ndarray:
+        """Values in the dead slots, [ld, ndead]."""
+        a = t.detach().cpu().numpy()[:, :self.gg.np]
+        mask = np.ones(self.gg.np, dtype=bool)
+        mask[self.live] = False
+        return a[:, mask]
 
     def pad_untouched(self, t: torch.Tensor) -> bool:
-        return pad_untouched(t, self.og.np)
+        return pad_untouched(t, self.gg.np)
 
 
 def orbital_rel_err(got: np.ndarray, ref: np.ndarray, nst: int) -> float:

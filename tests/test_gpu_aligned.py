@@ -1,0 +1,185 @@
+"""Row-aligned grids (rsg_grid_create_aligned): the points keep their order,
+every non-empty row's slots are its x-range widened to multiples of the
+alignment, and the extra slots hold no point.
+
+- Layout: the live slots carry the oracle's points in the oracle's order,
+  every row starts at a multiple of the alignment, dead slots read
+  coordinates -1 and position 0, for spheres and cubes and several
+  alignments.
+- H psi and a Taylor(4) step (wells, projectors, dipole field, spare
+  orbitals, padding points) equal the oracle on the live slots to the FP64
+  bar for every compiled tile, z-chunk and block order; every stencil output
+  holds exact zeros in the dead slots even when the output buffer held
+  other values; spare orbitals and padding stay untouched.
+- The mixed path, the batched path (bit for bit against single systems),
+  complex scaling, the reductions and the energy work on aligned grids.
+- A bad alignment and a grid-to-memory map on an aligned grid are
+  rejected."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_common import System, orbital_rel_err, rsg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.mark.parametrize("shape,size,align", [("sphere", 3.1, 8), ("sphere", 4.4, 4), ("sphere", 2.0, 16),
+                                              ("cube", 13, 8), ("cube", 16, 8), ("sphere", 0.2, 8)])
+def test_aligned_layout(shape, size, align):
+    R = rsg()
+    h = 0.3
+    kw = dict(R=size) if shape == "sphere" else dict(n=size)
+    og = oracle.Grid(h, **kw)
+    gg = R.Grid(h, align=align, **kw)
+    assert gg.align == align and gg.npoints == og.np and gg.np >= og.np
+    assert gg.np % align == 0
+    ijk = gg.coords()
+    live = gg.live()
+    np.testing.assert_array_equal(ijk[live], og.ijk)
+    dead = np.setdiff1d(np.arange(gg.np), live)
+    assert np.all(ijk[dead] == -1)
+    pos = gg.positions()
+    np.testing.assert_array_equal(pos[live], og.positions())
+    assert np.all(pos[dead] == 0)
+    # the slot of x = 0 of every row is a multiple of the alignment
+    assert np.all((live - ijk[live, 0]) % align == 0)
+    # each row's slots are its x-range widened to multiples of align
+    rows = {}
+    for p, (x, y, z) in zip(live, ijk[live]):
+        rows.setdefault((y, z), []).append((x, p))
+    total = 0
+    for v in rows.values():
+        x0, x1 = v[0][0], v[-1][0] + 1
+        total += ((x1 + align - 1) // align - x0 // align) * align
+    assert total == gg.np
+
+
+@pytest.fixture(scope="module")
+def asys():
+    return System(0.3, R=3.1, potential="wells", natoms=2, nst=13, ld=16, seed=71, dipole_axis=2,
+                  rcut=1.2, pad=5, align=8)
+
+
+def test_aligned_every_tile_matches_oracle(asys):
+    R = rsg()
+    s = asys
+    assert s.gg.np > s.og.np  # there are dead slots
+    field, dt = 0.07, 0.01
+    ref_h = oracle.hpsi(s.oh, s.psi, field=field, nst=s.nst)
+    ref_s = oracle.taylor_step(s.oh, s.psi, dt, field=field, nst=s.nst)
+    psi = s.to_gpu(s.psi)
+    n = 0
+    for t in R.tile_candidates("c128"):
+        for zc in (0, 4, 1):
+            for bo in (0, 1):
+                R.set_tile(s.gh, s.nst, t["B"], t["TX"], t["TY"], zc, t["PD"], 0, bo, 0)
+                out = torch.full_like(psi, 3.0 + 1.0j)
+                R.hpsi(s.gh, psi, field=field, out=out, nst=s.nst)
+                y = s.from_gpu(out)
+                assert orbital_rel_err(y, ref_h, s.nst) <= TOL, (t, zc, bo)
+                d = s.dead_values(out)
+                assert np.all(d[:s.nst] == 0), (t, zc, bo)
+                assert np.all(d[s.nst:] == 3.0 + 1.0j) and np.all(y[:, s.nst:] == 3.0 + 1.0j)
+                x = psi.clone()
+                R.propagate_step(s.gh, x, dt, field=field, nst=s.nst)
+                xs = s.from_gpu(x)
+                assert orbital_rel_err(xs, ref_s, s.nst) <= TOL, (t, zc, bo)
+                assert np.all(s.dead_values(x) == 0)
+                np.testing.assert_array_equal(xs[:, s.nst:], s.psi[:, s.nst:])
+                assert s.pad_untouched(x)
+                n += 1
+    assert n >= 60
+
+
+def test_aligned_step_clears_dead_slots(asys):
+    """Nonzero values left in dead slots of psi are never read: the live
+    result is unchanged and the step leaves zeros there."""
+    R = rsg()
+    s = asys
+    R.set_tile(s.gh, s.nst, 1, 32, 16, 0, 1, 0, 1, 0)
+    ref_s = oracle.taylor_step(s.oh, s.psi, 0.01, nst=s.nst)
+    x = s.to_gpu(s.psi)
+    mask = torch.ones(s.gg.np, dtype=torch.bool, device="cuda")
+    mask[torch.from_numpy(s.live).cuda()] = False
+    x[:, :s.gg.np][:, mask] = 5.0 - 2.0j
+    R.propagate_step(s.gh, x, 0.01, nst=s.nst)
+    assert orbital_rel_err(s.from_gpu(x), ref_s, s.nst) <= TOL
+    d = s.dead_values(x)
+    assert np.all(d[:s.nst] == 0) and np.all(d[s.nst:] == 5.0 - 2.0j)
+
+
+def test_aligned_reductions_energy_and_mixed(asys):
+    R = rsg()
+    s = asys
+    R.set_tile(s.gh, s.nst, 1, 32, 16, 0, 1, 0, 1, 0)
+    psi = s.to_gpu(s.psi)
+    h3 = s.og.h ** 3
+    n2 = R.norm2(s.gg, psi, nst=s.nst).cpu().numpy()
+    ref = h3 * np.sum(np.abs(s.psi[:, :s.nst]) ** 2, axis=0)
+    np.testing.assert_allclose(n2, ref, rtol=1e-13)
+    e = R.energy(s.gh, psi, field=0.07, nst=s.nst).cpu().numpy()
+    hp = oracle.hpsi(s.oh, s.psi, field=0.07, nst=s.nst)
+    e_ref = h3 * np.sum(np.conj(s.psi[:, :s.nst]) * hp[:, :s.nst], axis=0)
+    np.testing.assert_allclose(e, e_ref, rtol=0, atol=1e-12 * np.abs(e_ref).max())
+    # mixed path: FP32 H on complex64 work buffers, against the FP64 step
+    x64, x32 = psi.clone(), psi.clone()
+    R.propagate_step(s.gh, x64, 0.01, nst=s.nst)
+    R.propagate_step(s.gh, x32, 0.01, dtype="mixed", nst=s.nst)
+    assert orbital_rel_err(s.from_gpu(x32), s.from_gpu(x64), s.nst) <= 1e-5
+    assert np.all(s.dead_values(x32)[:s.nst] == 0)
+
+
+def test_aligned_batch_matches_single_systems():
+    """Two aligned systems (different radii and orbital counts) and one
+    compact one in a batch: every system's steps equal its single-system
+    steps bit for bit."""
+    R = rsg()
+    systems = [System(0.3, R=3.4, potential="wells", natoms=2, nst=5, seed=81, rcut=1.2, align=8),
+               System(0.3, R=2.6, potential="wells", natoms=1, nst=3, ld=4, seed=82, rcut=1.2, align=8),
+               System(0.3, R=2.9, potential="wells", natoms=1, nst=2, seed=83, rcut=1.2)]
+    tile = (1, 16, 8, 0, 1, 0, 1, 0)
+    singles, batched = [], []
+    for s in systems:
+        R.set_tile(s.gh, s.nst, *tile)
+        x = s.to_gpu(s.psi)
+        for _ in range(2):
+            R.propagate_step(s.gh, x, 0.01, nst=s.nst)
+        singles.append(x)
+        batched.append(s.to_gpu(s.psi))
+    b = R.Batch([(s.gh, x, s.nst) for s, x in zip(systems, batched)])
+    b.set_tile(1, 16, 8, 0, 1)
+    b.propagate(0.01, 2)
+    torch.cuda.synchronize()
+    for s, x, y in zip(systems, singles, batched):
+        np.testing.assert_array_equal(y.cpu().numpy(), x.cpu().numpy())
+        assert np.all(s.dead_values(y)[:s.nst] == 0)
+
+
+def test_aligned_complex_scaling():
+    R = rsg()
+    s = System(0.3, R=3.1, potential="wells", natoms=0, nst=5, ld=6, seed=51, dipole_axis=2, pad=4,
+               well_ball=1.2, align=8)
+    rng = np.random.default_rng(52)
+    vim = -0.3 * rng.random(s.og.np)
+    oh = oracle.Ham(s.og, V=s.V, kin=-0.5, dipole_axis=2, theta=0.3, V_im=vim)
+    s.gh.set_complex_scaling(0.3, torch.from_numpy(s.slots(vim)).cuda())
+    psi = s.to_gpu(s.psi)
+    out = torch.full_like(psi, 1.0 + 1.0j)
+    R.hpsi(s.gh, psi, field=0.05, out=out, nst=s.nst)
+    assert orbital_rel_err(s.from_gpu(out), oracle.hpsi(oh, s.psi, field=0.05, nst=s.nst), s.nst) <= TOL
+    assert np.all(s.dead_values(out)[:s.nst] == 0)
+
+
+def test_aligned_rejections():
+    R = rsg()
+    for bad in (0, 3, 128):
+        with pytest.raises(R.RSGError) as ei:
+            R.Grid(0.3, R=2.0, align=bad)
+        assert ei.value.code == -1
+    with pytest.raises(R.RSGError) as ei:
+        R.GridMap(R.Grid(0.3, R=2.0, align=8), R.MAP_STANDARD)
+    assert ei.value.code == -6
