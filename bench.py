@@ -37,10 +37,11 @@ def stencil_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(workload: str, tile=None):
+def read_traffic(workload: str, tile=None, align: int = 1):
     """HBM bytes per stencil launch from a committed rocprofv3 counter
     summary (profiles/traffic_stencil_<workload>*.txt) taken on the current
-    stencil source and with the tile shape in use; None if there is none."""
+    stencil source with the tile shape and grid row alignment in use; None
+    if there is none."""
     import glob
     key = None
     if tile is not None:
@@ -54,6 +55,8 @@ def read_traffic(workload: str, tile=None):
         if kv.get("stencil_source_sha256") != stencil_source_hash():
             continue
         if key is not None and kv.get("tile") != key:
+            continue
+        if int(kv.get("row_align", "1")) != align:
             continue
         try:
             return float(kv["hbm_bytes_per_launch"])
@@ -130,17 +133,24 @@ def bench_sphere(args):
     cfg = dict(synth.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
     log("grid")
-    gg = rsg.Grid(cfg["h"], R=cfg["R"])
-    pos = gg.positions()
+    # row-aligned storage (align 8: every row starts on a 128-byte line); the
+    # inputs are the same per point, placed in the live slots, zero elsewhere
+    gg = rsg.Grid(cfg["h"], R=cfg["R"], align=args.align)
+    live = gg.live()
+    pos = gg.positions()[live]
     V, proj = build_sphere_inputs(cfg, pos)
-    log(f"np={gg.np}, generating {cfg['nst']} orbitals")
-    psi_h = synth.white_noise(cfg["seed"], gg.np, cfg["nst"], cfg["h"])
+    log(f"points={gg.npoints}, slots={gg.np}, generating {cfg['nst']} orbitals")
+    psi_h = synth.white_noise(cfg["seed"], gg.npoints, cfg["nst"], cfg["h"])
     dev = torch.device("cuda:0")
-    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
-                         projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
+    Vs = np.zeros(gg.np)
+    Vs[live] = V
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(Vs).to(dev), kin=-0.5,
+                         projectors=[(torch.from_numpy(live[i].astype(np.int32)).to(dev),
+                                      torch.from_numpy(p).to(dev), E)
                                      for i, p, E in zip(proj.idx, proj.p, proj.E)])
-    # the library's layout is orbital-major [nst, np]
-    psi = torch.from_numpy(psi_h).to(dev).t().contiguous()
+    # the library's layout is orbital-major [nst, slots]
+    psi = torch.zeros((cfg["nst"], gg.np), dtype=torch.complex128, device=dev)
+    psi[:, torch.from_numpy(live).to(dev)] = torch.from_numpy(psi_h).to(dev).t()
     del psi_h
     nst = cfg["nst"]
     ws = torch.empty(gh.workspace_bytes("step", nst, psi.shape[1]), dtype=torch.uint8, device=dev)
@@ -168,14 +178,14 @@ def bench_sphere(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     el = t1 - t0
-    npts = gg.np
+    npts = gg.npoints  # box points; dead slots are not counted
     value = npts * nst * 4 * args.steps / el
     # algorithmic HBM bytes of the stencil stages of one step: stage 1 reads
     # psi and writes w (32 B per point-orbital), stages 2-4 read w and psi and
     # write (48 B); each stage reads V once (8 B per point)
     stage_bytes = (npts * nst * (32 + 3 * 48) + 4 * 8 * npts) / 4.0
     achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
-    traffic = read_traffic(args.workload, tile)
+    traffic = read_traffic(args.workload, tile, gg.align)
     norms = rsg.norm2(gg, psi).cpu().numpy()
     # plain device copy of 1 GiB: achievable copy bandwidth, and the
     # reference kernel for scaling the HBM byte counters
@@ -206,7 +216,7 @@ def bench_sphere(args):
         "data": "synthetic",
         "config": {"workload": args.workload, "np": npts, "nst": nst, "natoms": cfg["natoms"],
                    "R_bohr": cfg["R"], "h_bohr": cfg["h"], "dt": dt, "taylor_order": 4,
-                   "stencil": "8th-order 25-point star"},
+                   "stencil": "8th-order 25-point star", "row_align": gg.align, "slots": gg.np},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic, "kernel": "k_stencil (Horner stage)",
@@ -846,6 +856,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--align", type=int, default=8,
+                    help="sphere18_wells: row alignment of the grid's storage (1 = compact rows)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape instead of timing the candidates")
     ap.add_argument("--tile", default="",

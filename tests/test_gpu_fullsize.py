@@ -1,9 +1,10 @@
 """Full-size parity on the benchmark workload: the 3,053,617-point sphere
-(R = 18 bohr, h = 0.2) with 64 orbitals, 16 wells and 4 projectors each.
-The GPU runs all 64 orbitals in the launch configuration the benchmark
-times (the autotuner's tile, chosen the same way); the oracle recomputes a
-sample of orbitals, which is exact because orbitals are independent under H
-(pinned in the oracle tests)."""
+(R = 18 bohr, h = 0.2) with 64 orbitals, 16 wells and 4 projectors each,
+stored with row-aligned rows (align 8, the benchmark's storage) and with
+compact rows.  The GPU runs all 64 orbitals in the launch configuration the
+benchmark times (the autotuner's tile, chosen the same way); the oracle
+recomputes a sample of orbitals, which is exact because orbitals are
+independent under H (pinned in the oracle tests)."""
 import numpy as np
 import pytest
 import torch
@@ -17,46 +18,64 @@ pytestmark = pytest.mark.gpu
 SAMPLE = [0, 29, 63]
 
 
-@pytest.fixture(scope="module")
-def sphere18():
+@pytest.fixture(scope="module", params=[8, 1], ids=["align8", "compact"])
+def sphere18(request):
     cfg = synth.WORKLOADS["sphere18_wells"]
     R = rsg()
     og = oracle.Grid(cfg["h"], R=cfg["R"])
-    gg = R.Grid(cfg["h"], R=cfg["R"])
-    assert gg.np == og.np == 3053617
-    np.testing.assert_array_equal(gg.coords(), og.ijk)
+    gg = R.Grid(cfg["h"], R=cfg["R"], align=request.param)
+    assert gg.npoints == og.np == 3053617
+    live = gg.live()
+    np.testing.assert_array_equal(gg.coords()[live], og.ijk)
     pos = og.positions()
     wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
     V = synth.well_potential(pos, wells)
     proj = synth.kb_projectors(cfg["seed"], pos, wells.centres)
     psi = synth.white_noise(cfg["seed"], og.np, cfg["nst"], cfg["h"])
-    psi_om = np.ascontiguousarray(psi.T)  # the library's orbital-major layout
+    # the library's orbital-major layout over the grid's slots (dead slots zero)
+    psi_om = np.zeros((cfg["nst"], gg.np), dtype=np.complex128)
+    psi_om[:, live] = psi.T
+    Vs = np.zeros(gg.np)
+    Vs[live] = V
     oh = oracle.Ham(og, V=V, kin=-0.5, projectors=proj)
     dev = torch.device("cuda")
-    gh = R.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
-                       projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
+    gh = R.Hamiltonian(gg, V=torch.from_numpy(Vs).to(dev), kin=-0.5,
+                       projectors=[(torch.from_numpy(live[i].astype(np.int32)).to(dev),
+                                    torch.from_numpy(p).to(dev), E)
                                    for i, p, E in zip(proj.idx, proj.p, proj.E)])
     # the launch configuration the benchmark times: the autotuner's tile
     tile, _ = R.autotune(gh, torch.from_numpy(psi_om).to(dev), reps=1)
-    return dict(cfg=cfg, og=og, oh=oh, gg=gg, gh=gh, psi=psi, psi_om=psi_om, tile=tile)
+    return dict(cfg=cfg, og=og, oh=oh, gg=gg, gh=gh, psi=psi, psi_om=psi_om, tile=tile, live=live,
+                V=V, Vs=Vs)
+
+
+def _sample(t, s):
+    """Sampled orbitals of a GPU batch in the oracle's point order, and
+    the largest magnitude in their dead slots."""
+    a = t[SAMPLE, :].cpu().numpy()
+    dead = np.delete(a, s["live"], axis=1)
+    return np.ascontiguousarray(a[:, s["live"]].T), (float(np.abs(dead).max()) if dead.size else 0.0)
 
 
 def test_sphere18_hpsi_sampled_orbitals(sphere18):
     s = sphere18
     psi = torch.from_numpy(s["psi_om"]).cuda()
-    out = rsg().hpsi(s["gh"], psi)
-    got = out[SAMPLE, :].cpu().numpy().T
+    out = torch.full_like(psi, 2.0 - 1.0j)
+    rsg().hpsi(s["gh"], psi, out=out)
+    got, dead = _sample(out, s)
     ref = oracle.hpsi(s["oh"], np.ascontiguousarray(s["psi"][:, SAMPLE]))
     assert orbital_rel_err(got, ref, len(SAMPLE)) <= 1e-12
+    assert dead == 0.0
 
 
 def test_sphere18_taylor_step_sampled_orbitals(sphere18):
     s = sphere18
     psi = torch.from_numpy(s["psi_om"]).cuda()
     rsg().propagate_step(s["gh"], psi, s["cfg"]["dt"])
-    got = psi[SAMPLE, :].cpu().numpy().T
+    got, dead = _sample(psi, s)
     ref = oracle.taylor_step(s["oh"], np.ascontiguousarray(s["psi"][:, SAMPLE]), s["cfg"]["dt"])
     assert orbital_rel_err(got, ref, len(SAMPLE)) <= 1e-12
+    assert dead == 0.0
 
 
 def test_sphere18_norm_conserved_over_steps(sphere18):
@@ -83,12 +102,16 @@ def test_sphere18_complex_scaled_sampled_orbitals(sphere18):
     wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
     vz = synth.well_potential_scaled(s["og"].positions(), wells, th)
     oh = oracle.Ham(s["og"], V=vz.real.copy(), V_im=vz.imag.copy(), kin=-0.5, theta=th)
-    gh = R.Hamiltonian(s["gg"], V=torch.from_numpy(vz.real.copy()).cuda(), kin=-0.5)
-    gh.set_complex_scaling(th, torch.from_numpy(vz.imag.copy()).cuda())
+    vre, vim = np.zeros(s["gg"].np), np.zeros(s["gg"].np)
+    vre[s["live"]], vim[s["live"]] = vz.real, vz.imag
+    gh = R.Hamiltonian(s["gg"], V=torch.from_numpy(vre).cuda(), kin=-0.5)
+    gh.set_complex_scaling(th, torch.from_numpy(vim).cuda())
     psi = torch.from_numpy(s["psi_om"]).cuda()
     sub = np.ascontiguousarray(s["psi"][:, SAMPLE])
-    got = R.hpsi(gh, psi)[SAMPLE, :].cpu().numpy().T
+    got, dead = _sample(R.hpsi(gh, psi), s)
     assert orbital_rel_err(got, oracle.hpsi(oh, sub), len(SAMPLE)) <= 1e-12
+    assert dead == 0.0
     R.propagate_step(gh, psi, 0.005)
-    got = psi[SAMPLE, :].cpu().numpy().T
+    got, dead = _sample(psi, s)
     assert orbital_rel_err(got, oracle.taylor_step(oh, sub, 0.005), len(SAMPLE)) <= 1e-12
+    assert dead == 0.0
