@@ -65,6 +65,20 @@ def read_traffic(workload: str, tile=None, align: int = 1):
     return None
 
 
+def place_on_slots(gg, live, V, proj, psi_h, dev):
+    """Per-point inputs -> the grid's slots (dead slots zero): V tensor,
+    projector list with slot indices, orbital-major psi [nst, slots]."""
+    import numpy as np
+    import torch
+    Vs = np.zeros(gg.np)
+    Vs[live] = V
+    projs = [(torch.from_numpy(live[i].astype(np.int32)).to(dev), torch.from_numpy(p).to(dev), E)
+             for i, p, E in zip(proj.idx, proj.p, proj.E)]
+    psi = torch.zeros((psi_h.shape[1], gg.np), dtype=torch.complex128, device=dev)
+    psi[:, torch.from_numpy(live).to(dev)] = torch.from_numpy(psi_h).to(dev).t()
+    return torch.from_numpy(Vs).to(dev), projs, psi
+
+
 def build_sphere_inputs(cfg, positions):
     import synth
     wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
@@ -142,15 +156,9 @@ def bench_sphere(args):
     log(f"points={gg.npoints}, slots={gg.np}, generating {cfg['nst']} orbitals")
     psi_h = synth.white_noise(cfg["seed"], gg.npoints, cfg["nst"], cfg["h"])
     dev = torch.device("cuda:0")
-    Vs = np.zeros(gg.np)
-    Vs[live] = V
-    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(Vs).to(dev), kin=-0.5,
-                         projectors=[(torch.from_numpy(live[i].astype(np.int32)).to(dev),
-                                      torch.from_numpy(p).to(dev), E)
-                                     for i, p, E in zip(proj.idx, proj.p, proj.E)])
     # the library's layout is orbital-major [nst, slots]
-    psi = torch.zeros((cfg["nst"], gg.np), dtype=torch.complex128, device=dev)
-    psi[:, torch.from_numpy(live).to(dev)] = torch.from_numpy(psi_h).to(dev).t()
+    Vt, projs, psi = place_on_slots(gg, live, V, proj, psi_h, dev)
+    gh = rsg.Hamiltonian(gg, V=Vt, kin=-0.5, projectors=projs)
     del psi_h
     nst = cfg["nst"]
     ws = torch.empty(gh.workspace_bytes("step", nst, psi.shape[1]), dtype=torch.uint8, device=dev)
@@ -252,23 +260,23 @@ def bench_batch(args):
     tot = 0
     log(f"building {len(specs)} systems")
     for k, sp in enumerate(specs):
-        gg = rsg.Grid(sp.h, R=sp.R)
-        pos = gg.positions()
+        gg = rsg.Grid(sp.h, R=sp.R, align=args.align)
+        live = gg.live()
+        pos = gg.positions()[live]
         V = synth.well_potential(pos, sp.wells)
         proj = synth.kb_projectors(sp.seed, pos, sp.wells.centres)
-        gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
-                             projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
-                                         for i, p, E in zip(proj.idx, proj.p, proj.E)])
-        psi = torch.from_numpy(synth.white_noise(sp.seed, gg.np, sp.nst, sp.h)).to(dev).t().contiguous()
+        Vt, projs, psi = place_on_slots(gg, live, V, proj, synth.white_noise(sp.seed, gg.npoints, sp.nst, sp.h),
+                                        dev)
+        gh = rsg.Hamiltonian(gg, V=Vt, kin=-0.5, projectors=projs)
         systems.append((gh, psi, sp.nst))
         keep.append(gg)
-        tot += gg.np * sp.nst
+        tot += gg.npoints * sp.nst
     log(f"sum np*nst = {tot:.4e}")
     stream = torch.cuda.Stream()
     dt = cfg["dt"]
     with torch.cuda.stream(stream):
         b = rsg.Batch(systems)
-        tile, tms = b.autotune(reps=1)
+        tile, tms = b.autotune(reps=3)
         log(f"batch tile {tile}: {tms:.3f} ms per stage")
         # eager steps with per-launch HIP-event timing of the stencil kernel
         with rsg.kernel_timing() as kt:
@@ -299,7 +307,7 @@ def bench_batch(args):
         "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batch256", "nsys": len(specs), "sum_np_nst": tot, "h_bohr": cfg["h"],
-                   "dt": dt, "tile": tile},
+                   "dt": dt, "tile": tile, "row_align": args.align},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
                      "kernel": "k_stencil_batch (persistent, all systems)",
@@ -857,7 +865,8 @@ def main():
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--align", type=int, default=8,
-                    help="sphere18_wells: row alignment of the grid's storage (1 = compact rows)")
+                    help="sphere18_wells, batch256: row alignment of the sphere grids' storage "
+                         "(1 = compact rows)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape instead of timing the candidates")
     ap.add_argument("--tile", default="",
