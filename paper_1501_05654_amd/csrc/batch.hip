@@ -29,6 +29,7 @@ struct Batch {
     KbSys *kb[4] = {nullptr, nullptr, nullptr, nullptr};
     BatchItem *items = nullptr;
     int32_t nitems = 0;
+    int32_t *ctr = nullptr;  // device work counters of the persistent stencil (zero between launches)
     int4 *gitems = nullptr;
     int32_t ngitems = 0;
     int2 *sumitems = nullptr;  // projector chunk sums {system, block of 256 D entries}
@@ -44,6 +45,8 @@ struct Batch {
             kb[k] = nullptr;
         }
         if (items) (void)hipFree(items);
+        if (ctr) (void)hipFree(ctr);
+        ctr = nullptr;
         if (gitems) (void)hipFree(gitems);
         if (sumitems) (void)hipFree(sumitems);
         sumitems = nullptr;
@@ -179,6 +182,8 @@ int build_tables(Batch &b, hipStream_t s) {
         if ((rc = upload(&b.kb[k], kb[k], s))) return rc;
     }
     if ((rc = upload(&b.items, items, s))) return rc;
+    const std::vector<int32_t> ctr0{0, 0};  // lives until the stream synchronisation below
+    if ((rc = upload(&b.ctr, ctr0, s))) return rc;
     if ((rc = upload(&b.gitems, gitems, s))) return rc;
     if ((rc = upload(&b.sumitems, sumitems, s))) return rc;
     b.nitems = (int32_t)items.size();
@@ -199,7 +204,7 @@ int stage_launches(const Batch &b, int k, double dt, hipStream_t s) {
     int rc;
     if ((rc = launch_kb_gather_batch(b.kb[k], b.gitems, b.ngitems, s))) return rc;
     if ((rc = launch_kb_gather_sum_batch(b.kb[k], b.sumitems, b.nsumitems, s))) return rc;
-    if ((rc = launch_stencil_batch(b.tile, 1, k == 0, b.sp[k], b.items, b.nitems, 0.0, cim,
+    if ((rc = launch_stencil_batch(b.tile, 1, k == 0, b.sp[k], b.items, b.nitems, 0.0, cim, b.ctr,
                                    k == 0 ? b.grid_first : b.grid_rest, s)))
         return rc;
     for (size_t c = 0; c < b.sitems.size(); ++c)
@@ -339,7 +344,7 @@ extern "C" int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, d
                     // stage 2 (w1 -> w2): leaves the orbitals untouched
                     RSG_CHECK_HIP(hipEventRecord(e0, s));
                     if ((rc = launch_stencil_batch(b->tile, 1, false, b->sp[1], b->items, b->nitems, 0.0, -1e-3,
-                                                   b->grid_rest, s)))
+                                                   b->ctr, b->grid_rest, s)))
                         break;
                     RSG_CHECK_HIP(hipEventRecord(e1, s));
                     RSG_CHECK_HIP(hipEventSynchronize(e1));

@@ -199,9 +199,11 @@ struct BatchItem {
 };
 KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, const TilePlan *plan);
 int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s);
+// ctr: two device int32 work counters, zero before the first launch (each
+// launch leaves them zero again); launches sharing them must not overlap.
 int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
-                         const BatchItem *items, int32_t nitems, double cre, double cim, int grid,
-                         hipStream_t s);
+                         const BatchItem *items, int32_t nitems, double cre, double cim, int32_t *ctr,
+                         int grid, hipStream_t s);
 // Resident workgroups of the batched kernel for this shape (or an error code).
 int stencil_batch_grid(const TileShape &shape, bool first);
 TileShape default_shape(const Grid &g, int64_t nst, int compute);

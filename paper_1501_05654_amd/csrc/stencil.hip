@@ -542,18 +542,28 @@ __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK, CS>(a, a.items[item], n, tile);
 }
 
-// Persistent form over many independent systems (FP64): in round r the G
-// workgroups take items r G .. r G + G - 1 of the list {tile, system,
-// orbital}, remapped so that each XCD takes a contiguous run of them
-// (neighbouring tiles share that XCD's L2); each system's parameters come
-// from sysp[system].
+// Persistent form over many independent systems (FP64): each workgroup
+// takes the next item of the list {tile, system, orbital} from a work
+// counter as soon as it is free, so the items in flight at any time are
+// neighbours in the list (neighbouring tiles of one system and orbital,
+// which share halo lines in L2) however long each march is.  Each system's
+// parameters come from sysp[system].  ctr[0] counts items taken, ctr[1]
+// workgroups done; the last workgroup out sets both back to zero for the
+// next launch (every workgroup takes its last item before it counts itself
+// done, so no item is taken after the reset).
 template <int TX, int TY, int D, bool FIRST>
 __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__restrict__ sysp,
                                                            const BatchItem *__restrict__ items,
-                                                           int32_t nitems, double cre, double cim) {
+                                                           int32_t nitems, double cre, double cim,
+                                                           int32_t *ctr) {
     __shared__ double2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
-    const int slot = xcd_remap(blockIdx.x, gridDim.x);
-    for (int w = slot; w < nitems; w += gridDim.x) {
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        const int w = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();  // every thread has read next before it is written again
+        if (w >= nitems) break;
         const BatchItem bi = items[w];
         KParams a = sysp[__builtin_amdgcn_readfirstlane(bi.sys)];
         a.cre = cre;
@@ -561,6 +571,13 @@ __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__rest
         march<TX, TY, D, double2, double, double2, 1, FIRST, false, false>(
             a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile);
         __syncthreads();  // the next item reuses the plane buffer
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's last take precedes its count below
+        if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&ctr[0], 0);
+            atomicExch(&ctr[1], 0);
+        }
     }
 }
 
@@ -790,7 +807,7 @@ namespace {
 // launch with that many persistent workgroups.
 template <int TX, int TY, int D, bool FIRST>
 int launch_batch_inst(const KParams *sysp, const BatchItem *items, int32_t nitems, double cre, double cim,
-                      int grid, hipStream_t s) {
+                      int32_t *ctr, int grid, hipStream_t s) {
     constexpr int NT = TX * TY;
     auto kern = k_stencil_batch<TX, TY, D, FIRST>;
     if (grid < 0) {
@@ -801,15 +818,15 @@ int launch_batch_inst(const KParams *sysp, const BatchItem *items, int32_t nitem
         RSG_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0));
         return std::max(1, per_cu) * prop.multiProcessorCount;
     }
-    kern<<<(int)std::min<int64_t>(nitems, grid), NT, 0, s>>>(sysp, items, nitems, cre, cim);
+    kern<<<(int)std::min<int64_t>(nitems, grid), NT, 0, s>>>(sysp, items, nitems, cre, cim, ctr);
     return RSG_OK;
 }
 
 template <int TX, int TY, int D>
 int launch_batch_shape(bool first, const KParams *sysp, const BatchItem *items, int32_t nitems, double cre,
-                       double cim, int grid, hipStream_t s) {
-    if (first) return launch_batch_inst<TX, TY, D, true>(sysp, items, nitems, cre, cim, grid, s);
-    return launch_batch_inst<TX, TY, D, false>(sysp, items, nitems, cre, cim, grid, s);
+                       double cim, int32_t *ctr, int grid, hipStream_t s) {
+    if (first) return launch_batch_inst<TX, TY, D, true>(sysp, items, nitems, cre, cim, ctr, grid, s);
+    return launch_batch_inst<TX, TY, D, false>(sysp, items, nitems, cre, cim, ctr, grid, s);
 }
 }  // namespace
 
@@ -819,7 +836,7 @@ int stencil_batch_grid(const TileShape &shape, bool first) {
 #define RSG_TRY_G(X_, Y_, D_)                                                                        \
     if (!found && shape.TX == X_ && shape.TY == Y_ && shape.PD == D_) {                              \
         found = true;                                                                                \
-        g = launch_batch_shape<X_, Y_, D_>(first, nullptr, nullptr, 0, 0.0, 0.0, -1, nullptr);       \
+        g = launch_batch_shape<X_, Y_, D_>(first, nullptr, nullptr, 0, 0.0, 0.0, nullptr, -1, nullptr); \
     }
     if (shape.B == 1) { RSG_FP64_SHAPES(RSG_TRY_G) }
 #undef RSG_TRY_G
@@ -827,15 +844,15 @@ int stencil_batch_grid(const TileShape &shape, bool first) {
 }
 
 int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
-                         const BatchItem *items, int32_t nitems, double cre, double cim, int grid,
-                         hipStream_t s) {
+                         const BatchItem *items, int32_t nitems, double cre, double cim, int32_t *ctr,
+                         int grid, hipStream_t s) {
     if (nitems == 0) return RSG_OK;
     if (mode != 1) {
         set_error("batched stencil: only Horner stages are batched");
         return RSG_EUNSUPPORTED;
     }
-    if (grid <= 0) {
-        set_error("batched stencil: persistent grid size must be > 0");
+    if (grid <= 0 || !ctr) {
+        set_error("batched stencil: need a persistent grid size > 0 and a work counter");
         return RSG_EINVAL;
     }
     int rc = RSG_EUNSUPPORTED;
@@ -844,7 +861,7 @@ int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KPa
 #define RSG_TRY_B(X_, Y_, D_)                                                                      \
     if (!found && shape.TX == X_ && shape.TY == Y_ && shape.PD == D_) {                            \
         found = true;                                                                              \
-        rc = launch_batch_shape<X_, Y_, D_>(first, sysp, items, nitems, cre, cim, grid, s);        \
+        rc = launch_batch_shape<X_, Y_, D_>(first, sysp, items, nitems, cre, cim, ctr, grid, s);   \
     }
     if (shape.B == 1) { RSG_FP64_SHAPES(RSG_TRY_B) }
 #undef RSG_TRY_B
