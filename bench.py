@@ -549,14 +549,14 @@ def bench_mixed_sphere(args):
 
     cfg = dict(synth.WORKLOADS["sphere18_wells"])
     torch.cuda.set_device(0)
-    gg = rsg.Grid(cfg["h"], R=cfg["R"])
-    V, proj = build_sphere_inputs(cfg, gg.positions())
+    gg = rsg.Grid(cfg["h"], R=cfg["R"], align=args.align)
+    live = gg.live()
+    V, proj = build_sphere_inputs(cfg, gg.positions()[live])
     dev = torch.device("cuda:0")
-    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).to(dev), kin=-0.5,
-                         projectors=[(torch.from_numpy(i).to(dev), torch.from_numpy(p).to(dev), E)
-                                     for i, p, E in zip(proj.idx, proj.p, proj.E)])
     nst, dt = cfg["nst"], cfg["dt"]
-    psi0 = torch.from_numpy(synth.white_noise(cfg["seed"], gg.np, nst, cfg["h"])).to(dev).t().contiguous()
+    Vt, projs, psi0 = place_on_slots(gg, live, V, proj, synth.white_noise(cfg["seed"], gg.npoints, nst, cfg["h"]),
+                                     dev)
+    gh = rsg.Hamiltonian(gg, V=Vt, kin=-0.5, projectors=projs)
     ws = torch.empty(gh.workspace_bytes("step", nst, psi0.shape[1]), dtype=torch.uint8, device=dev)
     rsg.autotune(gh, psi0, reps=2)
     rsg.autotune(gh, psi0, dtype="mixed", reps=2)
@@ -577,14 +577,15 @@ def bench_mixed_sphere(args):
     full, el64, k64 = run("c128")
     mixed, el32, k32 = run("mixed")
     err = ((mixed - full).abs().pow(2).sum(1).sqrt() / full.abs().pow(2).sum(1).sqrt()).max().item()
-    npo = gg.np * nst
-    alg = (128 * npo + 16 * gg.np) / 4.0
+    npo = gg.npoints * nst
+    alg = (128 * npo + 16 * gg.npoints) / 4.0
     log(f"FP64 {el64 * 1e3 / steps:.3f} ms/step, mixed {el32 * 1e3 / steps:.3f} ms/step, error {err:.2e}")
     return {
         "metric": METRIC, "value": npo * 4 * steps / el32, "unit": UNIT, "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": el32 * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 H / f64 accumulation", "data": "synthetic",
-        "config": {"workload": "sphere18_mixed", "np": gg.np, "nst": nst, "natoms": cfg["natoms"], "dt": dt},
+        "config": {"workload": "sphere18_mixed", "np": gg.npoints, "nst": nst, "natoms": cfg["natoms"], "dt": dt,
+                   "row_align": gg.align},
         "roofline": {"bound": "hbm", "achieved": alg / (k32 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_stencil mixed (FP32 arithmetic, Horner stage)", "kernel_mean_ms": k32,
@@ -864,14 +865,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--align", type=int, default=8,
-                    help="sphere18_wells, batch256: row alignment of the sphere grids' storage "
-                         "(1 = compact rows)")
+    ap.add_argument("--align", type=int, default=0,
+                    help="sphere18_wells, sphere18_mixed, batch256: row alignment of the sphere grids' "
+                         "storage (1 = compact rows; default 8, and 16 for sphere18_mixed, whose "
+                         "complex64 work buffers need 16 slots per 128-byte line)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape instead of timing the candidates")
     ap.add_argument("--tile", default="",
                     help="B,TX,TY,ZC,PD,PT,BO[,ZM]: use this stencil tile instead of autotuning")
     args = ap.parse_args()
+    if args.align <= 0:
+        args.align = 16 if args.workload == "sphere18_mixed" else 8
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the path shards over orbitals or systems "

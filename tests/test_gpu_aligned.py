@@ -183,3 +183,23 @@ def test_aligned_rejections():
     with pytest.raises(R.RSGError) as ei:
         R.GridMap(R.Grid(0.3, R=2.0, align=8), R.MAP_STANDARD)
     assert ei.value.code == -6
+
+
+def test_align16_fp64_and_mixed_steps():
+    """Alignment 16 (the mixed benchmark's storage: 16 complex64 slots per
+    128-byte line): the FP64 step equals the oracle, the mixed step agrees
+    with it to FP32 rounding, and both leave zeros in the dead slots."""
+    R = rsg()
+    s = System(0.3, R=3.6, potential="wells", natoms=3, nst=6, ld=8, seed=91, rcut=1.2, pad=3, align=16)
+    assert s.gg.np % 16 == 0 and s.gg.np > s.og.np
+    ref = oracle.taylor_step(s.oh, s.psi, 0.01, nst=s.nst)
+    for tile in [(1, 32, 16, 0, 1, 0, 1, 0), (1, 32, 8, 4, 2, 0, 0, 1)]:
+        R.set_tile(s.gh, s.nst, *tile)
+        R.set_tile(s.gh, s.nst, *tile, dtype="mixed")
+        x64, x32 = s.to_gpu(s.psi), s.to_gpu(s.psi)
+        R.propagate_step(s.gh, x64, 0.01, nst=s.nst)
+        R.propagate_step(s.gh, x32, 0.01, dtype="mixed", nst=s.nst)
+        assert orbital_rel_err(s.from_gpu(x64), ref, s.nst) <= TOL, tile
+        assert orbital_rel_err(s.from_gpu(x32), ref, s.nst) <= 1e-5, tile
+        for x in (x64, x32):
+            assert np.all(s.dead_values(x) == 0) and s.pad_untouched(x)
