@@ -11,8 +11,10 @@ alignment, and the extra slots hold no point.
   bar for every compiled tile, z-chunk and block order; every stencil output
   holds exact zeros in the dead slots even when the output buffer held
   other values; spare orbitals and padding stay untouched.
-- The mixed path, the batched path (bit for bit against single systems),
-  complex scaling, the reductions and the energy work on aligned grids.
+- The mixed path (alignments 8 and 16), the batched path (bit for bit
+  against single systems), complex scaling, the reductions and the energy,
+  the adjoint step and control gradient, and the QMR / CG shifted solves
+  work on aligned grids.
 - A bad alignment and a grid-to-memory map on an aligned grid are
   rejected."""
 import numpy as np
@@ -203,3 +205,63 @@ def test_align16_fp64_and_mixed_steps():
         assert orbital_rel_err(s.from_gpu(x32), ref, s.nst) <= 1e-5, tile
         for x in (x64, x32):
             assert np.all(s.dead_values(x) == 0) and s.pad_untouched(x)
+
+
+def test_aligned_adjoint_and_control_gradient():
+    """The discrete adjoint step and the checkpointed control gradient on an
+    aligned grid equal the oracle's (dipole operator and laser field act on
+    the live slots only)."""
+    import synth
+    R = rsg()
+    s = System(0.3, R=3.6, potential="wells", natoms=3, nst=3, ld=4, seed=12, dipole_axis=2,
+               well_ball=1.0, pad=2, align=8)
+    lam0 = synth.white_noise(31, s.og.np, 3, s.og.h, ld=4)
+    lam_ref, g_ref = oracle.adjoint_step(s.oh, s.psi, lam0, 0.02, 0.15, nst=3)
+    lam = s.to_gpu(lam0)
+    g = R.adjoint_step(s.gh, s.to_gpu(s.psi), lam, 0.02, 0.15, nst=3).item()
+    assert orbital_rel_err(s.from_gpu(lam), lam_ref, 3) <= TOL
+    assert g == pytest.approx(g_ref, rel=1e-11, abs=1e-14)
+    assert np.all(s.dead_values(lam)[:3] == 0)
+    c = System(0.4, n=14, potential="wells", natoms=0, nst=2, seed=5, dipole_axis=2, well_box=1.5,
+               orbitals="packets", packet_box=1.0, align=8)
+    assert c.gg.np > c.og.np
+    coef = synth.laser_coefficients(5, 6, sigma=0.3)
+    dt, nsteps, ck = 0.05, 23, 5
+    J_ref, gr_ref, gs_ref = oracle.control_gradient(c.oh, c.psi, dt, nsteps, coef)
+    psi = c.to_gpu(c.psi)
+    cc = torch.from_numpy(coef).cuda()
+    J, store = R.control_forward(c.gh, psi, dt, nsteps, cc, ck)
+    grad, gs = R.control_backward(c.gh, psi, dt, nsteps, cc, ck, store)
+    assert J.item() == pytest.approx(J_ref, rel=1e-12)
+    np.testing.assert_allclose(gs.cpu().numpy(), gs_ref, rtol=1e-10, atol=1e-12 * np.abs(gs_ref).max())
+    np.testing.assert_allclose(grad.cpu().numpy(), gr_ref, rtol=1e-10, atol=1e-12 * np.abs(gr_ref).max())
+
+
+@pytest.mark.parametrize("method", ["qmr", "cg"])
+def test_aligned_shifted_solves(method):
+    """QMR and CG on an aligned grid: the iterates after 1, 2 and 6
+    iterations equal the oracle's, and a converged solve meets its residual
+    with zeros left in the dead slots."""
+    from oracle import shifted as sv
+    R = rsg()
+    s = System(0.5, R=2.9, potential="wells", natoms=2, nst=5, ld=6, seed=41, rcut=1.2, well_ball=1.0,
+               pad=3, align=8)
+    shifts = (np.array([0.3 + 0.1j, -0.2 + 0.05j, 1.0 + 0.5j, 0.05 + 0.02j, 2.0 - 0.3j]) if method == "qmr"
+              else np.array([4.0, 5.0, 6.0, 7.0, 8.0]))
+    rng = np.random.default_rng(8)
+    b = np.zeros((s.og.np, s.ld), dtype=np.complex128)
+    b[:, :s.nst] = rng.standard_normal((s.og.np, s.nst)) + 1j * rng.standard_normal((s.og.np, s.nst))
+    for k in (1, 2, 6):
+        xg, info = R.shifted_solve(s.gh, s.to_gpu(b), shifts, method=method, tol=0.0, maxiter=k, nst=s.nst)
+        ref, _, _, _ = sv.solve_batch(s.oh, b, shifts, method, tol=0.0, maxiter=k, nst=s.nst)
+        x = s.from_gpu(xg)
+        for n in range(s.nst):
+            assert np.linalg.norm(x[:, n] - ref[:, n]) <= 1e-10 * np.linalg.norm(ref[:, n]), (method, k, n)
+    xg, info = R.shifted_solve(s.gh, s.to_gpu(b), shifts, method=method, tol=1e-10, maxiter=3000, nst=s.nst)
+    assert np.all(info["status"] == 0)
+    x = s.from_gpu(xg)
+    Hx = oracle.hpsi(s.oh, x, nst=s.nst)
+    for n in range(s.nst):
+        r = b[:, n] - Hx[:, n] - shifts[n] * x[:, n]
+        assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b[:, n]), (method, n)
+    assert np.all(s.dead_values(xg)[:s.nst] == 0)
