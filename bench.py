@@ -613,12 +613,17 @@ def bench_cs(args):
     cfg = dict(synth.WORKLOADS["sphere18_cs"])
     torch.cuda.set_device(0)
     th, nst = cfg["theta"], cfg["nst"]
-    gg = rsg.Grid(cfg["h"], R=cfg["R"])
-    pos = gg.positions()
+    gg = rsg.Grid(cfg["h"], R=cfg["R"], align=args.align)
+    live = gg.live()
+    pos = gg.positions()[live]
     wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
     vz = synth.well_potential_scaled(pos, wells, th)
-    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(vz.real.copy()).cuda(), kin=-0.5)
-    psi = torch.from_numpy(synth.white_noise(cfg["seed"], gg.np, nst, cfg["h"])).cuda().t().contiguous()
+    vre, vim = np.zeros(gg.np), np.zeros(gg.np)
+    vre[live], vim[live] = vz.real, vz.imag
+    psi = torch.zeros((nst, gg.np), dtype=torch.complex128, device="cuda")
+    psi[:, torch.from_numpy(live).cuda()] = torch.from_numpy(
+        synth.white_noise(cfg["seed"], gg.npoints, nst, cfg["h"])).cuda().t()
+    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(vre).cuda(), kin=-0.5)
     out = torch.empty_like(psi)
     rsg.autotune(gh, psi, reps=2)
     reps = max(args.steps, 1)
@@ -636,10 +641,10 @@ def bench_cs(args):
         return el, kt.mean_ms
 
     el_plain, k_plain = timed()
-    gh.set_complex_scaling(th, torch.from_numpy(vz.imag.copy()).cuda())
+    gh.set_complex_scaling(th, torch.from_numpy(vim).cuda())
     el_cs, k_cs = timed()
-    npo = gg.np * nst
-    alg = 32 * npo + 16 * gg.np
+    npo = gg.npoints * nst
+    alg = 32 * npo + 16 * gg.npoints
     log(f"H {el_plain * 1e3:.3f} ms, H_theta {el_cs * 1e3:.3f} ms (stencil {k_plain:.3f} / {k_cs:.3f} ms)")
     del psi, out
     # (2) scaled oscillator
@@ -659,7 +664,7 @@ def bench_cs(args):
         "metric": "H_theta grid-pt·orbital applications/s", "value": npo / el_cs, "unit": "pt·orb·H/s",
         "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": el_cs * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "sphere18_cs", "np": gg.np, "nst": nst, "theta": th,
+        "config": {"workload": "sphere18_cs", "np": gg.npoints, "nst": nst, "theta": th, "row_align": gg.align,
                    "potential": "16 wells continued to r e^{i theta}, no projectors",
                    "step": "one H_theta application to the batch"},
         "roofline": {"bound": "hbm", "achieved": alg / (k_cs * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -693,18 +698,18 @@ def bench_solve(args):
     cfg = dict(synth.WORKLOADS["sphere500k_qmr"])
     torch.cuda.set_device(0)
     h, R, nst = cfg["h"], cfg["R"], cfg["nst"]
-    gg = rsg.Grid(h, R=R)
-    pos = gg.positions()
+    gg = rsg.Grid(h, R=R, align=args.align)
+    live = gg.live()
+    pos = gg.positions()[live]
     wells = synth.gaussian_wells(cfg["seed"], cfg["natoms"], ball=cfg["well_ball"])
     V = synth.well_potential(pos, wells)
     proj = synth.kb_projectors(cfg["seed"], pos, wells.centres)
-    projs = [(torch.from_numpy(i).cuda(), torch.from_numpy(p).cuda(), E)
-             for i, p, E in zip(proj.idx, proj.p, proj.E)]
-    gh = rsg.Hamiltonian(gg, V=torch.from_numpy(V).cuda(), kin=-0.5, projectors=projs)
+    Vt, projs, b = place_on_slots(gg, live, V, proj, synth.white_noise(cfg["seed"], gg.npoints, nst, h),
+                                  torch.device("cuda"))
+    gh = rsg.Hamiltonian(gg, V=Vt, kin=-0.5, projectors=projs)
     rng = synth.rng(cfg["seed"], 99)
     eps = rng.uniform(cfg["eps_lo"], cfg["eps_hi"], nst)
     shifts = -eps + cfg["omega"] + 1j * cfg["eta"]
-    b = torch.from_numpy(synth.white_noise(cfg["seed"], gg.np, nst, h)).cuda().t().contiguous()
     x = torch.zeros_like(b)
     ws = torch.empty(int(rsg._lib.rsg_solve_workspace_bytes(gh._h, 1, nst, b.shape[1])), dtype=torch.uint8,
                      device="cuda")
@@ -733,14 +738,14 @@ def bench_solve(args):
     rel = (rr.abs().pow(2).sum(1).sqrt() / b.abs().pow(2).sum(1).sqrt()).cpu().numpy()
     # the slowest orbital sets the number of launched iterations; every
     # orbital's passes run until it stops
-    pt_orb_iter = gg.np * float(np.sum(it))
-    alg = pt_orb_iter * 336 + float(np.max(it)) * gg.np * 8
+    pt_orb_iter = gg.npoints * float(np.sum(it))
+    alg = pt_orb_iter * 336 + float(np.max(it)) * gg.npoints * 8
     return {
         "metric": "QMR grid-pt·orbital iterations/s", "value": pt_orb_iter / el, "unit": "pt·orb·iter/s",
         "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": el * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "sphere500k_qmr", "np": gg.np, "nst": nst, "natoms": cfg["natoms"],
+        "config": {"workload": "sphere500k_qmr", "np": gg.npoints, "nst": nst, "natoms": cfg["natoms"], "row_align": gg.align,
                    "tol": cfg["tol"], "shift": "-eps_n + 0.3 + 0.1i, eps_n ~ U(-0.6, -0.1)",
                    "step": "one full solve from x = 0"},
         "roofline": {"bound": "hbm", "achieved": alg / el / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -866,16 +871,19 @@ def main():
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--align", type=int, default=0,
-                    help="sphere18_wells, sphere18_mixed, batch256: row alignment of the sphere grids' "
-                         "storage (1 = compact rows; default 8, and 16 for sphere18_mixed, whose "
-                         "complex64 work buffers need 16 slots per 128-byte line)")
+                    help="sphere workloads (sphere18_wells, sphere18_mixed, sphere18_cs, sphere500k_qmr, "
+                         "batch256): row alignment of the grids' storage (1 = compact rows; default 8, "
+                         "16 for sphere18_mixed, whose complex64 work buffers need 16 slots per "
+                         "128-byte line, and 1 for sphere500k_qmr)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape instead of timing the candidates")
     ap.add_argument("--tile", default="",
                     help="B,TX,TY,ZC,PD,PT,BO[,ZM]: use this stencil tile instead of autotuning")
     args = ap.parse_args()
     if args.align <= 0:
-        args.align = 16 if args.workload == "sphere18_mixed" else 8
+        # measured per workload: the QMR passes are pointwise over all slots,
+        # so dead slots cost them more than aligned rows gain the stencil
+        args.align = {"sphere18_mixed": 16, "sphere500k_qmr": 1}.get(args.workload, 8)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the path shards over orbitals or systems "

@@ -379,7 +379,9 @@ int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_gr
  * potential) and vim_dev (device [np] float64, copied; NULL = 0) its
  * imaginary part.  theta = 0 with vim_dev = NULL restores the Hermitian
  * operator.  Only the FP64 path is complex-scaled (RSG_C64_MIXED returns
- * RSG_EUNSUPPORTED).  Errors: RSG_EINVAL (theta not finite), RSG_EUNSUPPORTED
+ * RSG_EUNSUPPORTED).  The complex-scaled stencil runs the handle's tile at
+ * pipeline depth 1 (8x8, 16x8, 16x16 and 32x16 are built; another tile runs
+ * as 16x8).  Errors: RSG_EINVAL (theta not finite), RSG_EUNSUPPORTED
  * (the handle has projectors or an absorber mask; the adjoint, control,
  * batch and CG entry points reject a complex-scaled handle), RSG_EHIP. */
 int rsg_ham_set_complex_scaling(rsg_ham_t H, double theta, const double *vim_dev);

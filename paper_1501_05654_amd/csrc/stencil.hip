@@ -740,15 +740,16 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &tile, hipS
             set_error("stencil: a complex-scaled Hamiltonian needs the FP64 path");
             return RSG_EUNSUPPORTED;
         }
-        // complex-scaled kernels exist for a few depth-1 shapes; others map to 16 x 8
+        // complex-scaled kernels exist for a few depth-1 shapes: another
+        // depth maps to depth 1 of the same tile, another tile to 16 x 8
         bool have = false;
-#define RSG_CS_HAVE(X_, Y_, D_) have = have || (shape.TX == X_ && shape.TY == Y_ && shape.PD == D_);
+#define RSG_CS_HAVE(X_, Y_, D_) have = have || (shape.TX == X_ && shape.TY == Y_);
         RSG_CS_SHAPES(RSG_CS_HAVE)
 #undef RSG_CS_HAVE
+        shape.PD = 1;
         if (!have) {
             shape.TX = 16;
             shape.TY = 8;
-            shape.PD = 1;
         }
     }
     TileShape key = shape;
