@@ -499,7 +499,7 @@ def bench_cube32(args):
             for _ in range(cfg["steps"]):
                 rsg.propagate_step(gh, psi, dt, ws=ws)
 
-        tile, _ = rsg.autotune(gh, psi, reps=3)
+        tile, _ = rsg.autotune(gh, psi, reps=10)  # launches of a few microseconds: many repetitions
         seq()  # plans and tiles exist before capture
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
