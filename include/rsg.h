@@ -312,7 +312,8 @@ int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
  * buffer and psi, writes the other work buffer) for every compiled tile
  * shape, z-chunk lengths {whole, 64, 32, and 16, 8, 4, 2, 1 when the batch
  * has few tiles}, PT {0, 1}, BO {0, 1, 2, 4} and ZM {0, 1} with HIP events (best of
- * reps launches after a warm-up launch).  Phase 2 re-times the six fastest
+ * reps launches after a warm-up launch; a stage under 0.2 ms is timed as the
+ * mean of 16 back-to-back launches).  Phase 2 re-times the six fastest
  * on the stencil work of a whole step (the first stage plus three later
  * ones, 3 reps launches each), keeps the fastest for (nst, dtype) and
  * returns it in *best and that step time in *best_ms (either may be NULL).
