@@ -16,7 +16,8 @@ alignment, and the extra slots hold no point.
   the adjoint step and control gradient, and the QMR / CG shifted solves
   work on aligned grids.
 - A bad alignment and a grid-to-memory map on an aligned grid are
-  rejected."""
+  rejected; boxes smaller than the stencil reach work with mostly dead
+  rows."""
 import numpy as np
 import pytest
 import torch
@@ -265,3 +266,21 @@ def test_aligned_shifted_solves(method):
         r = b[:, n] - Hx[:, n] - shifts[n] * x[:, n]
         assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b[:, n]), (method, n)
     assert np.all(s.dead_values(xg)[:s.nst] == 0)
+
+
+def test_aligned_tiny_boxes():
+    """Boxes smaller than the stencil reach, stored row-aligned (every row
+    mostly dead slots): a 1-point sphere and 2^3, 3^3 cubes; H psi and a
+    step equal the oracle and leave zeros in the dead slots."""
+    R = rsg()
+    for kw in (dict(R=0.2), dict(n=3), dict(n=2)):
+        s = System(0.3, potential="harmonic", nst=2, seed=5, align=8, **kw)
+        assert s.gg.np > s.og.np
+        psi = s.to_gpu(s.psi)
+        out = torch.full_like(psi, 9.0)
+        R.hpsi(s.gh, psi, out=out)
+        assert orbital_rel_err(s.from_gpu(out), oracle.hpsi(s.oh, s.psi), 2) <= TOL, kw
+        assert np.all(s.dead_values(out) == 0), kw
+        R.propagate_step(s.gh, psi, 0.01)
+        assert orbital_rel_err(s.from_gpu(psi), oracle.taylor_step(s.oh, s.psi, 0.01), 2) <= TOL, kw
+        assert np.all(s.dead_values(psi) == 0), kw
