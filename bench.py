@@ -188,10 +188,11 @@ def bench_sphere(args):
     el = t1 - t0
     npts = gg.npoints  # box points; dead slots are not counted
     value = npts * nst * 4 * args.steps / el
-    # algorithmic HBM bytes of the stencil stages of one step: stage 1 reads
-    # psi and writes w (32 B per point-orbital), stages 2-4 read w and psi and
-    # write (48 B); each stage reads V once (8 B per point)
-    stage_bytes = (npts * nst * (32 + 3 * 48) + 4 * 8 * npts) / 4.0
+    # algorithmic HBM bytes of one stencil launch: an FP64 step runs as the
+    # product of the four linear factors of the Taylor polynomial, so every
+    # stage reads its input and writes its output (32 B per point-orbital)
+    # and reads V (8 B per point)
+    stage_bytes = npts * nst * 32 + 8 * npts
     achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
     traffic = read_traffic(args.workload, tile, gg.align)
     norms = rsg.norm2(gg, psi).cpu().numpy()
@@ -300,7 +301,7 @@ def bench_batch(args):
         t5 = time.perf_counter()
     el = t1 - t0
     value = tot * 4 * args.steps / el
-    stage_bytes = tot * 176 / 4.0
+    stage_bytes = tot * 32.0  # every stage of the product-form step: read its input, write its output
     achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
     return {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -435,13 +436,14 @@ def bench_control(args):
     with rsg.kernel_timing() as kt:
         rsg.control_backward(gh, psi, dt, nsteps, coef, ck, store)
         torch.cuda.synchronize()
-    # stencil launches of the backward sweep: per step 4 Horner stages of the
-    # checkpoint recompute (44 B/pt.orb on average) and 7 H applications of
-    # the adjoint step (32 B/pt.orb), each also reading V (8 B/pt)
-    per_launch = (4 * 44 + 7 * 32) / 11.0 * gg.np * nst + 8 * gg.np
+    # stencil launches of the backward sweep: per step the 4 product-form
+    # stages of the checkpoint recompute and 7 H applications of the adjoint
+    # step, each reading its input and writing its output (32 B/pt.orb) and
+    # reading V (8 B/pt)
+    per_launch = 32 * gg.np * nst + 8 * gg.np
     st_gbs = per_launch / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
-    # the whole sweep: 560 B/pt.orb + 88 B/pt per step (recompute, 7 H, adjoint pass)
-    sweep_gbs = (560 * gg.np * nst + 88 * gg.np) * nsteps / bwd / 1e9
+    # the whole sweep: 512 B/pt.orb + 88 B/pt per step (recompute, 7 H, adjoint pass)
+    sweep_gbs = (512 * gg.np * nst + 88 * gg.np) * nsteps / bwd / 1e9
     # central difference along a random unit direction d: (J(c+eps d) - J(c-eps d)) / 2 eps
     d = torch.from_numpy(synth.random_unit(cfg["seed"], cfg["ncoef"])).cuda()
     eps = 1e-4 * float(coef.abs().max())
@@ -459,7 +461,7 @@ def bench_control(args):
                    "checkpoint_every": ck},
         "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": st_gbs / HBM_PEAK_GBS if st_gbs else None, "traffic": None,
-                     "kernel": "k_stencil in the backward sweep (Horner recompute and H-only launches)",
+                     "kernel": "k_stencil in the backward sweep (checkpoint recompute stages and H-only launches)",
                      "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
                      "sweep_algorithmic_GBs": sweep_gbs},
         "forward_s": fwd, "gradient_s": bwd, "J": J.item(),
@@ -516,7 +518,7 @@ def bench_cube32(args):
         el = (time.perf_counter() - t0) / reps
     napp = cfg["hpsi_calls"] + 4 * cfg["steps"]
     npo = gg.np * nst
-    alg = cfg["hpsi_calls"] * (32 * npo + 8 * gg.np) + cfg["steps"] * (176 * npo + 32 * gg.np)
+    alg = cfg["hpsi_calls"] * (32 * npo + 8 * gg.np) + cfg["steps"] * (128 * npo + 32 * gg.np)
     return {
         "metric": METRIC, "value": npo * napp / el, "unit": UNIT, "n_gpus": 1, "steps": reps,
         "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak",

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstring>
 #include <mutex>
@@ -13,6 +14,38 @@
 #include <tuple>
 
 namespace rsg {
+
+// Roots r_1..r_4 of the Taylor(4) polynomial T4(z) = sum_{k<=4} z^k / k!
+// (of z^4 + 4 z^3 + 12 z^2 + 24 z + 24), largest modulus first: two
+// conjugate pairs of moduli 2.52 and 1.94.  Durand-Kerner iteration from the
+// usual spread start, then Newton steps on each root.
+const std::complex<double> *taylor4_roots() {
+    static std::complex<double> r[4];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        auto p = [](std::complex<double> z) { return (((z + 4.0) * z + 12.0) * z + 24.0) * z + 24.0; };
+        auto dp = [](std::complex<double> z) { return ((4.0 * z + 12.0) * z + 24.0) * z + 24.0; };
+        const std::complex<double> w(0.4, 0.9);
+        for (int k = 0; k < 4; ++k) r[k] = std::pow(w, k);
+        for (int it = 0; it < 500; ++it)
+            for (int k = 0; k < 4; ++k) {
+                std::complex<double> d = 1.0;
+                for (int j = 0; j < 4; ++j)
+                    if (j != k) d *= r[k] - r[j];
+                r[k] -= p(r[k]) / d;
+            }
+        for (int k = 0; k < 4; ++k)
+            for (int it = 0; it < 3; ++it) r[k] -= p(r[k]) / dp(r[k]);
+        std::sort(r, r + 4, [](const std::complex<double> &a, const std::complex<double> &b) {
+            return std::abs(a) != std::abs(b) ? std::abs(a) > std::abs(b) : a.imag() > b.imag();
+        });
+    });
+    return r;
+}
+
+// Whether a step of this handle in dtype runs as the product of the four
+// linear factors of T4 (FP64 without an absorber mask) or in Horner form.
+bool step_is_product(const Ham &H, int32_t dtype) { return dtype == RSG_C128 && !H.mask; }
 
 // ------------------------------------------------------------------ errors
 
@@ -178,10 +211,20 @@ size_t step_ws(const Ham &H, int64_t nst, int64_t ldp, int32_t dtype) {
     return 2 * rounded(batch_bytes(nst, ldp, e)) + rounded(kb_workspace_bytes(H, nst)) + 256;
 }
 
-// Taylor(4) in Horner form: y4 = psi, y_{k-1} = psi + (-i dt / k) H y_k,
-// psi_out <- y0.  Work buffers alternate; every stage reads its base from
-// psi and only the last one writes psi_out, which may be psi itself (each
-// output point reads only its own psi value).
+
+// Taylor(4) step psi_out <- T4(-i dt H) psi.
+//  - FP64 without a mask: T4(z) = prod_k (1 - z / r_k) over its roots, so
+//    the step is four stages y <- y + (i dt / r_k) H y.  Each stage reads
+//    only its input (whose centre value is its own base term) and writes
+//    one buffer: 32 B per point and orbital, against 48 for a Horner stage
+//    that also reads psi.  The factor moduli stay below 2.2 up to the
+//    stability limit dt |lambda| = 2 sqrt 2.
+//  - Mixed precision (complex64 work buffers: psi must enter every stage in
+//    FP64) and the masked step (the mask is fused into a stage with a
+//    separate base) use Horner form: y4 = psi, y_{k-1} = psi + (-i dt / k)
+//    H y_k, psi_out <- y0, every stage reading its base from psi.
+// Work buffers alternate; only the last stage writes psi_out, which may be
+// psi itself (each output point reads only its own input value).
 int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t ldp, int32_t dtype,
               double dt, double field, const double *field_dev, void *ws, size_t ws_bytes, hipStream_t s) {
     const size_t e = dtype == RSG_C128 ? 16 : 8;
@@ -196,6 +239,18 @@ int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t
     const int cmp = dtype == RSG_C128 ? 0 : 1;
     const int wt = dtype == RSG_C128 ? 0 : 1;  // work-buffer type
     int rc;
+    if (step_is_product(H, dtype)) {
+        const std::complex<double> *r = taylor4_roots();
+        const void *in[4] = {psi, w1, w2, w1};
+        void *out[4] = {w1, w2, w1, psi_out};
+        for (int k = 0; k < 4; ++k) {
+            const std::complex<double> c = std::complex<double>(0.0, dt) / r[k];  // i dt / r_k
+            if ((rc = stage_impl(H, in[k], 0, in[k], out[k], 0, 0, nst, ldp, c.real(), c.imag(), field, field_dev,
+                                 D, s)))
+                return rc;
+        }
+        return RSG_OK;
+    }
     if ((rc = stage_impl(H, psi, 0, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 4.0, field, field_dev, D, s))) return rc;
     if ((rc = stage_impl(H, w1, wt, psi, w2, wt, cmp, nst, ldp, 0.0, -dt / 3.0, field, field_dev, D, s))) return rc;
     if ((rc = stage_impl(H, w2, wt, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 2.0, field, field_dev, D, s))) return rc;
@@ -887,9 +942,9 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         hipEvent_t e0, e1;
         RSG_CHECK_HIP(hipEventCreate(&e0));
         RSG_CHECK_HIP(hipEventCreate(&e1));
-        // the two kinds of Horner stage of a step: the first (reads psi
-        // once, its centre tap is the base) and the others (read a work
-        // buffer and psi, write the other work buffer)
+        // the two kinds of stage of a step: the first (reads psi once, its
+        // centre tap is the base) and the others (read a work buffer, and
+        // psi in Horner form, and write the other work buffer)
         StageArgs first;
         first.in = psi;
         first.base = psi;
@@ -907,6 +962,11 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         rest.in_t = wt;
         rest.out = w2;
         rest.first = false;
+        if (step_is_product(*H, dtype)) {
+            // a product-form step: every stage reads only its input
+            rest.base = w1;
+            rest.first = true;
+        }
         int err = RSG_OK;
         // the work buffer read by the other stages holds a real stage output
         if ((rc = launch_stencil(*H, first, default_shape(*H->g, nst, cmp), s))) {

@@ -24,7 +24,7 @@ struct Batch {
     std::vector<rsg_system_desc> sys;
     std::vector<void *> w1, w2, D;  // per-system work buffers inside the caller's workspace
     TileShape tile{1, 32, 8, 0};
-    int grid_first = 0, grid_rest = 0;  // persistent workgroups per stencil launch
+    int grid_first = 0;  // persistent workgroups per stencil launch (every stage is a first-type stage)
     KParams *sp[4] = {nullptr, nullptr, nullptr, nullptr};  // device, per stage, one per system
     KbSys *kb[4] = {nullptr, nullptr, nullptr, nullptr};
     BatchItem *items = nullptr;
@@ -80,16 +80,17 @@ int upload(T **dst, const std::vector<T> &v, hipStream_t s) {
     return RSG_OK;
 }
 
-// Stage k (0..3) of the Horner scheme: in, base, out buffers of system i.
+// Stage k (0..3) of a step: in, base, out buffers of system i.  The stages
+// run in product form, each its own base (base = in).
 void stage_buffers(const Batch &b, size_t i, int k, const void **in, const void **base, void **out) {
     void *psi = b.sys[i].psi;
-    *base = psi;
     switch (k) {
         case 0: *in = psi; *out = b.w1[i]; break;
         case 1: *in = b.w1[i]; *out = b.w2[i]; break;
         case 2: *in = b.w2[i]; *out = b.w1[i]; break;
         default: *in = b.w1[i]; *out = psi; break;
     }
+    *base = *in;
 }
 
 // (Re)build the item lists and per-system parameter tables for the tile.
@@ -175,8 +176,7 @@ int build_tables(Batch &b, hipStream_t s) {
     for (const size_t i : by_work) items.insert(items.end(), sys_items[i].begin(), sys_items[i].end());
     int rc;
     b.grid_first = stencil_batch_grid(b.tile, true);
-    b.grid_rest = stencil_batch_grid(b.tile, false);
-    if (b.grid_first <= 0 || b.grid_rest <= 0) return b.grid_first <= 0 ? b.grid_first : b.grid_rest;
+    if (b.grid_first <= 0) return b.grid_first;
     for (int k = 0; k < 4; ++k) {
         if ((rc = upload(&b.sp[k], sp[k], s))) return rc;
         if ((rc = upload(&b.kb[k], kb[k], s))) return rc;
@@ -199,16 +199,20 @@ int build_tables(Batch &b, hipStream_t s) {
     return RSG_OK;
 }
 
+// Stage k of a step, the same product form as a single system's FP64 step:
+// y <- y + (i dt / r_k) H y over the roots r_k of the Taylor(4) polynomial
+// (every stage reads only its input; psi -> w1 -> w2 -> w1 -> psi).
 int stage_launches(const Batch &b, int k, double dt, hipStream_t s) {
-    const double cim = -dt / (double)(4 - k);  // c = -i dt / (4 - k): stages k = 0..3 use 1/4, 1/3, 1/2, 1
+    const std::complex<double> c = std::complex<double>(0.0, dt) / taylor4_roots()[k];
     int rc;
     if ((rc = launch_kb_gather_batch(b.kb[k], b.gitems, b.ngitems, s))) return rc;
     if ((rc = launch_kb_gather_sum_batch(b.kb[k], b.sumitems, b.nsumitems, s))) return rc;
-    if ((rc = launch_stencil_batch(b.tile, 1, k == 0, b.sp[k], b.items, b.nitems, 0.0, cim, b.ctr,
-                                   k == 0 ? b.grid_first : b.grid_rest, s)))
+    if ((rc = launch_stencil_batch(b.tile, 1, true, b.sp[k], b.items, b.nitems, c.real(), c.imag(), b.ctr,
+                                   b.grid_first, s)))
         return rc;
-    for (size_t c = 0; c < b.sitems.size(); ++c)
-        if ((rc = launch_kb_scatter_batch(b.kb[k], b.sitems[c], b.nsitems[c], 0.0, cim, s))) return rc;
+    for (size_t ci = 0; ci < b.sitems.size(); ++ci)
+        if ((rc = launch_kb_scatter_batch(b.kb[k], b.sitems[ci], b.nsitems[ci], c.real(), c.imag(), s)))
+            return rc;
     return RSG_OK;
 }
 
@@ -343,8 +347,8 @@ extern "C" int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, d
                 for (int r = 0; r <= reps; ++r) {
                     // stage 2 (w1 -> w2): leaves the orbitals untouched
                     RSG_CHECK_HIP(hipEventRecord(e0, s));
-                    if ((rc = launch_stencil_batch(b->tile, 1, false, b->sp[1], b->items, b->nitems, 0.0, -1e-3,
-                                                   b->ctr, b->grid_rest, s)))
+                    if ((rc = launch_stencil_batch(b->tile, 1, true, b->sp[1], b->items, b->nitems, 0.0, -1e-3,
+                                                   b->ctr, b->grid_first, s)))
                         break;
                     RSG_CHECK_HIP(hipEventRecord(e1, s));
                     RSG_CHECK_HIP(hipEventSynchronize(e1));

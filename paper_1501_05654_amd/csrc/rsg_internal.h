@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -286,6 +287,11 @@ int check_batch(const Ham *H, const void *p, int64_t nst, int64_t ldp, const cha
 // out = H(in) for an FP64 orbital-major batch; D: kb_workspace_bytes(H, nst).
 int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ldp, double field,
               const double *field_dev, void *D, hipStream_t s);
+// The four roots of the Taylor(4) polynomial sum_{k<=4} z^k/k!, largest
+// modulus first ({re, im} pairs), and whether a step of this handle in dtype
+// runs as the product of their linear factors (else in Horner form).
+const std::complex<double> *taylor4_roots();
+bool step_is_product(const Ham &H, int32_t dtype);
 
 // Reductions: partial sums per block then a fixed-order final pass.
 // kind 0: <a|b> (complex out [2*nst]); 1: |a|^2 (out [nst]);
