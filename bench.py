@@ -228,7 +228,7 @@ def bench_sphere(args):
                    "stencil": "8th-order 25-point star", "row_align": gg.align, "slots": gg.np},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "kernel": "k_stencil (Horner stage)",
+                     "traffic": traffic, "kernel": "k_stencil (Taylor stage, product form)",
                      "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
                      "algorithmic_bytes_per_launch": stage_bytes, "tile": tile,
                      "copy_gbs": copy_gbs},

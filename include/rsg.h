@@ -188,7 +188,11 @@ int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ldp,
 /* One Taylor(4) step in place: psi <- sum_{k=0}^{4} (-i dt H)^k / k! psi,
  * with H taken at `field` (the field at the step midpoint); the discrete
  * evolution operator of section "Photoemission".  psi: device [nst][ldp]
- * complex128.  dtype RSG_C128 or RSG_C64_MIXED.  ws: RSG_OP_STEP bytes. */
+ * complex128.  dtype RSG_C128 or RSG_C64_MIXED.  ws: RSG_OP_STEP bytes.
+ * RSG_C128 without an absorber mask evaluates the polynomial as the product
+ * of its four linear factors (1 + (i dt / r_k) H), r_k its roots: four
+ * stages that each read only their input; RSG_C64_MIXED and a masked step
+ * use Horner form, whose stages also read psi. */
 int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
                        double field, void *ws, size_t ws_bytes, void *stream);
 
@@ -308,8 +312,10 @@ int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_tile *t);
 int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
 
 /* Tile autotuner for the Taylor(4) step on psi (device [nst][ldp], left
- * unchanged).  Phase 1 times one of the later Horner stages (reads a work
- * buffer and psi, writes the other work buffer) for every compiled tile
+ * unchanged).  Phase 1 times one of the later Taylor stages (reads a work
+ * buffer, and psi in Horner form, and writes the other work buffer) as the
+ * step of this dtype runs it (product form for RSG_C128 without a mask,
+ * Horner form otherwise) for every compiled tile
  * shape, z-chunk lengths {whole, 64, 32, and 16, 8, 4, 2, 1 when the batch
  * has few tiles}, PT {0, 1}, BO {0, 1, 2, 4} and ZM {0, 1} with HIP events (best of
  * reps launches after a warm-up launch; a stage under 0.2 ms is timed as the

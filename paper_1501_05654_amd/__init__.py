@@ -625,7 +625,7 @@ def get_tile(ham: Hamiltonian, nst: int, dtype="c128") -> dict:
 
 def autotune(ham: Hamiltonian, psi: torch.Tensor, dtype="c128", reps: int = 3,
              nst: int | None = None):
-    """Time the compiled tile shapes on a later Horner stage of psi, re-time
+    """Time the compiled tile shapes on a later Taylor stage of psi, re-time
     the six fastest on a whole step's stencil work (first stage + three
     later ones) and keep the fastest for this (nst, dtype); returns (tile,
     milliseconds of stencil work per step)."""

@@ -179,7 +179,7 @@ int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ldp,
 
 namespace {
 
-// One Horner stage: out = base + c H(in).
+// One Taylor stage: out = base + c H(in) (base = in in a product-form step).
 int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *out, int out_t,
                int compute, int64_t nst, int64_t ldp, double cre, double cim, double field,
                const double *field_dev, void *D, hipStream_t s, const double *mask = nullptr) {
@@ -904,7 +904,7 @@ extern "C" int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t
     return RSG_OK;
 }
 
-// Times one Horner stage (out = psi + c H psi into the workspace, psi
+// Times one Taylor stage (out = psi + c H psi into the workspace, psi
 // untouched) for every compiled tile shape, z-chunk length, tile order,
 // block order and z-march, re-times the six fastest with three times the
 // launches, keeps the fastest for (nst, dtype) and reports it.

@@ -159,7 +159,7 @@ struct StageArgs {
     const void *base = nullptr;
     void *out = nullptr;
     int in_t = 0, out_t = 0, compute = 0, mode = 0;
-    bool first = false;  // base == in (first Horner stage)
+    bool first = false;  // base == in (a product-form stage, or the first Horner stage)
     const double *mask = nullptr;  // mode 1: out = mask * (base + c H in)
     int64_t nst = 0, ldp = 0;
     double field = 0;
