@@ -437,13 +437,14 @@ def bench_control(args):
         rsg.control_backward(gh, psi, dt, nsteps, coef, ck, store)
         torch.cuda.synchronize()
     # stencil launches of the backward sweep: per step the 4 product-form
-    # stages of the checkpoint recompute and 7 H applications of the adjoint
-    # step, each reading its input and writing its output (32 B/pt.orb) and
-    # reading V (8 B/pt)
+    # stages of the checkpoint recompute (keeping their outputs) and the 4
+    # adjoint factors on the costate, each reading its input and writing its
+    # output (32 B/pt.orb) and reading V (8 B/pt)
     per_launch = 32 * gg.np * nst + 8 * gg.np
     st_gbs = per_launch / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
-    # the whole sweep: 512 B/pt.orb + 88 B/pt per step (recompute, 7 H, adjoint pass)
-    sweep_gbs = (512 * gg.np * nst + 88 * gg.np) * nsteps / bwd / 1e9
+    # the whole sweep: 384 B/pt.orb + 64 B/pt per step (recompute, adjoint
+    # stages, one pass over the four stage pairs)
+    sweep_gbs = (384 * gg.np * nst + 64 * gg.np) * nsteps / bwd / 1e9
     # central difference along a random unit direction d: (J(c+eps d) - J(c-eps d)) / 2 eps
     d = torch.from_numpy(synth.random_unit(cfg["seed"], cfg["ncoef"])).cuda()
     eps = 1e-4 * float(coef.abs().max())
@@ -461,7 +462,7 @@ def bench_control(args):
                    "checkpoint_every": ck},
         "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": st_gbs / HBM_PEAK_GBS if st_gbs else None, "traffic": None,
-                     "kernel": "k_stencil in the backward sweep (checkpoint recompute stages and H-only launches)",
+                     "kernel": "k_stencil in the backward sweep (checkpoint recompute and adjoint stages)",
                      "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
                      "sweep_algorithmic_GBs": sweep_gbs},
         "forward_s": fwd, "gradient_s": bwd, "J": J.item(),

@@ -256,7 +256,10 @@ int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, 
                      void *stream);
 
 /* Scratch bytes for rsg_control_forward / rsg_control_backward with these
- * sizes (the checkpoint store is separate and owned by the caller). */
+ * sizes (the checkpoint store is separate and owned by the caller).  For a
+ * handle whose steps run in product form (no absorber mask) the segment
+ * store holds, per step, the state and its three stage outputs: about
+ * 4 ckpt_every orbital batches. */
 size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
                                    int64_t ckpt_every);
 
@@ -275,7 +278,13 @@ int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, double
  * first, recompute the segment's states from its checkpoint, then take
  * adjoint steps back through it.  grad_dev [ncoef] = dJ/dc; g_steps_dev
  * [nsteps] (may be NULL) = dJ/dE_n.  psi_T: device [nst][ldp], unchanged.
- * ws: rsg_control_workspace_bytes. */
+ * ws: rsg_control_workspace_bytes.  Product-form steps psi_{n+1} = F4 F3
+ * F2 F1 psi_n (F_k = 1 + a_k H, see rsg_propagate_step): the recompute
+ * keeps each step's stage outputs y_1..y_3 (y_0 = psi_n), the costate
+ * runs back through the adjoint factors, m_4 = lambda_{n+1}, m_{k-1} =
+ * (1 + conj(a_k) H) m_k, lambda_n = m_0, and dJ/dE_n = 2 Re sum_k a_k
+ * <m_k| x_axis |y_{k-1}>; equal in exact arithmetic to the rsg_adjoint_step
+ * formulas, which the Horner-form (masked) steps use. */
 int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ldp, double dt,
                          int64_t nsteps, const double *coef_dev, int32_t ncoef,
                          int64_t ckpt_every, const void *ckpt_dev, double *grad_dev,

@@ -212,6 +212,25 @@ size_t step_ws(const Ham &H, int64_t nst, int64_t ldp, int32_t dtype) {
 }
 
 
+// Coefficient a_k = i dt / r_k of the k-th linear factor 1 + a_k H of the
+// Taylor(4) polynomial in -i dt H.
+std::complex<double> factor_coef(int k, double dt) { return std::complex<double>(0.0, dt) / taylor4_roots()[k]; }
+
+// Product-form step y[0] = F1 psi, y[1] = F2 y[0], y[2] = F3 y[1], psi_out =
+// F4 y[2], F_k = 1 + a_k H; y[2] may alias y[0].  D: projector workspace.
+int step_product(const Ham &H, const void *psi, void *const y[3], void *psi_out, int64_t nst, int64_t ldp,
+                 double dt, double field, const double *field_dev, void *D, hipStream_t s) {
+    const void *in[4] = {psi, y[0], y[1], y[2]};
+    void *out[4] = {y[0], y[1], y[2], psi_out};
+    for (int k = 0; k < 4; ++k) {
+        const std::complex<double> c = factor_coef(k, dt);
+        const int rc = stage_impl(H, in[k], 0, in[k], out[k], 0, 0, nst, ldp, c.real(), c.imag(), field, field_dev,
+                                  D, s);
+        if (rc) return rc;
+    }
+    return RSG_OK;
+}
+
 // Taylor(4) step psi_out <- T4(-i dt H) psi.
 //  - FP64 without a mask: T4(z) = prod_k (1 - z / r_k) over its roots, so
 //    the step is four stages y <- y + (i dt / r_k) H y.  Each stage reads
@@ -240,16 +259,8 @@ int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t
     const int wt = dtype == RSG_C128 ? 0 : 1;  // work-buffer type
     int rc;
     if (step_is_product(H, dtype)) {
-        const std::complex<double> *r = taylor4_roots();
-        const void *in[4] = {psi, w1, w2, w1};
-        void *out[4] = {w1, w2, w1, psi_out};
-        for (int k = 0; k < 4; ++k) {
-            const std::complex<double> c = std::complex<double>(0.0, dt) / r[k];  // i dt / r_k
-            if ((rc = stage_impl(H, in[k], 0, in[k], out[k], 0, 0, nst, ldp, c.real(), c.imag(), field, field_dev,
-                                 D, s)))
-                return rc;
-        }
-        return RSG_OK;
+        void *y[3] = {w1, w2, w1};
+        return step_product(H, psi, y, psi_out, nst, ldp, dt, field, field_dev, D, s);
     }
     if ((rc = stage_impl(H, psi, 0, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 4.0, field, field_dev, D, s))) return rc;
     if ((rc = stage_impl(H, w1, wt, psi, w2, wt, cmp, nst, ldp, 0.0, -dt / 3.0, field, field_dev, D, s))) return rc;
@@ -306,6 +317,58 @@ int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int
     double2 ca[5];
     for (int k = 0; k < 5; ++k) ca[k] = make_double2(a[k].x, -a[k].y);
     return launch_adjoint_pass(*H.g, H.axis, mup, nup, pc, ca, (double2 *)lambda, nst, ldp, g_dev, R, rb, s);
+}
+
+size_t adjoint_product_ws(const Ham &H, int64_t nst, int64_t ldp) {
+    return 3 * rounded(batch_bytes(nst, ldp, 16)) + rounded(kb_workspace_bytes(H, nst)) +
+           rounded(reduce_workspace_bytes(*H.g, nst)) + 256;
+}
+
+// Discrete adjoint of a product-form step psi_{n+1} = F4 F3 F2 F1 psi_n,
+// F_k = 1 + a_k H(E_n), given y[0] = psi_n and the stage outputs y[1..3]
+// (y[k] = F_k ... F_1 psi_n).  With m_4 = lambda_{n+1} and m_{k-1} =
+// F_k^+ m_k (F_k^+ = 1 + conj(a_k) H, H Hermitian):
+//   lambda_n = m_0,   dJ/dE_n = 2 Re sum_{k=1}^{4} a_k <m_k | x_axis | y[k-1]>,
+// the derivative of the product by the rule for each factor (dF_k/dE =
+// a_k x_axis).  Stencil work: four first-type stages on the costate and one
+// pass over the four pairs.
+int adjoint_product_impl(const Ham &H, const void *const y[4], void *lambda, int64_t nst, int64_t ldp, double dt,
+                         double field, const double *field_dev, double *g_dev, void *ws, size_t ws_bytes,
+                         hipStream_t s) {
+    Carve c(ws, ws_bytes);
+    const size_t bb = batch_bytes(nst, ldp, 16);
+    void *m[5];
+    m[4] = lambda;
+    for (int k = 1; k < 4; ++k) m[k] = c.take(bb);
+    void *D = c.take(kb_workspace_bytes(H, nst));
+    const size_t rb = reduce_workspace_bytes(*H.g, nst);
+    void *R = c.take(rb);
+    if (!c.ok) {
+        set_error("adjoint: workspace too small (%zu < %zu bytes)", ws_bytes, adjoint_product_ws(H, nst, ldp));
+        return RSG_ENOMEM;
+    }
+    int rc;
+    for (int k = 4; k >= 2; --k) {
+        const std::complex<double> a = std::conj(factor_coef(k - 1, dt));
+        if ((rc = stage_impl(H, m[k], 0, m[k], m[k - 1], 0, 0, nst, ldp, a.real(), a.imag(), field, field_dev, D, s)))
+            return rc;
+    }
+    // pairs (m_k, y[k-1]) at (l, 3 - l) of the pass, l = k - 1
+    double2 pc[16], ca[5];
+    for (int q = 0; q < 16; ++q) pc[q] = make_double2(0.0, 0.0);
+    for (int l = 0; l < 4; ++l) {
+        const std::complex<double> a = factor_coef(l, dt);
+        pc[4 * l + (3 - l)] = make_double2(a.real(), a.imag());
+    }
+    for (int k = 0; k < 5; ++k) ca[k] = make_double2(0.0, 0.0);
+    const double2 *mup[5] = {(const double2 *)m[1], (const double2 *)m[2], (const double2 *)m[3],
+                             (const double2 *)m[4], (const double2 *)m[4]};
+    const double2 *nup[4] = {(const double2 *)y[3], (const double2 *)y[2], (const double2 *)y[1],
+                             (const double2 *)y[0]};
+    if ((rc = launch_adjoint_pass(*H.g, H.axis, mup, nup, pc, ca, nullptr, nst, ldp, g_dev, R, rb, s))) return rc;
+    // lambda_n = F_1^+ m_1, over lambda_{n+1} (read by the pass above)
+    const std::complex<double> a1 = std::conj(factor_coef(0, dt));
+    return stage_impl(H, m[1], 0, m[1], lambda, 0, 0, nst, ldp, a1.real(), a1.imag(), field, field_dev, D, s);
 }
 
 // Graph cache key for rsg_propagate.
@@ -746,11 +809,18 @@ extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, in
                         (hipStream_t)stream);
 }
 
+// Product-form steps (no mask): the segment store keeps, per step, the state
+// and its three stage outputs, and the adjoint needs three batches; Horner
+// form: the states only, and seven batches for the adjoint.
 static size_t control_ws(const Ham &H, int64_t nst, int64_t ldp, int64_t nsteps, int64_t ckpt) {
     const size_t bb = rounded(batch_bytes(nst, ldp, 16));
-    return rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 + rounded(sizeof(double) * (size_t)nst) +
-           bb + (size_t)std::max<int64_t>(ckpt, 1) * bb + std::max(step_ws(H, nst, ldp, RSG_C128), adjoint_ws(H, nst, ldp)) +
-           256;
+    const size_t head = rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 +
+                        rounded(sizeof(double) * (size_t)nst) + bb;
+    const size_t L = (size_t)std::max<int64_t>(ckpt, 1);
+    if (step_is_product(H, RSG_C128))
+        return head + 4 * L * bb + std::max(rounded(kb_workspace_bytes(H, nst)) + 256, adjoint_product_ws(H, nst, ldp)) +
+               256;
+    return head + L * bb + std::max(step_ws(H, nst, ldp, RSG_C128), adjoint_ws(H, nst, ldp)) + 256;
 }
 
 extern "C" size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
@@ -830,7 +900,9 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     double *gs = (double *)c.take(sizeof(double) * nsteps);
     (void)c.take(sizeof(double) * nst);
     void *lam = c.take(bb);
+    const bool product = step_is_product(*H, RSG_C128);
     char *states = (char *)c.take(std::max<int64_t>(ckpt_every, 1) * bbr);
+    char *ystore = product ? (char *)c.take(3 * std::max<int64_t>(ckpt_every, 1) * bbr) : nullptr;
     size_t rest = 0;
     void *sws = c.take_rest(&rest);
     if (!c.ok) {
@@ -841,6 +913,30 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     if ((rc = rsg_laser_field(coef, ncoef, T, dt, 0, nsteps, fields, stream))) return rc;
     if ((rc = launch_mul_axis(*H->g, H->axis, (const double2 *)psi_T, (double2 *)lam, nst, ldp, s))) return rc;
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    if (product) {
+        // per segment: recompute every step from the checkpoint keeping its
+        // stage outputs (state k in states slot k, k >= 1; the last step's
+        // output, the next checkpoint, goes to the unused slot 0), then the
+        // adjoint steps backward over the kept stages
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const int64_t s0 = seg * ckpt_every, s1 = std::min(nsteps, s0 + ckpt_every);
+            const char *ck = (const char *)ckpt_dev + (size_t)seg * bb;
+            auto st = [&](int64_t k) -> char * { return k == 0 ? const_cast<char *>(ck) : states + k * bbr; };
+            auto yk = [&](int64_t k, int j) -> char * { return ystore + (3 * k + j) * bbr; };
+            for (int64_t k = 0; k < s1 - s0; ++k) {
+                void *y[3] = {yk(k, 0), yk(k, 1), yk(k, 2)};
+                void *next = k + 1 < s1 - s0 ? (void *)st(k + 1) : (void *)states;
+                if ((rc = step_product(*H, st(k), y, next, nst, ldp, dt, 0.0, fields + s0 + k, sws, s))) return rc;
+            }
+            for (int64_t n = s1 - 1; n >= s0; --n) {
+                const int64_t k = n - s0;
+                const void *y[4] = {st(k), yk(k, 0), yk(k, 1), yk(k, 2)};
+                if ((rc = adjoint_product_impl(*H, y, lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws, rest, s)))
+                    return rc;
+            }
+        }
+        return rsg_laser_grad(gs, nsteps, T, dt, ncoef, grad_dev, stream);
+    }
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t s0 = seg * ckpt_every, s1 = std::min(nsteps, s0 + ckpt_every);
         // st(k) = psi_{s0 + k}, k = 0 .. s1 - s0 - 1: the checkpoint, then

@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(RB) k_adjoint_pass(XArgs r) {
             lr += r.ca[k].x * mu[k].x - r.ca[k].y * mu[k].y;
             li += r.ca[k].x * mu[k].y + r.ca[k].y * mu[k].x;
         }
-        r.lam[e] = make_double2(lr, li);
+        if (r.lam) r.lam[e] = make_double2(lr, li);
     }
     block_sum(re, im, red);
     if (threadIdx.x == 0) {

@@ -307,7 +307,8 @@ int launch_mul_axis(const Grid &g, int axis, const double2 *src, double2 *dst, i
 // One pass of the discrete adjoint over mu_0..mu_4 (H^k lambda_{n+1}) and
 // nu_0..nu_3 (H^m psi_n): *out = 2 Re sum_n h^3 sum_r sum_{l+m<=3}
 // pair_coef[4l+m] conj(mu_l) x_axis nu_m, and lam = sum_k lam_coef[k] mu_k
-// (lam may be mu_0: each point is read before it is written).
+// (lam may be mu_0: each point is read before it is written; lam = NULL
+// writes nothing).
 int launch_adjoint_pass(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
                         const double2 *pair_coef, const double2 *lam_coef, double2 *lam, int64_t nst,
                         int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s);
