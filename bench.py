@@ -373,12 +373,12 @@ def bench_mixed(args):
         report[name] = rows
         timing[name] = {"mixed_ms_per_step": tm * 1e3 / nsteps, "fp64_ms_per_step": tf * 1e3 / nsteps}
     tot = gg.np * nst
-    # mixed Horner stages per step: read complex128 psi and complex64 work
-    # buffers, write complex64 (last stage complex128): 128 B/pt.orb per step,
-    # 32 per launch, plus the FP32 potential (4 B/pt)
+    # mixed stages per step: psi (complex128) -> y1, y1 -> y2, y2 -> y3
+    # (complex64), then psi + c H y3 -> psi: 24 + 16 + 16 + 40 = 96 B/pt.orb
+    # per step, 24 per launch, plus the FP32 potential (4 B/pt)
     cnt = sum(c for _, c in kms)
     mean_ms = sum(m * c for m, c in kms) / cnt if cnt else None
-    mix_gbs = (32 * tot + 4 * gg.np) / (mean_ms * 1e-3) / 1e9 if mean_ms else None
+    mix_gbs = (24 * tot + 4 * gg.np) / (mean_ms * 1e-3) / 1e9 if mean_ms else None
     return {
         "metric": "mixed-precision orbital error vs the FP64 path", "value":
             report["white_noise"][-1]["orbital_rel_err_max"], "unit": "relative 2-norm",
@@ -387,7 +387,7 @@ def bench_mixed(args):
         "config": {"workload": "cube32_mixed", "np": gg.np, "nst": nst, "dt": dt},
         "roofline": {"bound": "hbm", "achieved": mix_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": mix_gbs / HBM_PEAK_GBS if mix_gbs else None, "traffic": None,
-                     "kernel": "k_stencil mixed (FP32 arithmetic, Horner stage)", "kernel_mean_ms": mean_ms,
+                     "kernel": "k_stencil mixed (FP32 arithmetic, Taylor stage)", "kernel_mean_ms": mean_ms,
                      "launches_timed": cnt,
                      "note": "2 MiB of orbitals stay in L2/MALL: a latency figure, not an HBM one"},
         "errors": report, "timing": timing,
@@ -540,10 +540,11 @@ def bench_mixed_sphere(args):
     16 wells with projectors): K Taylor(4) steps with FP32 Hamiltonian
     arithmetic on complex64 work buffers (FP64 accumulation), timed beside
     the FP64 path, and the orbital error of the mixed result against the
-    FP64 one after the K steps.  The roofline is the mixed Horner stage's:
-    per step it reads complex128 psi four times and complex64 work buffers
-    three times and writes three complex64 buffers and psi, 128 B/pt.orb,
-    plus the FP32 potential (4 B/pt) per stage."""
+    FP64 one after the K steps.  The roofline is the mixed stage's: per
+    step psi (complex128) is read by the first and the last stage, the
+    complex64 work buffers are read three times and written three times,
+    and psi is written once, 96 B/pt.orb, plus the FP32 potential (4 B/pt)
+    per stage."""
     import numpy as np
     import torch
 
@@ -581,7 +582,7 @@ def bench_mixed_sphere(args):
     mixed, el32, k32 = run("mixed")
     err = ((mixed - full).abs().pow(2).sum(1).sqrt() / full.abs().pow(2).sum(1).sqrt()).max().item()
     npo = gg.npoints * nst
-    alg = (128 * npo + 16 * gg.npoints) / 4.0
+    alg = (96 * npo + 16 * gg.npoints) / 4.0
     log(f"FP64 {el64 * 1e3 / steps:.3f} ms/step, mixed {el32 * 1e3 / steps:.3f} ms/step, error {err:.2e}")
     return {
         "metric": METRIC, "value": npo * 4 * steps / el32, "unit": UNIT, "n_gpus": 1, "steps": steps,
@@ -591,7 +592,7 @@ def bench_mixed_sphere(args):
                    "row_align": gg.align},
         "roofline": {"bound": "hbm", "achieved": alg / (k32 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stencil mixed (FP32 arithmetic, Horner stage)", "kernel_mean_ms": k32,
+                     "kernel": "k_stencil mixed (FP32 arithmetic, Taylor stage)", "kernel_mean_ms": k32,
                      "algorithmic_bytes_per_launch": alg},
         "fp64_value": npo * 4 * steps / el64, "fp64_stencil_ms": k64,
         "orbital_rel_err_vs_fp64": err,

@@ -44,7 +44,8 @@ const std::complex<double> *taylor4_roots() {
 }
 
 // Whether a step of this handle in dtype runs as the product of the four
-// linear factors of T4 (FP64 without an absorber mask) or in Horner form.
+// linear factors of T4 (FP64 without an absorber mask) or as 1 + z times
+// the product of its cubic tail's factors (mixed precision, masked).
 bool step_is_product(const Ham &H, int32_t dtype) { return dtype == RSG_C128 && !H.mask; }
 
 // ------------------------------------------------------------------ errors
@@ -199,7 +200,7 @@ int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *o
     a.field_dev = field_dev;
     a.cre = cre;
     a.cim = cim;
-    a.first = in == base && in_t == 0;
+    a.first = in == base;
     a.mask = mask;
     rc = launch_stencil(H, a, H.tile_for(nst, compute), s);
     if (rc) return rc;
@@ -231,17 +232,47 @@ int step_product(const Ham &H, const void *psi, void *const y[3], void *psi_out,
     return RSG_OK;
 }
 
-// Taylor(4) step psi_out <- T4(-i dt H) psi.
+// Roots s_1..s_3 of the cubic (T4(z) - 1) / z = 1 + z/2 + z^2/6 + z^3/24
+// (of z^3 + 4 z^2 + 12 z + 24), the real root first; same method as the
+// quartic's.
+const std::complex<double> *taylor4_tail_roots() {
+    static std::complex<double> r[3];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        auto p = [](std::complex<double> z) { return ((z + 4.0) * z + 12.0) * z + 24.0; };
+        auto dp = [](std::complex<double> z) { return (3.0 * z + 8.0) * z + 12.0; };
+        const std::complex<double> w(0.4, 0.9);
+        for (int k = 0; k < 3; ++k) r[k] = std::pow(w, k);
+        for (int it = 0; it < 500; ++it)
+            for (int k = 0; k < 3; ++k) {
+                std::complex<double> d = 1.0;
+                for (int j = 0; j < 3; ++j)
+                    if (j != k) d *= r[k] - r[j];
+                r[k] -= p(r[k]) / d;
+            }
+        for (int k = 0; k < 3; ++k)
+            for (int it = 0; it < 3; ++it) r[k] -= p(r[k]) / dp(r[k]);
+        std::sort(r, r + 3, [](const std::complex<double> &a, const std::complex<double> &b) {
+            return std::abs(a.imag()) != std::abs(b.imag()) ? std::abs(a.imag()) < std::abs(b.imag())
+                                                            : a.imag() > b.imag();
+        });
+    });
+    return r;
+}
+
+// Taylor(4) step psi_out <- T4(-i dt H) psi, z = -i dt H.
 //  - FP64 without a mask: T4(z) = prod_k (1 - z / r_k) over its roots, so
 //    the step is four stages y <- y + (i dt / r_k) H y.  Each stage reads
 //    only its input (whose centre value is its own base term) and writes
 //    one buffer: 32 B per point and orbital, against 48 for a Horner stage
 //    that also reads psi.  The factor moduli stay below 2.2 up to the
 //    stability limit dt |lambda| = 2 sqrt 2.
-//  - Mixed precision (complex64 work buffers: psi must enter every stage in
-//    FP64) and the masked step (the mask is fused into a stage with a
-//    separate base) use Horner form: y4 = psi, y_{k-1} = psi + (-i dt / k)
-//    H y_k, psi_out <- y0, every stage reading its base from psi.
+//  - Mixed precision and the masked step: T4(z) = 1 + z prod_j (1 - z/s_j)
+//    over the roots of the cubic tail.  Three stages y <- y + (i dt / s_j)
+//    H y from psi, then psi_out = psi + (-i dt) H y: psi enters only the
+//    first and the last stage, so with complex64 work buffers psi itself
+//    is carried in FP64 (the last stage adds the FP32 correction to it),
+//    and the mask is applied by the last stage, which has psi as its base.
 // Work buffers alternate; only the last stage writes psi_out, which may be
 // psi itself (each output point reads only its own input value).
 int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t ldp, int32_t dtype,
@@ -262,10 +293,17 @@ int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t
         void *y[3] = {w1, w2, w1};
         return step_product(H, psi, y, psi_out, nst, ldp, dt, field, field_dev, D, s);
     }
-    if ((rc = stage_impl(H, psi, 0, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 4.0, field, field_dev, D, s))) return rc;
-    if ((rc = stage_impl(H, w1, wt, psi, w2, wt, cmp, nst, ldp, 0.0, -dt / 3.0, field, field_dev, D, s))) return rc;
-    if ((rc = stage_impl(H, w2, wt, psi, w1, wt, cmp, nst, ldp, 0.0, -dt / 2.0, field, field_dev, D, s))) return rc;
-    // the last stage applies the absorber mask, if any: psi_out = M (psi + c H y1)
+    const std::complex<double> *sr = taylor4_tail_roots();
+    const void *in[3] = {psi, w1, w2};
+    const int in_t[3] = {0, wt, wt};
+    void *out[3] = {w1, w2, w1};
+    for (int j = 0; j < 3; ++j) {
+        const std::complex<double> cj = std::complex<double>(0.0, dt) / sr[j];  // i dt / s_j
+        if ((rc = stage_impl(H, in[j], in_t[j], in[j], out[j], wt, cmp, nst, ldp, cj.real(), cj.imag(), field,
+                             field_dev, D, s)))
+            return rc;
+    }
+    // psi_out = M (psi + (-i dt) H y3), the mask if any
     return stage_impl(H, w1, wt, psi, psi_out, 0, cmp, nst, ldp, 0.0, -dt, field, field_dev, D, s, H.mask);
 }
 
@@ -810,8 +848,8 @@ extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, in
 }
 
 // Product-form steps (no mask): the segment store keeps, per step, the state
-// and its three stage outputs, and the adjoint needs three batches; Horner
-// form: the states only, and seven batches for the adjoint.
+// and its three stage outputs, and the adjoint needs three batches; masked
+// handles: the states only, and seven batches for the power-form adjoint.
 static size_t control_ws(const Ham &H, int64_t nst, int64_t ldp, int64_t nsteps, int64_t ckpt) {
     const size_t bb = rounded(batch_bytes(nst, ldp, 16));
     const size_t head = rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 +
@@ -1039,8 +1077,8 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         RSG_CHECK_HIP(hipEventCreate(&e0));
         RSG_CHECK_HIP(hipEventCreate(&e1));
         // the two kinds of stage of a step: the first (reads psi once, its
-        // centre tap is the base) and the others (read a work buffer, and
-        // psi in Horner form, and write the other work buffer)
+        // centre tap is the base) and the middle ones (read a work buffer,
+        // the same base, and write the other work buffer)
         StageArgs first;
         first.in = psi;
         first.base = psi;
@@ -1057,12 +1095,9 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         rest.in = w1;
         rest.in_t = wt;
         rest.out = w2;
-        rest.first = false;
-        if (step_is_product(*H, dtype)) {
-            // a product-form step: every stage reads only its input
-            rest.base = w1;
-            rest.first = true;
-        }
+        // the middle stages of every step form read only their input
+        rest.base = w1;
+        rest.first = true;
         int err = RSG_OK;
         // the work buffer read by the other stages holds a real stage output
         if ((rc = launch_stencil(*H, first, default_shape(*H->g, nst, cmp), s))) {

@@ -612,16 +612,16 @@ int launch_fp64(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
 }
 
 // Mixed path: FP32 arithmetic; the first stage reads complex128 psi and
-// writes complex64, the middle stages complex64 to complex64, the last
-// complex64 to complex128 with the complex128 base.
+// writes complex64, the middle stages complex64 to complex64 (each its own
+// base), the last complex64 to complex128 with the complex128 base psi.
 template <int TX, int TY, int D>
 int launch_fp32(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
     constexpr int NT = TX * TY;
     if (a.mode != 1) return RSG_EUNSUPPORTED;
     if (a.in_t == 0 && a.out_t == 1 && a.first)
         k_stencil<TX, TY, D, double2, float, float2, 1, true><<<nb, NT, 0, s>>>(p);
-    else if (a.in_t == 1 && a.out_t == 1 && !a.first)
-        k_stencil<TX, TY, D, float2, float, float2, 1, false><<<nb, NT, 0, s>>>(p);
+    else if (a.in_t == 1 && a.out_t == 1 && a.first)
+        k_stencil<TX, TY, D, float2, float, float2, 1, true><<<nb, NT, 0, s>>>(p);
     else if (a.in_t == 1 && a.out_t == 0 && !a.first && a.mask)
         k_stencil<TX, TY, D, float2, float, double2, 1, false, true><<<nb, NT, 0, s>>>(p);
     else if (a.in_t == 1 && a.out_t == 0 && !a.first)
