@@ -168,7 +168,8 @@ int rsg_ham_destroy(rsg_ham_t H);
  * psi <- M(r) psi, the part (1 - M) psi leaving the simulation box.
  * mask_dev: device [np] float64, real values (normally in [0, 1]); the
  * handle copies it.  NULL removes the mask.  The multiply is fused into the
- * last Horner stage and its projector scatter.  The charge that leaves is
+ * last stage of the step (psi + (-i dt) H y, see rsg_propagate_step) and
+ * its projector scatter.  The charge that leaves is
  * the drop of rsg_norm2 across a step.  rsg_adjoint_step, the control entry
  * points and rsg_batch_create reject a masked Hamiltonian
  * (RSG_EUNSUPPORTED).  Errors: RSG_EINVAL, RSG_EHIP. */
@@ -191,8 +192,11 @@ int rsg_hpsi(rsg_ham_t H, const void *psi, void *hpsi, int64_t nst, int64_t ldp,
  * complex128.  dtype RSG_C128 or RSG_C64_MIXED.  ws: RSG_OP_STEP bytes.
  * RSG_C128 without an absorber mask evaluates the polynomial as the product
  * of its four linear factors (1 + (i dt / r_k) H), r_k its roots: four
- * stages that each read only their input; RSG_C64_MIXED and a masked step
- * use Horner form, whose stages also read psi. */
+ * stages that each read only their input.  RSG_C64_MIXED and a masked step
+ * use T4(z) = 1 + z prod_j (1 - z / s_j), s_j the roots of the cubic
+ * 1 + z/2 + z^2/6 + z^3/24: three such stages from psi into complex64
+ * (mixed) or complex128 work buffers, then psi_out = psi + (-i dt) H y, so
+ * psi is read only by the first and the last stage and stays FP64. */
 int rsg_propagate_step(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, int32_t dtype, double dt,
                        double field, void *ws, size_t ws_bytes, void *stream);
 
@@ -284,7 +288,7 @@ int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, double
  * runs back through the adjoint factors, m_4 = lambda_{n+1}, m_{k-1} =
  * (1 + conj(a_k) H) m_k, lambda_n = m_0, and dJ/dE_n = 2 Re sum_k a_k
  * <m_k| x_axis |y_{k-1}>; equal in exact arithmetic to the rsg_adjoint_step
- * formulas, which the Horner-form (masked) steps use. */
+ * formulas. */
 int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ldp, double dt,
                          int64_t nsteps, const double *coef_dev, int32_t ncoef,
                          int64_t ckpt_every, const void *ckpt_dev, double *grad_dev,
@@ -321,10 +325,8 @@ int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_tile *t);
 int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
 
 /* Tile autotuner for the Taylor(4) step on psi (device [nst][ldp], left
- * unchanged).  Phase 1 times one of the later Taylor stages (reads a work
- * buffer, and psi in Horner form, and writes the other work buffer) as the
- * step of this dtype runs it (product form for RSG_C128 without a mask,
- * Horner form otherwise) for every compiled tile
+ * unchanged).  Phase 1 times one of the middle Taylor stages (reads a work
+ * buffer, writes the other) for every compiled tile
  * shape, z-chunk lengths {whole, 64, 32, and 16, 8, 4, 2, 1 when the batch
  * has few tiles}, PT {0, 1}, BO {0, 1, 2, 4} and ZM {0, 1} with HIP events (best of
  * reps launches after a warm-up launch; a stage under 0.2 ms is timed as the

@@ -264,8 +264,8 @@ const std::complex<double> *taylor4_tail_roots() {
 //  - FP64 without a mask: T4(z) = prod_k (1 - z / r_k) over its roots, so
 //    the step is four stages y <- y + (i dt / r_k) H y.  Each stage reads
 //    only its input (whose centre value is its own base term) and writes
-//    one buffer: 32 B per point and orbital, against 48 for a Horner stage
-//    that also reads psi.  The factor moduli stay below 2.2 up to the
+//    one buffer: 32 B per point and orbital, against 48 for a stage that
+//    also reads psi (Horner form).  The factor moduli stay below 2.2 up to the
 //    stability limit dt |lambda| = 2 sqrt 2.
 //  - Mixed precision and the masked step: T4(z) = 1 + z prod_j (1 - z/s_j)
 //    over the roots of the cubic tail.  Three stages y <- y + (i dt / s_j)

@@ -159,7 +159,7 @@ struct StageArgs {
     const void *base = nullptr;
     void *out = nullptr;
     int in_t = 0, out_t = 0, compute = 0, mode = 0;
-    bool first = false;  // base == in (a product-form stage, or the first Horner stage)
+    bool first = false;  // base == in (every stage but the last of a mixed or masked step)
     const double *mask = nullptr;  // mode 1: out = mask * (base + c H in)
     int64_t nst = 0, ldp = 0;
     double field = 0;
@@ -289,7 +289,8 @@ int hpsi_impl(const Ham &H, const void *in, void *out, int64_t nst, int64_t ldp,
               const double *field_dev, void *D, hipStream_t s);
 // The four roots of the Taylor(4) polynomial sum_{k<=4} z^k/k!, largest
 // modulus first ({re, im} pairs), and whether a step of this handle in dtype
-// runs as the product of their linear factors (else in Horner form).
+// runs as the product of their linear factors (else as 1 + z times the
+// product of the cubic tail's factors).
 const std::complex<double> *taylor4_roots();
 bool step_is_product(const Ham &H, int32_t dtype);
 
