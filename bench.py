@@ -171,7 +171,7 @@ def bench_sphere(args):
         rsg.set_tile(gh, nst, B, TX, TY, ZC, PD, PT, BO, ZM)
         tile = rsg.get_tile(gh, nst)
     elif not args.no_autotune:
-        tile, tile_ms = rsg.autotune(gh, psi, reps=2)
+        tile, tile_ms = rsg.autotune(gh, psi, reps=4)
         log(f"autotuned tile {tile}: {tile_ms:.3f} ms of stencil work per step")
     if tile is None:
         tile = rsg.get_tile(gh, nst)
