@@ -847,18 +847,18 @@ extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, in
                         (hipStream_t)stream);
 }
 
-// Product-form steps (no mask): the segment store keeps, per step, the state
-// and its three stage outputs, and the adjoint needs three batches; masked
-// handles: the states only, and seven batches for the power-form adjoint.
+// The control entry points take handles without mask or complex scaling,
+// whose steps run in product form: the segment store keeps, per step, the
+// state and its three stage outputs, and the adjoint needs three batches.
 static size_t control_ws(const Ham &H, int64_t nst, int64_t ldp, int64_t nsteps, int64_t ckpt) {
     const size_t bb = rounded(batch_bytes(nst, ldp, 16));
     const size_t head = rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 +
                         rounded(sizeof(double) * (size_t)nst) + bb;
     const size_t L = (size_t)std::max<int64_t>(ckpt, 1);
-    if (step_is_product(H, RSG_C128))
-        return head + 4 * L * bb + std::max(rounded(kb_workspace_bytes(H, nst)) + 256, adjoint_product_ws(H, nst, ldp)) +
-               256;
-    return head + L * bb + std::max(step_ws(H, nst, ldp, RSG_C128), adjoint_ws(H, nst, ldp)) + 256;
+    return head + 4 * L * bb +
+           std::max({step_ws(H, nst, ldp, RSG_C128), rounded(kb_workspace_bytes(H, nst)) + 256,
+                     adjoint_product_ws(H, nst, ldp)}) +
+           256;
 }
 
 extern "C" size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
@@ -938,9 +938,8 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     double *gs = (double *)c.take(sizeof(double) * nsteps);
     (void)c.take(sizeof(double) * nst);
     void *lam = c.take(bb);
-    const bool product = step_is_product(*H, RSG_C128);
     char *states = (char *)c.take(std::max<int64_t>(ckpt_every, 1) * bbr);
-    char *ystore = product ? (char *)c.take(3 * std::max<int64_t>(ckpt_every, 1) * bbr) : nullptr;
+    char *ystore = (char *)c.take(3 * std::max<int64_t>(ckpt_every, 1) * bbr);
     size_t rest = 0;
     void *sws = c.take_rest(&rest);
     if (!c.ok) {
@@ -951,42 +950,24 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     if ((rc = rsg_laser_field(coef, ncoef, T, dt, 0, nsteps, fields, stream))) return rc;
     if ((rc = launch_mul_axis(*H->g, H->axis, (const double2 *)psi_T, (double2 *)lam, nst, ldp, s))) return rc;
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
-    if (product) {
-        // per segment: recompute every step from the checkpoint keeping its
-        // stage outputs (state k in states slot k, k >= 1; the last step's
-        // output, the next checkpoint, goes to the unused slot 0), then the
-        // adjoint steps backward over the kept stages
-        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-            const int64_t s0 = seg * ckpt_every, s1 = std::min(nsteps, s0 + ckpt_every);
-            const char *ck = (const char *)ckpt_dev + (size_t)seg * bb;
-            auto st = [&](int64_t k) -> char * { return k == 0 ? const_cast<char *>(ck) : states + k * bbr; };
-            auto yk = [&](int64_t k, int j) -> char * { return ystore + (3 * k + j) * bbr; };
-            for (int64_t k = 0; k < s1 - s0; ++k) {
-                void *y[3] = {yk(k, 0), yk(k, 1), yk(k, 2)};
-                void *next = k + 1 < s1 - s0 ? (void *)st(k + 1) : (void *)states;
-                if ((rc = step_product(*H, st(k), y, next, nst, ldp, dt, 0.0, fields + s0 + k, sws, s))) return rc;
-            }
-            for (int64_t n = s1 - 1; n >= s0; --n) {
-                const int64_t k = n - s0;
-                const void *y[4] = {st(k), yk(k, 0), yk(k, 1), yk(k, 2)};
-                if ((rc = adjoint_product_impl(*H, y, lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws, rest, s)))
-                    return rc;
-            }
-        }
-        return rsg_laser_grad(gs, nsteps, T, dt, ncoef, grad_dev, stream);
-    }
+    // per segment: recompute every step from the checkpoint keeping its
+    // stage outputs (state k in states slot k, k >= 1; the last step's
+    // output, the next checkpoint, goes to the unused slot 0), then the
+    // adjoint steps backward over the kept stages
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t s0 = seg * ckpt_every, s1 = std::min(nsteps, s0 + ckpt_every);
-        // st(k) = psi_{s0 + k}, k = 0 .. s1 - s0 - 1: the checkpoint, then
-        // states recomputed out of place from it
         const char *ck = (const char *)ckpt_dev + (size_t)seg * bb;
-        auto st = [&](int64_t k) -> const char * { return k == 0 ? ck : states + k * bbr; };
-        for (int64_t k = 1; k < s1 - s0; ++k)
-            if ((rc = step_impl(*H, st(k - 1), states + k * bbr, nst, ldp, RSG_C128, dt, 0.0,
-                                fields + s0 + k - 1, sws, rest, s)))
-                return rc;
+        auto st = [&](int64_t k) -> char * { return k == 0 ? const_cast<char *>(ck) : states + k * bbr; };
+        auto yk = [&](int64_t k, int j) -> char * { return ystore + (3 * k + j) * bbr; };
+        for (int64_t k = 0; k < s1 - s0; ++k) {
+            void *y[3] = {yk(k, 0), yk(k, 1), yk(k, 2)};
+            void *next = k + 1 < s1 - s0 ? (void *)st(k + 1) : (void *)states;
+            if ((rc = step_product(*H, st(k), y, next, nst, ldp, dt, 0.0, fields + s0 + k, sws, s))) return rc;
+        }
         for (int64_t n = s1 - 1; n >= s0; --n) {
-            if ((rc = adjoint_impl(*H, st(n - s0), lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws, rest, s)))
+            const int64_t k = n - s0;
+            const void *y[4] = {st(k), yk(k, 0), yk(k, 1), yk(k, 2)};
+            if ((rc = adjoint_product_impl(*H, y, lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws, rest, s)))
                 return rc;
         }
     }
