@@ -87,6 +87,35 @@ def test_taylor_steps_cube32():
     assert orbital_rel_err(s.from_gpu(psi), ref, 4) <= TOL
 
 
+def test_taylor_steps_at_the_stability_edge():
+    """Steps with dt |lambda| up to 2.79, just inside the Taylor(4)
+    stability limit 2 sqrt 2 (white noise holds the Nyquist modes: kinetic
+    108.4 at h = 0.3 plus V <= 7.6 on the 16^3 cube, dt = 0.024): the
+    product-form stages, whose factors reach their largest moduli there,
+    still equal the oracle's power series, for the plain step, the masked
+    step and in FP32 (mixed) to its own bar."""
+    s = System(0.3, n=16, potential="harmonic", nst=3, seed=17)
+    dt = 0.024
+    ref = oracle.propagate(s.oh, s.psi, dt, 3)
+    psi = s.to_gpu(s.psi)
+    for _ in range(3):
+        rsg().propagate_step(s.gh, psi, dt)
+    assert orbital_rel_err(s.from_gpu(psi), ref, 3) <= TOL
+    mixed = s.to_gpu(s.psi)
+    for _ in range(3):
+        rsg().propagate_step(s.gh, mixed, dt, dtype="mixed")
+    assert orbital_rel_err(s.from_gpu(mixed), ref, 3) <= 1e-5
+    # a mask of ones leaves the step unchanged, through the masked step form
+    s.gh.set_mask(torch.ones(s.og.np, dtype=torch.float64, device="cuda"))
+    try:
+        x = s.to_gpu(s.psi)
+        for _ in range(3):
+            rsg().propagate_step(s.gh, x, dt)
+        assert orbital_rel_err(s.from_gpu(x), ref, 3) <= TOL
+    finally:
+        s.gh.set_mask(None)
+
+
 def test_cube32_sequence_autotuned_in_graph():
     """The 32^3 harmonic system as the benchmark runs it: the autotuner's
     tile, 10 hpsi calls and 10 Taylor(4) steps captured in one graph.  Two
