@@ -267,6 +267,14 @@ int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, 
 size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
                                    int64_t ckpt_every);
 
+/* The least scratch bytes the control entry points accept: the segment
+ * store holds the states only (ckpt_every batches plus three), and each
+ * adjoint step recomputes its three stage outputs, so the backward pass
+ * runs 3 more stencil stages per step (about 25 % more stencil work).  Any
+ * workspace of at least rsg_control_workspace_bytes takes the faster path. */
+size_t rsg_control_workspace_bytes_min(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
+                                       int64_t ckpt_every);
+
 /* Forward pass of the control problem: nsteps Taylor(4) steps of psi (in:
  * psi(0), out: psi(T), T = nsteps*dt) under the field of coef_dev, storing
  * psi at every step that is a multiple of ckpt_every (step 0 included) in

@@ -68,6 +68,7 @@ def _load():
         "rsg_laser_grad": (C.c_int, [vp, i64, dbl, dbl, i32, vp, vp]),
         "rsg_adjoint_step": (C.c_int, [vp, vp, vp, i64, i64, dbl, dbl, vp, vp, sz, vp]),
         "rsg_control_workspace_bytes": (sz, [vp, i64, i64, i64, i64]),
+        "rsg_control_workspace_bytes_min": (sz, [vp, i64, i64, i64, i64]),
         "rsg_reduce_workspace_bytes": (sz, [vp, i64]),
         "rsg_control_forward": (C.c_int, [vp, vp, i64, i64, dbl, i64, vp, i32, i64, vp, vp, vp,
                                           sz, vp]),
@@ -511,14 +512,19 @@ def laser_grad(g: torch.Tensor, T: float, dt: float, ncoef: int) -> torch.Tensor
     return out
 
 
-def _control_ws(ham, n, ldp, nsteps, ckpt, device):
-    return _ws(int(_lib.rsg_control_workspace_bytes(ham._h, n, ldp, nsteps, ckpt)), device)
+def _control_ws(ham, n, ldp, nsteps, ckpt, device, workspace="full"):
+    if workspace not in ("full", "min"):
+        raise ValueError("workspace must be 'full' or 'min'")
+    fn = _lib.rsg_control_workspace_bytes if workspace == "full" else _lib.rsg_control_workspace_bytes_min
+    return _ws(int(fn(ham._h, n, ldp, nsteps, ckpt)), device)
 
 
 def control_forward(ham: Hamiltonian, psi: torch.Tensor, dt: float, nsteps: int,
-                    coef: torch.Tensor, ckpt_every: int, keep_checkpoints: bool = True):
+                    coef: torch.Tensor, ckpt_every: int, keep_checkpoints: bool = True,
+                    workspace: str = "full"):
     """Propagate psi in place to T = nsteps*dt under the sine-series field.
-    Returns (J as CUDA float64 [1], checkpoint store or None)."""
+    Returns (J as CUDA float64 [1], checkpoint store or None).  workspace:
+    "full" or "min" scratch size (the forward pass needs only the minimum)."""
     _batch(psi, "psi", ham.grid.np)
     n, ldp = psi.shape[0], psi.shape[1]
     c = coef.to(torch.float64).contiguous()
@@ -526,7 +532,7 @@ def control_forward(ham: Hamiltonian, psi: torch.Tensor, dt: float, nsteps: int,
     ck = (torch.empty((nck, n, ldp), dtype=torch.complex128, device=psi.device)
           if keep_checkpoints else None)
     J = torch.zeros(1, dtype=torch.float64, device=psi.device)
-    ws = _control_ws(ham, n, ldp, nsteps, ckpt_every, psi.device)
+    ws = _control_ws(ham, n, ldp, nsteps, ckpt_every, psi.device, workspace)
     _check(_lib.rsg_control_forward(ham._h, _ptr(psi), n, ldp, float(dt), int(nsteps), _ptr(c),
                                     c.numel(), int(ckpt_every), _ptr(ck), _ptr(J), _ptr(ws),
                                     ws.numel(), _stream()))
@@ -534,8 +540,11 @@ def control_forward(ham: Hamiltonian, psi: torch.Tensor, dt: float, nsteps: int,
 
 
 def control_backward(ham: Hamiltonian, psi_T: torch.Tensor, dt: float, nsteps: int,
-                     coef: torch.Tensor, ckpt_every: int, ckpt: torch.Tensor):
-    """(dJ/dc [ncoef], dJ/dE_n [nsteps]) by checkpointed discrete adjoint."""
+                     coef: torch.Tensor, ckpt_every: int, ckpt: torch.Tensor, workspace: str = "full"):
+    """(dJ/dc [ncoef], dJ/dE_n [nsteps]) by checkpointed discrete adjoint.
+    workspace "full" keeps every step's stage outputs of a segment (4 orbital
+    batches per step); "min" keeps the states only and recomputes the stage
+    outputs in each adjoint step (same results, more stencil work)."""
     _batch(psi_T, "psi_T", ham.grid.np)
     n, ldp = psi_T.shape[0], psi_T.shape[1]
     if ckpt is None or tuple(ckpt.shape) != (nsteps // ckpt_every + 1, n, ldp):
@@ -543,7 +552,7 @@ def control_backward(ham: Hamiltonian, psi_T: torch.Tensor, dt: float, nsteps: i
     c = coef.to(torch.float64).contiguous()
     grad = torch.zeros(c.numel(), dtype=torch.float64, device=psi_T.device)
     gs = torch.zeros(int(nsteps), dtype=torch.float64, device=psi_T.device)
-    ws = _control_ws(ham, n, ldp, nsteps, ckpt_every, psi_T.device)
+    ws = _control_ws(ham, n, ldp, nsteps, ckpt_every, psi_T.device, workspace)
     _check(_lib.rsg_control_backward(ham._h, _ptr(psi_T), n, ldp, float(dt), int(nsteps), _ptr(c),
                                      c.numel(), int(ckpt_every), _ptr(ckpt), _ptr(grad), _ptr(gs),
                                      _ptr(ws), ws.numel(), _stream()))

@@ -218,12 +218,13 @@ size_t step_ws(const Ham &H, int64_t nst, int64_t ldp, int32_t dtype) {
 std::complex<double> factor_coef(int k, double dt) { return std::complex<double>(0.0, dt) / taylor4_roots()[k]; }
 
 // Product-form step y[0] = F1 psi, y[1] = F2 y[0], y[2] = F3 y[1], psi_out =
-// F4 y[2], F_k = 1 + a_k H; y[2] may alias y[0].  D: projector workspace.
+// F4 y[2], F_k = 1 + a_k H; y[2] may alias y[0]; psi_out = NULL stops after
+// the three stage outputs.  D: projector workspace.
 int step_product(const Ham &H, const void *psi, void *const y[3], void *psi_out, int64_t nst, int64_t ldp,
                  double dt, double field, const double *field_dev, void *D, hipStream_t s) {
     const void *in[4] = {psi, y[0], y[1], y[2]};
     void *out[4] = {y[0], y[1], y[2], psi_out};
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < (psi_out ? 4 : 3); ++k) {
         const std::complex<double> c = factor_coef(k, dt);
         const int rc = stage_impl(H, in[k], 0, in[k], out[k], 0, 0, nst, ldp, c.real(), c.imag(), field, field_dev,
                                   D, s);
@@ -848,23 +849,41 @@ extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, in
 }
 
 // The control entry points take handles without mask or complex scaling,
-// whose steps run in product form: the segment store keeps, per step, the
-// state and its three stage outputs, and the adjoint needs three batches.
-static size_t control_ws(const Ham &H, int64_t nst, int64_t ldp, int64_t nsteps, int64_t ckpt) {
-    const size_t bb = rounded(batch_bytes(nst, ldp, 16));
-    const size_t head = rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 +
-                        rounded(sizeof(double) * (size_t)nst) + bb;
-    const size_t L = (size_t)std::max<int64_t>(ckpt, 1);
-    return head + 4 * L * bb +
-           std::max({step_ws(H, nst, ldp, RSG_C128), rounded(kb_workspace_bytes(H, nst)) + 256,
+// whose steps run in product form.  Full workspace: the segment store keeps,
+// per step, the state and its three stage outputs (the adjoint reads them).
+// Minimum workspace: the states only, plus three batches into which each
+// adjoint step recomputes its stage outputs.  Both need three batches for
+// the adjoint itself.
+static size_t control_ws_head(int64_t nst, int64_t ldp, int64_t nsteps) {
+    return rounded(sizeof(double) * (size_t)std::max<int64_t>(nsteps, 1)) * 2 + rounded(sizeof(double) * (size_t)nst) +
+           rounded(batch_bytes(nst, ldp, 16));
+}
+static size_t control_ws_tail(const Ham &H, int64_t nst, int64_t ldp) {
+    return std::max({step_ws(H, nst, ldp, RSG_C128), rounded(kb_workspace_bytes(H, nst)) + 256,
                      adjoint_product_ws(H, nst, ldp)}) +
            256;
+}
+static size_t control_ws(const Ham &H, int64_t nst, int64_t ldp, int64_t nsteps, int64_t ckpt) {
+    const size_t bb = rounded(batch_bytes(nst, ldp, 16));
+    return control_ws_head(nst, ldp, nsteps) + 4 * (size_t)std::max<int64_t>(ckpt, 1) * bb +
+           control_ws_tail(H, nst, ldp);
+}
+static size_t control_ws_min(const Ham &H, int64_t nst, int64_t ldp, int64_t nsteps, int64_t ckpt) {
+    const size_t bb = rounded(batch_bytes(nst, ldp, 16));
+    return control_ws_head(nst, ldp, nsteps) + ((size_t)std::max<int64_t>(ckpt, 1) + 3) * bb +
+           control_ws_tail(H, nst, ldp);
 }
 
 extern "C" size_t rsg_control_workspace_bytes(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
                                               int64_t ckpt_every) {
     if (!H || nst < 0 || ldp < 1 || nsteps < 0 || ckpt_every < 1) return 0;
     return control_ws(*H, nst, ldp, nsteps, ckpt_every);
+}
+
+extern "C" size_t rsg_control_workspace_bytes_min(rsg_ham_t H, int64_t nst, int64_t ldp, int64_t nsteps,
+                                                  int64_t ckpt_every) {
+    if (!H || nst < 0 || ldp < 1 || nsteps < 0 || ckpt_every < 1) return 0;
+    return control_ws_min(*H, nst, ldp, nsteps, ckpt_every);
 }
 
 static int check_control(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, double dt, int64_t nsteps,
@@ -878,8 +897,8 @@ static int check_control(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp,
     RSG_REQUIRE(nst > 0 && nsteps > 0 && dt > 0 && std::isfinite(dt), RSG_EINVAL, "%s: need nst, nsteps, dt > 0", who);
     RSG_REQUIRE(ncoef >= 0 && (ncoef == 0 || coef), RSG_EINVAL, "%s: bad coefficient array", who);
     RSG_REQUIRE(ckpt >= 1, RSG_EINVAL, "%s: ckpt_every must be >= 1", who);
-    RSG_REQUIRE(ws_bytes >= control_ws(*H, nst, ldp, nsteps, ckpt) - 256, RSG_ENOMEM,
-                "%s: workspace too small (%zu < %zu)", who, ws_bytes, control_ws(*H, nst, ldp, nsteps, ckpt));
+    RSG_REQUIRE(ws_bytes >= control_ws_min(*H, nst, ldp, nsteps, ckpt) - 256, RSG_ENOMEM,
+                "%s: workspace too small (%zu < %zu)", who, ws_bytes, control_ws_min(*H, nst, ldp, nsteps, ckpt));
     return RSG_OK;
 }
 
@@ -939,7 +958,10 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
     (void)c.take(sizeof(double) * nst);
     void *lam = c.take(bb);
     char *states = (char *)c.take(std::max<int64_t>(ckpt_every, 1) * bbr);
-    char *ystore = (char *)c.take(3 * std::max<int64_t>(ckpt_every, 1) * bbr);
+    // the full workspace keeps every step's stage outputs; the minimum one
+    // has room for one step's, recomputed by each adjoint step
+    const bool keep = ws_bytes + 256 >= control_ws(*H, nst, ldp, nsteps, ckpt_every);
+    char *ystore = (char *)c.take((keep ? 3 * std::max<int64_t>(ckpt_every, 1) : 3) * bbr);
     size_t rest = 0;
     void *sws = c.take_rest(&rest);
     if (!c.ok) {
@@ -959,14 +981,20 @@ extern "C" int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst,
         const char *ck = (const char *)ckpt_dev + (size_t)seg * bb;
         auto st = [&](int64_t k) -> char * { return k == 0 ? const_cast<char *>(ck) : states + k * bbr; };
         auto yk = [&](int64_t k, int j) -> char * { return ystore + (3 * k + j) * bbr; };
-        for (int64_t k = 0; k < s1 - s0; ++k) {
-            void *y[3] = {yk(k, 0), yk(k, 1), yk(k, 2)};
+        for (int64_t k = 0; k < (keep ? s1 - s0 : s1 - s0 - 1); ++k) {
+            void *y[3] = {yk(keep ? k : 0, 0), yk(keep ? k : 0, 1), yk(keep ? k : 0, 2)};
             void *next = k + 1 < s1 - s0 ? (void *)st(k + 1) : (void *)states;
             if ((rc = step_product(*H, st(k), y, next, nst, ldp, dt, 0.0, fields + s0 + k, sws, s))) return rc;
         }
         for (int64_t n = s1 - 1; n >= s0; --n) {
             const int64_t k = n - s0;
-            const void *y[4] = {st(k), yk(k, 0), yk(k, 1), yk(k, 2)};
+            if (!keep) {
+                // this step's stage outputs again, into the one-step store
+                void *y3[3] = {yk(0, 0), yk(0, 1), yk(0, 2)};
+                if ((rc = step_product(*H, st(k), y3, nullptr, nst, ldp, dt, 0.0, fields + n, sws, s))) return rc;
+            }
+            const int64_t kk = keep ? k : 0;
+            const void *y[4] = {st(k), yk(kk, 0), yk(kk, 1), yk(kk, 2)};
             if ((rc = adjoint_product_impl(*H, y, lam, nst, ldp, dt, 0.0, fields + n, gs + n, sws, rest, s)))
                 return rc;
         }

@@ -246,6 +246,30 @@ def test_control_gradient_matches_oracle():
     np.testing.assert_allclose(grad.cpu().numpy(), g_ref, rtol=1e-10, atol=1e-12 * np.abs(g_ref).max())
 
 
+def test_control_gradient_minimum_workspace():
+    """With the minimum workspace the backward pass recomputes each step's
+    stage outputs instead of keeping them: the same kernels on the same
+    inputs, so the gradient is bit for bit the full-workspace one (and the
+    oracle's to 1e-10)."""
+    s = System(0.4, n=14, potential="wells", natoms=0, nst=2, seed=5, dipole_axis=2,
+               well_box=1.5, orbitals="packets", packet_box=1.0)
+    coef = synth.laser_coefficients(5, 6, sigma=0.3)
+    dt, nsteps, ck = 0.05, 23, 5
+    _, g_ref, gs_ref = oracle.control_gradient(s.oh, s.psi, dt, nsteps, coef)
+    R = rsg()
+    c = torch.from_numpy(coef).cuda()
+    out = {}
+    for mode in ("full", "min"):
+        psi = s.to_gpu(s.psi)
+        J, store = R.control_forward(s.gh, psi, dt, nsteps, c, ck, workspace=mode)
+        out[mode] = R.control_backward(s.gh, psi, dt, nsteps, c, ck, store, workspace=mode)
+    np.testing.assert_array_equal(out["min"][0].cpu().numpy(), out["full"][0].cpu().numpy())
+    np.testing.assert_array_equal(out["min"][1].cpu().numpy(), out["full"][1].cpu().numpy())
+    np.testing.assert_allclose(out["min"][0].cpu().numpy(), g_ref, rtol=1e-10, atol=1e-12 * np.abs(g_ref).max())
+    assert R._lib.rsg_control_workspace_bytes_min(s.gh._h, 2, s.gg.np, nsteps, ck) < \
+        R._lib.rsg_control_workspace_bytes(s.gh._h, 2, s.gg.np, nsteps, ck)
+
+
 def test_optimal_control_autograd_matches_central_differences():
     s = System(0.4, n=14, potential="wells", natoms=0, nst=2, seed=8, dipole_axis=2,
                well_box=1.5, orbitals="packets", packet_box=1.0)
