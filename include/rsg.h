@@ -253,8 +253,11 @@ int rsg_laser_grad(const double *g_dev, int64_t nsteps, double T, double dt, int
  * T4(+i dt H_n) lambda_{n+1} (the costate one step back), and
  * g_dev[0] = dJ/dE_n = 2 Re sum_{l=0}^{3} <H^l lambda_{n+1}| x_axis |w_l>,
  * w_l = sum_{m=0}^{3-l} a_{l+m+1} H^m psi_n, a_j = (-i dt)^j / j!: the
- * time-discrete form of eq. (qoctgradient).  Needs a dipole axis.
- * ws: RSG_OP_ADJOINT bytes. */
+ * time-discrete form of eq. (qoctgradient).  Computed in the product form
+ * of the step (see rsg_control_backward): the three stage outputs of psi_n
+ * are recomputed, then four adjoint stages on lambda and one pass over the
+ * four stage pairs; equal to the formulas above in exact arithmetic.
+ * Needs a dipole axis.  ws: RSG_OP_ADJOINT bytes. */
 int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, int64_t nst, int64_t ldp,
                      double dt, double field, double *g_dev, void *ws, size_t ws_bytes,
                      void *stream);
@@ -295,8 +298,7 @@ int rsg_control_forward(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, double
  * keeps each step's stage outputs y_1..y_3 (y_0 = psi_n), the costate
  * runs back through the adjoint factors, m_4 = lambda_{n+1}, m_{k-1} =
  * (1 + conj(a_k) H) m_k, lambda_n = m_0, and dJ/dE_n = 2 Re sum_k a_k
- * <m_k| x_axis |y_{k-1}>; equal in exact arithmetic to the rsg_adjoint_step
- * formulas. */
+ * <m_k| x_axis |y_{k-1}>, as in rsg_adjoint_step. */
 int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ldp, double dt,
                          int64_t nsteps, const double *coef_dev, int32_t ncoef,
                          int64_t ckpt_every, const void *ckpt_dev, double *grad_dev,

@@ -308,56 +308,6 @@ int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t
     return stage_impl(H, w1, wt, psi, psi_out, 0, cmp, nst, ldp, 0.0, -dt, field, field_dev, D, s, H.mask);
 }
 
-size_t adjoint_ws(const Ham &H, int64_t nst, int64_t ldp) {
-    return 7 * rounded(batch_bytes(nst, ldp, 16)) + rounded(kb_workspace_bytes(H, nst)) +
-           rounded(reduce_workspace_bytes(*H.g, nst)) + 256;
-}
-
-// Discrete adjoint of one Taylor(4) step (see rsg_adjoint_step).
-int adjoint_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int64_t ldp, double dt,
-                 double field, const double *field_dev, double *g_dev, void *ws, size_t ws_bytes,
-                 hipStream_t s) {
-    Carve c(ws, ws_bytes);
-    const size_t bb = batch_bytes(nst, ldp, 16);
-    void *nu[4], *mu[5];
-    nu[0] = const_cast<void *>(psi_n);
-    mu[0] = lambda;
-    for (int k = 1; k < 4; ++k) nu[k] = c.take(bb);
-    for (int k = 1; k < 5; ++k) mu[k] = c.take(bb);
-    void *D = c.take(kb_workspace_bytes(H, nst));
-    const size_t rb = reduce_workspace_bytes(*H.g, nst);
-    void *R = c.take(rb);
-    if (!c.ok) {
-        set_error("adjoint: workspace too small (%zu < %zu bytes)", ws_bytes, adjoint_ws(H, nst, ldp));
-        return RSG_ENOMEM;
-    }
-    int rc;
-    for (int k = 1; k < 4; ++k)
-        if ((rc = hpsi_impl(H, nu[k - 1], nu[k], nst, ldp, field, field_dev, D, s))) return rc;
-    for (int k = 1; k < 5; ++k)
-        if ((rc = hpsi_impl(H, mu[k - 1], mu[k], nst, ldp, field, field_dev, D, s))) return rc;
-    // a_j = (-i dt)^j / j!
-    double2 a[5];
-    a[0] = make_double2(1.0, 0.0);
-    for (int j = 1; j < 5; ++j) {
-        // multiply a[j-1] by (-i dt / j): (x + i y)(-i d) = d y - i d x
-        const double d = dt / j;
-        a[j] = make_double2(d * a[j - 1].y, -d * a[j - 1].x);
-    }
-    double2 pc[16];
-    for (int l = 0; l < 4; ++l)
-        for (int m = 0; m < 4; ++m) pc[4 * l + m] = (l + m <= 3) ? a[l + m + 1] : make_double2(0, 0);
-    const double2 *mup[5] = {(const double2 *)mu[0], (const double2 *)mu[1], (const double2 *)mu[2],
-                             (const double2 *)mu[3], (const double2 *)mu[4]};
-    const double2 *nup[4] = {(const double2 *)nu[0], (const double2 *)nu[1], (const double2 *)nu[2],
-                             (const double2 *)nu[3]};
-    // lambda_n = sum_k conj(a_k) mu_k, written over mu_0 = lambda by the same
-    // pass that forms the pair sums
-    double2 ca[5];
-    for (int k = 0; k < 5; ++k) ca[k] = make_double2(a[k].x, -a[k].y);
-    return launch_adjoint_pass(*H.g, H.axis, mup, nup, pc, ca, (double2 *)lambda, nst, ldp, g_dev, R, rb, s);
-}
-
 size_t adjoint_product_ws(const Ham &H, int64_t nst, int64_t ldp) {
     return 3 * rounded(batch_bytes(nst, ldp, 16)) + rounded(kb_workspace_bytes(H, nst)) +
            rounded(reduce_workspace_bytes(*H.g, nst)) + 256;
@@ -408,6 +358,29 @@ int adjoint_product_impl(const Ham &H, const void *const y[4], void *lambda, int
     // lambda_n = F_1^+ m_1, over lambda_{n+1} (read by the pass above)
     const std::complex<double> a1 = std::conj(factor_coef(0, dt));
     return stage_impl(H, m[1], 0, m[1], lambda, 0, 0, nst, ldp, a1.real(), a1.imag(), field, field_dev, D, s);
+}
+
+// One adjoint step from psi_n alone: its three stage outputs recomputed
+// into the workspace, then adjoint_product_impl.
+size_t adjoint_ws(const Ham &H, int64_t nst, int64_t ldp) {
+    return 3 * rounded(batch_bytes(nst, ldp, 16)) + adjoint_product_ws(H, nst, ldp) + 256;
+}
+
+int adjoint_step_impl(const Ham &H, const void *psi_n, void *lambda, int64_t nst, int64_t ldp, double dt,
+                      double field, double *g_dev, void *ws, size_t ws_bytes, hipStream_t s) {
+    Carve c(ws, ws_bytes);
+    const size_t bb = batch_bytes(nst, ldp, 16);
+    void *y[3] = {c.take(bb), c.take(bb), c.take(bb)};
+    size_t rest = 0;
+    void *aws = c.take_rest(&rest);
+    if (!c.ok) {
+        set_error("adjoint: workspace too small (%zu < %zu bytes)", ws_bytes, adjoint_ws(H, nst, ldp));
+        return RSG_ENOMEM;
+    }
+    int rc = step_product(H, psi_n, y, nullptr, nst, ldp, dt, field, nullptr, aws, s);
+    if (rc) return rc;
+    const void *yy[4] = {psi_n, y[0], y[1], y[2]};
+    return adjoint_product_impl(H, yy, lambda, nst, ldp, dt, field, nullptr, g_dev, aws, rest, s);
 }
 
 // Graph cache key for rsg_propagate.
@@ -844,8 +817,7 @@ extern "C" int rsg_adjoint_step(rsg_ham_t H, const void *psi_n, void *lambda, in
     RSG_REQUIRE(ws_bytes >= adjoint_ws(*H, nst, ldp) - 256, RSG_ENOMEM,
                 "rsg_adjoint_step: workspace too small (%zu < %zu)", ws_bytes, adjoint_ws(*H, nst, ldp));
     RSG_REQUIRE(nst > 0, RSG_ESHAPE, "rsg_adjoint_step: nst must be > 0");
-    return adjoint_impl(*H, psi_n, lambda, nst, ldp, dt, field, nullptr, g_dev, ws, ws_bytes,
-                        (hipStream_t)stream);
+    return adjoint_step_impl(*H, psi_n, lambda, nst, ldp, dt, field, g_dev, ws, ws_bytes, (hipStream_t)stream);
 }
 
 // The control entry points take handles without mask or complex scaling,
