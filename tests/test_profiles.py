@@ -1,0 +1,37 @@
+"""The committed rocprofv3 summaries match the code they describe: every
+traffic summary of the benchmark's stencil was taken on the current
+stencil source, names its tile and row alignment, and bench.py finds its
+HBM bytes for that tile; the kernel-statistics summary lists the stencil."""
+import glob
+import os
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _kv(path):
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    return kv
+
+
+def test_traffic_summaries_are_current():
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_stencil_sphere18_wells_*.txt")))
+    assert paths
+    for p in paths:
+        kv = _kv(p)
+        assert kv["stencil_source_sha256"] == bench.stencil_source_hash(), p
+        B, TX, TY, ZC, PD, PT, BO, ZM = (int(v) for v in kv["tile"].split(","))
+        tile = dict(B=B, TX=TX, TY=TY, ZC=ZC, PD=PD, PT=PT, BO=BO, ZM=ZM)
+        got = bench.read_traffic("sphere18_wells", tile, int(kv.get("row_align", "1")))
+        assert got == float(kv["hbm_bytes_per_launch"]), p
+        assert 1.0 < got / float(kv["algorithmic_bytes_per_launch"]) < 3.0, p
+
+
+def test_kernel_statistics_list_the_stencil():
+    text = open(os.path.join(ROOT, "profiles", "kernel_stats_sphere18_wells.txt")).read()
+    assert "k_stencil<" in text and "rocprofv3 --kernel-trace --stats" in text
