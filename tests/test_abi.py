@@ -64,3 +64,18 @@ def test_host_side_argument_errors(lib):
     assert lib.rsg_copy(None, None, 15, None) == -1
     lib.rsg_version.restype = C.c_char_p
     assert b"gfx950" in lib.rsg_version()
+
+
+def test_row_alignment_argument_errors(lib):
+    lib.rsg_last_error.restype = C.c_char_p
+
+    class Desc(C.Structure):
+        _fields_ = [("shape", C.c_int32), ("n", C.c_int32), ("radius", C.c_double), ("h", C.c_double)]
+
+    lib.rsg_grid_create_aligned.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    out = C.c_void_p()
+    for align in (0, -8, 3, 12, 128):
+        assert lib.rsg_grid_create_aligned(C.byref(Desc(0, 8, 0.0, 0.3)), align, None, C.byref(out)) == -1
+        assert b"align" in lib.rsg_last_error()
+    assert lib.rsg_grid_create_aligned(None, 8, None, C.byref(out)) == -1
+    assert b"null" in lib.rsg_last_error()
