@@ -97,6 +97,27 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def fixed_tile(spec: str) -> list:
+    """'B,TX,TY,ZC,PD,PT,BO[,ZM]' -> the eight tile fields (ZM defaults to 0)."""
+    vals = [int(v) for v in spec.split(",")]
+    if len(vals) not in (7, 8):
+        raise SystemExit(f"a tile is B,TX,TY,ZC,PD,PT,BO[,ZM], got {spec!r}")
+    return vals + [0] * (8 - len(vals))
+
+
+def choose_tile(args, spec, gh, psi, reps, dtype="c128"):
+    """The stencil tile of gh for psi's batch: the one spec names, else the
+    autotuner's choice (the default shape with --no-autotune)."""
+    import paper_1501_05654_amd as rsg
+
+    nst = psi.shape[0]
+    if spec:
+        rsg.set_tile(gh, nst, *fixed_tile(spec), dtype=dtype)
+    elif not args.no_autotune:
+        rsg.autotune(gh, psi, dtype=dtype, reps=reps)
+    return rsg.get_tile(gh, nst, dtype=dtype)
+
+
 def cpu_baseline(cfg, seconds: float):
     """The FP64 oracle on the host: one Taylor(4) step over the full grid on
     a sample of the orbitals sized to take about `seconds` with every host
@@ -165,10 +186,7 @@ def bench_sphere(args):
     dt = cfg["dt"]
     tile = None
     if args.tile:
-        vals = [int(v) for v in args.tile.split(",")]
-        B, TX, TY, ZC, PD, PT, BO = vals[:7]
-        ZM = vals[7] if len(vals) > 7 else 0
-        rsg.set_tile(gh, nst, B, TX, TY, ZC, PD, PT, BO, ZM)
+        rsg.set_tile(gh, nst, *fixed_tile(args.tile))
         tile = rsg.get_tile(gh, nst)
     elif not args.no_autotune:
         tile, tile_ms = rsg.autotune(gh, psi, reps=4)
@@ -277,8 +295,14 @@ def bench_batch(args):
     dt = cfg["dt"]
     with torch.cuda.stream(stream):
         b = rsg.Batch(systems)
-        tile, tms = b.autotune(reps=3)
-        log(f"batch tile {tile}: {tms:.3f} ms per stage")
+        if args.tile:
+            B, TX, TY, ZC, PD, _, _, ZM = fixed_tile(args.tile)
+            b.set_tile(B, TX, TY, ZC, PD, ZM)
+            tile = b.get_tile()
+            log(f"batch tile {tile} (fixed)")
+        else:
+            tile, tms = b.autotune(reps=3)
+            log(f"batch tile {tile}: {tms:.3f} ms per stage")
         # eager steps with per-launch HIP-event timing of the stencil kernel
         with rsg.kernel_timing() as kt:
             b.propagate(dt, max(1, args.warmup))
@@ -502,7 +526,8 @@ def bench_cube32(args):
             for _ in range(cfg["steps"]):
                 rsg.propagate_step(gh, psi, dt, ws=ws)
 
-        tile, _ = rsg.autotune(gh, psi, reps=10)  # launches of a few microseconds: many repetitions
+        # launches of a few microseconds: many repetitions
+        tile = choose_tile(args, args.tile, gh, psi, reps=10)
         seq()  # plans and tiles exist before capture
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
@@ -562,8 +587,8 @@ def bench_mixed_sphere(args):
                                      dev)
     gh = rsg.Hamiltonian(gg, V=Vt, kin=-0.5, projectors=projs)
     ws = torch.empty(gh.workspace_bytes("step", nst, psi0.shape[1]), dtype=torch.uint8, device=dev)
-    rsg.autotune(gh, psi0, reps=2)
-    rsg.autotune(gh, psi0, dtype="mixed", reps=2)
+    tiles = {"c128": choose_tile(args, args.tile, gh, psi0, reps=2),
+             "mixed": choose_tile(args, args.tile_mixed, gh, psi0, reps=2, dtype="mixed")}
     steps = max(args.steps, 1)
 
     def run(dtype):
@@ -589,7 +614,7 @@ def bench_mixed_sphere(args):
         "warmup": args.warmup, "ms_per_step": el32 * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 H / f64 accumulation", "data": "synthetic",
         "config": {"workload": "sphere18_mixed", "np": gg.npoints, "nst": nst, "natoms": cfg["natoms"], "dt": dt,
-                   "row_align": gg.align},
+                   "row_align": gg.align, "tile": tiles["mixed"], "tile_fp64": tiles["c128"]},
         "roofline": {"bound": "hbm", "achieved": alg / (k32 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_stencil mixed (FP32 arithmetic, Taylor stage)", "kernel_mean_ms": k32,
@@ -629,7 +654,7 @@ def bench_cs(args):
         synth.white_noise(cfg["seed"], gg.npoints, nst, cfg["h"])).cuda().t()
     gh = rsg.Hamiltonian(gg, V=torch.from_numpy(vre).cuda(), kin=-0.5)
     out = torch.empty_like(psi)
-    rsg.autotune(gh, psi, reps=2)
+    tile = choose_tile(args, args.tile, gh, psi, reps=2)
     reps = max(args.steps, 1)
 
     def timed():
@@ -669,7 +694,7 @@ def bench_cs(args):
         "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": el_cs * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "sphere18_cs", "np": gg.npoints, "nst": nst, "theta": th, "row_align": gg.align,
-                   "potential": "16 wells continued to r e^{i theta}, no projectors",
+                   "tile": tile, "potential": "16 wells continued to r e^{i theta}, no projectors",
                    "step": "one H_theta application to the batch"},
         "roofline": {"bound": "hbm", "achieved": alg / (k_cs * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (k_cs * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
@@ -882,7 +907,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape instead of timing the candidates")
     ap.add_argument("--tile", default="",
-                    help="B,TX,TY,ZC,PD,PT,BO[,ZM]: use this stencil tile instead of autotuning")
+                    help="B,TX,TY,ZC,PD,PT,BO[,ZM]: use this stencil tile instead of autotuning "
+                         "(sphere18_wells, batch256 (PT and BO ignored), cube32_ho, sphere18_cs, and the "
+                         "FP64 steps of sphere18_mixed)")
+    ap.add_argument("--tile-mixed", default="",
+                    help="sphere18_mixed: the same for the FP32 stencil of the mixed steps")
     args = ap.parse_args()
     if args.align <= 0:
         # measured per workload: the QMR passes are pointwise over all slots,
