@@ -35,3 +35,11 @@ def test_traffic_summaries_are_current():
 def test_kernel_statistics_list_the_stencil():
     text = open(os.path.join(ROOT, "profiles", "kernel_stats_sphere18_wells.txt")).read()
     assert "k_stencil<" in text and "rocprofv3 --kernel-trace --stats" in text
+
+
+def test_every_workload_has_kernel_statistics():
+    for w in ["sphere18_wells", "batch256", "sphere18_mixed", "sphere18_cs", "cube32_ho", "cube96_control",
+              "qmr_sphere500k"]:
+        text = open(os.path.join(ROOT, "profiles", f"kernel_stats_{w}.txt")).read()
+        assert "rocprofv3 --kernel-trace --stats" in text and "bench.py" in text, w
+        assert "k_stencil" in text, w
