@@ -349,6 +349,21 @@ int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t);
 int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, void *ws,
                  size_t ws_bytes, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
 
+/* rsg_autotune with a tile cache in the text file cache_path, one line per
+ * tuned case: "<key> | B TX TY ZC PD PT BO ZM | ms".  The key names the box
+ * shape, its dimensions, point and slot counts, the row alignment, nst, the
+ * dtype, complex scaling and mask use, and the device (architecture name
+ * and compute-unit count).  If the file holds the key (the last such line
+ * wins) the tile is set with no kernel launch and *cached = 1; otherwise
+ * the autotuner runs as rsg_autotune does, its choice is appended to the
+ * file and *cached = 0.  best, best_ms and cached may be NULL.  The file is
+ * created if missing; concurrent writers may append the same key twice,
+ * which is harmless.  Errors: those of rsg_autotune, and RSG_EINVAL when
+ * the file cannot be written. */
+int rsg_autotune_cache(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, void *ws,
+                       size_t ws_bytes, int32_t reps, const char *cache_path, rsg_tile *best, double *best_ms,
+                       int32_t *cached, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Many independent systems                                            */
 /* ------------------------------------------------------------------ */
@@ -366,31 +381,65 @@ size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc *sys);
 
 /* Group nsys independent systems (the group of states of section
  * "Parallelization, optimizations and graphics processing units", extended
- * across systems) so that each stage of a Taylor(4) step of all of them runs
- * as one persistent stencil launch over a list of (system, tile, z-range,
- * orbital) items (largest systems first), with one projector gather launch and one
- * scatter launch per colour.  ws (rsg_batch_workspace_bytes) holds the work
- * buffers and must outlive the batch, as must every Hamiltonian and orbital
- * array named in sys.  Results are bitwise equal to propagating each system
- * alone with the same tile.  Errors: RSG_EINVAL, RSG_ESHAPE, RSG_ENOMEM,
- * RSG_EUNSUPPORTED (a system with a dipole axis), RSG_EHIP. */
+ * across systems).  The systems fall into size classes by the width of their
+ * tight box (narrower than 48 points, 48 to 79, 80 or more; empty classes
+ * are dropped), and each class has its own stencil tile shape (initially
+ * 32 x 8, depth 2).  Each stage of a Taylor(4) step of all systems runs as
+ * one persistent stencil launch per class over a list of (system, tile,
+ * z-range, orbital) items (largest systems first), with one projector
+ * gather launch and one scatter launch per colour for all systems.  ws
+ * (rsg_batch_workspace_bytes) holds the work buffers and must outlive the
+ * batch, as must every Hamiltonian and orbital array named in sys.  Results
+ * are bitwise equal to propagating each system alone with its class's tile.
+ * Errors: RSG_EINVAL, RSG_ESHAPE, RSG_ENOMEM, RSG_EUNSUPPORTED (a system
+ * with a dipole axis, a mask or complex scaling), RSG_EHIP. */
 int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *ws, size_t ws_bytes, void *stream,
                      rsg_batch_t *out);
+/* The same call under the name of the plan/run pair below. */
+int rsg_batch_plan_create(int32_t nsys, const rsg_system_desc *sys, void *ws, size_t ws_bytes, void *stream,
+                          rsg_batch_t *out);
 int rsg_batch_destroy(rsg_batch_t b);
 
-/* Tile shape used for every system of the batch (FP64 shapes of
- * rsg_tile_candidates; PT and BO are ignored). */
-int rsg_batch_set_tile(rsg_batch_t b, const rsg_tile *t, void *stream);
-int rsg_batch_get_tile(rsg_batch_t b, rsg_tile *t);
+/* Size classes: *nclass, and (if class_of_sys is not NULL) the class of
+ * every system.  rsg_batch_set_classes replaces the classes: class_of_sys[i]
+ * in 0..nclass-1 for every system, every class non-empty (RSG_EINVAL
+ * otherwise); every class restarts with the 32 x 8 depth-2 tile. */
+int rsg_batch_classes(rsg_batch_t b, int32_t *nclass, int32_t *class_of_sys);
+int rsg_batch_set_classes(rsg_batch_t b, const int32_t *class_of_sys, void *stream);
 
-/* Time one batched stage for every compiled tile shape (best of reps after a
- * warm-up) and keep the fastest.  The orbitals are not modified. */
+/* Tile shape of every class (rsg_batch_set_tile) or of class c (FP64 shapes
+ * of rsg_tile_candidates; PT and BO are ignored).  rsg_batch_get_tile
+ * reports the tile of the class with the most grid-point x orbital work.
+ * RSG_EUNSUPPORTED for a shape that is not compiled. */
+int rsg_batch_set_tile(rsg_batch_t b, const rsg_tile *t, void *stream);
+int rsg_batch_set_class_tile(rsg_batch_t b, int32_t c, const rsg_tile *t, void *stream);
+int rsg_batch_get_tile(rsg_batch_t b, rsg_tile *t);
+int rsg_batch_get_class_tile(rsg_batch_t b, int32_t c, rsg_tile *t);
+
+/* Class c: its number of systems, its stencil work items per stage
+ * (tiles x z-chunks x orbitals) and the workgroups its persistent launch
+ * runs (at most nitems; each takes items until the list is exhausted). */
+int rsg_batch_class_info(rsg_batch_t b, int32_t c, int32_t *nsys, int64_t *nitems, int32_t *grid);
+
+/* At most max_workgroups persistent workgroups per stencil launch (0: as
+ * many as are resident on the device, the default).  Fewer workgroups take
+ * more items each; the results do not change.  Drops captured graphs. */
+int rsg_batch_set_grid(rsg_batch_t b, int32_t max_workgroups);
+
+/* Autotuner over the size classes: for each class, every compiled FP64 tile
+ * shape x z-chunk {whole, 32} x z-march {upward, centre-out}, timed on that
+ * class's persistent launch of a middle Taylor stage (best of reps after a
+ * warm-up); the fastest per class is kept.  *best: the tile of the class
+ * with the most work; *best_ms: the sum over classes of their best stage
+ * times.  The orbitals are not modified.  Synchronises the stream. */
 int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, double *best_ms, void *stream);
 
 /* nsteps Taylor(4) steps of every system at time step dt, zero field.
  * use_graph != 0 captures the launch sequence into a HIP graph once per
  * (dt, nsteps, stream) and replays it; needs a non-default stream. */
 int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int32_t use_graph, void *stream);
+/* rsg_batch_propagate with graph capture: the run half of the plan/run pair. */
+int rsg_batch_run(rsg_batch_t b, int64_t nsteps, double dt, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Complex scaling                                                     */

@@ -83,6 +83,7 @@ def _load():
         "rsg_set_tile": (C.c_int, [vp, i64, i32, vp]),
         "rsg_get_tile": (C.c_int, [vp, i64, i32, vp]),
         "rsg_autotune": (C.c_int, [vp, vp, i64, i64, i32, vp, sz, i32, vp, vp, vp]),
+        "rsg_autotune_cache": (C.c_int, [vp, vp, i64, i64, i32, vp, sz, i32, C.c_char_p, vp, vp, vp, vp]),
         "rsg_batch_workspace_bytes": (sz, [i32, vp]),
         "rsg_batch_create": (C.c_int, [i32, vp, vp, sz, vp, vp]),
         "rsg_batch_destroy": (C.c_int, [vp]),
@@ -90,6 +91,14 @@ def _load():
         "rsg_batch_get_tile": (C.c_int, [vp, vp]),
         "rsg_batch_autotune": (C.c_int, [vp, i32, vp, vp, vp]),
         "rsg_batch_propagate": (C.c_int, [vp, dbl, i64, i32, vp]),
+        "rsg_batch_plan_create": (C.c_int, [i32, vp, vp, sz, vp, vp]),
+        "rsg_batch_run": (C.c_int, [vp, i64, dbl, vp]),
+        "rsg_batch_classes": (C.c_int, [vp, vp, vp]),
+        "rsg_batch_set_classes": (C.c_int, [vp, vp, vp]),
+        "rsg_batch_set_class_tile": (C.c_int, [vp, i32, vp, vp]),
+        "rsg_batch_get_class_tile": (C.c_int, [vp, i32, vp]),
+        "rsg_batch_set_grid": (C.c_int, [vp, i32]),
+        "rsg_batch_class_info": (C.c_int, [vp, i32, vp, vp, vp]),
         "rsg_ham_set_complex_scaling": (C.c_int, [vp, dbl, vp]),
         "rsg_bilinear": (C.c_int, [vp, vp, vp, i64, i64, vp, vp, sz, vp]),
         "rsg_cs_eigs_workspace_bytes": (sz, [vp, i64, i64]),
@@ -648,6 +657,23 @@ def autotune(ham: Hamiltonian, psi: torch.Tensor, dtype="c128", reps: int = 3,
     return _tile_dict(t), float(ms.value)
 
 
+def autotune_cached(ham: Hamiltonian, psi: torch.Tensor, cache_path: str, dtype="c128", reps: int = 3,
+                    nst: int | None = None):
+    """autotune through the tile cache file cache_path: returns (tile,
+    milliseconds, cached) with cached True when the tile came from the file
+    (no kernel was launched)."""
+    _batch(psi, "psi", ham.grid.np)
+    n = _nst(psi, nst)
+    ws = _ws(ham.workspace_bytes("step", n, psi.shape[1], _dt(dtype)), psi.device)
+    t = _Tile()
+    ms = C.c_double()
+    hit = C.c_int32()
+    _check(_lib.rsg_autotune_cache(ham._h, _ptr(psi), n, psi.shape[1], _dt(dtype), _ptr(ws), ws.numel(),
+                                   int(reps), os.fsencode(cache_path), C.byref(t), C.byref(ms), C.byref(hit),
+                                   _stream()))
+    return _tile_dict(t), float(ms.value), bool(hit.value)
+
+
 class _SysDesc(C.Structure):
     _fields_ = [("ham", C.c_void_p), ("psi", C.c_void_p), ("nst", C.c_int64), ("ldp", C.c_int64)]
 
@@ -679,14 +705,46 @@ class Batch:
         _check(_lib.rsg_batch_create(n, descs, _ptr(self.ws), self.ws.numel(), _stream(),
                                      C.byref(self._h)))
 
-    def set_tile(self, B: int, TX: int, TY: int, ZC: int = 0, PD: int = 1, ZM: int = 0):
+    def set_tile(self, B: int, TX: int, TY: int, ZC: int = 0, PD: int = 1, ZM: int = 0,
+                 cls: int | None = None):
+        """Tile of every size class (cls = None) or of class cls."""
         t = _Tile(B, TX, TY, ZC, PD, 0, 0, ZM)
-        _check(_lib.rsg_batch_set_tile(self._h, C.byref(t), _stream()))
+        if cls is None:
+            _check(_lib.rsg_batch_set_tile(self._h, C.byref(t), _stream()))
+        else:
+            _check(_lib.rsg_batch_set_class_tile(self._h, int(cls), C.byref(t), _stream()))
 
-    def get_tile(self) -> dict:
+    def get_tile(self, cls: int | None = None) -> dict:
         t = _Tile()
-        _check(_lib.rsg_batch_get_tile(self._h, C.byref(t)))
+        if cls is None:
+            _check(_lib.rsg_batch_get_tile(self._h, C.byref(t)))
+        else:
+            _check(_lib.rsg_batch_get_class_tile(self._h, int(cls), C.byref(t)))
         return _tile_dict(t)
+
+    def classes(self) -> np.ndarray:
+        """Size class of every system."""
+        n = C.c_int32()
+        out = np.zeros(len(self.systems), dtype=np.int32)
+        _check(_lib.rsg_batch_classes(self._h, C.byref(n), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_classes(self, class_of_sys):
+        c = np.ascontiguousarray(class_of_sys, dtype=np.int32)
+        if c.shape != (len(self.systems),):
+            raise ValueError("one class per system")
+        _check(_lib.rsg_batch_set_classes(self._h, c.ctypes.data_as(C.c_void_p), _stream()))
+
+    def class_info(self, cls: int) -> dict:
+        """{nsys, nitems, grid} of size class cls: systems, stencil work items
+        per stage, persistent workgroups per launch."""
+        ns, ni, gr = C.c_int32(), C.c_int64(), C.c_int32()
+        _check(_lib.rsg_batch_class_info(self._h, int(cls), C.byref(ns), C.byref(ni), C.byref(gr)))
+        return {"nsys": ns.value, "nitems": ni.value, "grid": gr.value}
+
+    def set_grid(self, max_workgroups: int):
+        """Cap the persistent grid of every stencil launch (0: no cap)."""
+        _check(_lib.rsg_batch_set_grid(self._h, int(max_workgroups)))
 
     def autotune(self, reps: int = 2):
         t = _Tile()
@@ -697,6 +755,10 @@ class Batch:
     def propagate(self, dt: float, nsteps: int, graph: bool = False):
         _check(_lib.rsg_batch_propagate(self._h, float(dt), int(nsteps), 1 if graph else 0,
                                         _stream()))
+
+    def run(self, nsteps: int, dt: float):
+        """rsg_batch_run: graph-captured steps (needs a non-default stream)."""
+        _check(_lib.rsg_batch_run(self._h, int(nsteps), float(dt), _stream()))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -1189,6 +1189,77 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
     });
 }
 
+// Key of a tuned tile in the cache file: everything the choice depends on
+// (box shape and size, storage alignment, orbital count, precision, the
+// kernel family in use, and the device).
+static int tile_cache_key(const Ham &H, int64_t nst, int32_t dtype, std::string *key) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    RSG_CHECK_HIP(hipGetDevice(&dev));
+    RSG_CHECK_HIP(hipGetDeviceProperties(&prop, dev));
+    const Grid &g = *H.g;
+    char buf[512];
+    snprintf(buf, sizeof buf, "box=%d dims=%dx%dx%d points=%lld slots=%lld align=%d nst=%lld dtype=%d cs=%d mask=%d dev=%s/%d",
+             g.shape, g.n[0], g.n[1], g.n[2], (long long)g.npts, (long long)g.np, g.align, (long long)nst, dtype,
+             H.complex_scaled() ? 1 : 0, H.mask ? 1 : 0, prop.gcnArchName, prop.multiProcessorCount);
+    *key = buf;
+    return RSG_OK;
+}
+
+extern "C" int rsg_autotune_cache(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t dtype, void *ws,
+                                  size_t ws_bytes, int32_t reps, const char *cache_path, rsg_tile *best,
+                                  double *best_ms, int32_t *cached, void *stream) {
+    clear_error();
+    RSG_REQUIRE(H && cache_path, RSG_EINVAL, "rsg_autotune_cache: null argument");
+    RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_autotune_cache: bad dtype");
+    RSG_REQUIRE(nst > 0 && reps > 0, RSG_EINVAL, "rsg_autotune_cache: need nst > 0 and reps > 0");
+    return guarded([&]() -> int {
+        std::string key;
+        int rc = tile_cache_key(*H, nst, dtype, &key);
+        if (rc) return rc;
+        if (cached) *cached = 0;
+        // the last entry of this key wins
+        bool found = false;
+        rsg_tile t{};
+        double ms = 0.0;
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            while (std::fgets(line, sizeof line, f)) {
+                char *bar = std::strchr(line, '|');
+                if (!bar || (size_t)(bar - line) != key.size() + 1 || std::strncmp(line, key.c_str(), key.size()))
+                    continue;
+                rsg_tile u{};
+                double m = 0.0;
+                if (std::sscanf(bar + 1, " %d %d %d %d %d %d %d %d | %lf", &u.B, &u.TX, &u.TY, &u.ZC, &u.PD, &u.PT,
+                                &u.BO, &u.ZM, &m) == 9) {
+                    t = u;
+                    ms = m;
+                    found = true;
+                }
+            }
+            std::fclose(f);
+        }
+        if (found && rsg_set_tile(H, nst, dtype, &t) == RSG_OK) {
+            if (best) *best = t;
+            if (best_ms) *best_ms = ms;
+            if (cached) *cached = 1;
+            return RSG_OK;
+        }
+        clear_error();  // a stale entry (a tile no longer compiled) is timed again
+        rc = rsg_autotune(H, psi, nst, ldp, dtype, ws, ws_bytes, reps, &t, &ms, stream);
+        if (rc) return rc;
+        if (best) *best = t;
+        if (best_ms) *best_ms = ms;
+        FILE *f = std::fopen(cache_path, "a");
+        RSG_REQUIRE(f, RSG_EINVAL, "rsg_autotune_cache: cannot append to %s", cache_path);
+        std::fprintf(f, "%s | %d %d %d %d %d %d %d %d | %.6f\n", key.c_str(), t.B, t.TX, t.TY, t.ZC, t.PD, t.PT,
+                     t.BO, t.ZM, ms);
+        const bool ok = std::fclose(f) == 0;
+        RSG_REQUIRE(ok, RSG_EINVAL, "rsg_autotune_cache: writing %s failed", cache_path);
+        return RSG_OK;
+    });
+}
+
 extern "C" int rsg_copy(const void *src, void *dst, size_t nbytes, void *stream) {
     clear_error();
     RSG_REQUIRE(nbytes % 16 == 0, RSG_EINVAL, "rsg_copy: size must be a multiple of 16");

@@ -2,15 +2,16 @@
 //
 // The paper's basic object is a group of states rather than one state
 // (section "Parallelization, optimizations and graphics processing units");
-// here the group extends across systems: every stage of a Taylor(4) step of
-// every system runs as one persistent stencil launch over a list of
-// (system, tile, z-range, orbital) items (largest systems first, each
-// sweeping its tiles orbital by orbital), preceded by one projector
-// gather launch and followed by one scatter launch per colour, all systems at
-// once.  A step sequence can be captured once into a HIP graph and replayed.
-// Each output point is computed by the same arithmetic as the single-system
-// path, so the results are bitwise equal to propagating each system alone
-// with the same tile shape.
+// here the group extends across systems.  The systems are grouped into size
+// classes (by the width of their box), each class with its own stencil tile
+// shape; every stage of a Taylor(4) step runs, per class, as one persistent
+// stencil launch over a list of (system, tile, z-range, orbital) items
+// (largest systems first, each sweeping its tiles orbital by orbital),
+// preceded by one projector gather launch and followed by one scatter launch
+// per colour, all systems at once.  A step sequence can be captured once into
+// a HIP graph and replayed.  Each output point is computed by the same
+// arithmetic as the single-system path, so the results are bitwise equal to
+// propagating each system alone with its class's tile shape.
 #include "rsg_internal.h"
 
 #include <algorithm>
@@ -20,15 +21,23 @@
 
 namespace rsg {
 
+// Systems of one size class share a tile shape and a persistent launch per
+// stage; the classes of a stage run back to back on the caller's stream.
+struct BatchClass {
+    TileShape tile{1, 32, 8, 0};
+    std::vector<int32_t> sys;    // member systems
+    BatchItem *items = nullptr;  // device work list of this class
+    int32_t nitems = 0;
+    int grid = 0;                // resident workgroups of the class's kernel
+};
+
 struct Batch {
     std::vector<rsg_system_desc> sys;
     std::vector<void *> w1, w2, D;  // per-system work buffers inside the caller's workspace
-    TileShape tile{1, 32, 8, 0};
-    int grid_first = 0;  // persistent workgroups per stencil launch (every stage is a first-type stage)
+    std::vector<BatchClass> cls;
+    int32_t grid_cap = 0;  // at most this many persistent workgroups per launch (0: no cap)
     KParams *sp[4] = {nullptr, nullptr, nullptr, nullptr};  // device, per stage, one per system
     KbSys *kb[4] = {nullptr, nullptr, nullptr, nullptr};
-    BatchItem *items = nullptr;
-    int32_t nitems = 0;
     int32_t *ctr = nullptr;  // device work counters of the persistent stencil (zero between launches)
     int4 *gitems = nullptr;
     int32_t ngitems = 0;
@@ -37,6 +46,10 @@ struct Batch {
     std::vector<int4 *> sitems;  // scatter items per colour
     std::vector<int32_t> nsitems;
     std::map<std::tuple<double, int64_t, hipStream_t>, hipGraphExec_t> graphs;
+    void drop_graphs() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
     void free_tables() {
         for (int k = 0; k < 4; ++k) {
             if (sp[k]) (void)hipFree(sp[k]);
@@ -44,7 +57,11 @@ struct Batch {
             sp[k] = nullptr;
             kb[k] = nullptr;
         }
-        if (items) (void)hipFree(items);
+        for (auto &c : cls) {
+            if (c.items) (void)hipFree(c.items);
+            c.items = nullptr;
+            c.nitems = 0;
+        }
         if (ctr) (void)hipFree(ctr);
         ctr = nullptr;
         if (gitems) (void)hipFree(gitems);
@@ -53,15 +70,20 @@ struct Batch {
         nsumitems = 0;
         for (auto *p : sitems)
             if (p) (void)hipFree(p);
-        items = nullptr;
         gitems = nullptr;
         sitems.clear();
         nsitems.clear();
-        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
-        graphs.clear();
+        drop_graphs();
     }
     ~Batch() { free_tables(); }
 };
+
+// Default size classes: systems whose tight box is narrower than 48 points,
+// 48 to 79 points, and 80 points or more (the spheres of radius 4 to 12 bohr
+// at h = 0.25 span 33 to 97 points).  A tile that suits the widest spheres
+// leaves most lanes of a narrow sphere's tiles idle, and the other way round
+// narrow tiles re-read more halo per output on wide spheres.
+constexpr int kClassEdges[] = {48, 80};
 
 namespace {
 
@@ -93,40 +115,58 @@ void stage_buffers(const Batch &b, size_t i, int k, const void **in, const void 
     *base = *in;
 }
 
-// (Re)build the item lists and per-system parameter tables for the tile.
-int build_tables(Batch &b, hipStream_t s) {
-    b.free_tables();
-    std::vector<BatchItem> items;
-    std::vector<int4> gitems;
-    std::vector<int2> sumitems;
-    std::vector<std::vector<int4>> sitems;
-    std::vector<KParams> sp[4];
-    std::vector<KbSys> kb[4];
-    int err = RSG_OK;
-    // stencil items: systems with the most work first (the small ones fill
-    // the tail of the persistent grid), each system sweeping its tiles one
-    // orbital at a time so that neighbouring tiles are resident together
-    std::vector<size_t> by_work(b.sys.size());
-    for (size_t i = 0; i < by_work.size(); ++i) by_work[i] = i;
-    std::stable_sort(by_work.begin(), by_work.end(), [&](size_t p, size_t q) {
+// Stencil items of class c for its tile: its systems with the most work
+// first (the small ones fill the tail of the persistent grid), each system
+// sweeping its tiles one orbital at a time so that neighbouring tiles are
+// resident together.  Replaces the class's device list.
+int build_class(Batch &b, size_t c, hipStream_t s) {
+    BatchClass &cl = b.cls[c];
+    if (cl.items) (void)hipFree(cl.items);
+    cl.items = nullptr;
+    cl.nitems = 0;
+    b.drop_graphs();
+    std::vector<int32_t> by_work = cl.sys;
+    std::stable_sort(by_work.begin(), by_work.end(), [&](int32_t p, int32_t q) {
         return b.sys[p].ham->g->np * b.sys[p].nst > b.sys[q].ham->g->np * b.sys[q].nst;
     });
-    std::vector<std::vector<BatchItem>> sys_items(b.sys.size());
-    for (size_t i = 0; i < b.sys.size(); ++i) {
+    std::vector<BatchItem> items;
+    int err = RSG_OK;
+    for (const int32_t i : by_work) {
         const rsg_system_desc &d = b.sys[i];
-        Ham &H = *d.ham;
-        TileShape sh = b.tile;
+        TileShape sh = cl.tile;
         sh.PT = 0;
         sh.BO = 0;
-        sh.ZC = sh.ZC > 0 ? sh.ZC : H.g->n[2];  // ZM as chosen for the batch
-        const TilePlan *plan = H.g->plan(sh, s, &err);
+        sh.ZC = sh.ZC > 0 ? sh.ZC : d.ham->g->n[2];  // ZM as chosen for the class
+        const TilePlan *plan = d.ham->g->plan(sh, s, &err);
         if (!plan) return err;
         // copy the plan's items back to the host to expand them per orbital
         std::vector<int4> pit(plan->nitems);
         if (plan->nitems)
             RSG_CHECK_HIP(hipMemcpy(pit.data(), plan->items, sizeof(int4) * plan->nitems, hipMemcpyDeviceToHost));
         for (int n = 0; n < (int)d.nst; ++n)
-            for (const int4 &t : pit) sys_items[i].push_back(BatchItem{t, (int32_t)i, n});
+            for (const int4 &t : pit) items.push_back(BatchItem{t, i, n});
+    }
+    cl.grid = stencil_batch_grid(cl.tile, true);
+    if (cl.grid <= 0) return cl.grid;
+    int rc = upload(&cl.items, items, s);
+    if (rc) return rc;
+    cl.nitems = (int32_t)items.size();
+    RSG_CHECK_HIP(hipStreamSynchronize(s));
+    return RSG_OK;
+}
+
+// (Re)build the per-system parameter tables, the projector work lists and
+// every class's stencil items.
+int build_tables(Batch &b, hipStream_t s) {
+    b.free_tables();
+    std::vector<int4> gitems;
+    std::vector<int2> sumitems;
+    std::vector<std::vector<int4>> sitems;
+    std::vector<KParams> sp[4];
+    std::vector<KbSys> kb[4];
+    for (size_t i = 0; i < b.sys.size(); ++i) {
+        const rsg_system_desc &d = b.sys[i];
+        Ham &H = *d.ham;
         for (int k = 0; k < 4; ++k) {
             StageArgs a;
             stage_buffers(b, i, k, &a.in, &a.base, &a.out);
@@ -134,7 +174,9 @@ int build_tables(Batch &b, hipStream_t s) {
             a.nst = d.nst;
             a.ldp = d.ldp;
             a.first = k == 0;
-            sp[k].push_back(make_params(H, a, sh, plan));
+            // the persistent kernel takes its tiles from the class's list,
+            // not from a plan
+            sp[k].push_back(make_params(H, a, TileShape{1, 32, 8, 0}, nullptr));
             KbSys ks;
             ks.in = (const double *)a.in;
             ks.out = (double *)a.out;
@@ -173,20 +215,15 @@ int build_tables(Batch &b, hipStream_t s) {
             }
         }
     }
-    for (const size_t i : by_work) items.insert(items.end(), sys_items[i].begin(), sys_items[i].end());
     int rc;
-    b.grid_first = stencil_batch_grid(b.tile, true);
-    if (b.grid_first <= 0) return b.grid_first;
     for (int k = 0; k < 4; ++k) {
         if ((rc = upload(&b.sp[k], sp[k], s))) return rc;
         if ((rc = upload(&b.kb[k], kb[k], s))) return rc;
     }
-    if ((rc = upload(&b.items, items, s))) return rc;
     const std::vector<int32_t> ctr0{0, 0};  // lives until the stream synchronisation below
     if ((rc = upload(&b.ctr, ctr0, s))) return rc;
     if ((rc = upload(&b.gitems, gitems, s))) return rc;
     if ((rc = upload(&b.sumitems, sumitems, s))) return rc;
-    b.nitems = (int32_t)items.size();
     b.ngitems = (int32_t)gitems.size();
     b.nsumitems = (int32_t)sumitems.size();
     for (auto &v : sitems) {
@@ -196,7 +233,18 @@ int build_tables(Batch &b, hipStream_t s) {
         b.nsitems.push_back((int32_t)v.size());
     }
     RSG_CHECK_HIP(hipStreamSynchronize(s));
+    for (size_t c = 0; c < b.cls.size(); ++c)
+        if ((rc = build_class(b, c, s))) return rc;
     return RSG_OK;
+}
+
+int class_grid(const Batch &b, const BatchClass &c) {
+    return b.grid_cap > 0 ? std::min(c.grid, (int)b.grid_cap) : c.grid;
+}
+
+// The persistent stencil launch of one class for stage k with factor (cre, cim).
+int class_launch(const Batch &b, const BatchClass &c, int k, double cre, double cim, hipStream_t s) {
+    return launch_stencil_batch(c.tile, 1, true, b.sp[k], c.items, c.nitems, cre, cim, b.ctr, class_grid(b, c), s);
 }
 
 // Stage k of a step, the same product form as a single system's FP64 step:
@@ -207,9 +255,10 @@ int stage_launches(const Batch &b, int k, double dt, hipStream_t s) {
     int rc;
     if ((rc = launch_kb_gather_batch(b.kb[k], b.gitems, b.ngitems, s))) return rc;
     if ((rc = launch_kb_gather_sum_batch(b.kb[k], b.sumitems, b.nsumitems, s))) return rc;
-    if ((rc = launch_stencil_batch(b.tile, 1, true, b.sp[k], b.items, b.nitems, c.real(), c.imag(), b.ctr,
-                                   b.grid_first, s)))
-        return rc;
+    // the classes' launches share the work counters: they run one after the
+    // other on this stream, and each leaves the counters zero
+    for (const auto &cl : b.cls)
+        if ((rc = class_launch(b, cl, k, c.real(), c.imag(), s))) return rc;
     for (size_t ci = 0; ci < b.sitems.size(); ++ci)
         if ((rc = launch_kb_scatter_batch(b.kb[k], b.sitems[ci], b.nsitems[ci], c.real(), c.imag(), s)))
             return rc;
@@ -260,6 +309,32 @@ extern "C" size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc 
     return n;
 }
 
+// Systems -> size classes by tight-box width (kClassEdges), empty classes
+// dropped; every class starts with the 32 x 8 depth-2 tile.
+static void default_classes(Batch &b) {
+    constexpr int ncl = (int)(sizeof(kClassEdges) / sizeof(kClassEdges[0])) + 1;
+    std::vector<BatchClass> cls(ncl);
+    for (size_t i = 0; i < b.sys.size(); ++i) {
+        const int w = b.sys[i].ham->g->n[0];
+        int c = 0;
+        while (c < ncl - 1 && w >= kClassEdges[c]) ++c;
+        cls[c].sys.push_back((int32_t)i);
+    }
+    b.cls.clear();
+    for (auto &c : cls)
+        if (!c.sys.empty()) {
+            c.tile = TileShape{1, 32, 8, 0};
+            c.tile.PD = 2;
+            b.cls.push_back(c);
+        }
+}
+
+static bool compiled_fp64(const rsg_tile *t) {
+    for (const auto &c : tile_candidates(0))
+        if (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == t->PD) return true;
+    return false;
+}
+
 extern "C" int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *ws, size_t ws_bytes,
                                 void *stream, rsg_batch_t *out) {
     clear_error();
@@ -287,8 +362,7 @@ extern "C" int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *
             delete b;
             return RSG_EHIP;
         }
-        b->tile = TileShape{1, 32, 8, 0};
-        b->tile.PD = 2;
+        default_classes(*b);
         const int r = build_tables(*b, s);
         if (r) {
             delete b;
@@ -299,33 +373,144 @@ extern "C" int rsg_batch_create(int32_t nsys, const rsg_system_desc *sys, void *
     });
 }
 
+extern "C" int rsg_batch_plan_create(int32_t nsys, const rsg_system_desc *sys, void *ws, size_t ws_bytes,
+                                     void *stream, rsg_batch_t *out) {
+    return rsg_batch_create(nsys, sys, ws, ws_bytes, stream, out);
+}
+
 extern "C" int rsg_batch_destroy(rsg_batch_t b) {
     clear_error();
     delete b;
     return RSG_OK;
 }
 
+extern "C" int rsg_batch_classes(rsg_batch_t b, int32_t *nclass, int32_t *class_of_sys) {
+    clear_error();
+    RSG_REQUIRE(b && nclass, RSG_EINVAL, "rsg_batch_classes: null argument");
+    *nclass = (int32_t)b->cls.size();
+    if (class_of_sys)
+        for (size_t c = 0; c < b->cls.size(); ++c)
+            for (const int32_t i : b->cls[c].sys) class_of_sys[i] = (int32_t)c;
+    return RSG_OK;
+}
+
+extern "C" int rsg_batch_set_classes(rsg_batch_t b, const int32_t *class_of_sys, void *stream) {
+    clear_error();
+    RSG_REQUIRE(b && class_of_sys, RSG_EINVAL, "rsg_batch_set_classes: null argument");
+    const int32_t nsys = (int32_t)b->sys.size();
+    int32_t ncl = 0;
+    for (int32_t i = 0; i < nsys; ++i) {
+        RSG_REQUIRE(class_of_sys[i] >= 0 && class_of_sys[i] < nsys, RSG_EINVAL,
+                    "rsg_batch_set_classes: class %d of system %d outside 0..nsys-1", class_of_sys[i], i);
+        ncl = std::max(ncl, class_of_sys[i] + 1);
+    }
+    return guarded([&]() -> int {
+        std::vector<BatchClass> cls(ncl);
+        for (int32_t i = 0; i < nsys; ++i) cls[class_of_sys[i]].sys.push_back(i);
+        for (int32_t c = 0; c < ncl; ++c)
+            RSG_REQUIRE(!cls[c].sys.empty(), RSG_EINVAL, "rsg_batch_set_classes: class %d has no system", c);
+        for (auto &c : cls) {
+            c.tile = TileShape{1, 32, 8, 0};
+            c.tile.PD = 2;
+        }
+        b->free_tables();
+        b->cls = cls;
+        return build_tables(*b, (hipStream_t)stream);
+    });
+}
+
+static int set_class_tile(rsg_batch_t b, int32_t c, const rsg_tile *t) {
+    BatchClass &cl = b->cls[c];
+    cl.tile = TileShape{t->B, t->TX, t->TY, t->ZC};
+    cl.tile.PD = t->PD;
+    cl.tile.ZM = t->ZM;
+    return RSG_OK;
+}
+
+static int check_batch_tile(const rsg_tile *t, const char *who) {
+    RSG_REQUIRE(compiled_fp64(t), RSG_EUNSUPPORTED, "%s: not a compiled FP64 tile", who);
+    RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "%s: ZC must be >= 0", who);
+    RSG_REQUIRE(t->ZM == 0 || t->ZM == 1, RSG_EINVAL, "%s: ZM must be 0 or 1", who);
+    return RSG_OK;
+}
+
 extern "C" int rsg_batch_set_tile(rsg_batch_t b, const rsg_tile *t, void *stream) {
     clear_error();
     RSG_REQUIRE(b && t, RSG_EINVAL, "rsg_batch_set_tile: null argument");
-    bool ok = false;
-    for (const auto &c : tile_candidates(0)) ok = ok || (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == t->PD);
-    RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_batch_set_tile: not a compiled FP64 tile");
-    RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "rsg_batch_set_tile: ZC must be >= 0");
-    RSG_REQUIRE(t->ZM == 0 || t->ZM == 1, RSG_EINVAL, "rsg_batch_set_tile: ZM must be 0 or 1");
-    b->tile = TileShape{t->B, t->TX, t->TY, t->ZC};
-    b->tile.PD = t->PD;
-    b->tile.ZM = t->ZM;
-    return guarded([&]() { return build_tables(*b, (hipStream_t)stream); });
+    int rc = check_batch_tile(t, "rsg_batch_set_tile");
+    if (rc) return rc;
+    return guarded([&]() -> int {
+        for (int32_t c = 0; c < (int32_t)b->cls.size(); ++c) {
+            set_class_tile(b, c, t);
+            const int r = build_class(*b, (size_t)c, (hipStream_t)stream);
+            if (r) return r;
+        }
+        return RSG_OK;
+    });
 }
+
+extern "C" int rsg_batch_set_class_tile(rsg_batch_t b, int32_t c, const rsg_tile *t, void *stream) {
+    clear_error();
+    RSG_REQUIRE(b && t, RSG_EINVAL, "rsg_batch_set_class_tile: null argument");
+    RSG_REQUIRE(c >= 0 && c < (int32_t)b->cls.size(), RSG_EINVAL, "rsg_batch_set_class_tile: no class %d", c);
+    int rc = check_batch_tile(t, "rsg_batch_set_class_tile");
+    if (rc) return rc;
+    set_class_tile(b, c, t);
+    return guarded([&]() { return build_class(*b, (size_t)c, (hipStream_t)stream); });
+}
+
+static rsg_tile tile_out(const TileShape &s) { return rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, 0, 0, s.ZM}; }
 
 extern "C" int rsg_batch_get_tile(rsg_batch_t b, rsg_tile *t) {
     clear_error();
     RSG_REQUIRE(b && t, RSG_EINVAL, "rsg_batch_get_tile: null argument");
-    *t = rsg_tile{b->tile.B, b->tile.TX, b->tile.TY, b->tile.ZC, b->tile.PD, 0, 0, b->tile.ZM};
+    // the tile of the class with the most work
+    size_t best = 0;
+    int64_t bw = -1;
+    for (size_t c = 0; c < b->cls.size(); ++c) {
+        int64_t w = 0;
+        for (const int32_t i : b->cls[c].sys) w += b->sys[i].ham->g->np * b->sys[i].nst;
+        if (w > bw) {
+            bw = w;
+            best = c;
+        }
+    }
+    *t = tile_out(b->cls[best].tile);
     return RSG_OK;
 }
 
+extern "C" int rsg_batch_get_class_tile(rsg_batch_t b, int32_t c, rsg_tile *t) {
+    clear_error();
+    RSG_REQUIRE(b && t, RSG_EINVAL, "rsg_batch_get_class_tile: null argument");
+    RSG_REQUIRE(c >= 0 && c < (int32_t)b->cls.size(), RSG_EINVAL, "rsg_batch_get_class_tile: no class %d", c);
+    *t = tile_out(b->cls[c].tile);
+    return RSG_OK;
+}
+
+extern "C" int rsg_batch_class_info(rsg_batch_t b, int32_t c, int32_t *nsys, int64_t *nitems, int32_t *grid) {
+    clear_error();
+    RSG_REQUIRE(b, RSG_EINVAL, "rsg_batch_class_info: null batch");
+    RSG_REQUIRE(c >= 0 && c < (int32_t)b->cls.size(), RSG_EINVAL, "rsg_batch_class_info: no class %d", c);
+    const BatchClass &cl = b->cls[c];
+    if (nsys) *nsys = (int32_t)cl.sys.size();
+    if (nitems) *nitems = cl.nitems;
+    if (grid) *grid = std::min<int64_t>(cl.nitems, class_grid(*b, cl));
+    return RSG_OK;
+}
+
+extern "C" int rsg_batch_set_grid(rsg_batch_t b, int32_t max_workgroups) {
+    clear_error();
+    RSG_REQUIRE(b, RSG_EINVAL, "rsg_batch_set_grid: null batch");
+    RSG_REQUIRE(max_workgroups >= 0, RSG_EINVAL, "rsg_batch_set_grid: max_workgroups must be >= 0");
+    b->grid_cap = max_workgroups;
+    b->drop_graphs();  // captured launches hold the old grid size
+    return RSG_OK;
+}
+
+// Per class: every compiled tile x z-chunk {whole, 32} x z-march {upward,
+// centre-out}, timed on that class's persistent launch of a middle stage
+// (w1 -> w2, the orbitals untouched), best of reps after a warm-up; the
+// fastest per class is kept.
 extern "C" int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, double *best_ms, void *stream) {
     clear_error();
     RSG_REQUIRE(b && reps > 0, RSG_EINVAL, "rsg_batch_autotune: bad argument");
@@ -334,44 +519,51 @@ extern "C" int rsg_batch_autotune(rsg_batch_t b, int32_t reps, rsg_tile *best, d
         hipEvent_t e0, e1;
         RSG_CHECK_HIP(hipEventCreate(&e0));
         RSG_CHECK_HIP(hipEventCreate(&e1));
-        double bt = 1e300;
-        TileShape bs = b->tile;
         int rc = RSG_OK;
-        for (const auto &cand : tile_candidates(0)) {
-            for (int zv = 0; zv < 4; ++zv) {
-                b->tile = cand;
-                b->tile.ZC = (zv & 1) ? 32 : 0;
-                b->tile.ZM = zv >> 1;
-                if ((rc = build_tables(*b, s))) break;
-                double tmin = 1e300;
-                for (int r = 0; r <= reps; ++r) {
-                    // stage 2 (w1 -> w2): leaves the orbitals untouched
-                    RSG_CHECK_HIP(hipEventRecord(e0, s));
-                    if ((rc = launch_stencil_batch(b->tile, 1, true, b->sp[1], b->items, b->nitems, 0.0, -1e-3,
-                                                   b->ctr, b->grid_first, s)))
-                        break;
-                    RSG_CHECK_HIP(hipEventRecord(e1, s));
-                    RSG_CHECK_HIP(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    RSG_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    if (r > 0) tmin = std::min(tmin, (double)ms);
+        double total = 0.0;
+        std::vector<TileShape> chosen;
+        for (auto &c : b->cls) chosen.push_back(c.tile);
+        for (size_t ci = 0; ci < b->cls.size() && !rc; ++ci) {
+            double bt = 1e300;
+            for (const auto &cand : tile_candidates(0)) {
+                for (int zv = 0; zv < 4; ++zv) {
+                    TileShape sh = cand;
+                    sh.ZC = (zv & 1) ? 32 : 0;
+                    sh.ZM = zv >> 1;
+                    b->cls[ci].tile = sh;
+                    if ((rc = build_class(*b, ci, s))) break;
+                    double tmin = 1e300;
+                    for (int r = 0; r <= reps; ++r) {
+                        RSG_CHECK_HIP(hipEventRecord(e0, s));
+                        if ((rc = class_launch(*b, b->cls[ci], 1, 0.0, -1e-3, s))) break;
+                        RSG_CHECK_HIP(hipEventRecord(e1, s));
+                        RSG_CHECK_HIP(hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        RSG_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        if (r > 0) tmin = std::min(tmin, (double)ms);
+                    }
+                    if (rc) break;
+                    if (tmin < bt) {
+                        bt = tmin;
+                        chosen[ci] = sh;
+                    }
                 }
                 if (rc) break;
-                if (tmin < bt) {
-                    bt = tmin;
-                    bs = b->tile;
-                }
             }
-            if (rc) break;
+            b->cls[ci].tile = chosen[ci];
+            total += bt;
+            if (!rc) rc = build_class(*b, ci, s);
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        b->tile = bs;
-        const int r2 = build_tables(*b, s);
-        if (rc) return rc;
-        if (r2) return r2;
-        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, 0, 0, bs.ZM};
-        if (best_ms) *best_ms = bt;
+        if (rc) {
+            // leave a consistent batch behind: every class on its chosen tile
+            for (size_t ci = 0; ci < b->cls.size(); ++ci) b->cls[ci].tile = chosen[ci];
+            (void)build_tables(*b, s);
+            return rc;
+        }
+        if (best) rsg_batch_get_tile(b, best);
+        if (best_ms) *best_ms = total;
         return RSG_OK;
     });
 }
@@ -410,4 +602,8 @@ extern "C" int rsg_batch_propagate(rsg_batch_t b, double dt, int64_t nsteps, int
     }
     RSG_CHECK_HIP(hipGraphLaunch(exec, s));
     return RSG_OK;
+}
+
+extern "C" int rsg_batch_run(rsg_batch_t b, int64_t nsteps, double dt, void *stream) {
+    return rsg_batch_propagate(b, dt, nsteps, 1, stream);
 }

@@ -136,13 +136,23 @@ const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
     auto it = plans.find(key);
     if (it != plans.end()) return &it->second;
     const int nx = n[0], ny = n[1], nz = n[2];
-    const int ntx = (nx + s.TX - 1) / s.TX, nty = (ny + s.TY - 1) / s.TY;
+    // A tile covers a row wherever the row owns slots: its x-range widened to
+    // multiples of the alignment, so that the stencil writes the zeros of
+    // every dead slot (the widened end may pass the box's last column).
+    const int A = align;
+    int xend = nx;
+    for (const int2 &r : rows_host) {
+        const int a = r.y & 0xffff, b = (r.y >> 16) & 0xffff;
+        if (a < b) xend = std::max(xend, (b + A - 1) & -A);
+    }
+    const int ntx = (xend + s.TX - 1) / s.TX, nty = (ny + s.TY - 1) / s.TY;
     std::vector<int> zlo((size_t)ntx * nty, nz), zhi((size_t)ntx * nty, -1);
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
             const int2 r = rows_host[(size_t)z * ny + y];
-            const int a = r.y & 0xffff, b = (r.y >> 16) & 0xffff;
-            if (a >= b) continue;
+            const int a0 = r.y & 0xffff, b0 = (r.y >> 16) & 0xffff;
+            if (a0 >= b0) continue;
+            const int a = a0 & -A, b = (b0 + A - 1) & -A;
             const int ty = y / s.TY;
             for (int tx = a / s.TX; tx <= (b - 1) / s.TX; ++tx) {
                 const size_t k = (size_t)ty * ntx + tx;

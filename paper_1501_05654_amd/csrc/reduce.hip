@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(RB) k_reduce_partial(RArgs r) {
         } else if (KIND == 1) {
             re += va.x * va.x + va.y * va.y;
         } else {
-            const double xc = r.h * ((double)r.ijk[3 * p + r.axis] - r.off);
+            const int32_t c = r.ijk[3 * p + r.axis];  // -1: dead slot of a row-aligned grid
+            const double xc = c < 0 ? 0.0 : r.h * ((double)c - r.off);
             re += xc * (va.x * va.x + va.y * va.y);
         }
     }
@@ -147,7 +148,8 @@ __global__ void __launch_bounds__(RB) k_adjoint_pass(XArgs r) {
     double re = 0.0, im = 0.0;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += RB) {
         const int64_t e = n * r.ldp + p;
-        const double xc = r.h * ((double)r.ijk[3 * p + r.axis] - r.off);
+        const int32_t c = r.ijk[3 * p + r.axis];  // -1: dead slot of a row-aligned grid
+        const double xc = c < 0 ? 0.0 : r.h * ((double)c - r.off);
         double2 nu[4], mu[5];
 #pragma unroll
         for (int m = 0; m < 4; ++m) nu[m] = r.nu[m][e];
@@ -203,7 +205,8 @@ __global__ void k_mul_axis(PwArgs a) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.np;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t e = base + p;
-        const double xc = a.h * ((double)a.ijk[3 * p + a.axis] - a.off);
+        const int32_t c = a.ijk[3 * p + a.axis];  // -1: dead slot of a row-aligned grid
+        const double xc = c < 0 ? 0.0 : a.h * ((double)c - a.off);
         const double2 v = a.src[0][e];
         a.dst[e] = make_double2(xc * v.x, xc * v.y);
     }

@@ -284,3 +284,35 @@ def test_aligned_tiny_boxes():
         R.propagate_step(s.gh, psi, 0.01)
         assert orbital_rel_err(s.from_gpu(psi), oracle.taylor_step(s.oh, s.psi, 0.01), 2) <= TOL, kw
         assert np.all(s.dead_values(psi) == 0), kw
+
+
+@pytest.mark.parametrize("align,tile", [(16, (1, 8, 8, 0, 1, 0, 1, 0)), (16, (1, 8, 8, 3, 2, 1, 0, 1)),
+                                        (32, (1, 16, 8, 0, 1, 0, 2, 0)), (64, (1, 32, 16, 0, 2, 0, 1, 0))])
+def test_tiles_narrower_than_alignment(align, tile):
+    """Tiles narrower than the row alignment: the launch plan covers each
+    row's widened x-range (which may pass the box's last column), so every
+    output zeroes every dead slot, and H psi, a step and an adjoint step
+    still equal the oracle on the live slots."""
+    import synth
+    R = rsg()
+    s = System(0.3, R=3.6, potential="wells", natoms=3, nst=3, ld=4, seed=17, dipole_axis=1,
+               well_ball=1.0, rcut=1.2, pad=2, align=align)
+    assert s.gg.np % align == 0 and s.gg.np > s.og.np
+    R.set_tile(s.gh, s.nst, *tile)
+    psi = s.to_gpu(s.psi)
+    out = torch.full_like(psi, 4.0 - 1.0j)
+    R.hpsi(s.gh, psi, field=0.05, out=out, nst=s.nst)
+    assert orbital_rel_err(s.from_gpu(out), oracle.hpsi(s.oh, s.psi, field=0.05, nst=s.nst), s.nst) <= TOL
+    assert np.all(s.dead_values(out)[:s.nst] == 0)
+    x = psi.clone()
+    R.propagate_step(s.gh, x, 0.01, field=0.05, nst=s.nst)
+    assert orbital_rel_err(s.from_gpu(x), oracle.taylor_step(s.oh, s.psi, 0.01, field=0.05, nst=s.nst),
+                           s.nst) <= TOL
+    assert np.all(s.dead_values(x) == 0) and s.pad_untouched(x)
+    lam0 = synth.white_noise(33, s.og.np, 3, s.og.h, ld=4)
+    lam_ref, g_ref = oracle.adjoint_step(s.oh, s.psi, lam0, 0.02, 0.15, nst=3)
+    lam = s.to_gpu(lam0)
+    g = R.adjoint_step(s.gh, psi, lam, 0.02, 0.15, nst=3).item()
+    assert orbital_rel_err(s.from_gpu(lam), lam_ref, 3) <= TOL
+    assert g == pytest.approx(g_ref, rel=1e-11, abs=1e-14)
+    assert np.all(s.dead_values(lam)[:3] == 0)

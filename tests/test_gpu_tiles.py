@@ -91,3 +91,30 @@ def test_every_mixed_tile_agrees(sys_):
         else:
             # each point's arithmetic does not depend on the tile
             np.testing.assert_allclose(xs, first, rtol=0, atol=1e-6 * np.abs(first).max())
+
+
+def test_autotune_cache_second_handle_launches_nothing(tmp_path):
+    """rsg_autotune_cache: the first handle times the candidates and appends
+    its choice to the cache file; a second handle on a grid of the same shape
+    finds the key and takes the same tile without launching a stencil, and
+    its step still equals the oracle.  A different orbital count is a
+    different key and is timed again."""
+    R = rsg()
+    path = str(tmp_path / "tiles.txt")
+    a = System(0.3, R=2.8, potential="wells", natoms=1, nst=3, seed=21, rcut=1.2)
+    psi = a.to_gpu(a.psi)
+    with R.kernel_timing() as k1:
+        t1, ms1, hit1 = R.autotune_cached(a.gh, psi, path, reps=1)
+    assert not hit1 and k1.count > 0 and ms1 > 0
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and "nst=3" in lines[0]
+    b = System(0.3, R=2.8, potential="wells", natoms=1, nst=3, seed=22, rcut=1.2)
+    psib = b.to_gpu(b.psi)
+    with R.kernel_timing() as k2:
+        t2, ms2, hit2 = R.autotune_cached(b.gh, psib, path, reps=1)
+    assert hit2 and k2.count == 0 and t2 == t1 and ms2 == pytest.approx(ms1, rel=1e-6)
+    assert R.get_tile(b.gh, 3) == t1
+    R.propagate_step(b.gh, psib, 0.01)
+    assert orbital_rel_err(b.from_gpu(psib), oracle.taylor_step(b.oh, b.psi, 0.01), 3) <= 1e-12
+    _, _, hit3 = R.autotune_cached(b.gh, psib[:2], path, reps=1, nst=2)
+    assert not hit3 and len(open(path).read().splitlines()) == 2
