@@ -183,7 +183,8 @@ namespace {
 // One Taylor stage: out = base + c H(in) (base = in in a product-form step).
 int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *out, int out_t,
                int compute, int64_t nst, int64_t ldp, double cre, double cim, double field,
-               const double *field_dev, void *D, hipStream_t s, const double *mask = nullptr) {
+               const double *field_dev, void *D, hipStream_t s, const double *mask = nullptr,
+               const void *pair_y = nullptr, double *pair_out = nullptr) {
     int rc = launch_kb_gather(H, in, in_t, compute, nst, ldp, D, s);
     if (rc) return rc;
     StageArgs a;
@@ -202,6 +203,8 @@ int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *o
     a.cim = cim;
     a.first = in == base;
     a.mask = mask;
+    a.pair_y = pair_y;
+    a.pair_out = pair_out;
     rc = launch_stencil(H, a, H.tile_for(nst, compute), s);
     if (rc) return rc;
     return launch_kb_scatter(H, out, out_t, compute, nst, ldp, D, cre, cim, mask, s);
@@ -308,9 +311,16 @@ int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t
     return stage_impl(H, w1, wt, psi, psi_out, 0, cmp, nst, ldp, 0.0, -dt, field, field_dev, D, s, H.mask);
 }
 
+// Pair partials of one adjoint stage: one complex value per stencil
+// workgroup of H's FP64 tile for nst orbitals.
+int64_t adjoint_pair_blocks(const Ham &H, int64_t nst) {
+    const int64_t nb = stencil_blocks(H, nst, 0, nullptr);
+    return nb < 0 ? 0 : nb;
+}
+
 size_t adjoint_product_ws(const Ham &H, int64_t nst, int64_t ldp) {
     return 3 * rounded(batch_bytes(nst, ldp, 16)) + rounded(kb_workspace_bytes(H, nst)) +
-           rounded(reduce_workspace_bytes(*H.g, nst)) + 256;
+           rounded(4 * (size_t)adjoint_pair_blocks(H, nst) * 16) + 256;
 }
 
 // Discrete adjoint of a product-form step psi_{n+1} = F4 F3 F2 F1 psi_n,
@@ -319,8 +329,10 @@ size_t adjoint_product_ws(const Ham &H, int64_t nst, int64_t ldp) {
 // F_k^+ m_k (F_k^+ = 1 + conj(a_k) H, H Hermitian):
 //   lambda_n = m_0,   dJ/dE_n = 2 Re sum_{k=1}^{4} a_k <m_k | x_axis | y[k-1]>,
 // the derivative of the product by the rule for each factor (dF_k/dE =
-// a_k x_axis).  Stencil work: four first-type stages on the costate and one
-// pass over the four pairs.
+// a_k x_axis).  Four first-type stencil stages on the costate; the stage
+// that reads m_k also reads y[k-1] at each point and sums its pair term, so
+// the pairs cost 16 B per point and orbital each and no separate pass; one
+// small kernel adds the per-workgroup partials in a fixed order.
 int adjoint_product_impl(const Ham &H, const void *const y[4], void *lambda, int64_t nst, int64_t ldp, double dt,
                          double field, const double *field_dev, double *g_dev, void *ws, size_t ws_bytes,
                          hipStream_t s) {
@@ -330,34 +342,25 @@ int adjoint_product_impl(const Ham &H, const void *const y[4], void *lambda, int
     m[4] = lambda;
     for (int k = 1; k < 4; ++k) m[k] = c.take(bb);
     void *D = c.take(kb_workspace_bytes(H, nst));
-    const size_t rb = reduce_workspace_bytes(*H.g, nst);
-    void *R = c.take(rb);
+    const int64_t nb = stencil_blocks(H, nst, 0, s);
+    if (nb < 0) return (int)nb;
+    double *P = (double *)c.take(4 * (size_t)nb * 16);
     if (!c.ok) {
         set_error("adjoint: workspace too small (%zu < %zu bytes)", ws_bytes, adjoint_product_ws(H, nst, ldp));
         return RSG_ENOMEM;
     }
     int rc;
-    for (int k = 4; k >= 2; --k) {
-        const std::complex<double> a = std::conj(factor_coef(k - 1, dt));
-        if ((rc = stage_impl(H, m[k], 0, m[k], m[k - 1], 0, 0, nst, ldp, a.real(), a.imag(), field, field_dev, D, s)))
+    double2 ak[4];
+    for (int k = 4; k >= 1; --k) {
+        const std::complex<double> a = factor_coef(k - 1, dt);
+        ak[k - 1] = make_double2(a.real(), a.imag());
+        const std::complex<double> ca = std::conj(a);
+        void *out = k > 1 ? m[k - 1] : lambda;  // lambda_{n+1} (= m_4) was read by the first of these stages
+        if ((rc = stage_impl(H, m[k], 0, m[k], out, 0, 0, nst, ldp, ca.real(), ca.imag(), field, field_dev, D, s,
+                             nullptr, y[k - 1], P + 2 * (size_t)nb * (k - 1))))
             return rc;
     }
-    // pairs (m_k, y[k-1]) at (l, 3 - l) of the pass, l = k - 1
-    double2 pc[16], ca[5];
-    for (int q = 0; q < 16; ++q) pc[q] = make_double2(0.0, 0.0);
-    for (int l = 0; l < 4; ++l) {
-        const std::complex<double> a = factor_coef(l, dt);
-        pc[4 * l + (3 - l)] = make_double2(a.real(), a.imag());
-    }
-    for (int k = 0; k < 5; ++k) ca[k] = make_double2(0.0, 0.0);
-    const double2 *mup[5] = {(const double2 *)m[1], (const double2 *)m[2], (const double2 *)m[3],
-                             (const double2 *)m[4], (const double2 *)m[4]};
-    const double2 *nup[4] = {(const double2 *)y[3], (const double2 *)y[2], (const double2 *)y[1],
-                             (const double2 *)y[0]};
-    if ((rc = launch_adjoint_pass(*H.g, H.axis, mup, nup, pc, ca, nullptr, nst, ldp, g_dev, R, rb, s))) return rc;
-    // lambda_n = F_1^+ m_1, over lambda_{n+1} (read by the pass above)
-    const std::complex<double> a1 = std::conj(factor_coef(0, dt));
-    return stage_impl(H, m[1], 0, m[1], lambda, 0, 0, nst, ldp, a1.real(), a1.imag(), field, field_dev, D, s);
+    return launch_pair_final(P, nb, ak, H.g->h * H.g->h * H.g->h, g_dev, s);
 }
 
 // One adjoint step from psi_n alone: its three stage outputs recomputed
@@ -688,11 +691,8 @@ extern "C" int rsg_propagate(rsg_ham_t H, void *psi, int64_t nst, int64_t ldp, i
     RSG_REQUIRE(s != nullptr, RSG_EINVAL, "rsg_propagate: graph capture needs a non-default stream");
     // make sure every launch plan exists before capture (plan creation syncs)
     int err = RSG_OK;
-    for (int cmp = 0; cmp < 2; ++cmp) {
-        TileShape sh = H->tile_for(nst, cmp);
-        if (sh.ZC <= 0) sh.ZC = H->g->n[2];
-        if (!H->g->plan(sh, s, &err)) return err;
-    }
+    for (int cmp = 0; cmp < 2; ++cmp)
+        if (!H->g->plan(launch_shape(*H, H->tile_for(nst, cmp)), s, &err)) return err;
     GraphKey key{psi, nst, ldp, dtype, dt, nsteps, fields_dev, ws, ws_bytes, s};
     hipGraphExec_t exec = nullptr;
     {
@@ -1252,7 +1252,7 @@ extern "C" int rsg_autotune_cache(rsg_ham_t H, const void *psi, int64_t nst, int
         if (best_ms) *best_ms = ms;
         FILE *f = std::fopen(cache_path, "a");
         RSG_REQUIRE(f, RSG_EINVAL, "rsg_autotune_cache: cannot append to %s", cache_path);
-        std::fprintf(f, "%s | %d %d %d %d %d %d %d %d | %.6f\n", key.c_str(), t.B, t.TX, t.TY, t.ZC, t.PD, t.PT,
+        std::fprintf(f, "%s | %d %d %d %d %d %d %d %d | %.17g\n", key.c_str(), t.B, t.TX, t.TY, t.ZC, t.PD, t.PT,
                      t.BO, t.ZM, ms);
         const bool ok = std::fclose(f) == 0;
         RSG_REQUIRE(ok, RSG_EINVAL, "rsg_autotune_cache: writing %s failed", cache_path);

@@ -124,70 +124,34 @@ __global__ void __launch_bounds__(RB) k_reduce_final(const double *part, int64_t
     }
 }
 
-// Adjoint pass: per orbital, the pair sum sum_r sum_{l+m<=3} coef[l][m]
-// conj(mu_l) x nu_m, and the new costate lam = sum_k ca[k] mu_k (k = 0..4)
-// written at the same point in the same pass.
-struct XArgs {
-    const double2 *mu[5];
-    const double2 *nu[4];
-    double2 coef[4][4];
-    double2 ca[5];
-    double2 *lam;
-    const int32_t *ijk;
-    int64_t np, nst, ldp, chunk;
-    double h, off;
-    int32_t axis;
-    double *part;
-};
-
-__global__ void __launch_bounds__(RB) k_adjoint_pass(XArgs r) {
-    __shared__ double red[RB / 64][2];
-    const int64_t n = blockIdx.y;
-    const int64_t p0 = (int64_t)blockIdx.x * r.chunk;
-    const int64_t p1 = min(r.np, p0 + r.chunk);
-    double re = 0.0, im = 0.0;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += RB) {
-        const int64_t e = n * r.ldp + p;
-        const int32_t c = r.ijk[3 * p + r.axis];  // -1: dead slot of a row-aligned grid
-        const double xc = c < 0 ? 0.0 : r.h * ((double)c - r.off);
-        double2 nu[4], mu[5];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) nu[m] = r.nu[m][e];
-#pragma unroll
-        for (int l = 0; l < 5; ++l) mu[l] = r.mu[l][e];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            double wr = 0.0, wi = 0.0;  // w_l = sum_m coef[l][m] nu_m
-#pragma unroll
-            for (int m = 0; m + l < 4; ++m) {
-                wr += r.coef[l][m].x * nu[m].x - r.coef[l][m].y * nu[m].y;
-                wi += r.coef[l][m].x * nu[m].y + r.coef[l][m].y * nu[m].x;
+// g = 2 Re sum_k a_k h3 sum_b P[k][b]: one workgroup, strided partial sums
+// then a fixed tree per stage.
+__global__ void __launch_bounds__(RB) k_pair_final(const double2 *P, int64_t nb, double2 a0, double2 a1,
+                                                   double2 a2, double2 a3, double h3, double *g) {
+    __shared__ double red[RB][2];
+    const int t = threadIdx.x;
+    const double2 a[4] = {a0, a1, a2, a3};
+    double acc = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int64_t b = t; b < nb; b += RB) {
+            re += P[(int64_t)k * nb + b].x;
+            im += P[(int64_t)k * nb + b].y;
+        }
+        red[t][0] = re;
+        red[t][1] = im;
+        __syncthreads();
+        for (int w = RB / 2; w > 0; w >>= 1) {
+            if (t < w) {
+                red[t][0] += red[t + w][0];
+                red[t][1] += red[t + w][1];
             }
-            re += xc * (mu[l].x * wr + mu[l].y * wi);
-            im += xc * (mu[l].x * wi - mu[l].y * wr);
+            __syncthreads();
         }
-        double lr = 0.0, li = 0.0;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            lr += r.ca[k].x * mu[k].x - r.ca[k].y * mu[k].y;
-            li += r.ca[k].x * mu[k].y + r.ca[k].y * mu[k].x;
-        }
-        if (r.lam) r.lam[e] = make_double2(lr, li);
+        if (t == 0) acc += a[k].x * red[0][0] - a[k].y * red[0][1];  // Re(a_k S_k)
+        __syncthreads();
     }
-    block_sum(re, im, red);
-    if (threadIdx.x == 0) {
-        r.part[((int64_t)blockIdx.x * r.nst + n) * 2 + 0] = re;
-        r.part[((int64_t)blockIdx.x * r.nst + n) * 2 + 1] = im;
-    }
-}
-
-// g = 2 Re sum_n h^3 S_n for the per-orbital complex sums S_n; added to *dst
-// when accumulate != 0.
-__global__ void k_two_re_sum(const double *per, int64_t nst, double *dst) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double g = 0.0;
-    for (int64_t s = 0; s < nst; ++s) g += per[2 * s];
-    *dst = 2.0 * g;
+    if (t == 0) *g = 2.0 * h3 * acc;
 }
 
 struct PwArgs {
@@ -265,43 +229,8 @@ int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const dou
     return RSG_OK;
 }
 
-int launch_adjoint_pass(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
-                        const double2 *pair_coef, const double2 *lam_coef, double2 *lam, int64_t nst,
-                        int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s) {
-    if (ws_bytes < reduce_workspace_bytes(g, nst)) {
-        set_error("adjoint reduction workspace too small");
-        return RSG_ENOMEM;
-    }
-    if (nst > 65535) {
-        set_error("adjoint: at most 65535 orbitals per call");
-        return RSG_EUNSUPPORTED;
-    }
-    const int64_t nblk = reduce_blocks(g.np);
-    XArgs r;
-    for (int k = 0; k < 5; ++k) {
-        r.mu[k] = mu[k];
-        r.ca[k] = lam_coef[k];
-    }
-    for (int k = 0; k < 4; ++k) {
-        r.nu[k] = nu[k];
-        for (int m = 0; m < 4; ++m) r.coef[k][m] = pair_coef[4 * k + m];
-    }
-    r.lam = lam;
-    r.ijk = g.ijk;
-    r.np = g.np;
-    r.nst = nst;
-    r.ldp = ldp;
-    r.chunk = (g.np + nblk - 1) / nblk;
-    r.h = g.h;
-    r.axis = axis;
-    r.off = 0.5 * (double)(g.n[axis] - 1);
-    r.part = (double *)ws;
-    double *per = r.part + nblk * nst * 2;
-    const dim3 grid((unsigned)nblk, (unsigned)nst);
-    k_adjoint_pass<<<grid, RB, 0, s>>>(r);
-    const double h3 = g.h * g.h * g.h;
-    k_reduce_final<<<(unsigned)nst, RB, 0, s>>>(r.part, nblk, nst, 2, h3, per);
-    k_two_re_sum<<<1, 64, 0, s>>>(per, nst, out);
+int launch_pair_final(const double *P, int64_t nb, const double2 a[4], double h3, double *g, hipStream_t s) {
+    k_pair_final<<<1, RB, 0, s>>>((const double2 *)P, nb, a[0], a[1], a[2], a[3], h3, g);
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }

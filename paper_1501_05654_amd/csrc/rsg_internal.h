@@ -161,6 +161,12 @@ struct StageArgs {
     int in_t = 0, out_t = 0, compute = 0, mode = 0;
     bool first = false;  // base == in (every stage but the last of a mixed or masked step)
     const double *mask = nullptr;  // mode 1: out = mask * (base + c H in)
+    // Adjoint pair (first-type FP64 stages only): with pair_y set, the stage
+    // also sums conj(in) x_axis pair_y over the points it computes, one
+    // complex partial per workgroup, written to pair_out at the workgroup's
+    // place in the launch order (stencil_blocks entries).
+    const void *pair_y = nullptr;
+    double *pair_out = nullptr;
     int64_t nst = 0, ldp = 0;
     double field = 0;
     const double *field_dev = nullptr;
@@ -179,6 +185,8 @@ struct KParams {
     const double *field_dev;
     const double *mask;
     const double *Vim;  // imaginary part of the local potential (complex scaling) or null
+    const void *pair_y; // adjoint pair operand, or null
+    double *pair_out;   // adjoint pair partials [blocks][2]
     int64_t nst, ldp, np;
     double kin_h2;
     double kin_h2_im;   // imaginary part of the kinetic prefactor over h^2 (complex scaling)
@@ -200,6 +208,15 @@ struct BatchItem {
 };
 KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, const TilePlan *plan);
 int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hipStream_t s);
+// The tile shape a stencil launch of H really runs for the requested one:
+// complex-scaled Hamiltonians have kernels for a few depth-1 shapes only
+// (another depth maps to depth 1 of the same tile, another tile to 16 x 8);
+// ZC = 0 becomes the whole z-extent.
+TileShape launch_shape(const Ham &H, const TileShape &tile);
+// Workgroups of one stencil launch of nst orbitals with H's tile for this
+// precision (the number of pair partials of an adjoint stage), or a negative
+// error code.  May create the tile's launch plan (not during capture).
+int64_t stencil_blocks(const Ham &H, int64_t nst, int compute, hipStream_t s);
 // ctr: two device int32 work counters, zero before the first launch (each
 // launch leaves them zero again); launches sharing them must not overlap.
 int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
@@ -305,14 +322,9 @@ int launch_reduce(const Grid &g, int kind, int axis, const double2 *a, const dou
 // Pointwise helpers.
 int launch_mul_axis(const Grid &g, int axis, const double2 *src, double2 *dst, int64_t nst,
                     int64_t ldp, hipStream_t s);
-// One pass of the discrete adjoint over mu_0..mu_4 (H^k lambda_{n+1}) and
-// nu_0..nu_3 (H^m psi_n): *out = 2 Re sum_n h^3 sum_r sum_{l+m<=3}
-// pair_coef[4l+m] conj(mu_l) x_axis nu_m, and lam = sum_k lam_coef[k] mu_k
-// (lam may be mu_0: each point is read before it is written; lam = NULL
-// writes nothing).
-int launch_adjoint_pass(const Grid &g, int axis, const double2 *const *mu, const double2 *const *nu,
-                        const double2 *pair_coef, const double2 *lam_coef, double2 *lam, int64_t nst,
-                        int64_t ldp, double *out, void *ws, size_t ws_bytes, hipStream_t s);
+// g = 2 Re sum_{k=1}^{4} a[k-1] h3 sum_b P[k-1][b] over the pair partials
+// P[4][nb] (complex) of the four adjoint stages, summed in a fixed order.
+int launch_pair_final(const double *P, int64_t nb, const double2 a[4], double h3, double *g, hipStream_t s);
 int launch_accumulate(const double *src, double *dst, hipStream_t s);
 
 // Kernel timing hooks around stencil launches.

@@ -212,15 +212,23 @@ struct Halo {
 // The per-point epilogue shared by both marches: H value from the Laplacian
 // taps, then the stage combination (times the absorber mask m_c when MASK),
 // stored at idx (dropped when idx = -1; zero at the dead slot -idx - 2 when
-// idx <= -2).
-template <class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
+// idx <= -2).  PAIR (a first-type FP64 stage of the discrete adjoint): b_c
+// holds the pair operand u at the point, and pacc gathers conj(in) x_axis u
+// (zero wherever the point is outside the box, since both loads read zero
+// there).
+template <class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS, bool PAIR = false>
 __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0, Tc lr, Tc li, Tc v_c,
                                        Tc vi_c, double2 b_c, double m_c, double E, int x, int y, int z,
-                                       int idx, __amdgpu_buffer_rsrc_t rout) {
+                                       int idx, __amdgpu_buffer_rsrc_t rout, double2 &pacc) {
     Tc vloc = v_c;
     if (a.axis >= 0) {
         const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
-        vloc += (Tc)(E * (a.h * ((double)cc - a.off[a.axis])));
+        const double xc = a.h * ((double)cc - a.off[a.axis]);
+        vloc += (Tc)(E * xc);
+        if constexpr (PAIR) {
+            pacc.x += xc * ((double)q0.x * b_c.x + (double)q0.y * b_c.y);
+            pacc.y += xc * ((double)q0.x * b_c.y - (double)q0.y * b_c.x);
+        }
     }
     const Tc kin_h2 = (Tc)a.kin_h2;
     Tc hr, hi;
@@ -263,9 +271,10 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
 // All rings are indexed by compile-time constants after unrolling the step
 // loop by a common period, so no register is moved while its load is in
 // flight.  FIRST: base == in, whose value at the point is the centre tap.
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS,
+          bool PAIR>
 __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, const int n,
-                                           typename CT<Tc>::c2 *tile) {
+                                           typename CT<Tc>::c2 *tile, double2 &pacc) {
     using C2 = typename CT<Tc>::c2;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
@@ -280,7 +289,8 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     const int x = it.x * TX + lx, y = it.y * TY + ly;
     const int64_t np = a.np;
     const auto rin = rsrc(static_cast<const Tin *>(a.in) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tin));
-    const auto rbase = rsrc(static_cast<const double2 *>(a.base) + (int64_t)n * a.ldp, np * 16);
+    // the base operand (later stages), or the pair operand of an adjoint stage
+    const auto rbase = rsrc(static_cast<const double2 *>(PAIR ? a.pair_y : a.base) + (int64_t)n * a.ldp, np * 16);
     const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
     const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
     const auto rm = rsrc(MASK ? a.mask : a.V, MASK ? np * 8 : 0);
@@ -290,7 +300,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
     auto fetch_v = [&](int idx) -> Tc { return BL<Tc>::ld(rv, boff<Tc>(idx)); };
     auto fetch_b = [&](int idx) -> double2 {
-        if (MODE != 1 || FIRST) return make_double2(0.0, 0.0);
+        if (MODE != 1 || (FIRST && !PAIR)) return make_double2(0.0, 0.0);
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
     auto fetch_m = [&](int idx) -> double { return MASK ? BL<double>::ld(rm, boff<double>(idx)) : 1.0; };
@@ -403,7 +413,8 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                      FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (zm4.y + zp4.y));
             }
 #undef SLOT
-            finish<Tc, Tout, MODE, FIRST, MASK, CS>(a, q0, lr, li, v_c, vi_c, b_c, m_c, E, x, y, z, idx_c, rout);
+            finish<Tc, Tout, MODE, FIRST, MASK, CS, PAIR>(a, q0, lr, li, v_c, vi_c, b_c, m_c, E, x, y, z, idx_c, rout,
+                                                       pacc);
             // no barrier here: the next step writes the other plane buffer,
             // and every wave has finished reading it once all have passed
             // this step's barrier
@@ -415,9 +426,10 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
 // registers and every load of plane k+1 (own column k+5, halo, V, base) is
 // issued one step ahead; a step starts by waiting for the previous step's
 // loads.  Planes run zs, zs + dir, ... as in the pipelined march.
-template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
+template <int TX, int TY, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS,
+          bool PAIR>
 __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, const int n,
-                                           typename CT<Tc>::c2 *tile) {
+                                           typename CT<Tc>::c2 *tile, double2 &pacc) {
     using C2 = typename CT<Tc>::c2;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
@@ -426,7 +438,8 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     const int x = it.x * TX + lx, y = it.y * TY + ly;
     const int64_t np = a.np;
     const auto rin = rsrc(static_cast<const Tin *>(a.in) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tin));
-    const auto rbase = rsrc(static_cast<const double2 *>(a.base) + (int64_t)n * a.ldp, np * 16);
+    // the base operand (later stages), or the pair operand of an adjoint stage
+    const auto rbase = rsrc(static_cast<const double2 *>(PAIR ? a.pair_y : a.base) + (int64_t)n * a.ldp, np * 16);
     const auto rout = rsrc(static_cast<Tout *>(a.out) + (int64_t)n * a.ldp, np * (int64_t)sizeof(Tout));
     const auto rv = rsrc(a.V, np * (int64_t)sizeof(Tc));
     const auto rm = rsrc(MASK ? a.mask : a.V, MASK ? np * 8 : 0);
@@ -436,7 +449,7 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     auto fetch = [&](int idx, bool ok) -> C2 { return load_c<Tc, Tin>(rin, ok ? boff<Tin>(idx) : OOB); };
     auto fetch_v = [&](int idx) -> Tc { return BL<Tc>::ld(rv, boff<Tc>(idx)); };
     auto fetch_b = [&](int idx) -> double2 {
-        if (MODE != 1 || FIRST) return make_double2(0.0, 0.0);
+        if (MODE != 1 || (FIRST && !PAIR)) return make_double2(0.0, 0.0);
         return BL<double2>::ld(rbase, boff<double2>(idx));
     };
     auto fetch_m = [&](int idx) -> double { return MASK ? BL<double>::ld(rm, boff<double>(idx)) : 1.0; };
@@ -509,7 +522,8 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
                  FD<Tc>::c3 * ((xm3.y + xp3.y) + (ym3.y + yp3.y) + (q[1].y + q[7].y)) +
                  FD<Tc>::c4 * ((xm4.y + xp4.y) + (ym4.y + yp4.y) + (q[0].y + q[8].y));
         }
-        finish<Tc, Tout, MODE, FIRST, MASK, CS>(a, q0, lr, li, v_c, vi_c, b_c, m_c, E, x, y, z, idx_c, rout);
+        finish<Tc, Tout, MODE, FIRST, MASK, CS, PAIR>(a, q0, lr, li, v_c, vi_c, b_c, m_c, E, x, y, z, idx_c, rout,
+                                                       pacc);
 #pragma unroll
         for (int j = 0; j < 8; ++j) q[j] = q[j + 1];
         idx_c = idx_n;
@@ -520,16 +534,40 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     }
 }
 
-template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS>
-__device__ __forceinline__ void march(const KParams &a, const int4 it, const int n, typename CT<Tc>::c2 *tile) {
+template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK, bool CS,
+          bool PAIR = false>
+__device__ __forceinline__ void march(const KParams &a, const int4 it, const int n, typename CT<Tc>::c2 *tile,
+                                      double2 &pacc) {
     if constexpr (D == 0)
-        march_lean<TX, TY, Tin, Tc, Tout, MODE, FIRST, MASK, CS>(a, it, n, tile);
+        march_lean<TX, TY, Tin, Tc, Tout, MODE, FIRST, MASK, CS, PAIR>(a, it, n, tile, pacc);
     else
-        march_ring<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK, CS>(a, it, n, tile);
+        march_ring<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK, CS, PAIR>(a, it, n, tile, pacc);
+}
+
+// Sum of v over the workgroup (xor shuffles within each wave, then the wave
+// totals in wave order through LDS); thread 0 gets the result.  The caller's
+// LDS buffer must be free: a barrier precedes its reuse.
+template <int NT>
+__device__ __forceinline__ double2 wg_sum(double2 v, double2 *lds) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        v.x += __shfl_xor(v.x, off);
+        v.y += __shfl_xor(v.y, off);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (NT + 63) / 64; ++w) {
+            s.x += lds[w].x;
+            s.y += lds[w].y;
+        }
+    return s;
 }
 
 template <int TX, int TY, int D, class Tin, class Tc, class Tout, int MODE, bool FIRST, bool MASK = false,
-          bool CS = false>
+          bool CS = false, bool PAIR = false>
 __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     __shared__ typename CT<Tc>::c2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -539,7 +577,14 @@ __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     // scalar registers (no per-lane loop around each buffer instruction)
     n = __builtin_amdgcn_readfirstlane(n);
     item = __builtin_amdgcn_readfirstlane(item);
-    march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK, CS>(a, a.items[item], n, tile);
+    double2 pacc = make_double2(0.0, 0.0);
+    march<TX, TY, D, Tin, Tc, Tout, MODE, FIRST, MASK, CS, PAIR>(a, a.items[item], n, tile, pacc);
+    if constexpr (PAIR) {
+        // this workgroup's part of the pair sum, at its place in the launch
+        // order (a fixed position, so the final sum has a fixed order)
+        const double2 s = wg_sum<TX * TY>(pacc, reinterpret_cast<double2 *>(tile));
+        if (threadIdx.x == 0) reinterpret_cast<double2 *>(a.pair_out)[blk] = s;
+    }
 }
 
 // Persistent form over many independent systems (FP64): each workgroup
@@ -568,8 +613,9 @@ __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__rest
         KParams a = sysp[__builtin_amdgcn_readfirstlane(bi.sys)];
         a.cre = cre;
         a.cim = cim;
+        double2 unused = make_double2(0.0, 0.0);
         march<TX, TY, D, double2, double, double2, 1, FIRST, false, false>(
-            a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile);
+            a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile, unused);
         __syncthreads();  // the next item reuses the plane buffer
     }
     if (threadIdx.x == 0) {
@@ -586,7 +632,7 @@ __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__rest
 template <int TX, int TY, int D>
 int launch_fp64_cs(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
     constexpr int NT = TX * TY;
-    if (a.in_t != 0 || a.out_t != 0 || a.mask) return RSG_EUNSUPPORTED;
+    if (a.in_t != 0 || a.out_t != 0 || a.mask || a.pair_y) return RSG_EUNSUPPORTED;
     if (a.mode == 0)
         k_stencil<TX, TY, D, double2, double, double2, 0, false, false, true><<<nb, NT, 0, s>>>(p);
     else if (a.first)
@@ -600,8 +646,11 @@ template <int TX, int TY, int D>
 int launch_fp64(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
     constexpr int NT = TX * TY;
     if (a.in_t != 0 || a.out_t != 0) return RSG_EUNSUPPORTED;
+    if (a.pair_y && !(a.mode == 1 && a.first && !a.mask)) return RSG_EUNSUPPORTED;
     if (a.mode == 0)
         k_stencil<TX, TY, D, double2, double, double2, 0, false><<<nb, NT, 0, s>>>(p);
+    else if (a.pair_y)
+        k_stencil<TX, TY, D, double2, double, double2, 1, true, false, false, true><<<nb, NT, 0, s>>>(p);
     else if (a.first)
         k_stencil<TX, TY, D, double2, double, double2, 1, true><<<nb, NT, 0, s>>>(p);
     else if (a.mask)
@@ -617,7 +666,7 @@ int launch_fp64(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
 template <int TX, int TY, int D>
 int launch_fp32(const StageArgs &a, const KParams &p, int nb, hipStream_t s) {
     constexpr int NT = TX * TY;
-    if (a.mode != 1) return RSG_EUNSUPPORTED;
+    if (a.mode != 1 || a.pair_y) return RSG_EUNSUPPORTED;
     if (a.in_t == 0 && a.out_t == 1 && a.first)
         k_stencil<TX, TY, D, double2, float, float2, 1, true><<<nb, NT, 0, s>>>(p);
     else if (a.in_t == 1 && a.out_t == 1 && a.first)
@@ -704,6 +753,8 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     p.V = a.compute == 0 ? (const void *)H.V : (const void *)H.V32;
     p.field_dev = a.field_dev;
     p.mask = a.mask;
+    p.pair_y = a.pair_y;
+    p.pair_out = a.pair_out;
     p.nst = a.nst;
     p.ldp = a.ldp;
     p.np = g.np;
@@ -730,18 +781,9 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     return p;
 }
 
-int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &tile, hipStream_t s) {
-    const Grid &g = *H.g;
-    int err = RSG_OK;
-    const bool cs = H.complex_scaled();
+TileShape launch_shape(const Ham &H, const TileShape &tile) {
     TileShape shape = tile;
-    if (cs) {
-        if (a.compute != 0) {
-            set_error("stencil: a complex-scaled Hamiltonian needs the FP64 path");
-            return RSG_EUNSUPPORTED;
-        }
-        // complex-scaled kernels exist for a few depth-1 shapes: another
-        // depth maps to depth 1 of the same tile, another tile to 16 x 8
+    if (H.complex_scaled()) {
         bool have = false;
 #define RSG_CS_HAVE(X_, Y_, D_) have = have || (shape.TX == X_ && shape.TY == Y_);
         RSG_CS_SHAPES(RSG_CS_HAVE)
@@ -752,9 +794,27 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &tile, hipS
             shape.TY = 8;
         }
     }
-    TileShape key = shape;
-    if (key.ZC <= 0) key.ZC = g.n[2];
-    const TilePlan *plan = const_cast<Grid &>(g).plan(key, s, &err);
+    if (shape.ZC <= 0) shape.ZC = H.g->n[2];
+    return shape;
+}
+
+int64_t stencil_blocks(const Ham &H, int64_t nst, int compute, hipStream_t s) {
+    int err = RSG_OK;
+    const TilePlan *plan = H.g->plan(launch_shape(H, H.tile_for(nst, compute)), s, &err);
+    if (!plan) return err;
+    return (int64_t)plan->nitems * nst;
+}
+
+int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &tile, hipStream_t s) {
+    const Grid &g = *H.g;
+    int err = RSG_OK;
+    const bool cs = H.complex_scaled();
+    if (cs && a.compute != 0) {
+        set_error("stencil: a complex-scaled Hamiltonian needs the FP64 path");
+        return RSG_EUNSUPPORTED;
+    }
+    const TileShape shape = launch_shape(H, tile);
+    const TilePlan *plan = const_cast<Grid &>(g).plan(shape, s, &err);
     if (!plan) return err;
     if (plan->nitems == 0 || a.nst == 0) return RSG_OK;
     if (g.np >= (int64_t)(OOB / 16)) {
