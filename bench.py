@@ -304,9 +304,13 @@ def bench_batch(args):
             tile, tms = b.autotune(reps=3)
             log(f"batch tile {tile}: {tms:.3f} ms per stage")
         # eager steps with per-launch HIP-event timing of the stencil kernel
+        # (one persistent launch per size class and stage)
+        timed_steps = max(1, args.warmup)
         with rsg.kernel_timing() as kt:
-            b.propagate(dt, max(1, args.warmup))
+            b.propagate(dt, timed_steps)
             torch.cuda.synchronize()
+        classes = b.classes()
+        class_tiles = [b.get_tile(c) for c in range(int(classes.max()) + 1)]
         b.propagate(dt, args.steps, graph=True)  # capture and first replay
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -315,8 +319,9 @@ def bench_batch(args):
         t1 = time.perf_counter()
         # one by one (eager), a few steps
         per_steps = max(1, min(5, args.steps))
-        for gh, psi, nst in systems:
-            rsg.set_tile(gh, nst, tile["B"], tile["TX"], tile["TY"], tile["ZC"], tile["PD"])
+        for (gh, psi, nst), c in zip(systems, classes):
+            t = class_tiles[c]
+            rsg.set_tile(gh, nst, t["B"], t["TX"], t["TY"], t["ZC"], t["PD"], ZM=t["ZM"])
         torch.cuda.synchronize()
         t4 = time.perf_counter()
         for gh, psi, nst in systems:
@@ -326,17 +331,20 @@ def bench_batch(args):
     el = t1 - t0
     value = tot * 4 * args.steps / el
     stage_bytes = tot * 32.0  # every stage of the product-form step: read its input, write its output
-    achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
+    stage_ms = kt.total_ms / (4 * timed_steps) if kt.count else None  # all classes' launches of a stage
+    achieved = stage_bytes / (stage_ms * 1e-3) / 1e9 if kt.count else None
     return {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batch256", "nsys": len(specs), "sum_np_nst": tot, "h_bohr": cfg["h"],
-                   "dt": dt, "tile": tile, "row_align": args.align},
+                   "dt": dt, "class_tiles": class_tiles,
+                   "class_sizes": [int((classes == c).sum()) for c in range(len(class_tiles))],
+                   "row_align": args.align},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-                     "kernel": "k_stencil_batch (persistent, all systems)",
-                     "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count},
+                     "kernel": "k_stencil_batch (persistent; one launch per size class and stage)",
+                     "stage_ms": stage_ms, "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count},
         "per_system_eager_value": tot * 4 * per_steps / (t5 - t4),
         "cpu_baseline": None,
     }
@@ -461,14 +469,14 @@ def bench_control(args):
         rsg.control_backward(gh, psi, dt, nsteps, coef, ck, store)
         torch.cuda.synchronize()
     # stencil launches of the backward sweep: per step the 4 product-form
-    # stages of the checkpoint recompute (keeping their outputs) and the 4
-    # adjoint factors on the costate, each reading its input and writing its
-    # output (32 B/pt.orb) and reading V (8 B/pt)
-    per_launch = 32 * gg.np * nst + 8 * gg.np
+    # stages of the checkpoint recompute (keeping their outputs: 32 B/pt.orb
+    # each) and the 4 adjoint factors on the costate, each of which also
+    # reads the stage output its pair term needs (48 B/pt.orb each); every
+    # launch reads V (8 B/pt)
+    per_launch = (4 * 32 + 4 * 48) / 8 * gg.np * nst + 8 * gg.np
     st_gbs = per_launch / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
-    # the whole sweep: 384 B/pt.orb + 64 B/pt per step (recompute, adjoint
-    # stages, one pass over the four stage pairs)
-    sweep_gbs = (384 * gg.np * nst + 64 * gg.np) * nsteps / bwd / 1e9
+    # the whole sweep: 320 B/pt.orb + 64 B/pt per step
+    sweep_gbs = (320 * gg.np * nst + 64 * gg.np) * nsteps / bwd / 1e9
     # central difference along a random unit direction d: (J(c+eps d) - J(c-eps d)) / 2 eps
     d = torch.from_numpy(synth.random_unit(cfg["seed"], cfg["ncoef"])).cuda()
     eps = 1e-4 * float(coef.abs().max())
@@ -887,6 +895,59 @@ def bench_gridmap(args):
     }
 
 
+def sub_results(args) -> dict:
+    """The rest of the metric, measured in the same run: the 32^3 cube's
+    50-H sequence in one graph (cache-resident), the 256-system batch, the
+    mixed-precision error after 1000 steps, and the optimal-control
+    gradient/forward time ratio at full size with its finite-difference
+    check.  Each entry is the compact form of that workload's own line."""
+    import argparse as _ap
+    import gc
+
+    import torch
+
+    def ns(**kw):
+        base = dict(vars(args))
+        base.update(tile="", tile_mixed="", no_autotune=False, nsys=0)
+        base.update(kw)
+        return _ap.Namespace(**base)
+
+    def run(name, fn, a):
+        t0 = time.perf_counter()
+        try:
+            r = fn(a)
+        finally:
+            gc.collect()
+            torch.cuda.empty_cache()
+        log(f"{name}: {time.perf_counter() - t0:.1f} s")
+        return r
+
+    out = {}
+    r = run("cube32_ho", bench_cube32, ns(steps=50, warmup=5))
+    out["cube32_ho"] = {"value": r["value"], "unit": r["unit"], "ms_per_sequence": r["ms_per_step"],
+                        "roofline_frac_cache_resident": r["roofline"]["frac"],
+                        "sequence": "10 hpsi + 10 Taylor(4) steps (50 H) in one HIP graph",
+                        "tile": r["config"]["tile"]}
+    r = run("cube32_mixed", bench_mixed, ns(steps=1000, warmup=0))
+    out["cube32_mixed"] = {"steps": r["steps"], "errors_vs_fp64_path": r["errors"],
+                           "mixed_ms_per_step": r["timing"]["white_noise"]["mixed_ms_per_step"],
+                           "fp64_ms_per_step": r["timing"]["white_noise"]["fp64_ms_per_step"]}
+    r = run("cube96_control", bench_control, ns(steps=0, warmup=0))
+    out["cube96_control"] = {"adjoint_ratio": r["value"], "unit": "gradient time / forward time",
+                             "forward_s": r["forward_s"], "gradient_s": r["gradient_s"], "steps": r["steps"],
+                             "checkpoint_every": r["config"]["checkpoint_every"], "ncoef": r["config"]["ncoef"],
+                             "fd_rel_err": r["fd_rel_err"], "directional_derivative": r["directional_derivative"],
+                             "central_fd": r["central_fd"],
+                             "sweep_algorithmic_GBs": r["roofline"]["sweep_algorithmic_GBs"]}
+    r = run("batch256", bench_batch, ns(steps=10, warmup=2, align=8))
+    out["batch256"] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
+                       "stencil_stage_ms": r["roofline"]["stage_ms"], "roofline_frac": r["roofline"]["frac"],
+                       "sum_np_nst": r["config"]["sum_np_nst"], "class_tiles": r["config"]["class_tiles"],
+                       "class_sizes": r["config"]["class_sizes"],
+                       "per_system_eager_value": r["per_system_eager_value"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -899,6 +960,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="sphere18_wells: skip the other workloads' figures (cube32_ho sequence, "
+                         "cube32_mixed error, cube96_control gradient ratio, batch256)")
     ap.add_argument("--align", type=int, default=0,
                     help="sphere workloads (sphere18_wells, sphere18_mixed, sphere18_cs, sphere500k_qmr, "
                          "batch256): row alignment of the grids' storage (1 = compact rows; default 8, "
@@ -942,6 +1006,8 @@ def main():
     else:
         out, cfg = bench_sphere(args)
         out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
+        if not args.no_sub:
+            out["sub"] = sub_results(args)
     print(json.dumps(out), flush=True)
 
 

@@ -124,6 +124,16 @@ int rsg_grid_create(const rsg_grid_desc *desc, void *stream, rsg_grid_t *out);
  * Errors as rsg_grid_create, RSG_EINVAL for a bad align. */
 int rsg_grid_create_aligned(const rsg_grid_desc *desc, int32_t align, void *stream, rsg_grid_t *out);
 
+/* Rectangular box of nx x ny x nz points (each 1..32767, fewer than 2^31 in
+ * all), positions h*(i - (n_a - 1)/2) along axis a, compact order z, y, x,
+ * row alignment as rsg_grid_create_aligned.  A box one point thick in y and
+ * z holds a one-dimensional problem: the y and z taps of the star stencil
+ * then reach only points outside the box (zero), so H is the
+ * one-dimensional Hamiltonian plus the constant 2 kin c_0 / h^2 (times
+ * e^{-2 i theta} under complex scaling).  Errors as rsg_grid_create. */
+int rsg_grid_create_box(int32_t nx, int32_t ny, int32_t nz, double h, int32_t align, void *stream,
+                        rsg_grid_t *out);
+
 /* np: slots per field (the number of box points unless the grid is
  * row-aligned); dims: tight bounding box (x, y, z); h.  Any output pointer
  * may be NULL. */

@@ -46,6 +46,8 @@ def lib():
         L.or_sphere_points.argtypes = [dbl, dbl, vp, vp]
         L.or_cube_points.restype = i64
         L.or_cube_points.argtypes = [i32, vp, vp]
+        L.or_box_points.restype = i64
+        L.or_box_points.argtypes = [i32, i32, i32, vp, vp]
         L.or_index_map.argtypes = [vp, i64, vp, vp]
         L.or_positions.argtypes = [vp, vp]
         L.or_hpsi.argtypes = [vp, vp, dbl, vp, i64, i64, vp]
@@ -96,13 +98,20 @@ class _HamS(C.Structure):
 
 
 class Grid:
-    """Uniform grid restricted to a sphere (radius R) or a cube (n per axis),
-    compact order z-major, then y, then x."""
+    """Uniform grid restricted to a sphere (radius R), a cube (n per axis) or
+    a rectangular box (box = (nx, ny, nz)), compact order z-major, then y,
+    then x."""
 
-    def __init__(self, h: float, *, R: float | None = None, n: int | None = None):
+    def __init__(self, h: float, *, R: float | None = None, n: int | None = None, box=None):
         L = lib()
         dims = np.zeros(3, dtype=np.int32)
-        if R is not None:
+        if box is not None:
+            nx, ny, nz = (int(v) for v in box)
+            npts = L.or_box_points(nx, ny, nz, _p(dims), None)
+            ijk = np.zeros((npts, 3), dtype=np.int32)
+            L.or_box_points(nx, ny, nz, _p(dims), _p(ijk))
+            self.kind = "box"
+        elif R is not None:
             npts = L.or_sphere_points(float(R), float(h), _p(dims), None)
             ijk = np.zeros((npts, 3), dtype=np.int32)
             L.or_sphere_points(float(R), float(h), _p(dims), _p(ijk))
@@ -112,7 +121,7 @@ class Grid:
             ijk = np.zeros((npts, 3), dtype=np.int32)
             L.or_cube_points(int(n), _p(dims), _p(ijk))
             self.kind = "cube"
-        self.R, self.n, self.h = R, n, float(h)
+        self.R, self.n, self.box, self.h = R, n, box, float(h)
         self.dims = dims
         self.ijk = ijk
         self.np = int(npts)

@@ -117,12 +117,12 @@ int64_t or_sphere_points(double R, double h, int32_t *dims, int32_t *ijk) {
     return np;
 }
 
-/* Cube of n points per axis. */
-int64_t or_cube_points(int32_t n, int32_t *dims, int32_t *ijk) {
+/* Rectangular box of nx x ny x nz points (every point of the tight box). */
+int64_t or_box_points(int32_t nx, int32_t ny, int32_t nz, int32_t *dims, int32_t *ijk) {
     int64_t np = 0;
-    for (int32_t k = 0; k < n; ++k)
-        for (int32_t j = 0; j < n; ++j)
-            for (int32_t i = 0; i < n; ++i) {
+    for (int32_t k = 0; k < nz; ++k)
+        for (int32_t j = 0; j < ny; ++j)
+            for (int32_t i = 0; i < nx; ++i) {
                 if (ijk) {
                     ijk[3 * np + 0] = i;
                     ijk[3 * np + 1] = j;
@@ -130,9 +130,16 @@ int64_t or_cube_points(int32_t n, int32_t *dims, int32_t *ijk) {
                 }
                 ++np;
             }
-    if (dims) dims[0] = dims[1] = dims[2] = n;
+    if (dims) {
+        dims[0] = nx;
+        dims[1] = ny;
+        dims[2] = nz;
+    }
     return np;
 }
+
+/* Cube of n points per axis. */
+int64_t or_cube_points(int32_t n, int32_t *dims, int32_t *ijk) { return or_box_points(n, n, n, dims, ijk); }
 
 /* Dense index map over the tight box. */
 void or_index_map(const int32_t *dims, int64_t np, const int32_t *ijk, int64_t *map) {

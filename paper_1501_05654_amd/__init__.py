@@ -48,6 +48,7 @@ def _load():
     sig = {
         "rsg_grid_create": (C.c_int, [vp, vp, vp]),
         "rsg_grid_create_aligned": (C.c_int, [vp, i32, vp, vp]),
+        "rsg_grid_create_box": (C.c_int, [i32, i32, i32, dbl, i32, vp, vp]),
         "rsg_grid_points": (C.c_int, [vp, vp, vp]),
         "rsg_grid_info": (C.c_int, [vp, vp, vp, vp]),
         "rsg_grid_coords": (C.c_int, [vp, vp]),
@@ -163,12 +164,17 @@ class Grid:
     the others are dead slots (coordinates -1) that inputs keep at zero.
     ``live()`` lists the slots of the box points."""
 
-    def __init__(self, h: float, *, R: float | None = None, n: int | None = None, align: int = 1):
-        if (R is None) == (n is None):
-            raise ValueError("give exactly one of R (sphere) or n (cube)")
-        d = _GridDesc(1 if R is not None else 0, int(n or 0), float(R or 0.0), float(h))
+    def __init__(self, h: float, *, R: float | None = None, n: int | None = None, box=None,
+                 align: int = 1):
+        if sum(v is not None for v in (R, n, box)) != 1:
+            raise ValueError("give exactly one of R (sphere), n (cube) or box=(nx, ny, nz)")
         self._h = C.c_void_p()
-        _check(_lib.rsg_grid_create_aligned(C.byref(d), int(align), _stream(), C.byref(self._h)))
+        if box is not None:
+            nx, ny, nz = (int(v) for v in box)
+            _check(_lib.rsg_grid_create_box(nx, ny, nz, float(h), int(align), _stream(), C.byref(self._h)))
+        else:
+            d = _GridDesc(1 if R is not None else 0, int(n or 0), float(R or 0.0), float(h))
+            _check(_lib.rsg_grid_create_aligned(C.byref(d), int(align), _stream(), C.byref(self._h)))
         np_ = C.c_int64()
         dims = (C.c_int32 * 3)()
         hh = C.c_double()

@@ -254,40 +254,20 @@ extern "C" int rsg_grid_create(const rsg_grid_desc *d, void *stream, rsg_grid_t 
     return rsg_grid_create_aligned(d, 1, stream, out);
 }
 
-extern "C" int rsg_grid_create_aligned(const rsg_grid_desc *d, int32_t align, void *stream, rsg_grid_t *out) {
-    clear_error();
-    RSG_REQUIRE(d && out, RSG_EINVAL, "rsg_grid_create: null argument");
-    RSG_REQUIRE(align >= 1 && align <= 64 && (align & (align - 1)) == 0, RSG_EINVAL,
-                "rsg_grid_create: align must be a power of two in 1..64");
-    RSG_REQUIRE(d->h > 0 && std::isfinite(d->h), RSG_EINVAL, "rsg_grid_create: h must be > 0");
-    RSG_REQUIRE(d->shape == RSG_BOX_CUBE || d->shape == RSG_BOX_SPHERE, RSG_EINVAL,
-                "rsg_grid_create: unknown box shape %d", d->shape);
-    int64_t Q = 0;
-    int32_t M = 0, nx;
-    if (d->shape == RSG_BOX_SPHERE) {
-        RSG_REQUIRE(d->radius > 0 && std::isfinite(d->radius), RSG_EINVAL,
-                    "rsg_grid_create: radius must be > 0");
-        const double q = std::floor((d->radius / d->h) * (d->radius / d->h) + 1e-9);
-        RSG_REQUIRE(q < 1.0e8, RSG_EINVAL, "rsg_grid_create: sphere too large (R/h > 10^4)");
-        Q = (int64_t)q;
-        int64_t m = (int64_t)std::sqrt((double)Q);
-        while ((m + 1) * (m + 1) <= Q) ++m;
-        while (m * m > Q) --m;
-        M = (int32_t)m;
-        nx = 2 * M + 1;
-    } else {
-        RSG_REQUIRE(d->n >= 1, RSG_EINVAL, "rsg_grid_create: cube needs n >= 1");
-        nx = d->n;
-    }
-    RSG_REQUIRE(nx < 32768, RSG_EINVAL, "rsg_grid_create: box wider than 32767 points");
+// Builds a grid of the given shape: a sphere (Q, M as above, nx = ny = nz
+// = 2M + 1) or a box of nx x ny x nz points.
+static int grid_create(int32_t shape, int32_t nx, int32_t ny, int32_t nz, int64_t Q, int32_t M, double h,
+                       int32_t align, void *stream, rsg_grid_t *out) {
     return guarded([&]() -> int {
         hipStream_t s = (hipStream_t)stream;
         auto *g = new rsg_grid_s();
-        g->shape = d->shape;
+        g->shape = shape;
         g->align = align;
-        g->n[0] = g->n[1] = g->n[2] = nx;
-        g->h = d->h;
-        const int64_t nrows = (int64_t)nx * nx;
+        g->n[0] = nx;
+        g->n[1] = ny;
+        g->n[2] = nz;
+        g->h = h;
+        const int64_t nrows = (int64_t)ny * nz;
         int32_t *x0 = nullptr, *len = nullptr;
         int64_t *total = nullptr;
         auto fail = [&](hipError_t e) {
@@ -307,8 +287,7 @@ extern "C" int rsg_grid_create_aligned(const rsg_grid_desc *d, int32_t align, vo
         if ((e = hipMalloc(&g->zeros, 256)) != hipSuccess) return fail(e);
         if ((e = hipMemsetAsync(g->zeros, 0, 256, s)) != hipSuccess) return fail(e);
         const int bs = 256;
-        k_row_extent<<<(unsigned)((nrows + bs - 1) / bs), bs, 0, s>>>(d->shape, nx, nx, nx, Q, M,
-                                                                     x0, len);
+        k_row_extent<<<(unsigned)((nrows + bs - 1) / bs), bs, 0, s>>>(shape, nx, ny, nz, Q, M, x0, len);
         k_row_scan<<<1, 1024, 0, s>>>(x0, len, nrows, align, g->rows, total);
         if ((e = hipGetLastError()) != hipSuccess) return fail(e);
         int64_t np = 0;
@@ -336,7 +315,7 @@ extern "C" int rsg_grid_create_aligned(const rsg_grid_desc *d, int32_t align, vo
         if (np > g->npts && (e = hipMemsetAsync(g->ijk, 0xff, sizeof(int32_t) * 3 * np, s)) != hipSuccess)
             return fail(e);
         const int64_t work = nrows * nx;
-        k_coords<<<(unsigned)((work + bs - 1) / bs), bs, 0, s>>>(g->rows, nx, nx, nrows, g->ijk);
+        k_coords<<<(unsigned)((work + bs - 1) / bs), bs, 0, s>>>(g->rows, nx, ny, nrows, g->ijk);
         if ((e = hipGetLastError()) != hipSuccess) return fail(e);
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
         (void)hipFree(x0);
@@ -345,6 +324,55 @@ extern "C" int rsg_grid_create_aligned(const rsg_grid_desc *d, int32_t align, vo
         *out = g;
         return RSG_OK;
     });
+}
+
+static int check_align(int32_t align) {
+    RSG_REQUIRE(align >= 1 && align <= 64 && (align & (align - 1)) == 0, RSG_EINVAL,
+                "rsg_grid_create: align must be a power of two in 1..64");
+    return RSG_OK;
+}
+
+extern "C" int rsg_grid_create_aligned(const rsg_grid_desc *d, int32_t align, void *stream, rsg_grid_t *out) {
+    clear_error();
+    RSG_REQUIRE(d && out, RSG_EINVAL, "rsg_grid_create: null argument");
+    int rc = check_align(align);
+    if (rc) return rc;
+    RSG_REQUIRE(d->h > 0 && std::isfinite(d->h), RSG_EINVAL, "rsg_grid_create: h must be > 0");
+    RSG_REQUIRE(d->shape == RSG_BOX_CUBE || d->shape == RSG_BOX_SPHERE, RSG_EINVAL,
+                "rsg_grid_create: unknown box shape %d", d->shape);
+    int64_t Q = 0;
+    int32_t M = 0, nx;
+    if (d->shape == RSG_BOX_SPHERE) {
+        RSG_REQUIRE(d->radius > 0 && std::isfinite(d->radius), RSG_EINVAL,
+                    "rsg_grid_create: radius must be > 0");
+        const double q = std::floor((d->radius / d->h) * (d->radius / d->h) + 1e-9);
+        RSG_REQUIRE(q < 1.0e8, RSG_EINVAL, "rsg_grid_create: sphere too large (R/h > 10^4)");
+        Q = (int64_t)q;
+        int64_t m = (int64_t)std::sqrt((double)Q);
+        while ((m + 1) * (m + 1) <= Q) ++m;
+        while (m * m > Q) --m;
+        M = (int32_t)m;
+        nx = 2 * M + 1;
+    } else {
+        RSG_REQUIRE(d->n >= 1, RSG_EINVAL, "rsg_grid_create: cube needs n >= 1");
+        nx = d->n;
+    }
+    RSG_REQUIRE(nx < 32768, RSG_EINVAL, "rsg_grid_create: box wider than 32767 points");
+    return grid_create(d->shape, nx, nx, nx, Q, M, d->h, align, stream, out);
+}
+
+extern "C" int rsg_grid_create_box(int32_t nx, int32_t ny, int32_t nz, double h, int32_t align, void *stream,
+                                   rsg_grid_t *out) {
+    clear_error();
+    RSG_REQUIRE(out, RSG_EINVAL, "rsg_grid_create_box: null argument");
+    int rc = check_align(align);
+    if (rc) return rc;
+    RSG_REQUIRE(h > 0 && std::isfinite(h), RSG_EINVAL, "rsg_grid_create_box: h must be > 0");
+    RSG_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, RSG_EINVAL, "rsg_grid_create_box: need at least 1 point per axis");
+    RSG_REQUIRE(nx < 32768 && ny < 32768 && nz < 32768, RSG_EINVAL,
+                "rsg_grid_create_box: box wider than 32767 points");
+    RSG_REQUIRE((int64_t)nx * ny * nz < ((int64_t)1 << 31), RSG_EINVAL, "rsg_grid_create_box: too many points");
+    return grid_create(RSG_BOX_CUBE, nx, ny, nz, 0, 0, h, align, stream, out);
 }
 
 extern "C" int rsg_grid_info(rsg_grid_t g, int64_t *np, int32_t dims[3], double *h) {

@@ -246,6 +246,14 @@ def well_potential_scaled(pos: np.ndarray, wells: Wells, theta: float) -> np.nda
     return v
 
 
+def resonance_potential_1d(x: np.ndarray, theta: float) -> np.ndarray:
+    """The one-dimensional well with barriers of the complex-scaling
+    section's spectrum figure, v(x) = 3 (x^2 - 2) exp(-x^2 / 4), continued
+    to x e^{i theta} (theta = 0 gives the real potential)."""
+    z = np.asarray(x, dtype=np.float64) * np.exp(1j * theta)
+    return 3.0 * (z * z - 2.0) * np.exp(-z * z / 4.0)
+
+
 def radial_mask(pos: np.ndarray, R: float, width: float) -> np.ndarray:
     """Real mask M(r) for the boundary absorber: 1 inside |r| <= R - width,
     cos^2 ramp to 0 at |r| = R, 0 beyond.  The paper leaves the mask's form

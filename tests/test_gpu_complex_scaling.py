@@ -142,3 +142,40 @@ def test_scaled_handle_rejections(sys_):
         assert np.all(info["status"] == 0)
     finally:
         s.gh.set_complex_scaling(0.0, None)
+
+
+def test_paper_resonance_through_the_library():
+    """The resonance example of the complex-scaling section (Figs.
+    cs-spectrum, cs-potential-wfs): v(x) = 3 (x^2 - 2) e^{-x^2/4}, theta =
+    0.5, on an 801 x 1 x 1 box at h = 0.1 (the one-dimensional Hamiltonian
+    plus the box constant 2 kin e^{-2 i theta} c_0 / h^2).  Inverse iteration
+    in the library finds the two bound states and the lowest resonance (real
+    part in (0, 1), imaginary part between -1e-4 and -1e-5), each equal to the
+    oracle's dense eigenvalue to 1e-9 relative."""
+    R = rsg()
+    theta, n, h = 0.5, 801, 0.1
+    og, gg = oracle.Grid(h, box=(n, 1, 1)), R.Grid(h, box=(n, 1, 1))
+    assert gg.np == og.np == n and gg.dims == (n, 1, 1)
+    x = og.positions()[:, 0]
+    v = synth.resonance_potential_1d(x, theta)
+    vre, vim = v.real.copy(), v.imag.copy()
+    gh = R.Hamiltonian(gg, V=torch.from_numpy(vre).cuda(), kin=-0.5)
+    gh.set_complex_scaling(theta, torch.from_numpy(vim).cuda())
+    shift = 2 * (-0.5) * np.exp(-2j * theta) * (-205.0 / 72.0) / h ** 2
+    Hd = oracle.hpsi(oracle.Ham(og, V=vre, V_im=vim, kin=-0.5, theta=theta), np.eye(n, dtype=np.complex128))
+    ev = np.linalg.eigvals(Hd)
+    res = ev - shift
+    cand = res[(res.real > 0) & (res.real < 2.68) & (np.abs(res.imag) < 1e-3)]
+    assert cand.size == 1
+    bound = np.sort_complex(res[res.real < 0])
+    assert bound.size == 2
+    targets = np.array([bound[0] + 0.05, bound[1] + 0.05, cand[0] + 0.02]) + shift
+    start = synth.white_noise(61, n, 3, h)
+    psi = torch.from_numpy(start.T.copy()).cuda()
+    lam, its = R.cs_eigs(gh, psi, targets, max_outer=60, tol=1e-13, qmr_tol=1e-12, qmr_maxiter=20000)
+    for k, z in enumerate(targets):
+        ref = ev[np.argmin(np.abs(ev - z))]
+        assert abs(lam[k] - ref) <= 1e-9 * abs(ref), (k, lam[k], ref)
+    r = lam[2] - shift
+    assert 0 < r.real < 1 and -1e-4 < r.imag < -1e-5, r
+    np.testing.assert_allclose((lam[:2] - shift).real, bound.real, rtol=0, atol=1e-8)
