@@ -242,6 +242,21 @@ int rsg_energy(rsg_ham_t H, const void *psi, int64_t nst, int64_t ldp, int32_t d
 int rsg_dipole_expectation(rsg_ham_t H, const void *a, int64_t nst, int64_t ldp, double *out_dev,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* rsg_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and the same result, bit for bit, with the partial sums in a
+ * static device array of rsg_dot_noalloc_max_bytes() bytes (1 MiB) instead of
+ * a caller workspace.  The call allocates nothing and synchronises nothing.
+ * Limit: rsg_reduce_workspace_bytes(g, nst) must not exceed that size
+ * (every grid up to 64 orbitals fits), else RSG_EUNSUPPORTED before
+ * anything is enqueued.  Each GPU holds one such array for the life of the
+ * process, shared by every call on that GPU: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ * Other arguments and errors as rsg_dot. */
+int rsg_dot_noalloc(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ldp, double *out_dev,
+                    void *stream);
+size_t rsg_dot_noalloc_max_bytes(void);
+
 /* ------------------------------------------------------------------ */
 /* Optimal control (section "Quantum optimal control")                 */
 /* ------------------------------------------------------------------ */

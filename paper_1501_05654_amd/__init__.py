@@ -62,6 +62,8 @@ def _load():
         "rsg_propagate_step": (C.c_int, [vp, vp, i64, i64, i32, dbl, dbl, vp, sz, vp]),
         "rsg_propagate": (C.c_int, [vp, vp, i64, i64, i32, dbl, i64, vp, i32, vp, sz, vp]),
         "rsg_dot": (C.c_int, [vp, vp, vp, i64, i64, vp, vp, sz, vp]),
+        "rsg_dot_noalloc": (C.c_int, [vp, vp, vp, i64, i64, vp, vp]),
+        "rsg_dot_noalloc_max_bytes": (sz, []),
         "rsg_norm2": (C.c_int, [vp, vp, i64, i64, vp, vp, sz, vp]),
         "rsg_energy": (C.c_int, [vp, vp, i64, i64, i32, dbl, vp, vp, sz, vp]),
         "rsg_dipole_expectation": (C.c_int, [vp, vp, i64, i64, vp, vp, sz, vp]),

@@ -331,3 +331,67 @@ extern "C" int rsg_laser_grad(const double *g_dev, int64_t nsteps, double T, dou
     RSG_CHECK_HIP(hipGetLastError());
     return RSG_OK;
 }
+
+// ------------------------------------------------------------------------
+// Allocation-free inner products: the partial sums live in a static device
+// array instead of a caller workspace, for callers that cannot allocate
+// (code under HIP graph capture, tight serving loops).
+// ------------------------------------------------------------------------
+
+#include <mutex>
+
+// 1 MiB: the partial sums of up to 64 orbitals at the largest partition
+// (1024 workgroups per orbital), plus the per-orbital totals.  External
+// linkage on purpose: a static device array gets a local symbol in the
+// code object, which the runtime's symbol lookup does not find.
+static constexpr size_t kScratchBytes = (size_t)1 << 20;
+__device__ __align__(256) char rsg_noalloc_scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_addr;  // device ordinal -> address of that device's copy
+
+// The device address of the scratch array on the current device, looked up once per
+// device with that device current.  In host code the array's name is only a
+// host-side stand-in; kernels get this address.
+int scratch_address(void **out) {
+    int dev = 0;
+    RSG_CHECK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void *p = nullptr;
+        RSG_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(rsg_noalloc_scratch)));
+        RSG_REQUIRE(p != nullptr, RSG_EHIP, "scratch: no device address");
+        it = g_scratch_addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return RSG_OK;
+}
+
+}  // namespace
+
+extern "C" size_t rsg_dot_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" int rsg_dot_noalloc(rsg_grid_t g, const void *a, const void *b, int64_t nst, int64_t ldp, double *out,
+                               void *stream) {
+    using namespace rsg;
+    clear_error();
+    RSG_REQUIRE(g, RSG_EINVAL, "rsg_dot_noalloc: null grid");
+    RSG_REQUIRE(nst >= 0 && ldp >= 1 && ldp >= g->np, RSG_ESHAPE, "rsg_dot_noalloc: need nst >= 0 and ldp >= np");
+    RSG_REQUIRE(nst == 0 || (a && b && out), RSG_EINVAL, "rsg_dot_noalloc: null pointer");
+    RSG_REQUIRE((((uintptr_t)a | (uintptr_t)b) & 15) == 0, RSG_EINVAL, "rsg_dot_noalloc: pointer not 16-byte aligned");
+    const size_t need = reduce_workspace_bytes(*g, nst);
+    RSG_REQUIRE(need <= kScratchBytes, RSG_EUNSUPPORTED,
+                "rsg_dot_noalloc: %lld orbitals on %lld slots need %zu scratch bytes, more than the %zu held",
+                (long long)nst, (long long)g->np, need, kScratchBytes);
+    if (nst == 0) return RSG_OK;
+    void *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    // every partial the final pass reads is written by the first pass of this
+    // call, so nothing needs clearing
+    return launch_reduce(*g, 0, 0, (const double2 *)a, (const double2 *)b, nst, ldp, out, ws, kScratchBytes,
+                         (hipStream_t)stream);
+}
