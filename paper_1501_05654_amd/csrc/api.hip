@@ -110,6 +110,8 @@ Ham::~Ham() {
     if (gather_items) (void)hipFree(gather_items);
     for (auto *p : scatter_items)
         if (p) (void)hipFree(p);
+    for (int32_t *p : {sup_slot, sup_nb, kb_cidx, ss_slot, ss_s, ss_nb})
+        if (p) (void)hipFree(p);
 }
 
 namespace {
@@ -212,7 +214,11 @@ int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *o
 
 size_t step_ws(const Ham &H, int64_t nst, int64_t ldp, int32_t dtype) {
     const size_t e = dtype == RSG_C128 ? 16 : 8;
-    return 2 * rounded(batch_bytes(nst, ldp, e)) + rounded(kb_workspace_bytes(H, nst)) + 256;
+    // single-factor stages: two work buffers and the projector workspace;
+    // fused factor pairs: one work buffer, then the projector correction's
+    // workspace in the rest
+    return 2 * rounded(batch_bytes(nst, ldp, e)) +
+           std::max(rounded(kb_workspace_bytes(H, nst)), rounded(fused_projector_ws(H, nst))) + 256;
 }
 
 
@@ -294,6 +300,27 @@ int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t
     const int wt = dtype == RSG_C128 ? 0 : 1;  // work-buffer type
     int rc;
     if (step_is_product(H, dtype)) {
+        const TileShape sh = H.tile_for(nst, 0);
+        if (sh.FU && !H.complex_scaled()) {
+            // two passes of two factors each: psi -> w1 -> psi_out, the
+            // projector terms corrected after each pass (workspace behind w1)
+            void *pws = (char *)ws + rounded(batch_bytes(nst, ldp, 16));
+            const size_t pbytes = ws_bytes - rounded(batch_bytes(nst, ldp, 16));
+            FusedArgs f;
+            f.nst = nst;
+            f.ldp = ldp;
+            f.field = field;
+            f.field_dev = field_dev;
+            for (int p = 0; p < 2; ++p) {
+                f.in = p == 0 ? psi : w1;
+                f.out = p == 0 ? w1 : psi_out;
+                f.ca = factor_coef(2 * p, dt);
+                f.cb = factor_coef(2 * p + 1, dt);
+                if ((rc = launch_fused(H, f, sh, s))) return rc;
+                if ((rc = fused_projector_fix(H, f, pws, pbytes, s))) return rc;
+            }
+            return RSG_OK;
+        }
         void *y[3] = {w1, w2, w1};
         return step_product(H, psi, y, psi_out, nst, ldp, dt, field, field_dev, D, s);
     }
@@ -560,6 +587,11 @@ extern "C" int rsg_ham_create(rsg_grid_t g, const double *vloc_dev, double kin, 
                 }
                 H->scatter_items.push_back(d);
                 H->scatter_counts.push_back((int32_t)v.size());
+            }
+            const int rs = build_support_tables(*H, idx_h);
+            if (rs) {
+                delete H;
+                return rs;
             }
         }
         if ((e = hipGetLastError()) != hipSuccess) return fail("conversion", e);
@@ -980,9 +1012,12 @@ extern "C" int rsg_tile_candidates(int32_t dtype, rsg_tile *out, int32_t max, in
     clear_error();
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_tile_candidates: bad dtype");
     RSG_REQUIRE(count && (max <= 0 || out), RSG_EINVAL, "rsg_tile_candidates: null output");
-    const auto v = tile_candidates(tile_compute(dtype));
+    auto v = tile_candidates(tile_compute(dtype));
+    if (dtype == RSG_C128)
+        for (const auto &f : fused_candidates()) v.push_back(f);
     *count = (int32_t)v.size();
-    for (int32_t k = 0; k < max && k < (int32_t)v.size(); ++k) out[k] = rsg_tile{v[k].B, v[k].TX, v[k].TY, 0, v[k].PD, 0, 0, 0};
+    for (int32_t k = 0; k < max && k < (int32_t)v.size(); ++k)
+        out[k] = rsg_tile{v[k].B, v[k].TX, v[k].TY, 0, v[k].PD, 0, 0, 0, v[k].FU};
     return RSG_OK;
 }
 
@@ -993,18 +1028,21 @@ extern "C" int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_t
     RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "rsg_set_tile: ZC must be >= 0");
     bool ok = false;
     const int pd = t->PD;
-    for (const auto &c : tile_candidates(tile_compute(dtype)))
+    RSG_REQUIRE(t->FU == 0 || t->FU == 1, RSG_EINVAL, "rsg_set_tile: FU must be 0 or 1");
+    RSG_REQUIRE(t->FU == 0 || dtype == RSG_C128, RSG_EUNSUPPORTED, "rsg_set_tile: fused tiles are FP64 only");
+    for (const auto &c : t->FU ? fused_candidates() : tile_candidates(tile_compute(dtype)))
         ok = ok || (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == pd);
-    RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_set_tile: %dx%dx%d (depth %d) is not a compiled tile shape", t->B,
-                t->TX, t->TY, t->PD);
+    RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_set_tile: %dx%dx%d (depth %d%s) is not a compiled tile shape", t->B,
+                t->TX, t->TY, t->PD, t->FU ? ", fused" : "");
     RSG_REQUIRE(t->PT >= 0 && t->PT <= 64, RSG_EINVAL, "rsg_set_tile: PT must be in 0..64");
     RSG_REQUIRE(t->BO >= 0 && t->BO <= 64, RSG_EINVAL, "rsg_set_tile: BO must be in 0..64");
-    RSG_REQUIRE(t->ZM == 0 || t->ZM == 1, RSG_EINVAL, "rsg_set_tile: ZM must be 0 or 1");
+    RSG_REQUIRE(t->ZM >= 0 && t->ZM <= 2, RSG_EINVAL, "rsg_set_tile: ZM must be 0, 1 or 2");
     TileShape sh{t->B, t->TX, t->TY, t->ZC};
     sh.PD = pd;
     sh.PT = t->PT;
     sh.BO = t->BO;
     sh.ZM = t->ZM;
+    sh.FU = t->FU;
     H->tiles[std::make_pair(nst, tile_compute(dtype))] = sh;
     drop_graphs(H);
     return RSG_OK;
@@ -1015,7 +1053,7 @@ extern "C" int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t
     RSG_REQUIRE(H && t, RSG_EINVAL, "rsg_get_tile: null argument");
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_get_tile: bad dtype");
     const TileShape s = H->tile_for(nst, tile_compute(dtype));
-    *t = rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, s.PT, s.BO, s.ZM};
+    *t = rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, s.PT, s.BO, s.ZM, s.FU};
     return RSG_OK;
 }
 
@@ -1044,7 +1082,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
     }
     return guarded([&]() -> int {
         std::vector<int> zcs = {0};
-        for (int z : {64, 32})
+        for (int z : {96, 64, 32})
             if (z < H->g->n[2]) zcs.push_back(z);
         // few tiles (small grid, few orbitals): short z-chunks for parallelism
         const int64_t small_tiles = (int64_t)((H->g->n[0] + 15) / 16) * ((H->g->n[1] + 7) / 8) * nst;
@@ -1053,7 +1091,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
                 if (z < H->g->n[2]) zcs.push_back(z);
         const std::vector<int> pts = {0, 1};
         const std::vector<int> bos = {0, 1, 2, 4};
-        const int nzp = (int)(zcs.size() * pts.size()), nvar = nzp * (int)bos.size() * 2;  // x BO x ZM
+        const int nzp = (int)(zcs.size() * pts.size()), nvar = nzp * (int)bos.size() * 3;  // x BO x ZM
         hipEvent_t e0, e1;
         RSG_CHECK_HIP(hipEventCreate(&e0));
         RSG_CHECK_HIP(hipEventCreate(&e1));
@@ -1151,6 +1189,9 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
                 sh.PT = pts[(zpi / zcs.size()) % pts.size()];
                 sh.BO = bos[(zpi / nzp) % bos.size()];
                 sh.ZM = zpi / (nzp * (int)bos.size());
+                // chunks aligned in z need chunks, and are tried in row order
+                // with the orbital slowest or in pairs only
+                if (sh.ZM == 2 && (zc == 0 || sh.PT != 0 || (sh.BO != 1 && sh.BO != 2))) continue;
                 if (!H->g->plan(sh, s, &err)) break;
                 double t = 0;
                 if ((rc = time_shape(sh, reps, &t))) break;
@@ -1183,7 +1224,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         if (rc) return rc;
         H->tiles[std::make_pair(nst, cmp)] = bs;
         drop_graphs(H);
-        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, bs.PT, bs.BO, bs.ZM};
+        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, bs.PT, bs.BO, bs.ZM, bs.FU};
         if (best_ms) *best_ms = bt;
         return RSG_OK;
     });

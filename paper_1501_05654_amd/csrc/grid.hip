@@ -125,6 +125,11 @@ Grid::~Grid() {
 //     tiles with the most planes come first.  Tiles resident together then
 //     start on the same plane and advance together, so neighbours read each
 //     other's planes from L2 while they are still there.
+//   ZM = 2: chunks are aligned to multiples of ZC in z (the same planes for
+//     every tile), items chunk-major and in tile order within a chunk.
+//     Workgroups launched together then march the same planes side by side,
+//     so each reads its halo lines while its neighbours' own loads of those
+//     lines are still in L2.
 //   PT >= 2 (with ZM = 0): tiles are grouped into PT x PT patches; all tiles
 //     of a patch march over the patch's common z-extent, and items are ordered
 //     patch-major, then chunk, then tile.
@@ -175,7 +180,14 @@ const TilePlan *Grid::plan(const TileShape &s, hipStream_t stream, int *err) {
         std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return key_of(p) < key_of(q); });
     }
     std::vector<int4> items;
-    if (s.ZM == 1) {
+    if (s.ZM == 2) {
+        const int L = std::max(1, s.ZC);
+        for (int c = 0; c * L < nz; ++c)
+            for (const int k : order) {
+                const int a = std::max(zlo[k], c * L), b = std::min(zhi[k] + 1, (c + 1) * L);
+                if (a < b) items.push_back(make_int4(k % ntx, k / ntx, a, b));
+            }
+    } else if (s.ZM == 1) {
         const int zc = nz / 2, L = s.ZC;
         const int nup = (nz - zc + L - 1) / L, ndn = (zc + L - 1) / L;
         for (int j = 0; j < std::max(nup, ndn); ++j)

@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 ZCS = (0, 4, 1)     # whole z-range, chunks of 4 planes (several per tile), single planes
 PTS = (0, 1, 2)     # row order, Morton order, 2 x 2 patches
 BOS = (0, 1, 3)     # orbital fastest / slowest / groups of 3 (13 = 4 x 3 + 1)
-ZMS = (0, 1)        # upward from each tile's lowest plane / outward from the centre plane
+ZMS = (0, 1, 2)     # upward from each tile's lowest plane / outward from the centre plane /
+                    # chunks aligned in z for all tiles
 
 
 @pytest.fixture(scope="module")
@@ -34,8 +35,10 @@ def _variants(dtype):
             for pt in PTS:
                 for bo in BOS:
                     for zm in ZMS:
-                        if zm == 1 and pt >= 2:
+                        if zm >= 1 and pt >= 2:
                             continue  # patches apply to the upward march only
+                        if zm == 2 and zc == 0:
+                            continue  # aligned chunks need chunks
                         if zc == 1 and pt != 0:
                             continue  # single planes: row order suffices
                         yield dict(t, ZC=zc, PT=pt, BO=bo, ZM=zm)
@@ -43,7 +46,7 @@ def _variants(dtype):
 
 def _set(R, s, t, dtype):
     R.set_tile(s.gh, s.nst, t["B"], t["TX"], t["TY"], t["ZC"], t["PD"], t["PT"], t["BO"],
-               t["ZM"], dtype=dtype)
+               t["ZM"], FU=t["FU"], dtype=dtype)
 
 
 def test_every_fp64_tile_matches_oracle(sys_):
