@@ -45,7 +45,7 @@ def read_traffic(workload: str, tile=None, align: int = 1):
     import glob
     key = None
     if tile is not None:
-        key = ",".join(str(tile.get(k, 0)) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM", "FU"))
+        key = ",".join(str(tile[k]) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM"))
     for p in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_stencil_{workload}*.txt"))):
         kv = {}
         for line in open(p):
@@ -98,12 +98,11 @@ def cpu_model() -> str:
 
 
 def fixed_tile(spec: str) -> list:
-    """'B,TX,TY,ZC,PD,PT,BO[,ZM[,FU]]' -> the nine tile fields (ZM and FU
-    default to 0)."""
+    """'B,TX,TY,ZC,PD,PT,BO[,ZM]' -> the eight tile fields (ZM defaults to 0)."""
     vals = [int(v) for v in spec.split(",")]
-    if len(vals) not in (7, 8, 9):
-        raise SystemExit(f"a tile is B,TX,TY,ZC,PD,PT,BO[,ZM[,FU]], got {spec!r}")
-    return vals + [0] * (9 - len(vals))
+    if len(vals) not in (7, 8):
+        raise SystemExit(f"a tile is B,TX,TY,ZC,PD,PT,BO[,ZM], got {spec!r}")
+    return vals + [0] * (8 - len(vals))
 
 
 def choose_tile(args, spec, gh, psi, reps, dtype="c128"):
@@ -297,7 +296,7 @@ def bench_batch(args):
     with torch.cuda.stream(stream):
         b = rsg.Batch(systems)
         if args.tile:
-            B, TX, TY, ZC, PD, _, _, ZM, _ = fixed_tile(args.tile)
+            B, TX, TY, ZC, PD, _, _, ZM = fixed_tile(args.tile)
             b.set_tile(B, TX, TY, ZC, PD, ZM)
             tile = b.get_tile()
             log(f"batch tile {tile} (fixed)")

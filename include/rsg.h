@@ -347,13 +347,9 @@ int rsg_control_backward(rsg_ham_t H, const void *psi_T, int64_t nst, int64_t ld
  * that workgroups resident together cover neighbouring tiles at the same
  * plane; ZM = 2 aligns the z-chunks to multiples of ZC for every tile
  * (chunk-major order), so that workgroups launched together march the same
- * planes side by side.  FU = 1 (FP64 product-form steps only; the shapes
- * rsg_tile_candidates lists with FU = 1) runs a step as two z-marches of two Taylor
- * factors each, the second factor four planes behind the first, with the
- * projector terms corrected on the projector supports afterwards. */
+ * planes side by side. */
 typedef struct {
     int32_t B, TX, TY, ZC, PD, PT, BO, ZM;
-    int32_t FU;
 } rsg_tile;
 
 /* Compiled tile shapes for a dtype (ZC = 0).  Writes up to max entries and

@@ -621,13 +621,12 @@ class kernel_timing:
 
 class _Tile(C.Structure):
     _fields_ = [("B", C.c_int32), ("TX", C.c_int32), ("TY", C.c_int32), ("ZC", C.c_int32),
-                ("PD", C.c_int32), ("PT", C.c_int32), ("BO", C.c_int32), ("ZM", C.c_int32),
-                ("FU", C.c_int32)]
+                ("PD", C.c_int32), ("PT", C.c_int32), ("BO", C.c_int32), ("ZM", C.c_int32)]
 
 
 def _tile_dict(t: _Tile) -> dict:
     return {"B": t.B, "TX": t.TX, "TY": t.TY, "ZC": t.ZC, "PD": t.PD, "PT": t.PT, "BO": t.BO,
-            "ZM": t.ZM, "FU": t.FU}
+            "ZM": t.ZM}
 
 
 def tile_candidates(dtype="c128") -> list:
@@ -639,8 +638,8 @@ def tile_candidates(dtype="c128") -> list:
 
 
 def set_tile(ham: Hamiltonian, nst: int, B: int, TX: int, TY: int, ZC: int = 0, PD: int = 1,
-             PT: int = 0, BO: int = 0, ZM: int = 0, FU: int = 0, dtype="c128"):
-    t = _Tile(B, TX, TY, ZC, PD, PT, BO, ZM, FU)
+             PT: int = 0, BO: int = 0, ZM: int = 0, dtype="c128"):
+    t = _Tile(B, TX, TY, ZC, PD, PT, BO, ZM)
     _check(_lib.rsg_set_tile(ham._h, int(nst), _dt(dtype), C.byref(t)))
 
 
@@ -717,7 +716,7 @@ class Batch:
     def set_tile(self, B: int, TX: int, TY: int, ZC: int = 0, PD: int = 1, ZM: int = 0,
                  cls: int | None = None):
         """Tile of every size class (cls = None) or of class cls."""
-        t = _Tile(B, TX, TY, ZC, PD, 0, 0, ZM, 0)
+        t = _Tile(B, TX, TY, ZC, PD, 0, 0, ZM)
         if cls is None:
             _check(_lib.rsg_batch_set_tile(self._h, C.byref(t), _stream()))
         else:

@@ -110,8 +110,6 @@ Ham::~Ham() {
     if (gather_items) (void)hipFree(gather_items);
     for (auto *p : scatter_items)
         if (p) (void)hipFree(p);
-    for (int32_t *p : {sup_slot, sup_nb, kb_cidx, ss_slot, ss_s, ss_nb})
-        if (p) (void)hipFree(p);
 }
 
 namespace {
@@ -214,11 +212,7 @@ int stage_impl(const Ham &H, const void *in, int in_t, const void *base, void *o
 
 size_t step_ws(const Ham &H, int64_t nst, int64_t ldp, int32_t dtype) {
     const size_t e = dtype == RSG_C128 ? 16 : 8;
-    // single-factor stages: two work buffers and the projector workspace;
-    // fused factor pairs: one work buffer, then the projector correction's
-    // workspace in the rest
-    return 2 * rounded(batch_bytes(nst, ldp, e)) +
-           std::max(rounded(kb_workspace_bytes(H, nst)), rounded(fused_projector_ws(H, nst))) + 256;
+    return 2 * rounded(batch_bytes(nst, ldp, e)) + rounded(kb_workspace_bytes(H, nst)) + 256;
 }
 
 
@@ -300,27 +294,6 @@ int step_impl(const Ham &H, const void *psi, void *psi_out, int64_t nst, int64_t
     const int wt = dtype == RSG_C128 ? 0 : 1;  // work-buffer type
     int rc;
     if (step_is_product(H, dtype)) {
-        const TileShape sh = H.tile_for(nst, 0);
-        if (sh.FU && !H.complex_scaled()) {
-            // two passes of two factors each: psi -> w1 -> psi_out, the
-            // projector terms corrected after each pass (workspace behind w1)
-            void *pws = (char *)ws + rounded(batch_bytes(nst, ldp, 16));
-            const size_t pbytes = ws_bytes - rounded(batch_bytes(nst, ldp, 16));
-            FusedArgs f;
-            f.nst = nst;
-            f.ldp = ldp;
-            f.field = field;
-            f.field_dev = field_dev;
-            for (int p = 0; p < 2; ++p) {
-                f.in = p == 0 ? psi : w1;
-                f.out = p == 0 ? w1 : psi_out;
-                f.ca = factor_coef(2 * p, dt);
-                f.cb = factor_coef(2 * p + 1, dt);
-                if ((rc = launch_fused(H, f, sh, s))) return rc;
-                if ((rc = fused_projector_fix(H, f, pws, pbytes, s))) return rc;
-            }
-            return RSG_OK;
-        }
         void *y[3] = {w1, w2, w1};
         return step_product(H, psi, y, psi_out, nst, ldp, dt, field, field_dev, D, s);
     }
@@ -587,11 +560,6 @@ extern "C" int rsg_ham_create(rsg_grid_t g, const double *vloc_dev, double kin, 
                 }
                 H->scatter_items.push_back(d);
                 H->scatter_counts.push_back((int32_t)v.size());
-            }
-            const int rs = build_support_tables(*H, idx_h);
-            if (rs) {
-                delete H;
-                return rs;
             }
         }
         if ((e = hipGetLastError()) != hipSuccess) return fail("conversion", e);
@@ -1012,12 +980,10 @@ extern "C" int rsg_tile_candidates(int32_t dtype, rsg_tile *out, int32_t max, in
     clear_error();
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_tile_candidates: bad dtype");
     RSG_REQUIRE(count && (max <= 0 || out), RSG_EINVAL, "rsg_tile_candidates: null output");
-    auto v = tile_candidates(tile_compute(dtype));
-    if (dtype == RSG_C128)
-        for (const auto &f : fused_candidates()) v.push_back(f);
+    const auto v = tile_candidates(tile_compute(dtype));
     *count = (int32_t)v.size();
     for (int32_t k = 0; k < max && k < (int32_t)v.size(); ++k)
-        out[k] = rsg_tile{v[k].B, v[k].TX, v[k].TY, 0, v[k].PD, 0, 0, 0, v[k].FU};
+        out[k] = rsg_tile{v[k].B, v[k].TX, v[k].TY, 0, v[k].PD, 0, 0, 0};
     return RSG_OK;
 }
 
@@ -1028,12 +994,10 @@ extern "C" int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_t
     RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "rsg_set_tile: ZC must be >= 0");
     bool ok = false;
     const int pd = t->PD;
-    RSG_REQUIRE(t->FU == 0 || t->FU == 1, RSG_EINVAL, "rsg_set_tile: FU must be 0 or 1");
-    RSG_REQUIRE(t->FU == 0 || dtype == RSG_C128, RSG_EUNSUPPORTED, "rsg_set_tile: fused tiles are FP64 only");
-    for (const auto &c : t->FU ? fused_candidates() : tile_candidates(tile_compute(dtype)))
+    for (const auto &c : tile_candidates(tile_compute(dtype)))
         ok = ok || (c.B == t->B && c.TX == t->TX && c.TY == t->TY && c.PD == pd);
-    RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_set_tile: %dx%dx%d (depth %d%s) is not a compiled tile shape", t->B,
-                t->TX, t->TY, t->PD, t->FU ? ", fused" : "");
+    RSG_REQUIRE(ok, RSG_EUNSUPPORTED, "rsg_set_tile: %dx%dx%d (depth %d) is not a compiled tile shape", t->B,
+                t->TX, t->TY, t->PD);
     RSG_REQUIRE(t->PT >= 0 && t->PT <= 64, RSG_EINVAL, "rsg_set_tile: PT must be in 0..64");
     RSG_REQUIRE(t->BO >= 0 && t->BO <= 64, RSG_EINVAL, "rsg_set_tile: BO must be in 0..64");
     RSG_REQUIRE(t->ZM >= 0 && t->ZM <= 2, RSG_EINVAL, "rsg_set_tile: ZM must be 0, 1 or 2");
@@ -1042,7 +1006,6 @@ extern "C" int rsg_set_tile(rsg_ham_t H, int64_t nst, int32_t dtype, const rsg_t
     sh.PT = t->PT;
     sh.BO = t->BO;
     sh.ZM = t->ZM;
-    sh.FU = t->FU;
     H->tiles[std::make_pair(nst, tile_compute(dtype))] = sh;
     drop_graphs(H);
     return RSG_OK;
@@ -1053,7 +1016,7 @@ extern "C" int rsg_get_tile(rsg_ham_t H, int64_t nst, int32_t dtype, rsg_tile *t
     RSG_REQUIRE(H && t, RSG_EINVAL, "rsg_get_tile: null argument");
     RSG_REQUIRE(dtype == RSG_C128 || dtype == RSG_C64_MIXED, RSG_EDTYPE, "rsg_get_tile: bad dtype");
     const TileShape s = H->tile_for(nst, tile_compute(dtype));
-    *t = rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, s.PT, s.BO, s.ZM, s.FU};
+    *t = rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, s.PT, s.BO, s.ZM};
     return RSG_OK;
 }
 
@@ -1224,7 +1187,7 @@ extern "C" int rsg_autotune(rsg_ham_t H, const void *psi, int64_t nst, int64_t l
         if (rc) return rc;
         H->tiles[std::make_pair(nst, cmp)] = bs;
         drop_graphs(H);
-        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, bs.PT, bs.BO, bs.ZM, bs.FU};
+        if (best) *best = rsg_tile{bs.B, bs.TX, bs.TY, bs.ZC, bs.PD, bs.PT, bs.BO, bs.ZM};
         if (best_ms) *best_ms = bt;
         return RSG_OK;
     });

@@ -428,7 +428,7 @@ static int set_class_tile(rsg_batch_t b, int32_t c, const rsg_tile *t) {
 }
 
 static int check_batch_tile(const rsg_tile *t, const char *who) {
-    RSG_REQUIRE(compiled_fp64(t) && t->FU == 0, RSG_EUNSUPPORTED, "%s: not a compiled single-factor FP64 tile", who);
+    RSG_REQUIRE(compiled_fp64(t), RSG_EUNSUPPORTED, "%s: not a compiled FP64 tile", who);
     RSG_REQUIRE(t->ZC >= 0, RSG_EINVAL, "%s: ZC must be >= 0", who);
     RSG_REQUIRE(t->ZM >= 0 && t->ZM <= 2, RSG_EINVAL, "%s: ZM must be 0, 1 or 2", who);
     return RSG_OK;
@@ -459,7 +459,7 @@ extern "C" int rsg_batch_set_class_tile(rsg_batch_t b, int32_t c, const rsg_tile
     return guarded([&]() { return build_class(*b, (size_t)c, (hipStream_t)stream); });
 }
 
-static rsg_tile tile_out(const TileShape &s) { return rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, 0, 0, s.ZM, 0}; }
+static rsg_tile tile_out(const TileShape &s) { return rsg_tile{s.B, s.TX, s.TY, s.ZC, s.PD, 0, 0, s.ZM}; }
 
 extern "C" int rsg_batch_get_tile(rsg_batch_t b, rsg_tile *t) {
     clear_error();

@@ -293,9 +293,8 @@ size_t kb_workspace_bytes(const Ham &H, int64_t nst) {
 }
 
 int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ldp,
-                     void *D, hipStream_t s, const int32_t *idx) {
+                     void *D, hipStream_t s) {
     if (H.natoms == 0 || nst == 0) return RSG_OK;
-    const int32_t *ix = idx ? idx : H.kb_idx;
     const int64_t ncols = 2 * nst;
     const int nchunk = gather_chunks(H, nst);
     const dim3 grid((unsigned)H.natoms, (unsigned)((ncols + 15) / 16), (unsigned)nchunk);
@@ -307,18 +306,18 @@ int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_
     if (compute == 0) {
         if (in_t != 0) return RSG_EUNSUPPORTED;
         k_kb_gather<double, double><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ldp, ncols,
-                                                        H.gather_items, ix, H.kb_p, h3,
+                                                        H.gather_items, H.kb_idx, H.kb_p, h3,
                                                         (double *)D, (double *)P);
         if (nchunk > 1)
             k_kb_gather_sum<double><<<sblk, 256, 0, s>>>((const double *)P, (double *)D, nrows, nchunk, ncols, h3);
     } else {
         if (in_t == 0)
             k_kb_gather<double, float><<<grid, GW * 64, 0, s>>>((const double *)in, 2 * ldp, ncols,
-                                                           H.gather_items, ix, H.kb_p32,
+                                                           H.gather_items, H.kb_idx, H.kb_p32,
                                                            (float)h3, (float *)D, (float *)P);
         else
             k_kb_gather<float, float><<<grid, GW * 64, 0, s>>>((const float *)in, 2 * ldp, ncols,
-                                                          H.gather_items, ix, H.kb_p32,
+                                                          H.gather_items, H.kb_idx, H.kb_p32,
                                                           (float)h3, (float *)D, (float *)P);
         if (nchunk > 1)
             k_kb_gather_sum<float><<<sblk, 256, 0, s>>>((const float *)P, (float *)D, nrows, nchunk, ncols,
@@ -329,10 +328,8 @@ int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_
 }
 
 int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ldp,
-                      const void *D, double cre, double cim, const double *mask, hipStream_t s,
-                      const int32_t *idx) {
+                      const void *D, double cre, double cim, const double *mask, hipStream_t s) {
     if (H.natoms == 0 || nst == 0) return RSG_OK;
-    const int32_t *ix = idx ? idx : H.kb_idx;
     const int64_t ncols = 2 * nst;
     for (size_t c = 0; c < H.scatter_items.size(); ++c) {
         const int32_t n = H.scatter_counts[c];
@@ -341,15 +338,15 @@ int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t n
         if (compute == 0) {
             if (out_t != 0) return RSG_EUNSUPPORTED;
             k_kb_scatter<double, double><<<grid, 256, 0, s>>>(
-                (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, ix,
+                (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
                 H.kb_p, H.kb_E, (const double *)D, cre, cim, mask);
         } else if (out_t == 0) {
             k_kb_scatter<double, float><<<grid, 256, 0, s>>>(
-                (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, ix,
+                (double *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
                 H.kb_p32, H.kb_E, (const float *)D, cre, cim, mask);
         } else {
             k_kb_scatter<float, float><<<grid, 256, 0, s>>>(
-                (float *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, ix,
+                (float *)out, 2 * ldp, ncols, H.scatter_items[c], n, H.gather_items, H.kb_idx,
                 H.kb_p32, H.kb_E, (const float *)D, cre, cim, mask);
         }
         RSG_CHECK_HIP(hipGetLastError());

@@ -68,9 +68,7 @@ struct TileShape {
     int PT = 0;
     int BO = 0;  // block order: 0 = orbital fastest, 1 = orbital slowest, G >= 2 = groups of G orbitals
     int ZM = 0;  // z-march: 0 = upward from each tile's lowest plane, 1 = outward from the centre
-    int FU = 0;  // 1: FP64 product-form steps run two factors per z-march (fused.hip)
     bool operator<(const TileShape &o) const {
-        if (FU != o.FU) return FU < o.FU;
         if (B != o.B) return B < o.B;
         if (TX != o.TX) return TX < o.TX;
         if (TY != o.TY) return TY < o.TY;
@@ -137,16 +135,6 @@ struct Ham {
     // scatter work: per colour a device list of {atom, entry0} (16 entries each)
     std::vector<int2 *> scatter_items;
     std::vector<int32_t> scatter_counts;
-    // Support tables of the fused two-factor step (built with the projectors):
-    //   S  = union of the supports: slot of each point, its 24 star
-    //        neighbours' slots (-1 outside the box), and for every padded
-    //        support entry its position in S (kb_cidx);
-    //   SS = S dilated by the star: slot of each point, its position in S
-    //        (-1 if none) and its 24 star neighbours' positions in S (-1 if
-    //        not in S).
-    int64_t nS = 0, nSS = 0;
-    int32_t *sup_slot = nullptr, *sup_nb = nullptr, *kb_cidx = nullptr;
-    int32_t *ss_slot = nullptr, *ss_s = nullptr, *ss_nb = nullptr;
     // stencil tile shape per (nst, compute) chosen by rsg_autotune / rsg_set_tile
     std::map<std::pair<int64_t, int>, TileShape> tiles;
     TileShape tile_for(int64_t nst, int compute) const;
@@ -225,25 +213,6 @@ int launch_stencil(const Ham &H, const StageArgs &a, const TileShape &shape, hip
 // (another depth maps to depth 1 of the same tile, another tile to 16 x 8);
 // ZC = 0 becomes the whole z-extent.
 TileShape launch_shape(const Ham &H, const TileShape &tile);
-// Two local Taylor factors in one z-march (FP64): out = (1 + cb L)(1 + ca L) in
-// with L = kin Lap + V + field x_axis (no projector terms).
-struct FusedArgs {
-    const void *in = nullptr;
-    void *out = nullptr;
-    int64_t nst = 0, ldp = 0;
-    std::complex<double> ca, cb;
-    double field = 0;
-    const double *field_dev = nullptr;
-};
-int launch_fused(const Ham &H, const FusedArgs &f, const TileShape &tile, hipStream_t s);
-// Support tables of H (from its projector index lists; host work plus uploads).
-int build_support_tables(Ham &H, const std::vector<int32_t> &idx_padded);
-// The projector terms of a fused pass: w = (1 + cb L)(1 + ca L) y0 on entry,
-// (1 + cb H)(1 + ca H) y0 on return (H = L + projectors).  ws:
-// fused_projector_ws bytes.
-size_t fused_projector_ws(const Ham &H, int64_t nst);
-int fused_projector_fix(const Ham &H, const FusedArgs &f, void *ws, size_t ws_bytes, hipStream_t s);
-std::vector<TileShape> fused_candidates();
 // Workgroups of one stencil launch of nst orbitals with H's tile for this
 // precision (the number of pair partials of an adjoint stage), or a negative
 // error code.  May create the tile's launch plan (not during capture).
@@ -263,14 +232,10 @@ std::vector<TileShape> tile_candidates(int compute);
 // out(idx[e], col) += sum_i p[e][i] (c E_i D[a][i][.])[col], times mask(idx[e])
 // when a mask is given.  Operands are orbital-major with ldp complex values
 // between orbitals.
-// idx (optional) replaces the handle's support indices: the projector rows
-// are then read from / added to a field stored on other positions (the
-// compact support arrays of the fused step).
 int launch_kb_gather(const Ham &H, const void *in, int in_t, int compute, int64_t nst, int64_t ldp,
-                     void *D, hipStream_t s, const int32_t *idx = nullptr);
+                     void *D, hipStream_t s);
 int launch_kb_scatter(const Ham &H, void *out, int out_t, int compute, int64_t nst, int64_t ldp,
-                      const void *D, double cre, double cim, const double *mask, hipStream_t s,
-                      const int32_t *idx = nullptr);
+                      const void *D, double cre, double cim, const double *mask, hipStream_t s);
 size_t kb_workspace_bytes(const Ham &H, int64_t nst);
 
 // Per-system projector parameters of one stage of the batched path (FP64).

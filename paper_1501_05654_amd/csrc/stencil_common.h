@@ -1,8 +1,6 @@
-// Device helpers shared by the z-marching stencil kernels (single-factor
-// stages in stencil.hip, fused factor pairs in fused.hip): finite-difference
+// Device helpers of the z-marching stencil kernels: finite-difference
 // weights, workgroup-to-XCD remapping, block orders, row-table lookups and
-// CDNA buffer loads/stores.  Included inside namespace rsg's anonymous
-// namespace of each translation unit.
+// CDNA buffer loads/stores.
 #pragma once
 
 #include "rsg_internal.h"

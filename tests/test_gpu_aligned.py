@@ -79,7 +79,7 @@ def test_aligned_every_tile_matches_oracle(asys):
     for t in R.tile_candidates("c128"):
         for zc in (0, 4, 1):
             for bo in (0, 1):
-                R.set_tile(s.gh, s.nst, t["B"], t["TX"], t["TY"], zc, t["PD"], 0, bo, 0, FU=t["FU"])
+                R.set_tile(s.gh, s.nst, t["B"], t["TX"], t["TY"], zc, t["PD"], 0, bo, 0)
                 out = torch.full_like(psi, 3.0 + 1.0j)
                 R.hpsi(s.gh, psi, field=field, out=out, nst=s.nst)
                 y = s.from_gpu(out)

@@ -46,7 +46,7 @@ def _variants(dtype):
 
 def _set(R, s, t, dtype):
     R.set_tile(s.gh, s.nst, t["B"], t["TX"], t["TY"], t["ZC"], t["PD"], t["PT"], t["BO"],
-               t["ZM"], FU=t["FU"], dtype=dtype)
+               t["ZM"], dtype=dtype)
 
 
 def test_every_fp64_tile_matches_oracle(sys_):

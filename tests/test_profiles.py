@@ -27,8 +27,8 @@ def test_traffic_summaries_are_used_only_when_current():
     assert paths
     for p in paths:
         kv = _kv(p)
-        vals = [int(v) for v in kv["tile"].split(",")]
-        tile = dict(zip(("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM", "FU"), vals + [0] * (9 - len(vals))))
+        B, TX, TY, ZC, PD, PT, BO, ZM = (int(v) for v in kv["tile"].split(","))
+        tile = dict(B=B, TX=TX, TY=TY, ZC=ZC, PD=PD, PT=PT, BO=BO, ZM=ZM)
         got = bench.read_traffic("sphere18_wells", tile, int(kv.get("row_align", "1")))
         if kv["stencil_source_sha256"] == bench.stencil_source_hash():
             assert got == float(kv["hbm_bytes_per_launch"]), p
