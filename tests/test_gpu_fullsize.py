@@ -115,3 +115,32 @@ def test_sphere18_complex_scaled_sampled_orbitals(sphere18):
     got, dead = _sample(psi, s)
     assert orbital_rel_err(got, oracle.taylor_step(oh, sub, 0.005), len(SAMPLE)) <= 1e-12
     assert dead == 0.0
+
+
+def test_sphere18_reductions_sampled_orbitals(sphere18):
+    """The reductions at full size, where every orbital's sum is split over
+    the capped number of partial-sum workgroups: <a|b>, |a|^2, the energy
+    and the dipole moment of all 64 orbitals in one call, against the
+    oracle's serial sums on the sampled orbitals (1e-12 relative)."""
+    s = sphere18
+    R = rsg()
+    psi = torch.from_numpy(s["psi_om"]).cuda()
+    phi_h = synth.white_noise(s["cfg"]["seed"] + 7, s["og"].np, s["cfg"]["nst"], s["cfg"]["h"])
+    phi = torch.zeros_like(psi)
+    phi[:, torch.from_numpy(s["live"]).cuda()] = torch.from_numpy(phi_h).cuda().t()
+    sub = np.ascontiguousarray(s["psi"][:, SAMPLE])
+    subp = np.ascontiguousarray(phi_h[:, SAMPLE])
+    d = R.dot(s["gg"], phi, psi).cpu().numpy()[SAMPLE]
+    np.testing.assert_allclose(d, oracle.dot(s["og"], subp, sub), rtol=1e-12, atol=0)
+    n2 = R.norm2(s["gg"], psi).cpu().numpy()[SAMPLE]
+    np.testing.assert_allclose(n2, oracle.norm2(s["og"], sub), rtol=1e-12, atol=0)
+    e = R.energy(s["gh"], psi).cpu().numpy()[SAMPLE]
+    _, e_ref = oracle.energy(s["oh"], sub)
+    np.testing.assert_allclose(e.real, e_ref.real, rtol=1e-12, atol=0)
+    assert np.abs(e.imag - e_ref.imag).max() <= 1e-12 * np.abs(e_ref.real).max()
+    # the dipole expectation along z, with a handle that has a dipole axis
+    gz = R.Hamiltonian(s["gg"], V=torch.from_numpy(s["Vs"]).cuda(), kin=-0.5, dipole_axis=2)
+    dz = R.dipole_expectation(gz, psi).cpu().numpy()[SAMPLE]
+    oz = oracle.Ham(s["og"], V=s["V"], kin=-0.5, dipole_axis=2)
+    ref = np.array([oracle.dipole_target(oz, sub[:, [k]]) for k in range(len(SAMPLE))])
+    np.testing.assert_allclose(dz, ref, rtol=1e-12, atol=1e-14)
