@@ -6,8 +6,9 @@
 // classes (by the width of their box), each class with its own stencil tile
 // shape; every stage of a Taylor(4) step runs, per class, as one persistent
 // stencil launch over a list of (system, tile, z-range, orbital) items
-// (largest systems first, each sweeping its tiles orbital by orbital),
-// preceded by one projector gather launch and followed by one scatter launch
+// (largest systems first, each sweeping its tiles orbital by orbital; the
+// list is cut into one contiguous segment per XCD, so that each XCD's L2
+// holds the halos its neighbouring tiles share), preceded by one projector gather launch and followed by one scatter launch
 // per colour, all systems at once.  A step sequence can be captured once into
 // a HIP graph and replayed.  Each output point is computed by the same
 // arithmetic as the single-system path, so the results are bitwise equal to
@@ -27,6 +28,7 @@ struct BatchClass {
     TileShape tile{1, 32, 8, 0};
     std::vector<int32_t> sys;    // member systems
     BatchItem *items = nullptr;  // device work list of this class
+    int32_t *seg = nullptr;      // device bounds of the list's per-XCD segments
     int32_t nitems = 0;
     int grid = 0;                // resident workgroups of the class's kernel
 };
@@ -59,7 +61,9 @@ struct Batch {
         }
         for (auto &c : cls) {
             if (c.items) (void)hipFree(c.items);
+            if (c.seg) (void)hipFree(c.seg);
             c.items = nullptr;
+            c.seg = nullptr;
             c.nitems = 0;
         }
         if (ctr) (void)hipFree(ctr);
@@ -122,7 +126,9 @@ void stage_buffers(const Batch &b, size_t i, int k, const void **in, const void 
 int build_class(Batch &b, size_t c, hipStream_t s) {
     BatchClass &cl = b.cls[c];
     if (cl.items) (void)hipFree(cl.items);
+    if (cl.seg) (void)hipFree(cl.seg);
     cl.items = nullptr;
+    cl.seg = nullptr;
     cl.nitems = 0;
     b.drop_graphs();
     std::vector<int32_t> by_work = cl.sys;
@@ -146,10 +152,21 @@ int build_class(Batch &b, size_t c, hipStream_t s) {
         for (int n = 0; n < (int)d.nst; ++n)
             for (const int4 &t : pit) items.push_back(BatchItem{t, i, n});
     }
+    // per-XCD segments of about equal work: a march costs its z-planes plus
+    // the planes that fill the register ring
+    std::vector<int64_t> cum(items.size() + 1, 0);
+    for (size_t w = 0; w < items.size(); ++w)
+        cum[w + 1] = cum[w] + std::abs(items[w].tile.w - items[w].tile.z) + 8;
+    std::vector<int32_t> seg(kBatchQueues + 1, 0);
+    for (int q = 1; q < kBatchQueues; ++q)
+        seg[q] = (int32_t)(std::lower_bound(cum.begin(), cum.end(), cum.back() * q / kBatchQueues) - cum.begin());
+    seg[kBatchQueues] = (int32_t)items.size();
+    for (int q = 1; q <= kBatchQueues; ++q) seg[q] = std::max(seg[q], seg[q - 1]);
     cl.grid = stencil_batch_grid(cl.tile, true);
     if (cl.grid <= 0) return cl.grid;
     int rc = upload(&cl.items, items, s);
     if (rc) return rc;
+    if ((rc = upload(&cl.seg, seg, s))) return rc;
     cl.nitems = (int32_t)items.size();
     RSG_CHECK_HIP(hipStreamSynchronize(s));
     return RSG_OK;
@@ -220,7 +237,7 @@ int build_tables(Batch &b, hipStream_t s) {
         if ((rc = upload(&b.sp[k], sp[k], s))) return rc;
         if ((rc = upload(&b.kb[k], kb[k], s))) return rc;
     }
-    const std::vector<int32_t> ctr0{0, 0};  // lives until the stream synchronisation below
+    const std::vector<int32_t> ctr0(kBatchQueues + 1, 0);  // lives until the stream synchronisation below
     if ((rc = upload(&b.ctr, ctr0, s))) return rc;
     if ((rc = upload(&b.gitems, gitems, s))) return rc;
     if ((rc = upload(&b.sumitems, sumitems, s))) return rc;
@@ -244,7 +261,8 @@ int class_grid(const Batch &b, const BatchClass &c) {
 
 // The persistent stencil launch of one class for stage k with factor (cre, cim).
 int class_launch(const Batch &b, const BatchClass &c, int k, double cre, double cim, hipStream_t s) {
-    return launch_stencil_batch(c.tile, 1, true, b.sp[k], c.items, c.nitems, cre, cim, b.ctr, class_grid(b, c), s);
+    return launch_stencil_batch(c.tile, 1, true, b.sp[k], c.items, c.seg, c.nitems, cre, cim, b.ctr, class_grid(b, c),
+                                s);
 }
 
 // Stage k of a step, the same product form as a single system's FP64 step:

@@ -192,7 +192,7 @@ struct KParams {
     double kin_h2_im;   // imaginary part of the kinetic prefactor over h^2 (complex scaling)
     double field;
     double h;
-    double off[3];
+    double off_axis;    // box centre along the field axis, in grid steps
     double cre, cim;
     int32_t nitems;
     int32_t block_order;
@@ -217,11 +217,16 @@ TileShape launch_shape(const Ham &H, const TileShape &tile);
 // precision (the number of pair partials of an adjoint stage), or a negative
 // error code.  May create the tile's launch plan (not during capture).
 int64_t stencil_blocks(const Ham &H, int64_t nst, int compute, hipStream_t s);
-// ctr: two device int32 work counters, zero before the first launch (each
-// launch leaves them zero again); launches sharing them must not overlap.
+// Work queues of the batched stencil: one per XCD of the device.
+constexpr int kBatchQueues = 8;
+// seg: kBatchQueues + 1 device int32 bounds, segment q of the item list is
+// [seg[q], seg[q + 1]) with seg[0] = 0 and seg[kBatchQueues] = nitems.
+// ctr: kBatchQueues + 1 device int32 work counters, zero before the first
+// launch (each launch leaves them zero again); launches sharing them must
+// not overlap.
 int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
-                         const BatchItem *items, int32_t nitems, double cre, double cim, int32_t *ctr,
-                         int grid, hipStream_t s);
+                         const BatchItem *items, const int32_t *seg, int32_t nitems, double cre, double cim,
+                         int32_t *ctr, int grid, hipStream_t s);
 // Resident workgroups of the batched kernel for this shape (or an error code).
 int stencil_batch_grid(const TileShape &shape, bool first);
 TileShape default_shape(const Grid &g, int64_t nst, int compute);

@@ -86,7 +86,7 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
     Tc vloc = v_c;
     if (a.axis >= 0) {
         const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
-        const double xc = a.h * ((double)cc - a.off[a.axis]);
+        const double xc = a.h * ((double)cc - a.off_axis);
         vloc += (Tc)(E * xc);
         if constexpr (PAIR) {
             pacc.x += xc * ((double)q0.x * b_c.x + (double)q0.y * b_c.y);
@@ -450,42 +450,50 @@ __global__ void __launch_bounds__(TX * TY) k_stencil(KParams a) {
     }
 }
 
-// Persistent form over many independent systems (FP64): each workgroup
-// takes the next item of the list {tile, system, orbital} from a work
-// counter as soon as it is free, so the items in flight at any time are
+// Persistent form over many independent systems (FP64).  The item list
+// {tile, system, orbital} is cut into kBatchQueues contiguous segments of
+// about equal work, one per XCD: a workgroup takes the next item of its own
+// XCD's segment (workgroup b runs on XCD b mod 8) from that segment's
+// counter as soon as it is free, so the items in flight on one XCD are
 // neighbours in the list (neighbouring tiles of one system and orbital,
-// which share halo lines in L2) however long each march is.  Each system's
-// parameters come from sysp[system].  ctr[0] counts items taken, ctr[1]
-// workgroups done; the last workgroup out sets both back to zero for the
-// next launch (every workgroup takes its last item before it counts itself
-// done, so no item is taken after the reset).
+// which then share halo lines in that XCD's L2) however long each march is.
+// A workgroup whose segment is used up takes items from the following
+// segments in turn.  Each system's parameters come from sysp[system].
+// ctr[q] counts the items taken from segment q, ctr[kBatchQueues] the
+// workgroups done; the last workgroup out sets them all back to zero for
+// the next launch (every workgroup has found every segment used up before
+// it counts itself done, so no item is taken after the reset).
 template <int TX, int TY, int D, bool FIRST>
 __global__ void __launch_bounds__(TX * TY) k_stencil_batch(const KParams *__restrict__ sysp,
                                                            const BatchItem *__restrict__ items,
-                                                           int32_t nitems, double cre, double cim,
-                                                           int32_t *ctr) {
+                                                           const int32_t *__restrict__ seg, double cre,
+                                                           double cim, int32_t *ctr) {
     __shared__ double2 tile[2 * (TY + 8) * (TX + 8)];  // two plane buffers
     __shared__ int32_t next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
-        __syncthreads();
-        const int w = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();  // every thread has read next before it is written again
-        if (w >= nitems) break;
-        const BatchItem bi = items[w];
-        KParams a = sysp[__builtin_amdgcn_readfirstlane(bi.sys)];
-        a.cre = cre;
-        a.cim = cim;
-        double2 unused = make_double2(0.0, 0.0);
-        march<TX, TY, D, double2, double, double2, 1, FIRST, false, false>(
-            a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile, unused);
-        __syncthreads();  // the next item reuses the plane buffer
+    const int home = blockIdx.x % kBatchQueues;
+    for (int j = 0; j < kBatchQueues; ++j) {
+        const int q = (home + j) % kBatchQueues;
+        const int32_t s0 = seg[q], s1 = seg[q + 1];
+        for (;;) {
+            if (threadIdx.x == 0) next = s0 + atomicAdd(&ctr[q], 1);
+            __syncthreads();
+            const int w = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();  // every thread has read next before it is written again
+            if (w >= s1) break;
+            const BatchItem bi = items[w];
+            KParams a = sysp[__builtin_amdgcn_readfirstlane(bi.sys)];
+            a.cre = cre;
+            a.cim = cim;
+            double2 unused = make_double2(0.0, 0.0);
+            march<TX, TY, D, double2, double, double2, 1, FIRST, false, false>(
+                a, bi.tile, __builtin_amdgcn_readfirstlane(bi.ob), tile, unused);
+            __syncthreads();  // the next item reuses the plane buffer
+        }
     }
     if (threadIdx.x == 0) {
-        __threadfence();  // this workgroup's last take precedes its count below
-        if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
-            atomicExch(&ctr[0], 0);
-            atomicExch(&ctr[1], 0);
+        __threadfence();  // this workgroup's last takes precede its count below
+        if (atomicAdd(&ctr[kBatchQueues], 1) == (int)gridDim.x - 1) {
+            for (int q = 0; q <= kBatchQueues; ++q) atomicExch(&ctr[q], 0);
         }
     }
 }
@@ -632,7 +640,9 @@ KParams make_params(const Ham &H, const StageArgs &a, const TileShape &shape, co
     }
     p.field = a.field;
     p.h = g.h;
-    for (int k = 0; k < 3; ++k) p.off[k] = 0.5 * (double)(g.n[k] - 1);
+    // box centre along the field axis (one scalar, so that a register copy
+    // of these parameters needs no indexed private-memory array)
+    p.off_axis = H.axis >= 0 ? 0.5 * (double)(g.n[H.axis] - 1) : 0.0;
     p.cre = a.cre;
     p.cim = a.cim;
     p.nitems = plan ? plan->nitems : 0;
@@ -730,8 +740,8 @@ namespace {
 // device (occupancy query, not allowed during graph capture); grid > 0:
 // launch with that many persistent workgroups.
 template <int TX, int TY, int D, bool FIRST>
-int launch_batch_inst(const KParams *sysp, const BatchItem *items, int32_t nitems, double cre, double cim,
-                      int32_t *ctr, int grid, hipStream_t s) {
+int launch_batch_inst(const KParams *sysp, const BatchItem *items, const int32_t *seg, int32_t nitems, double cre,
+                      double cim, int32_t *ctr, int grid, hipStream_t s) {
     constexpr int NT = TX * TY;
     auto kern = k_stencil_batch<TX, TY, D, FIRST>;
     if (grid < 0) {
@@ -742,15 +752,15 @@ int launch_batch_inst(const KParams *sysp, const BatchItem *items, int32_t nitem
         RSG_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0));
         return std::max(1, per_cu) * prop.multiProcessorCount;
     }
-    kern<<<(int)std::min<int64_t>(nitems, grid), NT, 0, s>>>(sysp, items, nitems, cre, cim, ctr);
+    kern<<<(int)std::min<int64_t>(nitems, grid), NT, 0, s>>>(sysp, items, seg, cre, cim, ctr);
     return RSG_OK;
 }
 
 template <int TX, int TY, int D>
-int launch_batch_shape(bool first, const KParams *sysp, const BatchItem *items, int32_t nitems, double cre,
-                       double cim, int32_t *ctr, int grid, hipStream_t s) {
-    if (first) return launch_batch_inst<TX, TY, D, true>(sysp, items, nitems, cre, cim, ctr, grid, s);
-    return launch_batch_inst<TX, TY, D, false>(sysp, items, nitems, cre, cim, ctr, grid, s);
+int launch_batch_shape(bool first, const KParams *sysp, const BatchItem *items, const int32_t *seg, int32_t nitems,
+                       double cre, double cim, int32_t *ctr, int grid, hipStream_t s) {
+    if (first) return launch_batch_inst<TX, TY, D, true>(sysp, items, seg, nitems, cre, cim, ctr, grid, s);
+    return launch_batch_inst<TX, TY, D, false>(sysp, items, seg, nitems, cre, cim, ctr, grid, s);
 }
 }  // namespace
 
@@ -760,7 +770,7 @@ int stencil_batch_grid(const TileShape &shape, bool first) {
 #define RSG_TRY_G(X_, Y_, D_)                                                                        \
     if (!found && shape.TX == X_ && shape.TY == Y_ && shape.PD == D_) {                              \
         found = true;                                                                                \
-        g = launch_batch_shape<X_, Y_, D_>(first, nullptr, nullptr, 0, 0.0, 0.0, nullptr, -1, nullptr); \
+        g = launch_batch_shape<X_, Y_, D_>(first, nullptr, nullptr, nullptr, 0, 0.0, 0.0, nullptr, -1, nullptr); \
     }
     if (shape.B == 1) { RSG_FP64_SHAPES(RSG_TRY_G) }
 #undef RSG_TRY_G
@@ -768,15 +778,15 @@ int stencil_batch_grid(const TileShape &shape, bool first) {
 }
 
 int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
-                         const BatchItem *items, int32_t nitems, double cre, double cim, int32_t *ctr,
-                         int grid, hipStream_t s) {
+                         const BatchItem *items, const int32_t *seg, int32_t nitems, double cre, double cim,
+                         int32_t *ctr, int grid, hipStream_t s) {
     if (nitems == 0) return RSG_OK;
     if (mode != 1) {
         set_error("batched stencil: only Horner stages are batched");
         return RSG_EUNSUPPORTED;
     }
-    if (grid <= 0 || !ctr) {
-        set_error("batched stencil: need a persistent grid size > 0 and a work counter");
+    if (grid <= 0 || !ctr || !seg) {
+        set_error("batched stencil: need a persistent grid size > 0, work counters and segment bounds");
         return RSG_EINVAL;
     }
     int rc = RSG_EUNSUPPORTED;
@@ -785,7 +795,7 @@ int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KPa
 #define RSG_TRY_B(X_, Y_, D_)                                                                      \
     if (!found && shape.TX == X_ && shape.TY == Y_ && shape.PD == D_) {                            \
         found = true;                                                                              \
-        rc = launch_batch_shape<X_, Y_, D_>(first, sysp, items, nitems, cre, cim, ctr, grid, s);   \
+        rc = launch_batch_shape<X_, Y_, D_>(first, sysp, items, seg, nitems, cre, cim, ctr, grid, s); \
     }
     if (shape.B == 1) { RSG_FP64_SHAPES(RSG_TRY_B) }
 #undef RSG_TRY_B
