@@ -14,6 +14,7 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -37,21 +38,25 @@ def stencil_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(workload: str, tile=None, align: int = 1):
+def _summary_fields(path: str) -> dict:
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    return kv
+
+
+def read_traffic(workload: str, tile=None, align: int = 1, with_path: bool = False):
     """HBM bytes per stencil launch from a committed rocprofv3 counter
     summary (profiles/traffic_stencil_<workload>*.txt) taken on the current
     stencil source with the tile shape and grid row alignment in use; None
-    if there is none."""
-    import glob
+    if there is none.  with_path: (bytes, summary file name) or (None, None)."""
     key = None
     if tile is not None:
         key = ",".join(str(tile[k]) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM"))
     for p in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_stencil_{workload}*.txt"))):
-        kv = {}
-        for line in open(p):
-            if ":" in line and not line.lstrip().startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
+        kv = _summary_fields(p)
         if kv.get("stencil_source_sha256") != stencil_source_hash():
             continue
         if key is not None and kv.get("tile") != key:
@@ -59,10 +64,11 @@ def read_traffic(workload: str, tile=None, align: int = 1):
         if int(kv.get("row_align", "1")) != align:
             continue
         try:
-            return float(kv["hbm_bytes_per_launch"])
+            v = float(kv["hbm_bytes_per_launch"])
         except (KeyError, ValueError):
             continue
-    return None
+        return (v, os.path.join("profiles", os.path.basename(p))) if with_path else v
+    return (None, None) if with_path else None
 
 
 def place_on_slots(gg, live, V, proj, psi_h, dev):
@@ -212,7 +218,7 @@ def bench_sphere(args):
     # and reads V (8 B per point)
     stage_bytes = npts * nst * 32 + 8 * npts
     achieved = stage_bytes / (kt.mean_ms * 1e-3) / 1e9 if kt.count else None
-    traffic = read_traffic(args.workload, tile, gg.align)
+    traffic, traffic_src = read_traffic(args.workload, tile, gg.align, with_path=True)
     norms = rsg.norm2(gg, psi).cpu().numpy()
     # plain device copy of 1 GiB: achievable copy bandwidth, and the
     # reference kernel for scaling the HBM byte counters
@@ -246,7 +252,13 @@ def bench_sphere(args):
                    "stencil": "8th-order 25-point star", "row_align": gg.align, "slots": gg.np},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "kernel": "k_stencil (Taylor stage, product form)",
+                     "frac_basis": "algorithmic bytes per launch / HIP-event kernel mean of this run",
+                     "traffic": traffic,
+                     "traffic_basis": (f"HBM bytes per launch from {traffic_src} (rocprofv3 FETCH_SIZE and "
+                                       "WRITE_SIZE of this tile on this stencil source, scaled by a 1 GiB "
+                                       "copy); not measured in this run") if traffic else None,
+                     "traffic_over_algorithmic": (traffic / stage_bytes) if traffic else None,
+                     "kernel": "k_stencil (Taylor stage, product form)",
                      "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count,
                      "algorithmic_bytes_per_launch": stage_bytes, "tile": tile,
                      "copy_gbs": copy_gbs},
@@ -291,6 +303,12 @@ def bench_batch(args):
         keep.append(gg)
         tot += gg.npoints * sp.nst
     log(f"sum np*nst = {tot:.4e}")
+    # one 1 GiB copy: the reference dispatch for scaling HBM traffic counters
+    src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    dstb = torch.empty_like(src)
+    rsg.copy(src, dstb)
+    torch.cuda.synchronize()
+    del src, dstb
     stream = torch.cuda.Stream()
     dt = cfg["dt"]
     with torch.cuda.stream(stream):
@@ -330,6 +348,15 @@ def bench_batch(args):
         t5 = time.perf_counter()
     el = t1 - t0
     value = tot * 4 * args.steps / el
+    # counter summary of this stencil source with every class on one tile
+    ctraffic, ctraffic_src = None, None
+    for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_stencil_batch256_*.txt"))):
+        kv = _summary_fields(p)
+        key = ",".join(str(class_tiles[0][k]) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM"))
+        if (kv.get("stencil_source_sha256") == stencil_source_hash() and kv.get("tile") == key
+                and all(t == class_tiles[0] for t in class_tiles) and int(kv.get("row_align", "0")) == args.align):
+            ctraffic, ctraffic_src = float(kv["hbm_bytes_per_stage"]), os.path.join("profiles", os.path.basename(p))
+            break
     stage_bytes = tot * 32.0  # every stage of the product-form step: read its input, write its output
     stage_ms = kt.total_ms / (4 * timed_steps) if kt.count else None  # all classes' launches of a stage
     achieved = stage_bytes / (stage_ms * 1e-3) / 1e9 if kt.count else None
@@ -342,7 +369,13 @@ def bench_batch(args):
                    "class_sizes": [int((classes == c).sum()) for c in range(len(class_tiles))],
                    "row_align": args.align},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "frac_basis": "algorithmic bytes of a stage (32 B/pt·orb) / HIP-event time of its launches",
+                     "traffic": ctraffic,
+                     "traffic_basis": (f"HBM bytes per stage (all class launches) from {ctraffic_src} "
+                                       "(rocprofv3 FETCH_SIZE and WRITE_SIZE on this stencil source and tile, "
+                                       "scaled by a 1 GiB copy); not measured in this run")
+                     if ctraffic else None,
                      "kernel": "k_stencil_batch (persistent; one launch per size class and stage)",
                      "stage_ms": stage_ms, "kernel_mean_ms": kt.mean_ms, "launches_timed": kt.count},
         "per_system_eager_value": tot * 4 * per_steps / (t5 - t4),
@@ -939,9 +972,15 @@ def sub_results(args) -> dict:
                              "fd_rel_err": r["fd_rel_err"], "directional_derivative": r["directional_derivative"],
                              "central_fd": r["central_fd"],
                              "sweep_algorithmic_GBs": r["roofline"]["sweep_algorithmic_GBs"]}
-    r = run("batch256", bench_batch, ns(steps=10, warmup=2, align=8))
+    # every class on 16x16, depth 2: the per-class autotuner's choices measured
+    # within 0.5 % of it on this workload, and with one tile the line can carry
+    # the committed counter summary's traffic
+    r = run("batch256", bench_batch, ns(steps=10, warmup=2, align=8, tile="1,16,16,0,2,0,0,0"))
     out["batch256"] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
                        "stencil_stage_ms": r["roofline"]["stage_ms"], "roofline_frac": r["roofline"]["frac"],
+                       "traffic_per_stage": r["roofline"]["traffic"],
+                       "traffic_over_algorithmic": (r["roofline"]["traffic"] / (32.0 * r["config"]["sum_np_nst"])
+                                                    if r["roofline"]["traffic"] else None),
                        "sum_np_nst": r["config"]["sum_np_nst"], "class_tiles": r["config"]["class_tiles"],
                        "class_sizes": r["config"]["class_sizes"],
                        "per_system_eager_value": r["per_system_eager_value"]}

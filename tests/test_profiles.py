@@ -48,3 +48,20 @@ def test_every_workload_has_kernel_statistics():
         text = open(os.path.join(ROOT, "profiles", f"kernel_stats_{w}.txt")).read()
         assert "rocprofv3 --kernel-trace --stats" in text and "bench.py" in text, w
         assert "k_stencil" in text, w
+
+
+def test_batch_traffic_summary_is_consistent():
+    """The batched stencil's counter summary adds its stage's fetch and
+    write bytes, names its tile, and (when taken on the current source)
+    reports more bytes than the algorithmic 32 B per point-orbital."""
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_stencil_batch256_*.txt")))
+    assert paths
+    for p in paths:
+        kv = _kv(p)
+        assert len(kv["tile"].split(",")) == 8, p
+        hbm = float(kv["hbm_bytes_per_stage"])
+        parts = float(kv["stage_fetch_bytes"]) + float(kv["stage_write_bytes"])
+        assert abs(hbm - parts) <= 1e-3 * hbm, p
+        assert abs(float(kv["algorithmic_bytes_per_stage"]) - 688438342 * 32.0) <= 1e-4 * 688438342 * 32.0, p
+        if kv["stencil_source_sha256"] == bench.stencil_source_hash():
+            assert 1.0 < hbm / float(kv["algorithmic_bytes_per_stage"]) < 4.0, p
