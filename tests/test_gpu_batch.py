@@ -234,3 +234,70 @@ def test_batch_uneven_spheres_at_scale():
         dead = np.ones(s["gg"].np, dtype=bool)
         dead[s["live"]] = False
         assert np.all(e[:, dead] == 0)
+
+
+def test_batch256_workload_sampled_against_oracle():
+    """The 256-system workload at full size (R ~ U(4, 12) bohr at h = 0.25,
+    1..32 orbitals, 1..8 wells with projectors; 688,438,342
+    point-orbitals), in its default size classes, one step as the benchmark
+    runs it: every system in the batch, the step replayed from a HIP graph
+    with the eager step's bits, and one orbital of each of 24 sampled
+    systems equal to the oracle's step to 1e-12 (dead slots zero)."""
+    R = rsg()
+    cfg = dict(synth.WORKLOADS["batch256"])
+    specs = synth.batch_specs(cfg["seed"], cfg["nsys"], cfg["Rmin"], cfg["Rmax"], cfg["h"], cfg["nst_max"],
+                              cfg["atoms_max"])
+    assert len(specs) == 256
+    pick = synth.rng(cfg["seed"], 78)
+    sample = set(int(k) for k in pick.choice(256, size=24, replace=False))
+    systems, total = [], 0
+    for k, sp in enumerate(specs):
+        gg = R.Grid(sp.h, R=sp.R, align=8)
+        live = gg.live()
+        pos = gg.positions()[live]
+        V = synth.well_potential(pos, sp.wells)
+        proj = synth.kb_projectors(sp.seed, pos, sp.wells.centres)
+        psi = synth.white_noise(sp.seed, gg.npoints, sp.nst, sp.h)
+        Vs = np.zeros(gg.np)
+        Vs[live] = V
+        projs = [(torch.from_numpy(live[i].astype(np.int32)).cuda(), torch.from_numpy(p).cuda(), E)
+                 for i, p, E in zip(proj.idx, proj.p, proj.E)]
+        gh = R.Hamiltonian(gg, V=torch.from_numpy(Vs).cuda(), kin=-0.5, projectors=projs)
+        t = torch.zeros((sp.nst, gg.np), dtype=torch.complex128, device="cuda")
+        t[:, torch.from_numpy(live).cuda()] = torch.from_numpy(psi).cuda().t()
+        n = int(pick.integers(0, sp.nst))
+        keep = dict(sp=sp, pos=pos, V=V, proj=proj, psi=psi[:, [n]].copy(), n=n) if k in sample else None
+        systems.append(dict(gg=gg, gh=gh, live=live, psi0=t.clone(), t=t, nst=sp.nst, keep=keep))
+        total += gg.npoints * sp.nst
+        del psi
+    assert total == 688438342
+    dt = cfg["dt"]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = R.Batch([(s["gh"], s["t"], s["nst"]) for s in systems])
+        b.propagate(dt, 1)
+        torch.cuda.synchronize()
+        for s in systems:  # the graph's batch starts from the same inputs
+            s["eager"] = s["t"]
+            s["t"] = s["psi0"]
+        bg = R.Batch([(s["gh"], s["t"], s["nst"]) for s in systems])
+        bg.propagate(dt, 1, graph=True)
+        torch.cuda.synchronize()
+        for s in systems:
+            assert torch.equal(s["t"], s["eager"])
+    for s in systems:
+        kp = s["keep"]
+        if kp is None:
+            continue
+        sp = kp["sp"]
+        og = oracle.Grid(sp.h, R=sp.R)
+        assert og.np == s["gg"].npoints
+        np.testing.assert_array_equal(og.positions(), kp["pos"])
+        oh = oracle.Ham(og, V=kp["V"], kin=-0.5, projectors=kp["proj"])
+        ref = oracle.propagate(oh, kp["psi"], dt, 1)
+        e = s["eager"][kp["n"]].cpu().numpy()
+        got = e[s["live"]][:, None]
+        assert orbital_rel_err(got, ref, 1) <= 1e-12, (sp.R, sp.nst, kp["n"])
+        dead = np.ones(s["gg"].np, dtype=bool)
+        dead[s["live"]] = False
+        assert np.all(e[dead] == 0)
