@@ -79,3 +79,28 @@ def test_row_alignment_argument_errors(lib):
         assert b"align" in lib.rsg_last_error()
     assert lib.rsg_grid_create_aligned(None, 8, None, C.byref(out)) == -1
     assert b"null" in lib.rsg_last_error()
+
+
+def test_box_grid_and_noalloc_argument_errors(lib):
+    """Rectangular boxes and the allocation-free inner product reject bad
+    arguments on the host, before any device call."""
+    lib.rsg_last_error.restype = C.c_char_p
+    lib.rsg_grid_create_box.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_void_p,
+                                        C.c_void_p]
+    out = C.c_void_p()
+    assert lib.rsg_grid_create_box(8, 8, 8, 0.3, 1, None, None) == -1
+    assert b"null" in lib.rsg_last_error()
+    for nx, ny, nz in ((0, 4, 4), (4, -1, 4), (4, 4, 0)):
+        assert lib.rsg_grid_create_box(nx, ny, nz, 0.3, 1, None, C.byref(out)) == -1
+        assert b"at least 1 point" in lib.rsg_last_error()
+    assert lib.rsg_grid_create_box(40000, 1, 1, 0.3, 1, None, C.byref(out)) == -1
+    assert b"32767" in lib.rsg_last_error()
+    assert lib.rsg_grid_create_box(4, 4, 4, 0.0, 1, None, C.byref(out)) == -1
+    assert b"h must be" in lib.rsg_last_error()
+    assert lib.rsg_grid_create_box(4, 4, 4, 0.3, 3, None, C.byref(out)) == -1
+    assert b"align" in lib.rsg_last_error()
+    lib.rsg_dot_noalloc_max_bytes.restype = C.c_size_t
+    assert lib.rsg_dot_noalloc_max_bytes() == 1 << 20
+    lib.rsg_dot_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                    C.c_void_p]
+    assert lib.rsg_dot_noalloc(None, None, None, 1, 1, None, None) < 0
