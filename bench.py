@@ -1023,7 +1023,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the path shards over orbitals or systems "
-              "with no exchange, and this build measures the single-GPU share only "
+              "with no exchange, and the benchmark measures one GPU's share only "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch256":

@@ -68,7 +68,7 @@ enum {
     RSG_EDTYPE = -3,       /* unknown dtype */
     RSG_EHIP = -4,         /* a HIP runtime call failed */
     RSG_ENOMEM = -5,       /* workspace too small or allocation failed */
-    RSG_EUNSUPPORTED = -6  /* valid request this build does not serve */
+    RSG_EUNSUPPORTED = -6  /* valid request the library does not serve */
 };
 
 enum { RSG_C128 = 0, RSG_C64_MIXED = 1 };

@@ -53,7 +53,7 @@ int guarded(F &&f) {
 
 // ----------------------------------------------------------- launch plan --
 
-// Tile shape of the z-marching stencil: B orbitals (1 in this build) x TX x
+// Tile shape of the z-marching stencil: B orbitals (only B = 1 is compiled) x TX x
 // TY columns per workgroup, marching along z in chunks of at most ZC planes.
 // PD is the software-pipeline depth (planes in flight: 1..2; 0 selects the
 // lean march).  PT = 1 launches the tiles of a z-chunk in Morton order;
