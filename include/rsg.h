@@ -413,7 +413,9 @@ size_t rsg_batch_workspace_bytes(int32_t nsys, const rsg_system_desc *sys);
  * are dropped), and each class has its own stencil tile shape (initially
  * 32 x 8, depth 2).  Each stage of a Taylor(4) step of all systems runs as
  * one persistent stencil launch per class over a list of (system, tile,
- * z-range, orbital) items (largest systems first), with one projector
+ * z-range, orbital) items (largest systems first; cut into one segment per
+ * XCD, each workgroup taking items from its own XCD's segment first and
+ * then from the others), with one projector
  * gather launch and one scatter launch per colour for all systems.  ws
  * (rsg_batch_workspace_bytes) holds the work buffers and must outlive the
  * batch, as must every Hamiltonian and orbital array named in sys.  Results
