@@ -267,15 +267,18 @@ __global__ void __launch_bounds__(256) k_kb_scatter_batch(const KbSys *__restric
 }  // namespace
 
 // Support chunks per (atom, column tile): enough workgroups to fill the chip
-// when there are few atoms or few orbitals, each chunk at least 2 GW groups
-// of 4 support entries of the smallest support.
+// when there are few atoms or few orbitals, each chunk at least 8 GW groups
+// of 4 support entries of the smallest support (8 groups per wave: with
+// fewer, a batch of many small systems ran tens of thousands of nearly
+// empty gather workgroups).  The count depends on the system alone, so a
+// system gives the same bits alone or in a batch.
 int gather_chunks(const Ham &H, int64_t nst) {
     if (H.natoms == 0 || nst == 0) return 1;
     int64_t min_groups = INT64_MAX;
     for (int32_t a = 0; a < H.natoms; ++a) min_groups = std::min(min_groups, (H.kb_off[a + 1] - H.kb_off[a]) / 4);
     const int64_t tiles = (int64_t)H.natoms * ((2 * nst + 15) / 16);
     const int64_t want = (512 + tiles - 1) / tiles;
-    const int64_t cap = std::max<int64_t>(1, min_groups / (2 * GW));
+    const int64_t cap = std::max<int64_t>(1, min_groups / (8 * GW));
     return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(want, cap), 64));
 }
 
