@@ -172,7 +172,7 @@ __device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldo
                                              const Tc *__restrict__ p,
                                              const double *__restrict__ E,
                                              const Tc *__restrict__ D, double cre, double cim,
-                                             const double *__restrict__ mask) {
+                                             const double *__restrict__ mask, Tc (*buf)[17]) {
     using V = typename V4<Tc>::type;
     const int l = threadIdx.x & 63;
     const int lo = l & 15, hi = l >> 4;
@@ -188,15 +188,30 @@ __device__ __forceinline__ void scatter_tile(Tout *__restrict__ out, int64_t ldo
     }
     V zero = {0, 0, 0, 0};
     const V acc = mfma16(av, bv, zero);
-    const int64_t end = (int64_t)at.x + at.z;
+    // the 16 x 16 tile (support entry x column) through this wave's LDS
+    // slice, so that each lane then adds one complex value: a wave covers
+    // 16 consecutive entries of 4 orbitals per pass (256-byte runs where the
+    // support's points are consecutive)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t e = (int64_t)itm.y + acc_row(Tc(0), hi, r);
-        if (e < end && col < ncols) {
-            const int64_t pt = idx[e];
-            Tout *dst = out + (col >> 1) * ldo + 2 * pt + (col & 1);
-            const double add = mask ? mask[pt] * (double)acc[r] : (double)acc[r];
-            *dst = (Tout)((double)*dst + add);
+    for (int r = 0; r < 4; ++r) buf[acc_row(Tc(0), hi, r)][lo] = acc[r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t end = (int64_t)at.x + at.z;
+    const int el = l & 15;
+    const int64_t e = (int64_t)itm.y + el;
+    const int64_t pt = e < end ? idx[e] : 0;
+    const double m = (mask && e < end) ? mask[pt] : 1.0;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        const int o = (l >> 4) + 4 * pass;  // orbital within the column tile
+        const int64_t c = (int64_t)ct * 16 + 2 * o;
+        if (e < end && c < ncols) {
+            Tout *dst = out + (c >> 1) * ldo + 2 * pt;
+            const double are = (double)buf[el][2 * o], aim = (double)buf[el][2 * o + 1];
+            const double addr = mask ? m * are : are, addi = mask ? m * aim : aim;
+            dst[0] = (Tout)((double)dst[0] + addr);
+            dst[1] = (Tout)((double)dst[1] + addi);
         }
     }
 }
@@ -211,10 +226,12 @@ __global__ void __launch_bounds__(256) k_kb_scatter(Tout *__restrict__ out, int6
                                                     const double *__restrict__ E,
                                                     const Tc *__restrict__ D, double cre,
                                                     double cim, const double *__restrict__ mask) {
+    __shared__ Tc buf[4][16][17];  // one 16 x 16 tile per wave (padded rows)
     const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (item >= nitems) return;
     const int2 itm = items[item];  // {atom, first entry}
-    scatter_tile<Tout, Tc>(out, ldo, ncols, itm, atoms[itm.x], blockIdx.y, idx, p, E, D, cre, cim, mask);
+    scatter_tile<Tout, Tc>(out, ldo, ncols, itm, atoms[itm.x], blockIdx.y, idx, p, E, D, cre, cim, mask,
+                           buf[threadIdx.x >> 6]);
 }
 
 // Batched forms over many systems (FP64): item {system, atom, column tile}
@@ -256,12 +273,13 @@ __global__ void __launch_bounds__(256) k_kb_gather_sum_batch(const KbSys *__rest
 __global__ void __launch_bounds__(256) k_kb_scatter_batch(const KbSys *__restrict__ sys,
                                                           const int4 *__restrict__ items, int32_t nitems,
                                                           double cre, double cim) {
+    __shared__ double buf[4][16][17];  // one 16 x 16 tile per wave (padded rows)
     const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (item >= nitems) return;
     const int4 it = items[item];
     const KbSys &s = sys[it.x];
     scatter_tile<double, double>(s.out, s.ldo, s.ncols, make_int2(it.y, it.z), s.atoms[it.y], it.w, s.idx,
-                                 s.p, s.E, s.D, cre, cim, nullptr);
+                                 s.p, s.E, s.D, cre, cim, nullptr, buf[threadIdx.x >> 6]);
 }
 
 }  // namespace
