@@ -51,12 +51,16 @@ class System:
     point with align 1, and on its live slots (in the same order) for a
     row-aligned grid, whose dead slots the tests fill with zero."""
 
-    def __init__(self, h, *, R=None, n=None, potential="wells", natoms=0, nst=4, ld=None,
+    def __init__(self, h, *, R=None, n=None, box=None, potential="wells", natoms=0, nst=4, ld=None,
                  seed=0, dipole_axis=-1, kin=-0.5, well_ball=None, well_box=None, rcut=2.0,
                  orbitals="white", packet_box=5.0, pad=0, align=1):
         R_ = rsg()
-        self.og = oracle.Grid(h, R=R, n=n)
-        self.gg = R_.Grid(h, R=R, n=n, align=align)
+        if box is not None:
+            self.og = oracle.Grid(h, box=box)
+            self.gg = R_.Grid(h, box=box, align=align)
+        else:
+            self.og = oracle.Grid(h, R=R, n=n)
+            self.gg = R_.Grid(h, R=R, n=n, align=align)
         self.live = self.gg.live()
         assert self.gg.npoints == self.og.np and self.gg.dims == tuple(self.og.dims)
         assert align > 1 or self.gg.np == self.og.np

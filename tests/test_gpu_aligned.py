@@ -23,6 +23,7 @@ import pytest
 import torch
 
 import oracle
+import synth
 from tests.gpu_common import System, orbital_rel_err, rsg
 
 pytestmark = pytest.mark.gpu
@@ -316,3 +317,34 @@ def test_tiles_narrower_than_alignment(align, tile):
     assert orbital_rel_err(s.from_gpu(lam), lam_ref, 3) <= TOL
     assert g == pytest.approx(g_ref, rel=1e-11, abs=1e-14)
     assert np.all(s.dead_values(lam)[:3] == 0)
+
+
+@pytest.mark.parametrize("box,align,axis", [((40, 24, 17), 1, 0), ((40, 24, 17), 8, 1), ((7, 33, 20), 8, 2),
+                                            ((45, 9, 30), 16, 0)])
+def test_rectangular_boxes_hpsi_step_and_adjoint(box, align, axis):
+    """Rectangular boxes (every width, including ones that are not multiples
+    of the tile or of the row alignment), with wells, overlapping projectors
+    and a dipole field: H psi, a Taylor(4) step and an adjoint step equal the
+    oracle's to 1e-12, and the dead slots of aligned rows stay zero."""
+    s = System(0.3, box=box, potential="wells", natoms=3, nst=5, seed=21, dipole_axis=axis, well_box=1.5,
+               align=align)
+    R = rsg()
+    psi = s.to_gpu(s.psi)
+    ref = oracle.hpsi(s.oh, s.psi, field=0.17)
+    out = R.hpsi(s.gh, psi, field=0.17)
+    assert orbital_rel_err(s.from_gpu(out), ref, s.nst) <= 1e-12
+    if align > 1:
+        assert np.all(s.dead_values(out) == 0)
+    ref = oracle.taylor_step(s.oh, s.psi, 0.01, field=0.17)
+    R.propagate_step(s.gh, psi, 0.01, field=0.17)
+    assert orbital_rel_err(s.from_gpu(psi), ref, s.nst) <= 1e-12
+    if align > 1:
+        assert np.all(s.dead_values(psi) == 0)
+    lam0 = synth.white_noise(77, s.og.np, s.nst, s.og.h)
+    lam_ref, g_ref = oracle.adjoint_step(s.oh, s.psi, lam0, 0.01, 0.17)
+    lam = s.to_gpu(lam0)
+    g = R.adjoint_step(s.gh, s.to_gpu(s.psi), lam, 0.01, 0.17).item()
+    assert orbital_rel_err(s.from_gpu(lam), lam_ref, s.nst) <= 1e-12
+    assert g == pytest.approx(g_ref, rel=1e-10, abs=1e-12)
+    if align > 1:
+        assert np.all(s.dead_values(lam) == 0)
