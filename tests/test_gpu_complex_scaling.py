@@ -179,3 +179,30 @@ def test_paper_resonance_through_the_library():
     r = lam[2] - shift
     assert 0 < r.real < 1 and -1e-4 < r.imag < -1e-5, r
     np.testing.assert_allclose((lam[:2] - shift).real, bound.real, rtol=0, atol=1e-8)
+
+
+def test_scaled_propagate_in_a_graph_matches_eager():
+    """A complex-scaled handle whose tile is remapped at launch (64 x 8 and
+    32 x 8 have no complex-scaled kernel; 32 x 16 runs at depth 1) captures
+    its steps into a HIP graph, and every replay gives the eager steps'
+    bits."""
+    R = rsg()
+    s = System(0.3, R=3.6, potential="wells", natoms=0, nst=3, seed=53, well_ball=1.2)
+    rng = np.random.default_rng(54)
+    vim = -0.2 * rng.random(s.og.np)
+    s.gh.set_complex_scaling(0.25, torch.from_numpy(vim).cuda())
+    stream = torch.cuda.Stream()
+    for tile in [(1, 64, 8, 0, 2, 0, 1, 0), (1, 32, 8, 0, 2, 0, 1, 0), (1, 32, 16, 0, 2, 0, 2, 0)]:
+        R.set_tile(s.gh, s.nst, *tile)
+        with torch.cuda.stream(stream):
+            eager = s.to_gpu(s.psi)
+            R.propagate(s.gh, eager, 0.01, 4)
+            g = s.to_gpu(s.psi)
+            R.propagate(s.gh, g, 0.01, 4, graph=True)  # capture and first replay
+            torch.cuda.synchronize()
+            assert torch.equal(g, eager), tile
+            for _ in range(2):  # later replays, with eager work in between
+                h = s.to_gpu(s.psi)
+                R.propagate(s.gh, h, 0.01, 4, graph=True)
+                torch.cuda.synchronize()
+                assert torch.equal(h, eager), tile
