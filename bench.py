@@ -33,9 +33,15 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# the sources of the stencil kernels and their launch
+STENCIL_SOURCES = ("stencil.hip", "stencil_common.h", "stencil_inst.hip", "stencil_inst_nt.hip", "stencil_kernels.h")
+
+
 def stencil_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1501_05654_amd", "csrc", "stencil.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in STENCIL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1501_05654_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _summary_fields(path: str) -> dict:

@@ -38,6 +38,7 @@ struct Batch {
     std::vector<void *> w1, w2, D;  // per-system work buffers inside the caller's workspace
     std::vector<BatchClass> cls;
     int32_t grid_cap = 0;  // at most this many persistent workgroups per launch (0: no cap)
+    bool nt = false;       // stage outputs written with non-temporal stores
     KParams *sp[4] = {nullptr, nullptr, nullptr, nullptr};  // device, per stage, one per system
     KbSys *kb[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *ctr = nullptr;  // device work counters of the persistent stencil (zero between launches)
@@ -162,7 +163,7 @@ int build_class(Batch &b, size_t c, hipStream_t s) {
         seg[q] = (int32_t)(std::lower_bound(cum.begin(), cum.end(), cum.back() * q / kBatchQueues) - cum.begin());
     seg[kBatchQueues] = (int32_t)items.size();
     for (int q = 1; q <= kBatchQueues; ++q) seg[q] = std::max(seg[q], seg[q - 1]);
-    cl.grid = stencil_batch_grid(cl.tile, true);
+    cl.grid = stencil_batch_grid(cl.tile, true, b.nt);
     if (cl.grid <= 0) return cl.grid;
     int rc = upload(&cl.items, items, s);
     if (rc) return rc;
@@ -232,6 +233,10 @@ int build_tables(Batch &b, hipStream_t s) {
             }
         }
     }
+    // the stage outputs of all systems together decide the store policy
+    double out_bytes = 0;
+    for (const auto &d : b.sys) out_bytes += (double)d.nst * (double)d.ham->g->np * 16.0;
+    b.nt = out_bytes >= kNtStoreBytes;
     int rc;
     for (int k = 0; k < 4; ++k) {
         if ((rc = upload(&b.sp[k], sp[k], s))) return rc;
@@ -261,8 +266,8 @@ int class_grid(const Batch &b, const BatchClass &c) {
 
 // The persistent stencil launch of one class for stage k with factor (cre, cim).
 int class_launch(const Batch &b, const BatchClass &c, int k, double cre, double cim, hipStream_t s) {
-    return launch_stencil_batch(c.tile, 1, true, b.sp[k], c.items, c.seg, c.nitems, cre, cim, b.ctr, class_grid(b, c),
-                                s);
+    return launch_stencil_batch(c.tile, 1, true, b.nt, b.sp[k], c.items, c.seg, c.nitems, cre, cim, b.ctr,
+                                class_grid(b, c), s);
 }
 
 // Stage k of a step, the same product form as a single system's FP64 step:

@@ -200,6 +200,9 @@ struct KParams {
     int32_t axis;
     int32_t align;  // row alignment of the grid (1: compact rows, no dead slots)
 };
+// Stage outputs of at least this many bytes (the size of the last-level
+// cache behind L2) are written with non-temporal stores.
+constexpr double kNtStoreBytes = 256.0 * 1024 * 1024;
 // One work item of the batched stencil: tile (tx, ty, z0, z1) of system sys,
 // orbital ob.
 struct BatchItem {
@@ -223,12 +226,12 @@ constexpr int kBatchQueues = 8;
 // [seg[q], seg[q + 1]) with seg[0] = 0 and seg[kBatchQueues] = nitems.
 // ctr: kBatchQueues + 1 device int32 work counters, zero before the first
 // launch (each launch leaves them zero again); launches sharing them must
-// not overlap.
-int launch_stencil_batch(const TileShape &shape, int mode, bool first, const KParams *sysp,
+// not overlap.  nt: the kernel set with non-temporal output stores.
+int launch_stencil_batch(const TileShape &shape, int mode, bool first, bool nt, const KParams *sysp,
                          const BatchItem *items, const int32_t *seg, int32_t nitems, double cre, double cim,
                          int32_t *ctr, int grid, hipStream_t s);
 // Resident workgroups of the batched kernel for this shape (or an error code).
-int stencil_batch_grid(const TileShape &shape, bool first);
+int stencil_batch_grid(const TileShape &shape, bool first, bool nt);
 TileShape default_shape(const Grid &g, int64_t nst, int compute);
 std::vector<TileShape> tile_candidates(int compute);
 

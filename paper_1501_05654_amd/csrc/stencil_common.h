@@ -110,6 +110,10 @@ template <> struct BL<double2> {
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned o, double2 v) {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i_t, v), r, (int)o, 0, 0);
     }
+    // non-temporal (cache policy NT): the line is not kept in L2
+    static __device__ __forceinline__ void st_nt(__amdgpu_buffer_rsrc_t r, unsigned o, double2 v) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i_t, v), r, (int)o, 0, 2);
+    }
 };
 template <> struct BL<float2> {
     static __device__ __forceinline__ float2 ld(__amdgpu_buffer_rsrc_t r, unsigned o) {
@@ -117,6 +121,9 @@ template <> struct BL<float2> {
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned o, float2 v) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i_t, v), r, (int)o, 0, 0);
+    }
+    static __device__ __forceinline__ void st_nt(__amdgpu_buffer_rsrc_t r, unsigned o, float2 v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i_t, v), r, (int)o, 0, 2);
     }
 };
 template <> struct BL<double> {
@@ -136,11 +143,23 @@ __device__ __forceinline__ typename CT<Tc>::c2 load_c(__amdgpu_buffer_rsrc_t r, 
     return typename CT<Tc>::c2{(Tc)v.x, (Tc)v.y};
 }
 
+// NTS: non-temporal stores, for a stage output much larger than the caches
+// (streamed past L2, which then keeps the input planes and the halo lines
+// that neighbouring tiles still read); a compile-time choice, since a branch
+// per store costs more than the policy gains
+template <bool NTS>
 __device__ __forceinline__ void store_c(__amdgpu_buffer_rsrc_t r, unsigned o, double2 *, double re, double im) {
-    BL<double2>::st(r, o, make_double2(re, im));
+    if constexpr (NTS)
+        BL<double2>::st_nt(r, o, make_double2(re, im));
+    else
+        BL<double2>::st(r, o, make_double2(re, im));
 }
+template <bool NTS>
 __device__ __forceinline__ void store_c(__amdgpu_buffer_rsrc_t r, unsigned o, float2 *, double re, double im) {
-    BL<float2>::st(r, o, make_float2((float)re, (float)im));
+    if constexpr (NTS)
+        BL<float2>::st_nt(r, o, make_float2((float)re, (float)im));
+    else
+        BL<float2>::st(r, o, make_float2((float)re, (float)im));
 }
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
