@@ -57,9 +57,18 @@ __device__ __forceinline__ void block_item(const KParams &a, int blk, int *n, in
 // compiler would place the select where the load is issued and wait there);
 // a masked-off lane issues its load at an out-of-range offset, which the
 // buffer hardware answers with zero.
+// SEL: the test as unsigned compares and selects, which keeps the march's
+// step free of branches (used by the FP64 kernels; the FP32 ones keep the
+// plain form, whose code the compiler fits in fewer registers there).
+template <bool SEL>
 __device__ __forceinline__ int2 row_of(const KParams &a, int y, int z) {
-    const bool v = y >= 0 && y < a.ny && z >= 0 && z < a.nz;
-    return a.rows[v ? z * a.ny + y : a.ny * a.nz];
+    if constexpr (SEL) {
+        const bool v = (unsigned)y < (unsigned)a.ny && (unsigned)z < (unsigned)a.nz;
+        return a.rows[v ? z * a.ny + y : a.ny * a.nz];
+    } else {
+        const bool v = y >= 0 && y < a.ny && z >= 0 && z < a.nz;
+        return a.rows[v ? z * a.ny + y : a.ny * a.nz];
+    }
 }
 __device__ __forceinline__ int idx_in_row(int2 r, int x) {
     const int x0 = r.y & 0xffff, x1 = (r.y >> 16) & 0xffff;
@@ -69,11 +78,19 @@ __device__ __forceinline__ int idx_in_row(int2 r, int x) {
 // dead slot of a row-aligned grid (inside the row's x-range widened to
 // multiples of align, outside the box) gives -(index) - 2, which every load
 // treats as out of range and the store fills with zero; anything else -1.
+// SEL as for row_of: selects only.
+template <bool SEL>
 __device__ __forceinline__ int slot_in_row(int2 r, int x, int align) {
     const int x0 = r.y & 0xffff, x1 = (r.y >> 16) & 0xffff;
-    if (x >= x0 && x < x1) return r.x + x;
     const int a0 = x0 & -align, a1 = (x1 + align - 1) & -align;
-    return (x0 < x1 && x >= a0 && x < a1) ? -(r.x + x) - 2 : -1;
+    if constexpr (SEL) {
+        const int v = r.x + x;
+        const bool in = x >= x0 && x < x1, dead = x0 < x1 && x >= a0 && x < a1;
+        return in ? v : (dead ? -v - 2 : -1);
+    } else {
+        if (x >= x0 && x < x1) return r.x + x;
+        return (x0 < x1 && x >= a0 && x < a1) ? -(r.x + x) - 2 : -1;
+    }
 }
 
 // Buffer loads and stores (CDNA): a per-workgroup resource (base address,

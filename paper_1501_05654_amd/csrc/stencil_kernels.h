@@ -41,6 +41,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace rsg {
 namespace sk {
@@ -89,14 +90,22 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
                                        Tc vi_c, double2 b_c, double m_c, double E, int x, int y, int z,
                                        int idx, __amdgpu_buffer_rsrc_t rout, double2 &pacc) {
     Tc vloc = v_c;
-    if (a.axis >= 0) {
-        const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
-        const double xc = a.h * ((double)cc - a.off_axis);
-        vloc += (Tc)(E * xc);
-        if constexpr (PAIR) {
+    if constexpr (PAIR || !std::is_same<Tc, double>::value) {
+        if (a.axis >= 0) {
+            const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
+            const double xc = a.h * ((double)cc - a.off_axis);
+            vloc += (Tc)(E * xc);
             pacc.x += xc * ((double)q0.x * b_c.x + (double)q0.y * b_c.y);
             pacc.y += xc * ((double)q0.x * b_c.y - (double)q0.y * b_c.x);
         }
+    } else {
+        // the field term as a select (FP64): a branch in the march's step
+        // costs more than the few operations it would skip.  (In the FP32
+        // stages the select costs registers at the 4-wave occupancy limit.)
+        const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
+        const double xc = a.h * ((double)cc - a.off_axis);
+        const Tc vf = vloc + (Tc)(E * xc);
+        vloc = a.axis >= 0 ? vf : vloc;
     }
     const Tc kin_h2 = (Tc)a.kin_h2;
     Tc hr, hi;
@@ -144,6 +153,8 @@ template <bool NTS, int TX, int TY, int D, class Tin, class Tc, class Tout, int 
 __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile, double2 &pacc) {
     using C2 = typename CT<Tc>::c2;
+    // selects instead of branches in the row lookups (FP64 kernels)
+    constexpr bool SEL = std::is_same<Tc, double>::value;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
     static_assert(D >= 1 && D <= 2, "pipeline depth 1..2");
@@ -183,7 +194,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     int oid[Q];
 #pragma unroll
     for (int j = 0; j < Q - 1; ++j) {
-        oid[j] = slot_in_row(row_of(a, y, zs + dir * (j - 4)), x, a.align);
+        oid[j] = slot_in_row<SEL>(row_of<SEL>(a, y, zs + dir * (j - 4)), x, a.align);
         cv[j] = fetch(oid[j], true);
     }
     cv[Q - 1] = C2{(Tc)0, (Tc)0};
@@ -193,7 +204,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     for (int d = 0; d < HQ; ++d)
 #pragma unroll
         for (int k = 0; k < HPT; ++k)
-            hal[d][k] = d < HA ? fetch(idx_in_row(row_of(a, hl.y[k], zs + dir * d), hl.x[k]), hl.ok[k] && d < nk)
+            hal[d][k] = d < HA ? fetch(idx_in_row(row_of<SEL>(a, hl.y[k], zs + dir * d), hl.x[k]), hl.ok[k] && d < nk)
                                : C2{(Tc)0, (Tc)0};
     Tc vr[VD], vir[VD];
     double2 br[VD];
@@ -211,9 +222,9 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     mr[D] = 0.0;
     // step k reads row slot k % 2 and fills the other one
     int2 rfr[2], rhl[2][HPT];
-    rfr[0] = row_of(a, y, zs + dir * (4 + D));
+    rfr[0] = row_of<SEL>(a, y, zs + dir * (4 + D));
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of(a, hl.y[k], zs + dir * HA);
+    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of<SEL>(a, hl.y[k], zs + dir * HA);
     rfr[1] = make_int2(0, 0);
 #pragma unroll
     for (int k = 0; k < HPT; ++k) rhl[1][k] = make_int2(0, 0);
@@ -246,10 +257,16 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
             {
                 // row entries for the next step first, then the loads that use
                 // the entries read last step
-                rfr[srp] = row_of(a, y, z + dir * (5 + D));
+                rfr[srp] = row_of<SEL>(a, y, z + dir * (5 + D));
 #pragma unroll
-                for (int j = 0; j < HPT; ++j) rhl[srp][j] = row_of(a, hl.y[j], z + dir * (1 + HA));
-                const int idf = (k + 4 + D < nk + 4) ? slot_in_row(rfr[sr], x, a.align) : -1;
+                for (int j = 0; j < HPT; ++j) rhl[srp][j] = row_of<SEL>(a, hl.y[j], z + dir * (1 + HA));
+                int idf;
+                if constexpr (SEL) {
+                    const int sl = slot_in_row<true>(rfr[sr], x, a.align);
+                    idf = (k + 4 + D < nk + 4) ? sl : -1;
+                } else {
+                    idf = (k + 4 + D < nk + 4) ? slot_in_row<false>(rfr[sr], x, a.align) : -1;
+                }
                 oid[SLOT(4 + D)] = idf;
                 cv[SLOT(4 + D)] = fetch(idf, true);
                 const bool hlive = k + HA < nk;
@@ -299,6 +316,8 @@ template <bool NTS, int TX, int TY, class Tin, class Tc, class Tout, int MODE, b
 __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile, double2 &pacc) {
     using C2 = typename CT<Tc>::c2;
+    // selects instead of branches in the row lookups (FP64 kernels)
+    constexpr bool SEL = std::is_same<Tc, double>::value;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
     constexpr int PLANE = (TY + 8) * LX;  // one plane buffer; tile holds two
@@ -327,21 +346,21 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     const int nk = (it.w - it.z) * dir;
     C2 q[9];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(row_of(a, y, zs + dir * (j - 4)), x), true);
-    int idx_c = slot_in_row(row_of(a, y, zs), x, a.align);
-    C2 nxt = fetch(idx_in_row(row_of(a, y, zs + dir * 4), x), true);
+    for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(row_of<SEL>(a, y, zs + dir * (j - 4)), x), true);
+    int idx_c = slot_in_row<SEL>(row_of<SEL>(a, y, zs), x, a.align);
+    C2 nxt = fetch(idx_in_row(row_of<SEL>(a, y, zs + dir * 4), x), true);
     C2 hv[HPT];
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
+    for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of<SEL>(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
     Tc v_c = fetch_v(idx_c);
     Tc vi_c = fetch_vi(idx_c);
     double2 b_c = fetch_b(idx_c);
     double m_c = fetch_m(idx_c);
-    int2 rf = row_of(a, y, zs + dir * 5);  // rows for the loads of the first step
-    int2 ro = row_of(a, y, zs + dir);
+    int2 rf = row_of<SEL>(a, y, zs + dir * 5);  // rows for the loads of the first step
+    int2 ro = row_of<SEL>(a, y, zs + dir);
     int2 rh[HPT];
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) rh[j] = row_of(a, hl.y[j], zs + dir);
+    for (int j = 0; j < HPT; ++j) rh[j] = row_of<SEL>(a, hl.y[j], zs + dir);
 
     const double E = a.field_dev ? *a.field_dev : a.field;
     const int own = (ly + 4) * LX + lx + 4;
@@ -356,15 +375,15 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
             if (hl.ok[j]) pl[hl.l[j]] = hv[j];
         __syncthreads();
         // row entries for the next step, then this step's loads (plane k+1)
-        const int2 rf_n = row_of(a, y, z + dir * 6), ro_n = row_of(a, y, z + dir * 2);
+        const int2 rf_n = row_of<SEL>(a, y, z + dir * 6), ro_n = row_of<SEL>(a, y, z + dir * 2);
         int2 rh_n[HPT];
 #pragma unroll
-        for (int j = 0; j < HPT; ++j) rh_n[j] = row_of(a, hl.y[j], z + dir * 2);
+        for (int j = 0; j < HPT; ++j) rh_n[j] = row_of<SEL>(a, hl.y[j], z + dir * 2);
         const bool live = k + 1 < nk;
         nxt = fetch(live ? idx_in_row(rf, x) : -1, true);
 #pragma unroll
         for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(rh[j], hl.x[j]), hl.ok[j] && live);
-        const int idx_n = live ? slot_in_row(ro, x, a.align) : -1;
+        const int idx_n = live ? slot_in_row<SEL>(ro, x, a.align) : -1;
         const Tc v_n = fetch_v(idx_n);
         const Tc vi_n = fetch_vi(idx_n);
         const double2 b_n = fetch_b(idx_n);
