@@ -58,8 +58,7 @@ __device__ __forceinline__ void block_item(const KParams &a, int blk, int *n, in
 // a masked-off lane issues its load at an out-of-range offset, which the
 // buffer hardware answers with zero.
 // SEL: the test as unsigned compares and selects, which keeps the march's
-// step free of branches (used by the FP64 kernels; the FP32 ones keep the
-// plain form, whose code the compiler fits in fewer registers there).
+// step free of branches.
 template <bool SEL>
 __device__ __forceinline__ int2 row_of(const KParams &a, int y, int z) {
     if constexpr (SEL) {

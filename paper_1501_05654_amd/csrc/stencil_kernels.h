@@ -153,7 +153,9 @@ template <bool NTS, int TX, int TY, int D, class Tin, class Tc, class Tout, int 
 __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile, double2 &pacc) {
     using C2 = typename CT<Tc>::c2;
-    // selects instead of branches in the row lookups (FP64 kernels)
+    // selects instead of branches in the row lookups: the row index always,
+    // the slot in the row in the FP64 kernels (in the FP32 ones that select
+    // costs registers at the 4-wave occupancy limit)
     constexpr bool SEL = std::is_same<Tc, double>::value;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
@@ -194,7 +196,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     int oid[Q];
 #pragma unroll
     for (int j = 0; j < Q - 1; ++j) {
-        oid[j] = slot_in_row<SEL>(row_of<SEL>(a, y, zs + dir * (j - 4)), x, a.align);
+        oid[j] = slot_in_row<SEL>(row_of<true>(a, y, zs + dir * (j - 4)), x, a.align);
         cv[j] = fetch(oid[j], true);
     }
     cv[Q - 1] = C2{(Tc)0, (Tc)0};
@@ -204,7 +206,7 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     for (int d = 0; d < HQ; ++d)
 #pragma unroll
         for (int k = 0; k < HPT; ++k)
-            hal[d][k] = d < HA ? fetch(idx_in_row(row_of<SEL>(a, hl.y[k], zs + dir * d), hl.x[k]), hl.ok[k] && d < nk)
+            hal[d][k] = d < HA ? fetch(idx_in_row(row_of<true>(a, hl.y[k], zs + dir * d), hl.x[k]), hl.ok[k] && d < nk)
                                : C2{(Tc)0, (Tc)0};
     Tc vr[VD], vir[VD];
     double2 br[VD];
@@ -222,9 +224,9 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     mr[D] = 0.0;
     // step k reads row slot k % 2 and fills the other one
     int2 rfr[2], rhl[2][HPT];
-    rfr[0] = row_of<SEL>(a, y, zs + dir * (4 + D));
+    rfr[0] = row_of<true>(a, y, zs + dir * (4 + D));
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of<SEL>(a, hl.y[k], zs + dir * HA);
+    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of<true>(a, hl.y[k], zs + dir * HA);
     rfr[1] = make_int2(0, 0);
 #pragma unroll
     for (int k = 0; k < HPT; ++k) rhl[1][k] = make_int2(0, 0);
@@ -257,9 +259,9 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
             {
                 // row entries for the next step first, then the loads that use
                 // the entries read last step
-                rfr[srp] = row_of<SEL>(a, y, z + dir * (5 + D));
+                rfr[srp] = row_of<true>(a, y, z + dir * (5 + D));
 #pragma unroll
-                for (int j = 0; j < HPT; ++j) rhl[srp][j] = row_of<SEL>(a, hl.y[j], z + dir * (1 + HA));
+                for (int j = 0; j < HPT; ++j) rhl[srp][j] = row_of<true>(a, hl.y[j], z + dir * (1 + HA));
                 int idf;
                 if constexpr (SEL) {
                     const int sl = slot_in_row<true>(rfr[sr], x, a.align);
@@ -316,7 +318,9 @@ template <bool NTS, int TX, int TY, class Tin, class Tc, class Tout, int MODE, b
 __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, const int n,
                                            typename CT<Tc>::c2 *tile, double2 &pacc) {
     using C2 = typename CT<Tc>::c2;
-    // selects instead of branches in the row lookups (FP64 kernels)
+    // selects instead of branches in the row lookups: the row index always,
+    // the slot in the row in the FP64 kernels (in the FP32 ones that select
+    // costs registers at the 4-wave occupancy limit)
     constexpr bool SEL = std::is_same<Tc, double>::value;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
@@ -346,21 +350,21 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
     const int nk = (it.w - it.z) * dir;
     C2 q[9];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(row_of<SEL>(a, y, zs + dir * (j - 4)), x), true);
-    int idx_c = slot_in_row<SEL>(row_of<SEL>(a, y, zs), x, a.align);
-    C2 nxt = fetch(idx_in_row(row_of<SEL>(a, y, zs + dir * 4), x), true);
+    for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(row_of<true>(a, y, zs + dir * (j - 4)), x), true);
+    int idx_c = slot_in_row<SEL>(row_of<true>(a, y, zs), x, a.align);
+    C2 nxt = fetch(idx_in_row(row_of<true>(a, y, zs + dir * 4), x), true);
     C2 hv[HPT];
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of<SEL>(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
+    for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of<true>(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
     Tc v_c = fetch_v(idx_c);
     Tc vi_c = fetch_vi(idx_c);
     double2 b_c = fetch_b(idx_c);
     double m_c = fetch_m(idx_c);
-    int2 rf = row_of<SEL>(a, y, zs + dir * 5);  // rows for the loads of the first step
-    int2 ro = row_of<SEL>(a, y, zs + dir);
+    int2 rf = row_of<true>(a, y, zs + dir * 5);  // rows for the loads of the first step
+    int2 ro = row_of<true>(a, y, zs + dir);
     int2 rh[HPT];
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) rh[j] = row_of<SEL>(a, hl.y[j], zs + dir);
+    for (int j = 0; j < HPT; ++j) rh[j] = row_of<true>(a, hl.y[j], zs + dir);
 
     const double E = a.field_dev ? *a.field_dev : a.field;
     const int own = (ly + 4) * LX + lx + 4;
@@ -375,10 +379,10 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
             if (hl.ok[j]) pl[hl.l[j]] = hv[j];
         __syncthreads();
         // row entries for the next step, then this step's loads (plane k+1)
-        const int2 rf_n = row_of<SEL>(a, y, z + dir * 6), ro_n = row_of<SEL>(a, y, z + dir * 2);
+        const int2 rf_n = row_of<true>(a, y, z + dir * 6), ro_n = row_of<true>(a, y, z + dir * 2);
         int2 rh_n[HPT];
 #pragma unroll
-        for (int j = 0; j < HPT; ++j) rh_n[j] = row_of<SEL>(a, hl.y[j], z + dir * 2);
+        for (int j = 0; j < HPT; ++j) rh_n[j] = row_of<true>(a, hl.y[j], z + dir * 2);
         const bool live = k + 1 < nk;
         nxt = fetch(live ? idx_in_row(rf, x) : -1, true);
 #pragma unroll
