@@ -320,10 +320,13 @@ def bench_batch(args):
     with torch.cuda.stream(stream):
         b = rsg.Batch(systems)
         if args.tile:
-            B, TX, TY, ZC, PD, _, _, ZM = fixed_tile(args.tile)
-            b.set_tile(B, TX, TY, ZC, PD, ZM)
+            # one tile for every size class, or one per class (';'-separated)
+            specs_t = args.tile.split(";")
+            for c, spec in enumerate(specs_t):
+                B, TX, TY, ZC, PD, _, _, ZM = fixed_tile(spec)
+                b.set_tile(B, TX, TY, ZC, PD, ZM, cls=None if len(specs_t) == 1 else c)
             tile = b.get_tile()
-            log(f"batch tile {tile} (fixed)")
+            log(f"batch tiles {args.tile} (fixed)")
         else:
             tile, tms = b.autotune(reps=3)
             log(f"batch tile {tile}: {tms:.3f} ms per stage")
@@ -354,13 +357,15 @@ def bench_batch(args):
         t5 = time.perf_counter()
     el = t1 - t0
     value = tot * 4 * args.steps / el
-    # counter summary of this stencil source with every class on one tile
+    # counter summary of this stencil source with these class tiles (one
+    # tile when every class has the same, else one per class, ';'-separated)
     ctraffic, ctraffic_src = None, None
+    keys = [",".join(str(t[k]) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM")) for t in class_tiles]
+    key = keys[0] if all(k == keys[0] for k in keys) else ";".join(keys)
     for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_stencil_batch256_*.txt"))):
         kv = _summary_fields(p)
-        key = ",".join(str(class_tiles[0][k]) for k in ("B", "TX", "TY", "ZC", "PD", "PT", "BO", "ZM"))
         if (kv.get("stencil_source_sha256") == stencil_source_hash() and kv.get("tile") == key
-                and all(t == class_tiles[0] for t in class_tiles) and int(kv.get("row_align", "0")) == args.align):
+                and int(kv.get("row_align", "0")) == args.align):
             ctraffic, ctraffic_src = float(kv["hbm_bytes_per_stage"]), os.path.join("profiles", os.path.basename(p))
             break
     stage_bytes = tot * 32.0  # every stage of the product-form step: read its input, write its output
@@ -978,10 +983,12 @@ def sub_results(args) -> dict:
                              "fd_rel_err": r["fd_rel_err"], "directional_derivative": r["directional_derivative"],
                              "central_fd": r["central_fd"],
                              "sweep_algorithmic_GBs": r["roofline"]["sweep_algorithmic_GBs"]}
-    # every class on 16x16, depth 2: the per-class autotuner's choices measured
-    # within 0.5 % of it on this workload, and with one tile the line can carry
-    # the committed counter summary's traffic
-    r = run("batch256", bench_batch, ns(steps=10, warmup=2, align=8, tile="1,16,16,0,2,0,0,0"))
+    # one tile per size class, timed per class on this workload: 16x16 at
+    # depth 2 for the narrowest and widest classes, 8x8 at depth 2 for the
+    # middle one (fixed, so that the line can carry the committed counter
+    # summary's traffic for exactly these tiles)
+    r = run("batch256", bench_batch, ns(steps=10, warmup=2, align=8,
+                                        tile="1,16,16,0,2,0,0,0;1,8,8,0,2,0,0,0;1,16,16,0,2,0,0,0"))
     out["batch256"] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
                        "stencil_stage_ms": r["roofline"]["stage_ms"], "roofline_frac": r["roofline"]["frac"],
                        "traffic_per_stage": r["roofline"]["traffic"],
@@ -1017,8 +1024,8 @@ def main():
                     help="use the default tile shape instead of timing the candidates")
     ap.add_argument("--tile", default="",
                     help="B,TX,TY,ZC,PD,PT,BO[,ZM]: use this stencil tile instead of autotuning "
-                         "(sphere18_wells, batch256 (PT and BO ignored), cube32_ho, sphere18_cs, and the "
-                         "FP64 steps of sphere18_mixed)")
+                         "(sphere18_wells, batch256 (PT and BO ignored; there also one tile per size class, "
+                         "';'-separated), cube32_ho, sphere18_cs, and the FP64 steps of sphere18_mixed)")
     ap.add_argument("--tile-mixed", default="",
                     help="sphere18_mixed: the same for the FP32 stencil of the mixed steps")
     args = ap.parse_args()
