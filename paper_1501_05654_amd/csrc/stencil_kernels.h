@@ -90,18 +90,22 @@ __device__ __forceinline__ void finish(const KParams &a, typename CT<Tc>::c2 q0,
                                        Tc vi_c, double2 b_c, double m_c, double E, int x, int y, int z,
                                        int idx, __amdgpu_buffer_rsrc_t rout, double2 &pacc) {
     Tc vloc = v_c;
-    if constexpr (PAIR || !std::is_same<Tc, double>::value) {
+    if constexpr (PAIR || (!std::is_same<Tc, double>::value && FIRST)) {
+        // a branch here: in the FP32 first-type stages a select costs
+        // registers at the 4-wave occupancy limit, and the pair stages (which
+        // always have a field axis) measured the same either way
         if (a.axis >= 0) {
             const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
             const double xc = a.h * ((double)cc - a.off_axis);
             vloc += (Tc)(E * xc);
-            pacc.x += xc * ((double)q0.x * b_c.x + (double)q0.y * b_c.y);
-            pacc.y += xc * ((double)q0.x * b_c.y - (double)q0.y * b_c.x);
+            if constexpr (PAIR) {
+                pacc.x += xc * ((double)q0.x * b_c.x + (double)q0.y * b_c.y);
+                pacc.y += xc * ((double)q0.x * b_c.y - (double)q0.y * b_c.x);
+            }
         }
     } else {
-        // the field term as a select (FP64): a branch in the march's step
-        // costs more than the few operations it would skip.  (In the FP32
-        // stages the select costs registers at the 4-wave occupancy limit.)
+        // the field term as a select: a branch in the march's step costs
+        // more than the few operations it would skip
         const int cc = a.axis == 0 ? x : (a.axis == 1 ? y : z);
         const double xc = a.h * ((double)cc - a.off_axis);
         const Tc vf = vloc + (Tc)(E * xc);
@@ -154,9 +158,9 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
                                            typename CT<Tc>::c2 *tile, double2 &pacc) {
     using C2 = typename CT<Tc>::c2;
     // selects instead of branches in the row lookups: the row index always,
-    // the slot in the row in the FP64 kernels (in the FP32 ones that select
-    // costs registers at the 4-wave occupancy limit)
-    constexpr bool SEL = std::is_same<Tc, double>::value;
+    // the slot in the row except in the FP32 stage that reads complex128
+    // (there that select costs registers at the 4-wave occupancy limit)
+    constexpr bool SEL = std::is_same<Tc, double>::value || std::is_same<Tin, float2>::value;
     constexpr int NT = TX * TY, LX = TX + 8;
     constexpr int HPT = (8 * TX + 8 * TY + NT - 1) / NT;
     static_assert(D >= 1 && D <= 2, "pipeline depth 1..2");
