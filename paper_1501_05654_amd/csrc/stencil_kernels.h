@@ -195,12 +195,40 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     const int nk = (it.w - it.z) * dir;  // planes to compute
     // prologue: planes k = -4 .. 3+D into ring slots 0 .. Q-2 (slot of plane
     // k is k + 4), halo of planes 0 .. HA-1, V/base of planes 0 .. D-1, rows
-    // for step 0
+    // for step 0.  Every row entry the prologue needs is requested before
+    // any is used, so that they arrive in one round trip (taking them one
+    // at a time chained a dozen L2 round trips ahead of the first plane);
+    // except in the FP32 stage that reads complex128, where holding them
+    // all costs registers at the 4-wave occupancy limit.
+    constexpr bool HOIST = !(std::is_same<Tc, float>::value && std::is_same<Tin, double2>::value);
+    int2 rw[Q - 1];
+    int2 rwh[HQ][HPT];
+    if constexpr (HOIST) {
+#pragma unroll
+        for (int j = 0; j < Q - 1; ++j) rw[j] = row_of<true>(a, y, zs + dir * (j - 4));
+#pragma unroll
+        for (int d = 0; d < HQ; ++d)
+#pragma unroll
+            for (int k = 0; k < HPT; ++k) rwh[d][k] = row_of<true>(a, hl.y[k], zs + dir * d);
+    }
+    // step k reads row slot k % 2 and fills the other one
+    int2 rfr[2], rhl[2][HPT];
+    rfr[0] = row_of<true>(a, y, zs + dir * (4 + D));
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of<true>(a, hl.y[k], zs + dir * HA);
+    rfr[1] = make_int2(0, 0);
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) rhl[1][k] = make_int2(0, 0);
     C2 cv[Q];
     int oid[Q];
 #pragma unroll
     for (int j = 0; j < Q - 1; ++j) {
-        oid[j] = slot_in_row<SEL>(row_of<true>(a, y, zs + dir * (j - 4)), x, a.align);
+        int2 r;
+        if constexpr (HOIST)
+            r = rw[j];
+        else
+            r = row_of<true>(a, y, zs + dir * (j - 4));
+        oid[j] = slot_in_row<SEL>(r, x, a.align);
         cv[j] = fetch(oid[j], true);
     }
     cv[Q - 1] = C2{(Tc)0, (Tc)0};
@@ -209,9 +237,14 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
 #pragma unroll
     for (int d = 0; d < HQ; ++d)
 #pragma unroll
-        for (int k = 0; k < HPT; ++k)
-            hal[d][k] = d < HA ? fetch(idx_in_row(row_of<true>(a, hl.y[k], zs + dir * d), hl.x[k]), hl.ok[k] && d < nk)
-                               : C2{(Tc)0, (Tc)0};
+        for (int k = 0; k < HPT; ++k) {
+            int2 r;
+            if constexpr (HOIST)
+                r = rwh[d][k];
+            else
+                r = row_of<true>(a, hl.y[k], zs + dir * d);
+            hal[d][k] = fetch(idx_in_row(r, hl.x[k]), hl.ok[k] && d < nk);
+        }
     Tc vr[VD], vir[VD];
     double2 br[VD];
     double mr[VD];
@@ -226,14 +259,6 @@ __device__ __forceinline__ void march_ring(const KParams &a, const int4 it, cons
     vir[D] = (Tc)0;
     br[D] = make_double2(0.0, 0.0);
     mr[D] = 0.0;
-    // step k reads row slot k % 2 and fills the other one
-    int2 rfr[2], rhl[2][HPT];
-    rfr[0] = row_of<true>(a, y, zs + dir * (4 + D));
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) rhl[0][k] = row_of<true>(a, hl.y[k], zs + dir * HA);
-    rfr[1] = make_int2(0, 0);
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) rhl[1][k] = make_int2(0, 0);
 
     const double E = a.field_dev ? *a.field_dev : a.field;
     const int own = (ly + 4) * LX + lx + 4;
@@ -352,23 +377,31 @@ __device__ __forceinline__ void march_lean(const KParams &a, const int4 it, cons
 
     const int zs = it.z, dir = it.w > it.z ? 1 : -1;
     const int nk = (it.w - it.z) * dir;
+    // every row entry of the prologue is requested before any is used (one
+    // round trip, not one per entry)
+    int2 rq[9];  // planes zs - 4 .. zs + 4
+#pragma unroll
+    for (int j = 0; j < 9; ++j) rq[j] = row_of<true>(a, y, zs + dir * (j - 4));
+    int2 rh0[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) rh0[j] = row_of<true>(a, hl.y[j], zs);
+    int2 rf = row_of<true>(a, y, zs + dir * 5);  // rows for the loads of the first step
+    int2 ro = rq[5];                             // plane zs + 1
+    int2 rh[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) rh[j] = row_of<true>(a, hl.y[j], zs + dir);
     C2 q[9];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(row_of<true>(a, y, zs + dir * (j - 4)), x), true);
-    int idx_c = slot_in_row<SEL>(row_of<true>(a, y, zs), x, a.align);
-    C2 nxt = fetch(idx_in_row(row_of<true>(a, y, zs + dir * 4), x), true);
+    for (int j = 0; j < 8; ++j) q[j] = fetch(idx_in_row(rq[j], x), true);
+    int idx_c = slot_in_row<SEL>(rq[4], x, a.align);
+    C2 nxt = fetch(idx_in_row(rq[8], x), true);
     C2 hv[HPT];
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(row_of<true>(a, hl.y[j], zs), hl.x[j]), hl.ok[j]);
+    for (int j = 0; j < HPT; ++j) hv[j] = fetch(idx_in_row(rh0[j], hl.x[j]), hl.ok[j]);
     Tc v_c = fetch_v(idx_c);
     Tc vi_c = fetch_vi(idx_c);
     double2 b_c = fetch_b(idx_c);
     double m_c = fetch_m(idx_c);
-    int2 rf = row_of<true>(a, y, zs + dir * 5);  // rows for the loads of the first step
-    int2 ro = row_of<true>(a, y, zs + dir);
-    int2 rh[HPT];
-#pragma unroll
-    for (int j = 0; j < HPT; ++j) rh[j] = row_of<true>(a, hl.y[j], zs + dir);
 
     const double E = a.field_dev ? *a.field_dev : a.field;
     const int own = (ly + 4) * LX + lx + 4;
