@@ -117,6 +117,12 @@ def fixed_tile(spec: str) -> list:
     return vals + [0] * (8 - len(vals))
 
 
+def class_tiles_spec(spec: str) -> list:
+    """batch256 --tile: one tile for every size class, or one per class
+    separated by ';' (narrowest class first) -> list of eight-field tiles."""
+    return [fixed_tile(t) for t in spec.split(";")]
+
+
 def choose_tile(args, spec, gh, psi, reps, dtype="c128"):
     """The stencil tile of gh for psi's batch: the one spec names, else the
     autotuner's choice (the default shape with --no-autotune)."""
@@ -321,10 +327,9 @@ def bench_batch(args):
         b = rsg.Batch(systems)
         if args.tile:
             # one tile for every size class, or one per class (';'-separated)
-            specs_t = args.tile.split(";")
-            for c, spec in enumerate(specs_t):
-                B, TX, TY, ZC, PD, _, _, ZM = fixed_tile(spec)
-                b.set_tile(B, TX, TY, ZC, PD, ZM, cls=None if len(specs_t) == 1 else c)
+            tiles_t = class_tiles_spec(args.tile)
+            for c, (B, TX, TY, ZC, PD, _, _, ZM) in enumerate(tiles_t):
+                b.set_tile(B, TX, TY, ZC, PD, ZM, cls=None if len(tiles_t) == 1 else c)
             tile = b.get_tile()
             log(f"batch tiles {args.tile} (fixed)")
         else:

@@ -33,3 +33,18 @@ def test_help_names_the_workloads():
     assert r.returncode == 0
     for w in ("sphere18_wells", "batch256", "cube96_control", "cube32_ho", "sphere18_mixed"):
         assert w in r.stdout
+
+
+def test_batch_tiles_one_or_one_per_class():
+    """batch256 --tile: one tile for every size class, or one per class
+    separated by ';'; each tile takes its ZM default and a malformed one
+    stops the run."""
+    import pytest
+
+    import bench
+
+    assert bench.class_tiles_spec("1,16,16,0,2,0,0,0") == [[1, 16, 16, 0, 2, 0, 0, 0]]
+    assert bench.class_tiles_spec("1,16,16,0,2,0,0;1,8,8,0,2,0,0,0") == [[1, 16, 16, 0, 2, 0, 0, 0],
+                                                                         [1, 8, 8, 0, 2, 0, 0, 0]]
+    with pytest.raises(SystemExit):
+        bench.class_tiles_spec("1,16,16;1,8,8,0,2,0,0,0")
